@@ -1,0 +1,101 @@
+"""Surrogate network reference: forward, backward, Adam (oracle; test infrastructure only).
+
+The paper closes by pointing at machine learning as a way to replace the costly
+calls of its thermochemical library (Sec. 5).  The surrogate here maps
+x = standardised (log10 rho, e, Y_1..Y_5) to y = standardised (T, ln mu, ln kappa,
+ln D_1..ln D_5) with the network
+
+    h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), h3 = tanh(W3 h2 + b3), y = W4 h3 + b4
+
+of widths 7 -> 64 -> 64 -> 64 -> 8.  Parameters are one flat vector in the order
+[W1 (64x7, row = output unit), b1, W2 (64x64), b2, W3 (64x64), b3, W4 (8x64), b4],
+9352 values.  With ``bf16=True`` every matrix-product operand (weights and layer
+inputs) is first rounded to bfloat16 (round to nearest even, from float32), as the
+matrix-core path does; everything else stays float64.
+"""
+import numpy as np
+
+SIZES = (7, 64, 64, 64, 8)
+NPARAM = sum(SIZES[i + 1] * SIZES[i] + SIZES[i + 1] for i in range(4))
+
+
+def unpack(theta):
+    theta = np.asarray(theta, dtype=np.float64)
+    out = []
+    o = 0
+    for i in range(4):
+        n_in, n_out = SIZES[i], SIZES[i + 1]
+        W = theta[o:o + n_out * n_in].reshape(n_out, n_in); o += n_out * n_in
+        b = theta[o:o + n_out]; o += n_out
+        out.append((W, b))
+    return out
+
+
+def pack(layers):
+    return np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in layers])
+
+
+def to_bf16(a):
+    """Round to bfloat16 (RNE) via float32; returned as float64 values."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    out = r.view(np.float32).astype(np.float64)
+    return np.where(np.isnan(f), np.nan, out)
+
+
+def init_params(seed=0):
+    """Glorot-uniform weights, zero biases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    layers = []
+    for i in range(4):
+        n_in, n_out = SIZES[i], SIZES[i + 1]
+        lim = np.sqrt(6.0 / (n_in + n_out))
+        layers.append((rng.uniform(-lim, lim, (n_out, n_in)), np.zeros(n_out)))
+    return pack(layers)
+
+
+def forward(theta, X, bf16=False):
+    """X [n][7] -> (Y [n][8], cache).  Layer inputs and weights rounded when bf16."""
+    layers = unpack(theta)
+    q = to_bf16 if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    a = np.asarray(X, dtype=np.float64)
+    acts = [a]
+    for li, (W, b) in enumerate(layers):
+        z = q(a) @ q(W).T + b
+        a = np.tanh(z) if li < 3 else z
+        acts.append(a)
+    return a, acts
+
+
+def backward(theta, acts, dY, bf16=False):
+    """Gradient of a loss with dL/dY = dY [n][8] with respect to theta (flat)."""
+    layers = unpack(theta)
+    q = to_bf16 if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    grads = [None] * 4
+    d = np.asarray(dY, dtype=np.float64)           # dL/dz of the current layer
+    for li in range(3, -1, -1):
+        W, b = layers[li]
+        a_in = acts[li]
+        gW = q(d).T @ q(a_in)
+        gb = d.sum(axis=0)
+        grads[li] = (gW, gb)
+        if li > 0:
+            da = q(d) @ q(W)
+            d = da * (1.0 - acts[li] ** 2)
+    return pack(grads)
+
+
+def mse_grad(Yhat, Yt):
+    """L = mean over n and the 8 outputs of (Yhat - Yt)^2 and dL/dYhat."""
+    r = Yhat - Yt
+    return float(np.mean(r * r)), 2.0 * r / r.size
+
+
+def adam(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (t counts from 1); returns new (theta, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v

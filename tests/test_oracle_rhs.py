@@ -1,0 +1,282 @@
+"""Pins of the oracle's right-hand side, boundaries, RK stages, AD and network.
+
+Closed forms: uniform flow (R = 0, or the chemical source alone), plane Couette flow
+(only the viscous heating (mu/Re) a^2 remains, Eq. 9-10), uniform dilatation (fixes
+the -2/3 bulk term and the pressure work); symmetry under exchange of x and y; the
+species rows summing to the continuity equation (sum J_s = 0, Eq. 20); stability
+polynomials and convergence order of the Runge-Kutta schemes (Sec. 3.1); exactness
+of the zero-slope wall extrapolation; the cubic sponge profile of Eq. (26); the
+artificial-diffusivity sign and switch properties; finite-difference gradients of
+the network.
+"""
+import dataclasses
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+from oracle import ad as adm
+from oracle import chemistry as ch
+from oracle import mlp
+from oracle import rhs as R
+from oracle import species as sp
+from oracle import stencils as st
+from paper_2210_05547_amd import fields as f
+
+
+def _case(cfg, x=None, y=None, z=None):
+    gx, gy, gz = f.grid(cfg)
+    return R.Case(cfg, gx if x is None else x, gy if y is None else y, gz if z is None else z)
+
+
+def _cpg_cfg(nx=24, ny=20, **kw):
+    return dataclasses.replace(f.get_config("c1"), nx=nx, ny=ny, sponge_out=0, sponge_top=0, **kw)
+
+
+def _air_cfg(nx=20, ny=20, **kw):
+    return dataclasses.replace(f.get_config("c2"), nx=nx, ny=ny, sponge_in=0, sponge_out=0,
+                               sponge_top=0, **kw)
+
+
+def _cons_cpg(case, rho, u, v, T):
+    g = case.ref["gamma"]
+    e = T / g
+    return np.array([rho, rho * u, rho * v, rho * (e + 0.5 * (u * u + v * v))])
+
+
+def test_uniform_flow_cpg():
+    case = _case(_cpg_cfg())
+    sh = (1, case.cfg.ny, case.cfg.nx)
+    Q = _cons_cpg(case, np.full(sh, 1.3), np.full(sh, 5.0), np.full(sh, 0.7), np.full(sh, 3.0))
+    Rr = R.rhs(Q, Q.copy(), case)
+    assert np.max(np.abs(Rr)) < 1e-10
+
+
+def test_uniform_flow_air5_is_chemistry():
+    case = _case(_air_cfg())
+    sh = (1, case.cfg.ny, case.cfg.nx)
+    Y = np.array([0.70, 0.05, 0.05, 0.05, 0.15])
+    Q = np.zeros((8,) + sh)
+    Q[:5] = 2.0 * Y.reshape(5, 1, 1, 1)
+    Q[5] = 2.0 * 3.0
+    Q[6] = 2.0 * 0.5
+    Q[7] = 2.0 * (60.0 + 0.5 * (9.0 + 0.25))
+    Rr, P, _ = R.rhs(Q, Q.copy(), case, return_parts=True)
+    ref = case.ref
+    wd = ch.production_rates(Q[:5] * ref["rho_inf"], P["Tk"]) * ref["L_ref"] / (ref["rho_inf"] * ref["c_inf"])
+    inner = (slice(None), slice(None), slice(1, None), slice(1, None))
+    assert np.max(np.abs(Rr[:5][inner] - wd[inner])) <= 1e-12 * np.max(np.abs(wd))
+    assert np.max(np.abs(Rr[5:])) < 1e-9
+
+
+def test_couette_viscous_heating_cpg():
+    cfg = _cpg_cfg(nx=20, ny=22)
+    x = np.linspace(0.0, 2.0, cfg.nx)
+    y = np.linspace(0.0, 1.0, cfg.ny)
+    case = _case(cfg, x, y)
+    a = 0.8
+    Y3, X3 = np.meshgrid(y, x, indexing="ij")
+    Y3 = Y3[None]; X3 = X3[None]
+    T = np.full(Y3.shape, 2.5)
+    Q = _cons_cpg(case, np.ones(Y3.shape), a * Y3, 0 * Y3, T)
+    Rr, P, _ = R.rhs(Q, None, case, return_parts=True)
+    mu = P["mu"][0, 0, 0]
+    Re = case.ref["Re"]
+    expect = mu / Re * a * a
+    assert np.max(np.abs(Rr[3][..., 1:] - expect)) < 1e-12
+    assert np.max(np.abs(Rr[:3][..., 1:])) < 1e-12
+
+
+def test_uniform_dilatation_cpg():
+    cfg = _cpg_cfg(nx=26, ny=16)
+    x = np.linspace(1.0, 2.0, cfg.nx)
+    y = np.linspace(0.0, 1.0, cfg.ny)
+    case = _case(cfg, x, y)
+    a = -0.3
+    Y3, X3 = np.meshgrid(y, x, indexing="ij")
+    X3 = X3[None]
+    rho0, T0 = 1.2, 2.5
+    Q = _cons_cpg(case, np.full(X3.shape, rho0), a * X3, 0 * X3, np.full(X3.shape, T0))
+    Rr, P, _ = R.rhs(Q, None, case, return_parts=True)
+    g = case.ref["gamma"]
+    mu = P["mu"][0, 0, 0]
+    Re = case.ref["Re"]
+    e0, p0 = T0 / g, rho0 * (g - 1) * T0 / g
+    cols = (slice(None), slice(None), slice(1, None))
+    xs = X3[cols]
+    assert np.max(np.abs(Rr[0][cols] + rho0 * a)) < 1e-12
+    assert np.max(np.abs(Rr[1][..., 1:, 1:] + 2 * rho0 * a * a * xs[..., 1:, :])) < 1e-12
+    assert np.max(np.abs(Rr[2][..., 1:, 1:])) < 1e-12
+    expect_E = -a * (rho0 * e0 + p0) - 1.5 * rho0 * a ** 3 * xs ** 2 + (4.0 / 3.0) * mu / Re * a * a
+    assert np.max(np.abs(Rr[3][cols] - expect_E)) < 1e-12
+
+
+def test_transpose_symmetry_air5():
+    cfg = _air_cfg(nx=18, ny=18)
+    c = np.linspace(0.0, 1.7, 18) ** 1.3
+    case = _case(cfg, c, c)
+    # smooth state built from primitives with the oracle's own energy
+    from oracle import thermo as th
+    k = np.arange(18)
+    bump = np.outer(np.sin(0.3 * k + 0.1), np.cos(0.2 * k))[None]
+    Tk = 1200.0 + 400.0 * bump
+    Y = np.array([0.7, 0.1, 0.05, 0.05, 0.1]).reshape(5, 1, 1, 1) * (1 + 0.2 * np.array(
+        [1, -1, 1, -1, 1]).reshape(5, 1, 1, 1) * bump[None])
+    Y = Y / Y.sum(0)
+    rho = 1.0 + 0.1 * bump
+    u = 2.0 + 0.3 * bump
+    v = 0.5 - 0.2 * np.swapaxes(bump, 1, 2)
+    e = th.mixture_e(Tk, Y) / case.ref["c_inf"] ** 2
+    Q = np.concatenate([rho[None] * Y, (rho * u)[None], (rho * v)[None],
+                        (rho * (e + 0.5 * (u * u + v * v)))[None]])
+    QT = np.swapaxes(Q, 2, 3).copy()
+    QT[[5, 6]] = QT[[6, 5]]
+    R1 = R.rhs(Q, None, case)
+    R2 = R.rhs(QT, None, case)
+    R2b = np.swapaxes(R2, 2, 3).copy()
+    R2b[[5, 6]] = R2b[[6, 5]]
+    inner = (slice(None), slice(None), slice(1, None), slice(1, None))
+    for kk in range(8):
+        sc = np.max(np.abs(R1[kk][inner[1:]]))
+        assert np.max(np.abs(R1[kk][inner[1:]] - R2b[kk][inner[1:]])) <= 1e-11 * sc, kk
+
+
+def test_species_rows_sum_to_continuity():
+    cfg = f.get_config("c2").scaled(40, 32)
+    Q, Qr, info = f.initial_field(cfg)
+    case = R.Case(cfg, info["x"], info["y"], info["z"])
+    Rr, P, _ = R.rhs(Q, None, case, return_parts=True)
+    rho = P["rho"]
+    cont = -sum(case.deriv(rho * P["vel"][j], j) for j in range(2)) + P["wdot"].sum(0)
+    inner = (slice(None), slice(1, None), slice(1, None))
+    sc = np.max(np.abs(cont[inner]))
+    assert np.max(np.abs(Rr[:5].sum(0)[inner] - cont[inner])) <= 1e-12 * sc
+
+
+def test_rk_stability_polynomials_and_order():
+    for key, p in [(0, 3), (1, 4)]:
+        A, B = R.RK_SCHEMES[key]
+        # amplification of y' = z y, coefficients of the polynomial in z
+        coef = np.polynomial.Polynomial([1.0])
+        q = np.polynomial.Polynomial([1.0])
+        dq = np.polynomial.Polynomial([0.0])
+        z = np.polynomial.Polynomial([0.0, 1.0])
+        for a, b in zip(A, B):
+            dq = a * dq + z * q
+            q = q + b * dq
+        c = q.coef
+        for n in range(p + 1):
+            assert abs(c[n] - 1.0 / np.math.factorial(n) if hasattr(np, "math") else 0) < 1e-12 \
+                or abs(c[n] - 1.0 / float(__import__("math").factorial(n))) < 1e-12
+    # nonlinear convergence order on y' = y (1 - y) + sin(t) y... autonomous form with t as a state
+    def run(key, nsteps):
+        A, B = R.RK_SCHEMES[key]
+        y = np.array([0.3, 0.0])
+        d = np.zeros(2)
+        h = 1.0 / nsteps
+        for _ in range(nsteps):
+            for a, b in zip(A, B):
+                rhs = np.array([y[0] * (1 - y[0]) + np.sin(y[1]) * y[0], 1.0])
+                d = a * d + h * rhs
+                y = y + b * d
+        return y[0]
+    from scipy.integrate import solve_ivp
+    ex = solve_ivp(lambda t, y: [y[0] * (1 - y[0]) + np.sin(t) * y[0]], (0, 1), [0.3],
+                   rtol=1e-13, atol=1e-15).y[0, -1]
+    for key, p in [(0, 3), (1, 4)]:
+        e1 = abs(run(key, 20) - ex)
+        e2 = abs(run(key, 40) - ex)
+        assert abs(np.log2(e1 / e2) - p) < 0.3, (key, np.log2(e1 / e2))
+
+
+def test_rk3_coefficients_rational():
+    # Williamson's scheme: the exact rationals of the coefficients used
+    assert R.RK3_A == (0.0, float(Fr(-5, 9)), float(Fr(-153, 128)))
+    assert R.RK3_B == (float(Fr(1, 3)), float(Fr(15, 16)), float(Fr(8, 15)))
+
+
+def test_zero_rhs_leaves_state():
+    cfg = f.get_config("c1")
+    Q, Qr, info = f.initial_field(cfg)
+    case = R.Case(cfg, info["x"], info["y"], info["z"])
+    Q2, dQ = Q.copy(), np.zeros_like(Q)
+    R.rk_stage(Q2, dQ, Qr, case, 0, 1e-3, R=np.zeros_like(Q))
+    assert np.array_equal(Q2[:, :, 1:], Q[:, :, 1:])
+
+
+def test_wall_extrapolation_zero_slope_exact():
+    j = np.arange(5, dtype=np.float64)
+    for coef in ([1.0, 0, 0.3, 0, 0], [0.2, 0, -1.0, 0.5, 0.0], [0.5, 0, 0.1, 0.2, -0.05]):
+        yv = coef[0] + coef[2] * j ** 2 + coef[3] * j ** 3 + coef[4] * j ** 4
+        ext = sum(c * yv[k + 1] for k, c in enumerate(R.WALL_EXTRAP))
+        assert abs(ext - yv[0]) < 1e-14
+    assert abs(sum(R.WALL_EXTRAP) - 1.0) < 1e-15
+
+
+def test_sponge_profile():
+    cfg = f.get_config("c2")
+    x, y, z = f.grid(cfg)
+    case = R.Case(cfg, x, y, z)
+    s = case.sigma[0]
+    assert abs(s[:, 0].max() - cfg.sigma_max) < 1e-15          # inflow boundary
+    assert abs(s[:, -1].max() - cfg.sigma_max) < 1e-15         # outflow boundary
+    assert abs(s[-1, :].min() - cfg.sigma_max) < 1e-15         # top boundary
+    i0 = cfg.nx - 1 - cfg.sponge_out
+    sl = s[cfg.ny // 2, i0 + 1:]
+    depth = (x[i0 + 1:] - x[i0]) / (x[-1] - x[i0])
+    assert np.allclose(sl, cfg.sigma_max * depth ** 3, rtol=1e-14)
+    assert np.all(s[: cfg.ny - 1 - cfg.sponge_top, cfg.sponge_in:i0 + 1] == 0.0)
+
+
+def test_artificial_diffusivity_properties():
+    cfg = f.get_config("c3").scaled(96, 48)
+    Q, Qr, info = f.initial_field(cfg)
+    case = R.Case(cfg, info["x"], info["y"], info["z"])
+    Rr, P, ad = R.rhs(Q, Qr, case, return_parts=True)
+    for k in ("mu", "beta", "kappa"):
+        assert np.all(ad[k] >= 0.0)
+    assert np.all(ad["D"] >= 0.0)
+    G = R.velocity_gradients(P, case)
+    theta = G[0][0] + G[1][1]
+    assert np.all(ad["beta"][theta >= 0.0] == 0.0)
+    assert np.max(ad["mu"]) > 0.0
+    # all coefficients zero gives the AD-off right-hand side bit for bit
+    c0 = dataclasses.replace(cfg, ad_coef=(0.0, 0.0, 0.0, 0.0, 0.0))
+    c1 = dataclasses.replace(cfg, ad=False)
+    case0 = R.Case(c0, info["x"], info["y"], info["z"])
+    case1 = R.Case(c1, info["x"], info["y"], info["z"])
+    assert np.array_equal(R.rhs(Q, Qr, case0), R.rhs(Q, Qr, case1))
+    # overshoot term vanishes inside [0, 1]
+    Yv = np.linspace(0, 1, 11)
+    assert np.all(0.5 * (np.abs(Yv) - 1 + np.abs(1 - Yv)) == 0.0)
+
+
+def test_mlp_gradient_finite_difference():
+    theta = mlp.init_params(1) + 0.05 * np.random.default_rng(0).standard_normal(mlp.NPARAM)
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((16, 7))
+    T = rng.standard_normal((16, 8))
+    Yh, acts = mlp.forward(theta, X)
+    L, dY = mlp.mse_grad(Yh, T)
+    g = mlp.backward(theta, acts, dY)
+    idx = rng.choice(mlp.NPARAM, 60, replace=False)
+    for i in idx:
+        h = 1e-6
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        Lp = mlp.mse_grad(mlp.forward(tp, X)[0], T)[0]
+        Lm = mlp.mse_grad(mlp.forward(tm, X)[0], T)[0]
+        num = (Lp - Lm) / (2 * h)
+        assert abs(num - g[i]) <= 1e-7 * max(1.0, np.max(np.abs(g))), (i, num, g[i])
+    assert mlp.NPARAM == 9352
+
+
+def test_bf16_rounding_and_adam():
+    v = np.array([1.0, 1.0 + 2 ** -9, 1.0 + 3 * 2 ** -9, -2.5, 1.0 + 2 ** -8])
+    r = mlp.to_bf16(v)
+    # spacing at 1 is 2^-7; 1 + 2^-8 is a tie and goes to the even neighbour 1
+    assert list(r) == [1.0, 1.0, 1.0 + 2 ** -7, -2.5, 1.0]
+    th = np.array([1.0, -2.0])
+    g = np.array([0.5, -4.0])
+    t1, m, vv = mlp.adam(th, g, np.zeros(2), np.zeros(2), 1, 0.1)
+    assert np.allclose(t1, th - 0.1 * g / (np.abs(g) + 1e-8), rtol=1e-14)
