@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Throughput of the right-hand side + low-storage RK stage on one MI355X.
+
+One step = one hrx_rk_stage call: primitive/thermochemistry pass (Newton energy
+inversion, mixture transport, finite-rate chemistry), flux pass (stencil gradients,
+convective + viscous + diffusive fluxes), divergence + source + sponge + RK update,
+wall-row update.  Inputs are the seeded synthetic 5-species-air flat-plate field
+(512 x 256, M = 10, FP64), resident in HBM before timing starts.
+
+Prints one JSON line with the metric, the dominant kernel's roofline position
+(per-kernel HIP-event durations inside the timed region) and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+# Algorithmic HBM bytes per grid point of each kernel (FP64 planes read once + written
+# once; stencil neighbours counted once), for a 2-D 5-species-air stage without AD:
+#   prim : read Q (8 planes), write W (u, v, T, X_1..5, p, mu, kappa, D_1..5, wdot_1..5: 21)
+#   flux : read W (u, v, T, X_s, p, mu, kappa, D_s: 16) + Q (8), write F (2 x 8)
+#   div  : read F (16) + wdot (5) + Q (8) + dQ (8), write Q, dQ (16)  (+ Q_ref in sponges)
+BYTES_PER_POINT_AIR5_2D = {"prim": 8 * (8 + 21), "flux": 8 * (16 + 8 + 16),
+                           "div": 8 * (16 + 5 + 8 + 8 + 16)}
+
+
+def sponge_fraction(cfg):
+    import numpy as np
+    from paper_2210_05547_amd import fields
+    nx, ny = cfg.nx, cfg.ny
+    m = np.zeros((ny, nx), bool)
+    if cfg.sponge_in:
+        m[:, :cfg.sponge_in] = True
+    if cfg.sponge_out:
+        m[:, nx - cfg.sponge_out:] = True
+    if cfg.sponge_top:
+        m[ny - cfg.sponge_top:, :] = True
+    return float(m.mean())
+
+
+def cpu_baseline(cfg, Q, Qr, info, budget_s):
+    """Oracle stages on the same field until about budget_s seconds of CPU work."""
+    import numpy as np
+    from oracle import rhs as orhs
+    case = orhs.Case(cfg, info["x"], info["y"], info["z"], info["hold"])
+    Qo, dQo = Q.copy(), np.zeros_like(Q)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        orhs.rk_stage(Qo, dQo, Qr, case, n, info["dt"])
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=cfg.npts * n / dt / 1e6, unit="Mpts/s", cores=1, kind="oracle",
+                sample=f"{n} RK stages of the same {cfg.nx}x{cfg.ny} field, numpy FP64, "
+                       f"single thread, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path's multi-GPU sharding is described in DESIGN.md, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2210_05547_amd import fields, hrx
+
+    cfg = fields.get_config(args.config)
+    Q, Qr, info = fields.initial_field(cfg)
+    dev = torch.device("cuda:0")
+    ctx = hrx.Context(cfg, info["x"], info["y"], info["z"], info["hold"])
+    Qd = torch.from_numpy(Q).to(dev)
+    Qrd = torch.from_numpy(Qr).to(dev)
+    dQd = torch.zeros_like(Qd)
+    stage = 0
+    for _ in range(args.warmup):
+        hrx.rk_stage(ctx, stage, info["dt"], Qd, dQd, Qrd)
+        stage += 1
+    torch.cuda.synchronize()
+    hrx.timing_enable(ctx, True)
+    hrx.timing_read(ctx)
+    hrx.timing_enable(ctx, False)
+    hrx.timing_enable(ctx, True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(args.steps):
+        hrx.rk_stage(ctx, stage, info["dt"], Qd, dQd, Qrd)
+        stage += 1
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    kt = hrx.timing_read(ctx)
+    hrx.timing_enable(ctx, False)
+    cnt = ctx.counters()
+    finite = bool(torch.isfinite(Qd).all())
+    value = cfg.npts * args.steps / (ms * 1e-3) / 1e6
+
+    kernels = {}
+    for name, (tms, nl) in kt.items():
+        if nl:
+            kernels[name] = dict(avg_us=1e3 * tms / nl, launches=nl)
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+    bpp = dict(BYTES_PER_POINT_AIR5_2D)
+    if cfg.gas == 1 and cfg.ndim == 2 and not cfg.ad:
+        bpp["div"] = bpp["div"] + 8 * 8 * sponge_fraction(cfg)
+    for name, kd in kernels.items():
+        if name in bpp:
+            kd["GBps"] = bpp[name] * cfg.npts / (kd["avg_us"] * 1e-6) / 1e9
+    roof = None
+    if dom in bpp:
+        ach = bpp[dom] * cfg.npts / (kernels[dom]["avg_us"] * 1e-6) / 1e9
+        roof = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+    out = {
+        "metric": "grid-point RHS+RK-stage evals/s (Mpts/s), FP64",
+        "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded flat-plate boundary-layer field)",
+        "config": {"workload": cfg.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "points": cfg.npts,
+                   "gas": "air5" if cfg.gas == 1 else "cpg", "rk": "2N-RK3",
+                   "fd_order": cfg.fd_order, "artificial_diffusivity": bool(cfg.ad)},
+        "roofline": roof,
+        "kernels": kernels,
+        "state_finite": finite,
+        "newton_failures": cnt["newton_nonconverged"] + cnt["energy_below_min"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, Q, Qr, info, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,156 @@
+/* hrx: right-hand side and explicit Runge-Kutta stage of the multi-species reacting
+ * compressible Navier-Stokes equations on a structured grid, for AMD MI355X (gfx950).
+ *
+ * The method is that of Margaritis et al., "Development of a high-fidelity
+ * computational tool for chemically reacting hypersonic flow simulations"
+ * (arXiv 2210.05547): the governing equations of Sec. 2.1 in the compact flux form of
+ * Eqs. (5)-(6), nondimensionalised by Eq. (7), with the thermodynamic, transport
+ * and finite-rate chemistry models of Sec. 2.2, the sponge of Eq. (26) (Sec. 3.2),
+ * artificial-diffusivity shock capturing (Sec. 3.3) and low-storage explicit
+ * Runge-Kutta stages (Sec. 3.1).
+ *
+ * Conventions for every call below.
+ *  - Array arguments are DEVICE pointers owned by the caller unless marked (host).
+ *    The library never allocates or frees in the compute calls; hrx_create allocates
+ *    the context's scratch once.
+ *  - Fields are structure-of-arrays planes of doubles, x fastest:
+ *    f[v][k][j][i] at offset ((v*nz + k)*ny + j)*nx + i, N = nx*ny*nz points.
+ *  - Conserved state Q (nondimensional, Eq. 7):
+ *      calorically perfect gas:  [rho, rho u, rho v, (rho w), rho E]
+ *      5-species air:            [rho_N2, rho_O2, rho_NO, rho_N, rho_O, rho u, rho v,
+ *                                 (rho w), rho E]  (all species equations, no global
+ *                                 continuity: the alternative named in Sec. 2.1)
+ *  - Calls are asynchronous on the given HIP stream (NULL = default stream).  Argument
+ *    errors are returned synchronously; per-point failures (energy inversion) are
+ *    reported through status arrays and the counters of hrx_get_counters.
+ *  - A context is not thread-safe; calls on one context must not overlap.
+ *  - Every function returns HRX_OK (0) or a negative hrx_status; nothing aborts.
+ */
+#ifndef HRX_H
+#define HRX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HRX_OK = 0,
+  HRX_EINVAL = -1,   /* bad argument or configuration */
+  HRX_EHIP = -2,     /* a HIP runtime call failed */
+  HRX_ENOMEM = -3,   /* scratch allocation failed in hrx_create */
+  HRX_EUNSUP = -4    /* valid request that this build does not support */
+} hrx_status;
+
+enum { HRX_GAS_CPG = 0, HRX_GAS_AIR5 = 1 };
+enum { HRX_WALL_ADIABATIC = 0, HRX_WALL_ISOTHERMAL = 1 };
+enum { HRX_RK3_2N = 0, HRX_RK45_2N = 1 };
+enum { HRX_PREC_FP64 = 0, HRX_PREC_MIXED = 1 };
+
+/* Workload description (host).  Sec. 2.1 (reference scales, Eq. 7 and 11), Sec. 3.2
+ * (sponges, wall), Sec. 3.3 (artificial diffusivity), Sec. 4 (case parameters). */
+typedef struct hrx_config {
+  int gas;                  /* HRX_GAS_* */
+  int nx, ny, nz;           /* grid points; nz = 1 for a 2-D problem; nx, ny >= 8 */
+  const double *x, *y, *z;  /* (host) separable coordinates, nondimensional; x, y
+                               non-periodic, z uniform and periodic (may be NULL if nz = 1) */
+  int fd_order;             /* 4 or 6: explicit central differences, one-sided ends */
+  int rk_scheme;            /* HRX_RK3_2N or HRX_RK45_2N */
+  int precision;            /* HRX_PREC_FP64 or HRX_PREC_MIXED */
+  int ad_on;                /* artificial diffusivity on/off */
+  double ad_coef[5];        /* C_mu, C_beta, C_kappa, C_D, C_Y */
+  double gamma, Pr;         /* calorically perfect gas only */
+  double mach;              /* free-stream Mach number (informational) */
+  double T_inf;             /* K */
+  double p_inf;             /* Pa (air5) */
+  double Re;                /* free-stream Reynolds number (used when L_ref <= 0) */
+  double L_ref;             /* m (air5); > 0 fixes L_ref and derives Re */
+  double Y_inf[5];          /* free-stream mass fractions (air5) */
+  int wall;                 /* HRX_WALL_* at j = 0 */
+  double T_wall;            /* K, isothermal wall */
+  int sponge_in, sponge_out, sponge_top;  /* sponge extents in points */
+  double sigma_max;         /* sponge strength at the boundary (nondimensional) */
+  const int64_t *hold;      /* (host) flat indices of held (Dirichlet) points, all in
+                               the first three wall rows, or NULL */
+  int64_t n_hold;
+  int newton_max_iter;      /* <= 0: 50 */
+  double newton_rtol;       /* <= 0: 1e-13 */
+} hrx_config;
+
+typedef struct hrx_ctx hrx_ctx;
+
+/* Reference state derived by hrx_create (host), for callers that convert units. */
+typedef struct hrx_reference {
+  double gamma, Re, Pr, Ec;         /* Ec is the computed value (1 by construction) */
+  double T_ref;                     /* K: (gamma_inf - 1) T_inf (Sec. 2.1) */
+  double rho_inf, c_inf, mu_inf, kappa_inf, R_inf, L_ref;   /* SI (air5) */
+} hrx_reference;
+
+typedef struct hrx_counters {
+  int64_t newton_nonconverged;      /* points with no convergence in newton_max_iter */
+  int64_t energy_below_min;         /* points with e < e(50 K) */
+  int64_t surrogate_fallbacks;      /* reserved */
+} hrx_counters;
+
+/* Validate cfg, derive the reference state (Sec. 2.1, Eqs. 7 and 11), the metrics and
+ * sponge profiles, and allocate the context's scratch on the current HIP device.
+ * Returns HRX_EINVAL for an invalid configuration, HRX_ENOMEM if scratch does not
+ * fit.  Runs no kernels. */
+int hrx_create(const hrx_config *cfg, hrx_ctx **out);
+void hrx_destroy(hrx_ctx *ctx);
+int hrx_get_reference(const hrx_ctx *ctx, hrx_reference *out /* (host) */);
+
+/* R = F(Q) - sigma (Q - Q_ref): Eq. (5)-(6) with Eq. (26).  Q, Q_ref, R: [nvar][N].
+ * Q_ref may be NULL (no sponge term).  Rows with boundary conditions: the inflow
+ * column (i = 0) and held points get R = 0; the wall row (j = 0) gets zero momentum
+ * rows.  R must not alias Q. */
+int hrx_rhs_eval(hrx_ctx *ctx, const double *Q, const double *Q_ref, double *R,
+                 void *hip_stream);
+
+/* One low-storage stage k = stage mod (number of stages of the scheme), Sec. 3.1:
+ *   dQ <- A_k dQ + dt F(Q);  Q <- Q + B_k dQ;  then the wall-row update
+ * (no-slip, non-catalytic zero-gradient mass fractions, isothermal or adiabatic
+ * energy).  Q, dQ: [nvar][N], updated in place; dQ must be zero-initialised or hold
+ * the previous stage's register.  Q_ref as in hrx_rhs_eval. */
+int hrx_rk_stage(hrx_ctx *ctx, int stage, double dt, double *Q, double *dQ,
+                 const double *Q_ref, void *hip_stream);
+
+/* Pointwise 5-species-air state in SI units (Sec. 2.2.1, Sec. 3.4): from density
+ * rho [kg/m^3], internal energy e [J/kg] (including formation enthalpies) and mass
+ * fractions Y [5][n], return T [K] (Newton inversion of e(T)), p = rho R_mix T [Pa],
+ * species enthalpies h [5][n] [J/kg], viscosity mu [Pa s], frozen conductivity kappa
+ * [W/(m K)], averaged diffusion coefficients D [5][n] [m^2/s] (Eq. 19) and status
+ * [n] (0 converged, 1 no convergence, 2 e below e(50 K)); status may be NULL.
+ * Any of p, h, mu, kappa, D may be NULL to skip it.  ctx must be an air5 context. */
+int hrx_thermo_eval(hrx_ctx *ctx, int64_t n, const double *rho, const double *e,
+                    const double *Y, double *T, double *p, double *h, double *mu,
+                    double *kappa, double *D, int32_t *status, void *hip_stream);
+
+/* Net mass production rates of the 5-species mechanism (Eqs. 13-15), SI:
+ * rho_s [5][n] kg/m^3 and T [n] K -> wdot [5][n] kg/(m^3 s).  ctx: air5 context. */
+int hrx_chem_source(hrx_ctx *ctx, int64_t n, const double *rho_s, const double *T,
+                    double *wdot, void *hip_stream);
+
+/* Accumulated failure counters; synchronises the context's last stream.  reset != 0
+ * zeroes them afterwards. */
+int hrx_get_counters(hrx_ctx *ctx, hrx_counters *out /* (host) */, int reset);
+
+/* Per-kernel timing with HIP events recorded on the launching stream around every
+ * kernel of the calls that follow hrx_timing_enable(ctx, 1).  Kernel ids (index into
+ * the arrays of hrx_timing_read): 0 prim, 1 ad_src, 2 ad_d4, 3 ad_filter_x,
+ * 4 ad_filter_y, 5 ad_filter_z, 6 flux, 7 div, 8 bc, 9 thermo_eval, 10 chem_source.
+ * hrx_timing_read synchronises, returns the summed milliseconds and launch counts
+ * per kernel since enabling (arrays of HRX_NKERNELS, host) and keeps timing on.
+ * hrx_timing_enable(ctx, 0) stops and releases the events. */
+#define HRX_NKERNELS 11
+int hrx_timing_enable(hrx_ctx *ctx, int on);
+int hrx_timing_read(hrx_ctx *ctx, double *ms /* (host) */, int64_t *launches /* (host) */);
+
+const char *hrx_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,370 @@
+// Pointwise thermochemistry of 5-species air (N2, O2, NO, N, O) and of a calorically
+// perfect gas, written for gfx950 device code and usable on the host.
+//
+// Paper: Sec. 2.2.1 (mixture sums, Eq. 12; finite-rate chemistry, Eqs. 13-15;
+// Ramshaw diffusion with the averaged coefficient, Eqs. 18-19; frozen conductivity
+// in the heat flux), Sec. 2.2.2 (CPG, Eq. 22; Sutherland, Eq. 24) and Sec. 3.4 (every
+// state evaluation needs the iterative solution of a nonlinear equation: here the
+// Newton inversion of e(T)).  The paper delegates species data and mixture rules to
+// a thermochemical library without printing them; the model used here is
+//  * rigid-rotor/harmonic-oscillator species with the ground electronic multiplet
+//    lumped into a degeneracy and 0 K formation enthalpies,
+//  * first Chapman-Enskog transport with Lennard-Jones 12-6 collision integrals
+//    (Neufeld-Janzen-Aziz fits), Eucken conductivities and Wilke mixing,
+//  * Park's 5-species air mechanism in third-body form with equilibrium constants
+//    from the species Gibbs energies.
+// Every function is templated on the floating type R of the transport and rate
+// arithmetic (double for the FP64 path, float where the mixed form allows it);
+// the energy inversion is always double.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#define HRX_HD __host__ __device__ __forceinline__
+
+namespace hrx {
+
+constexpr int NS = 5;
+
+// SI 2019 exact constants
+constexpr double KB = 1.380649e-23;
+constexpr double HPL = 6.62607015e-34;
+constexpr double NAV = 6.02214076e23;
+constexpr double RU = KB * NAV;
+constexpr double P0 = 1.0e5;          // standard-state pressure of the Gibbs energies
+constexpr double PI = 3.14159265358979323846;
+
+// species order N2, O2, NO, N, O
+HRX_HD double molar_mass(int s) {
+  constexpr double m[NS] = {28.0134e-3, 31.9988e-3, 30.0061e-3, 14.0067e-3, 15.9994e-3};
+  return m[s];
+}
+HRX_HD double theta_vib(int s) {
+  constexpr double t[NS] = {3393.5, 2273.6, 2739.7, 0.0, 0.0};
+  return t[s];
+}
+HRX_HD double theta_rot(int s) {
+  constexpr double t[NS] = {2.875, 2.080, 2.406, 1.0, 1.0};
+  return t[s];
+}
+HRX_HD double sym_number(int s) {
+  constexpr double t[NS] = {2.0, 2.0, 1.0, 1.0, 1.0};
+  return t[s];
+}
+HRX_HD double g_elec(int s) {
+  constexpr double t[NS] = {1.0, 3.0, 4.0, 4.0, 9.0};
+  return t[s];
+}
+HRX_HD double hf0_molar(int s) {   // J/mol at 0 K
+  constexpr double t[NS] = {0.0, 0.0, 89.775e3, 470.82e3, 246.79e3};
+  return t[s];
+}
+HRX_HD bool is_diatomic(int s) { return s < 3; }
+HRX_HD double lj_sigma(int s) {    // m
+  constexpr double t[NS] = {3.798e-10, 3.467e-10, 3.492e-10, 3.298e-10, 3.050e-10};
+  return t[s];
+}
+HRX_HD double lj_eps(int s) {      // K
+  constexpr double t[NS] = {71.4, 106.7, 116.7, 71.4, 106.7};
+  return t[s];
+}
+HRX_HD double gas_const(int s) { return RU / molar_mass(s); }
+
+// ----------------------------------------------------------------- thermodynamics
+// Species energy and heat capacity per unit mass at one temperature:
+//   e_s = R_s [(3/2 + r_s) T + r_s theta_s / (exp(theta_s/T) - 1)] + h_f,s(0 K)/M_s
+// with r_s = 1 for the diatomics (one rotational and one vibrational mode), 0 for atoms.
+struct SpeciesThermo {
+  double e[NS];    // J/kg
+  double cv[NS];   // J/(kg K)
+};
+
+HRX_HD void species_e_cv(double T, SpeciesThermo& st) {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double Rs = gas_const(s);
+    const double hf = hf0_molar(s) / molar_mass(s);
+    if (is_diatomic(s)) {
+      const double x = theta_vib(s) / T;
+      const double em1 = expm1(x);
+      const double ex = em1 + 1.0;
+      st.e[s] = Rs * (2.5 * T + theta_vib(s) / em1) + hf;
+      st.cv[s] = Rs * (2.5 + x * x * ex / (em1 * em1));
+    } else {
+      st.e[s] = Rs * (1.5 * T) + hf;
+      st.cv[s] = Rs * 1.5;
+    }
+  }
+}
+
+HRX_HD void species_h(double T, double* h) {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double Rs = gas_const(s);
+    const double hf = hf0_molar(s) / molar_mass(s);
+    if (is_diatomic(s)) {
+      const double em1 = expm1(theta_vib(s) / T);
+      h[s] = Rs * (2.5 * T + theta_vib(s) / em1) + hf + Rs * T;
+    } else {
+      h[s] = Rs * (1.5 * T) + hf + Rs * T;
+    }
+  }
+}
+
+HRX_HD double mixture_e(double T, const double* Y) {
+  SpeciesThermo st;
+  species_e_cv(T, st);
+  double e = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) e += Y[s] * st.e[s];
+  return e;
+}
+
+HRX_HD double mixture_R(const double* Y) {
+  double r = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) r += Y[s] * gas_const(s);
+  return r;
+}
+
+constexpr double T_MIN = 50.0;
+
+// Newton inversion of e = sum_s Y_s e_s(T) (Sec. 3.4).  The start T0 solves the
+// energy equation with fully excited vibration, which over-estimates e_s(T), so T0
+// lies below the root; e(T) is increasing and convex, so the iterates approach the
+// root from above after the first step.  status: 0 converged, 1 no convergence in
+// max_iter, 2 energy below e(T_MIN).
+HRX_HD double temperature_from_energy(double e, const double* Y, double rtol, int max_iter,
+                                      int* status, int* iters, double* cv_out) {
+  double ef = 0.0, cfull = 0.0, emin = 0.0;
+  SpeciesThermo st;
+  species_e_cv(T_MIN, st);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    ef += Y[s] * (hf0_molar(s) / molar_mass(s));
+    cfull += Y[s] * gas_const(s) * (is_diatomic(s) ? 3.5 : 1.5);
+    emin += Y[s] * st.e[s];
+  }
+  double T = (e - ef) / cfull;
+  *iters = 0;
+  if (!(e >= emin)) {
+    *status = 2;
+    if (cv_out) *cv_out = 0.0;
+    return T_MIN;
+  }
+  if (T < T_MIN) T = T_MIN;
+  for (int it = 0; it < max_iter; ++it) {
+    species_e_cv(T, st);
+    double f = 0.0, cv = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      f += Y[s] * st.e[s];
+      cv += Y[s] * st.cv[s];
+    }
+    f -= e;
+    const double dT = f / cv;
+    T = T - dT;
+    *iters = it + 1;
+    if (cv_out) *cv_out = cv;
+    if (fabs(dT) <= rtol * T) {
+      *status = 0;
+      return T;
+    }
+  }
+  *status = 1;
+  return T;
+}
+
+// Frozen c_v at T (one more evaluation; used where the sound speed is needed).
+HRX_HD double mixture_cv(double T, const double* Y) {
+  SpeciesThermo st;
+  species_e_cv(T, st);
+  double cv = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) cv += Y[s] * st.cv[s];
+  return cv;
+}
+
+// ----------------------------------------------------------------- transport
+template <class R>
+HRX_HD R omega22(R Ts) {
+  return R(1.16145) * pow(Ts, R(-0.14874)) + R(0.52487) * exp(R(-0.77320) * Ts) +
+         R(2.16178) * exp(R(-2.43787) * Ts);
+}
+template <class R>
+HRX_HD R omega11(R Ts) {
+  return R(1.06036) * pow(Ts, R(-0.15610)) + R(0.19300) * exp(R(-0.47635) * Ts) +
+         R(1.03587) * exp(R(-1.52996) * Ts) + R(1.76474) * exp(R(-3.89411) * Ts);
+}
+
+constexpr double X_CLIP = 1e-12;
+
+template <class R>
+struct Transport {
+  R mu, kappa;     // Pa s, W/(m K)
+  R D[NS];         // m^2/s, averaged coefficients of Eq. (19)
+};
+
+// Mixture viscosity, frozen conductivity (Wilke/Eucken) and averaged diffusion
+// coefficients at (T, p, X).  cv[s] is the species c_v at T (J/(kg K)).
+//   mu_s  = (5/16) sqrt(pi m_s k T) / (pi sigma_s^2 Omega22*(T/eps_s))
+//   D_sr  = (3/16) sqrt(2 pi k^3 T^3 / m_sr) / (p pi sigma_sr^2 Omega11*(T/eps_sr))
+//   kappa_s = mu_s (15/4 R_s + c_v,int,s)   (Eucken; c_v,int = c_v - 3/2 R_s)
+//   phi_sr = [1 + sqrt(mu_s/mu_r) (M_r/M_s)^(1/4)]^2 / sqrt(8 (1 + M_s/M_r))
+//   mu = sum_s X_s mu_s / sum_r X_r phi_sr, kappa likewise;
+//   D_s = (1 - X_s) / sum_{r != s} X_r / D_sr (Eq. 19) with 1 - X_s formed as
+//   sum_{r != s} X_r and every X_r clipped below at 1e-12 in this formula only.
+// The molecular constants are folded in double precision so that the float
+// instantiation sees only well-scaled numbers.
+template <class R>
+HRX_HD void mixture_transport(double T, double p, const double* X, const double* cv,
+                              Transport<R>& out) {
+  R mu_s[NS], k_s[NS];
+  const R Tr = R(T);
+  const R sqT = sqrt(Tr);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double m = molar_mass(s) / NAV;
+    const double sig = lj_sigma(s);
+    const R A = R((5.0 / 16.0) * sqrt(PI * m * KB) / (PI * sig * sig));
+    mu_s[s] = A * sqT / omega22<R>(Tr / R(lj_eps(s)));
+    const R Rs = R(gas_const(s));
+    const R cv_int = R(cv[s]) - R(1.5) * Rs;
+    k_s[s] = mu_s[s] * (R(3.75) * Rs + cv_int);
+  }
+  R mu = R(0), kap = R(0);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    R den = R(0);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const R a = R(1) + sqrt(mu_s[s] / mu_s[r]) * R(pow(molar_mass(r) / molar_mass(s), 0.25));
+      const R phi = a * a / R(sqrt(8.0 * (1.0 + molar_mass(s) / molar_mass(r))));
+      den += R(X[r]) * phi;
+    }
+    mu += R(X[s]) * mu_s[s] / den;
+    kap += R(X[s]) * k_s[s] / den;
+  }
+  out.mu = mu;
+  out.kappa = kap;
+  R Dsr[NS][NS];
+  const R T15 = Tr * sqT;
+  const R pr = R(p);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+#pragma unroll
+    for (int r = s + 1; r < NS; ++r) {
+      const double ms = molar_mass(s) / NAV, mr = molar_mass(r) / NAV;
+      const double msr = ms * mr / (ms + mr);
+      const double sig = 0.5 * (lj_sigma(s) + lj_sigma(r));
+      const R B = R((3.0 / 16.0) * sqrt(2.0 * PI * KB * KB * KB / msr) / (PI * sig * sig));
+      const R eps = R(sqrt(lj_eps(s) * lj_eps(r)));
+      const R d = B * T15 / (pr * omega11<R>(Tr / eps));
+      Dsr[s][r] = d;
+      Dsr[r][s] = d;
+    }
+  }
+  R Xc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Xc[s] = R(X[s] > X_CLIP ? X[s] : X_CLIP);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    R num = R(0), den = R(0);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      if (r == s) continue;
+      num += Xc[r];
+      den += Xc[r] / Dsr[s][r];
+    }
+    out.D[s] = num / den;
+  }
+}
+
+// Sutherland's law, Eq. (24): C1 = 1.458e-6 kg/(m s K^1/2), T_S = 110.4 K.
+template <class R>
+HRX_HD R sutherland(R T) {
+  return R(1.458e-6) * T * sqrt(T) / (T + R(110.4));
+}
+
+// ----------------------------------------------------------------- chemistry
+// Standard-state molar Gibbs energy g_s/(R_u T) at p0 (statistical mechanics).
+HRX_HD void gibbs_over_RT(double T, double* g) {
+  const double lnT = log(T);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double m = molar_mass(s) / NAV;
+    // ln[(2 pi m k T / h^2)^(3/2) k T / p0]
+    const double ltr = 1.5 * log(2.0 * PI * m * KB / (HPL * HPL)) + 2.5 * lnT + log(KB / P0);
+    double gs = hf0_molar(s) / (RU * T) - ltr - log(g_elec(s));
+    if (is_diatomic(s)) {
+      gs -= lnT - log(sym_number(s) * theta_rot(s));
+      gs += log(-expm1(-theta_vib(s) / T));
+    }
+    g[s] = gs;
+  }
+}
+
+struct Reaction {
+  double C;          // cm^3 / (mol s)
+  double n;
+  double theta;      // K
+};
+
+// Park-type mechanism, third-body form (Eq. 13-14):
+//   0: N2 + M = 2N + M      1: O2 + M = 2O + M     2: NO + M = N + O + M
+//   3: N2 + O = NO + N      4: NO + O = O2 + N
+HRX_HD Reaction reaction(int r) {
+  constexpr Reaction t[5] = {{7.0e21, -1.6, 113200.0}, {2.0e21, -1.5, 59500.0},
+                             {5.0e15, 0.0, 75500.0},   {6.4e17, -1.0, 38400.0},
+                             {8.4e12, 0.0, 19450.0}};
+  return t[r];
+}
+// third-body efficiencies (relative to the reference partner)
+HRX_HD double tb_eff(int r, int s) {
+  constexpr double z[3][NS] = {{1.0, 1.0, 1.0, 30.0 / 7.0, 30.0 / 7.0},
+                               {1.0, 1.0, 1.0, 5.0, 5.0},
+                               {1.0, 1.0, 22.0, 22.0, 22.0}};
+  return z[r][s];
+}
+
+// Net mass production rates wdot_s [kg/(m^3 s)] from partial densities [kg/m^3] and T.
+// Rates of progress R_r = (k_f prod c^nu' - k_b prod c^nu'') * (sum Z c) (Eq. 14),
+// k_f = C T^n exp(-theta/T) (the printed exponent read with a minus sign), k_b = k_f/K_c,
+// K_c = (p0/(R_u T))^dnu exp(-sum dnu g/(R_u T)); wdot_s = M_s sum_r (nu'' - nu') R_r (Eq. 15).
+template <class R>
+HRX_HD void production_rates(const double* rho_s, double T, R* wdot) {
+  double g[NS];
+  gibbs_over_RT(T, g);
+  double c[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) c[s] = rho_s[s] / molar_mass(s);
+  const double c0 = P0 / (RU * T);
+  double Rr[5];
+  // delta g of each reaction and its sum of stoichiometric changes
+  const double dG[5] = {2.0 * g[3] - g[0], 2.0 * g[4] - g[1], g[3] + g[4] - g[2],
+                        g[2] + g[3] - g[0] - g[4], g[1] + g[3] - g[2] - g[4]};
+  const double dnu[5] = {1.0, 1.0, 1.0, 0.0, 0.0};
+  double fwdp[5] = {c[0], c[1], c[2], c[0] * c[4], c[2] * c[4]};
+  double bwdp[5] = {c[3] * c[3], c[4] * c[4], c[3] * c[4], c[2] * c[3], c[1] * c[3]};
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    const Reaction re = reaction(r);
+    const double kf = re.C * 1e-6 * pow(T, re.n) * exp(-re.theta / T);
+    const double Kc = pow(c0, dnu[r]) * exp(-dG[r]);
+    const double kb = kf / Kc;
+    double tb = 1.0;
+    if (r < 3) {
+      tb = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) tb += tb_eff(r, s) * c[s];
+    }
+    Rr[r] = (kf * fwdp[r] - kb * bwdp[r]) * tb;
+  }
+  wdot[0] = R(molar_mass(0) * (-Rr[0] - Rr[3]));
+  wdot[1] = R(molar_mass(1) * (-Rr[1] + Rr[4]));
+  wdot[2] = R(molar_mass(2) * (-Rr[2] + Rr[3] - Rr[4]));
+  wdot[3] = R(molar_mass(3) * (2.0 * Rr[0] + Rr[2] + Rr[3] + Rr[4]));
+  wdot[4] = R(molar_mass(4) * (2.0 * Rr[1] + Rr[2] - Rr[3] - Rr[4]));
+}
+
+}  // namespace hrx

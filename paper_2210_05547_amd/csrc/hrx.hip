@@ -1,0 +1,1210 @@
+// hrx: HIP kernels for gfx950 and the C-ABI of include/hrx.h.
+//
+// One right-hand-side evaluation (Eqs. 5-6 with the sponge of Eq. 26) runs as
+//   k_prim     pointwise: Q -> velocities, T (Newton, Sec. 3.4), p, X_s, mu, kappa,
+//              D_s (Eq. 19), wdot_s (Eqs. 13-15)            [FP64-ALU bound]
+//   k_ad_*     artificial diffusivity (Sec. 3.3 reading): sources, fourth
+//              differences, separable 9-point Gaussian filter  [HBM bound]
+//   k_flux     stencil gradients of u, T, X_s at each point, then the total flux
+//              F_j = F_C,j - F_D,j for every direction j (Eqs. 9, 10, 18)  [HBM bound]
+//   k_div      -sum_j dF_j/dx_j + S - sigma (Q - Q_ref), boundary rows, and either
+//              the R output or the fused low-storage RK update (Sec. 3.1)  [HBM bound]
+//   k_bc       wall row after a stage (no slip, non-catalytic, T_w or adiabatic)
+// Fields are SoA planes with x fastest; a thread owns one grid point, so x-neighbour
+// loads of a wavefront are contiguous and y/z neighbours are reused through L2.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "air5.h"
+#include "hrx.h"
+
+namespace hrx {
+
+enum { CPG = 0, AIR5 = 1 };
+enum { MODE_RHS = 0, MODE_RK = 1 };
+
+struct Dev {
+  int nx, ny, nz, ndim, nvar, ns, fd_order;
+  long N;
+  double gamma, Re, Pr, T_ref, mu_inf, kappa_inf, c_inf, rho_inf, L_ref, R_inf;
+  int wall;
+  double T_wall;  // K
+  double newton_rtol;
+  int newton_max;
+  int ad_on;
+  double Cmu, Cbeta, Ckap, CD, CY;
+  const double *mx, *my, *mz;     // metrics d(xi)/dx
+  const double *sx, *sy;          // sponge profiles
+  const double *dlx, *dly, *dlz;  // local spacings dx/d(xi)
+  const unsigned char *hold;      // [nz][3][nx] or null
+  unsigned long long *counters;   // [0] Newton non-converged, [1] below e(T_min)
+  // W plane offsets
+  int nsrc, w_p, w_mu, w_kap, w_D, w_wdot, w_c;
+  int nad;                        // artificial-diffusivity planes (3 + ns)
+};
+
+// ------------------------------------------------------------------ stencils
+// First derivative in index space along a line of n points with stride s, at
+// position i of the line (flat index idx).  Interior: explicit central 6th (or 4th)
+// order; ends: one-sided 4th-order closures and their mirror images.
+template <int ORDER>
+__device__ __forceinline__ double dline(const double* __restrict__ f, long idx, long s, int i,
+                                        int n) {
+  if (ORDER == 6) {
+    if (i >= 3 && i <= n - 4) {
+      double acc = 0.75 * (f[idx + s] - f[idx - s]);
+      acc += -0.15 * (f[idx + 2 * s] - f[idx - 2 * s]);
+      acc += (1.0 / 60.0) * (f[idx + 3 * s] - f[idx - 3 * s]);
+      return acc;
+    }
+  } else {
+    if (i >= 2 && i <= n - 3) {
+      double acc = (2.0 / 3.0) * (f[idx + s] - f[idx - s]);
+      acc += (-1.0 / 12.0) * (f[idx + 2 * s] - f[idx - 2 * s]);
+      return acc;
+    }
+  }
+  constexpr double b00 = -25.0 / 12.0, b01 = 4.0, b02 = -3.0, b03 = 4.0 / 3.0, b04 = -0.25;
+  constexpr double b10 = -0.25, b11 = -5.0 / 6.0, b12 = 1.5, b13 = -0.5, b14 = 1.0 / 12.0;
+  if (i == 0)
+    return b00 * f[idx] + b01 * f[idx + s] + b02 * f[idx + 2 * s] + b03 * f[idx + 3 * s] +
+           b04 * f[idx + 4 * s];
+  if (i == 1)
+    return b10 * f[idx - s] + b11 * f[idx] + b12 * f[idx + s] + b13 * f[idx + 2 * s] +
+           b14 * f[idx + 3 * s];
+  if (i == n - 1)
+    return -(b00 * f[idx] + b01 * f[idx - s] + b02 * f[idx - 2 * s] + b03 * f[idx - 3 * s] +
+             b04 * f[idx - 4 * s]);
+  if (i == n - 2)
+    return -(b10 * f[idx + s] + b11 * f[idx] + b12 * f[idx - s] + b13 * f[idx - 2 * s] +
+             b14 * f[idx - 3 * s]);
+  // 6th order only: points 2 and n-3 use the central 4th-order stencil
+  double acc = (2.0 / 3.0) * (f[idx + s] - f[idx - s]);
+  acc += (-1.0 / 12.0) * (f[idx + 2 * s] - f[idx - 2 * s]);
+  return acc;
+}
+
+// Periodic central first derivative (z direction).
+template <int ORDER>
+__device__ __forceinline__ double dper(const double* __restrict__ f, long idx, long s, int i,
+                                       int n) {
+  const long base = idx - (long)i * s;
+  auto at = [&](int m) {
+    int q = i + m;
+    q = q < 0 ? q + n : (q >= n ? q - n : q);
+    return f[base + (long)q * s];
+  };
+  if (ORDER == 6) {
+    double acc = 0.75 * (at(1) - at(-1));
+    acc += -0.15 * (at(2) - at(-2));
+    acc += (1.0 / 60.0) * (at(3) - at(-3));
+    return acc;
+  }
+  double acc = (2.0 / 3.0) * (at(1) - at(-1));
+  acc += (-1.0 / 12.0) * (at(2) - at(-2));
+  return acc;
+}
+
+struct Pt {
+  long idx;
+  int i, j, k;
+};
+
+__device__ __forceinline__ Pt point_of(const Dev& d, long idx) {
+  Pt p;
+  p.idx = idx;
+  p.i = (int)(idx % d.nx);
+  long r = idx / d.nx;
+  p.j = (int)(r % d.ny);
+  p.k = (int)(r / d.ny);
+  return p;
+}
+
+// physical derivative of plane f along direction dir at point p
+template <int ORDER>
+__device__ __forceinline__ double dphys(const Dev& d, const double* __restrict__ f, const Pt& p,
+                                        int dir) {
+  if (dir == 0) return dline<ORDER>(f, p.idx, 1, p.i, d.nx) * d.mx[p.i];
+  if (dir == 1) return dline<ORDER>(f, p.idx, d.nx, p.j, d.ny) * d.my[p.j];
+  return dper<ORDER>(f, p.idx, (long)d.nx * d.ny, p.k, d.nz) * d.mz[p.k];
+}
+
+__device__ __forceinline__ void count(const Dev& d, int status) {
+  if (status == 1) atomicAdd(&d.counters[0], 1ull);
+  if (status == 2) atomicAdd(&d.counters[1], 1ull);
+}
+
+// ------------------------------------------------------------------ k_prim
+template <int GAS, int ND>
+__global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ Q,
+                                              double* __restrict__ W) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.N) return;
+  const long N = d.N;
+  if (GAS == CPG) {
+    const double rho = Q[idx];
+    double u[3] = {0.0, 0.0, 0.0};
+    double ke = 0.0;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+      u[a] = Q[(1 + a) * N + idx] / rho;
+      ke += u[a] * u[a];
+    }
+    const double E = Q[(1 + ND) * N + idx] / rho;
+    const double e = E - 0.5 * ke;
+    const double g = d.gamma;
+    const double T = g * e;
+    const double p = rho * (g - 1.0) * T / g;
+    const double mu = sutherland<double>(T * d.T_ref) / d.mu_inf;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) W[a * N + idx] = u[a];
+    W[ND * N + idx] = T;
+    W[d.w_p * N + idx] = p;
+    W[d.w_mu * N + idx] = mu;
+    if (d.ad_on) W[d.w_c * N + idx] = sqrt(g * p / rho);
+    return;
+  }
+  double rs[NS], Y[NS];
+  double rho = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    rs[s] = Q[s * N + idx];
+    rho += rs[s];
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Y[s] = rs[s] / rho;
+  double u[3] = {0.0, 0.0, 0.0};
+  double ke = 0.0;
+#pragma unroll
+  for (int a = 0; a < ND; ++a) {
+    u[a] = Q[(NS + a) * N + idx] / rho;
+    ke += u[a] * u[a];
+  }
+  const double E = Q[(NS + ND) * N + idx] / rho;
+  const double e = E - 0.5 * ke;
+  const double c2 = d.c_inf * d.c_inf;
+  int status, iters;
+  const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
+                                            &iters, nullptr);
+  if (status) count(d, status);
+  const double T = Tk / d.T_ref;
+  const double Rmix = mixture_R(Y);
+  const double g = d.gamma;
+  const double p = rho * T * (g - 1.0) / g * Rmix / d.R_inf;
+  const double p_d = p * d.rho_inf * c2;
+  double X[NS], n = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    X[s] = Y[s] / molar_mass(s);
+    n += X[s];
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) X[s] = X[s] / n;
+  SpeciesThermo st;
+  species_e_cv(Tk, st);
+  Transport<double> tr;
+  mixture_transport<double>(Tk, p_d, X, st.cv, tr);
+  double rsd[NS], wd[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rsd[s] = rs[s] * d.rho_inf;
+  production_rates<double>(rsd, Tk, wd);
+  const double wscale = d.L_ref / (d.rho_inf * d.c_inf);
+#pragma unroll
+  for (int a = 0; a < ND; ++a) W[a * N + idx] = u[a];
+  W[ND * N + idx] = T;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) W[(ND + 1 + s) * N + idx] = X[s];
+  W[d.w_p * N + idx] = p;
+  W[d.w_mu * N + idx] = tr.mu / d.mu_inf;
+  W[d.w_kap * N + idx] = tr.kappa / d.kappa_inf;
+  const double Dscale = d.c_inf * d.L_ref;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) W[(d.w_D + s) * N + idx] = tr.D[s] / Dscale;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) W[(d.w_wdot + s) * N + idx] = wd[s] * d.L_ref / (d.rho_inf * d.c_inf);
+  (void)wscale;
+  if (d.ad_on) {
+    double cv = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) cv += Y[s] * st.cv[s];
+    const double gf = (cv + Rmix) / cv;
+    W[d.w_c * N + idx] = sqrt(gf * Rmix * Tk) / d.c_inf;
+  }
+}
+
+// ------------------------------------------------------------------ artificial diffusivity
+// A planes: [|S|, theta, e, Y_1..Y_ns]
+template <int GAS, int ND, int ORDER>
+__global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict__ Q,
+                                                const double* __restrict__ W,
+                                                double* __restrict__ A) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.N) return;
+  const long N = d.N;
+  const Pt p = point_of(d, idx);
+  double G[3][3];
+#pragma unroll
+  for (int a = 0; a < ND; ++a)
+#pragma unroll
+    for (int b = 0; b < ND; ++b) G[a][b] = dphys<ORDER>(d, W + a * N, p, b);
+  double s2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < ND; ++a)
+#pragma unroll
+    for (int b = 0; b < ND; ++b) {
+      const double sab = 0.5 * (G[a][b] + G[b][a]);
+      s2 += sab * sab;
+    }
+  double theta = 0.0;
+#pragma unroll
+  for (int a = 0; a < ND; ++a) theta += G[a][a];
+  const int ns = (GAS == CPG) ? 1 : NS;
+  double rho = 0.0;
+  if (GAS == CPG) {
+    rho = Q[idx];
+  } else {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) rho += Q[s * N + idx];
+  }
+  double ke = 0.0;
+#pragma unroll
+  for (int a = 0; a < ND; ++a) {
+    const double ua = Q[(ns + a) * N + idx] / rho;
+    ke += ua * ua;
+  }
+  const double e = Q[(ns + ND) * N + idx] / rho - 0.5 * ke;
+  A[0 * N + idx] = sqrt(s2);
+  A[1 * N + idx] = theta;
+  A[2 * N + idx] = e;
+  if (GAS == AIR5) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) A[(3 + s) * N + idx] = Q[s * N + idx] / rho;
+  }
+}
+
+// fourth difference along a line, copying the nearest interior value at the two
+// first and last points of a non-periodic line
+__device__ __forceinline__ double d4line(const double* __restrict__ f, long idx, long s, int i,
+                                         int n) {
+  int ic = i < 2 ? 2 : (i > n - 3 ? n - 3 : i);
+  const long c = idx + (long)(ic - i) * s;
+  return f[c - 2 * s] - 4.0 * f[c - s] + 6.0 * f[c] - 4.0 * f[c + s] + f[c + 2 * s];
+}
+__device__ __forceinline__ double d4per(const double* __restrict__ f, long idx, long s, int i,
+                                        int n) {
+  const long base = idx - (long)i * s;
+  auto at = [&](int m) {
+    int q = i + m;
+    q = q < 0 ? q + n : (q >= n ? q - n : q);
+    return f[base + (long)q * s];
+  };
+  return at(-2) - 4.0 * at(-1) + 6.0 * f[idx] - 4.0 * at(1) + at(2);
+}
+
+// B planes: [a_mu, a_beta, a_kappa, a_D,1..ns] before filtering
+template <int GAS, int ND>
+__global__ __launch_bounds__(128) void k_ad_d4(Dev d, const double* __restrict__ A,
+                                               double* __restrict__ B) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.N) return;
+  const long N = d.N;
+  const Pt p = point_of(d, idx);
+  const double dl[3] = {d.dlx[p.i], d.dly[p.j], ND == 3 ? d.dlz[p.k] : 1.0};
+  double dbar;
+  if (ND == 2)
+    dbar = pow(dl[0] * dl[1], 0.5);
+  else
+    dbar = pow(dl[0] * dl[1] * dl[2], 1.0 / 3.0);
+  const int nplanes = 3 + ((GAS == AIR5) ? NS : 0);
+  for (int v = 0; v < nplanes; ++v) {
+    const double* f = A + (long)v * N;
+    const bool sq = v < 2;
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < ND; ++l) {
+      double q;
+      if (l == 0)
+        q = d4line(f, idx, 1, p.i, d.nx);
+      else if (l == 1)
+        q = d4line(f, idx, d.nx, p.j, d.ny);
+      else
+        q = d4per(f, idx, (long)d.nx * d.ny, p.k, d.nz);
+      acc += q * (sq ? dl[l] * dl[l] : dl[l]);
+    }
+    double out = fabs(acc);
+    if (v >= 3) {
+      const double Ys = f[idx];
+      const double over = 0.5 * (fabs(Ys) - 1.0 + fabs(1.0 - Ys));
+      out = d.CD * out + d.CY * over * dbar;
+    }
+    B[(long)v * N + idx] = out;
+  }
+}
+
+// 9-point truncated Gaussian filter along one direction (renormalised at
+// non-periodic ends; periodic in z)
+__constant__ double c_gauss9[5] = {3565.0 / 10368.0, 3091.0 / 12960.0, 1997.0 / 25920.0,
+                                   149.0 / 12960.0, 107.0 / 103680.0};
+
+template <int DIR>
+__global__ __launch_bounds__(128) void k_ad_filter(Dev d, const double* __restrict__ in,
+                                                   double* __restrict__ out) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.N) return;
+  const long N = d.N;
+  const Pt p = point_of(d, idx);
+  const int i = DIR == 0 ? p.i : (DIR == 1 ? p.j : p.k);
+  const int n = DIR == 0 ? d.nx : (DIR == 1 ? d.ny : d.nz);
+  const long s = DIR == 0 ? 1 : (DIR == 1 ? (long)d.nx : (long)d.nx * d.ny);
+  for (int v = 0; v < d.nad; ++v) {
+    const double* f = in + (long)v * N;
+    double r;
+    if (DIR == 2) {
+      const long base = idx - (long)i * s;
+      auto at = [&](int m) {
+        int q = i + m;
+        q = q < 0 ? q + n : (q >= n ? q - n : q);
+        return f[base + (long)q * s];
+      };
+      r = c_gauss9[0] * f[idx];
+#pragma unroll
+      for (int k = 1; k <= 4; ++k) r += c_gauss9[k] * (at(-k) + at(k));
+    } else {
+      double acc = 0.0, wsum = 0.0;
+#pragma unroll
+      for (int k = -4; k <= 4; ++k) {
+        const int q = i + k;
+        const double w = (q >= 0 && q < n) ? c_gauss9[k < 0 ? -k : k] : 0.0;
+        const int qc = q < 0 ? 0 : (q >= n ? n - 1 : q);
+        acc += w * f[idx + (long)(qc - i) * s];
+        wsum += w;
+      }
+      r = acc / wsum;
+    }
+    out[(long)v * N + idx] = r;
+  }
+}
+
+// ------------------------------------------------------------------ k_flux
+// F planes: F[j][k] for direction j and conserved component k.
+template <int GAS, int ND, int ORDER, bool AD>
+__global__ __launch_bounds__(128) void k_flux(Dev d, const double* __restrict__ Q,
+                                              const double* __restrict__ W,
+                                              const double* __restrict__ Gad,
+                                              double* __restrict__ F) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.N) return;
+  const long N = d.N;
+  const Pt p = point_of(d, idx);
+  constexpr int ns = (GAS == CPG) ? 1 : NS;
+  constexpr int nvar = ns + ND + 1;
+  double G[3][3], dT[3];
+#pragma unroll
+  for (int a = 0; a < ND; ++a)
+#pragma unroll
+    for (int b = 0; b < ND; ++b) G[a][b] = dphys<ORDER>(d, W + a * N, p, b);
+#pragma unroll
+  for (int b = 0; b < ND; ++b) dT[b] = dphys<ORDER>(d, W + ND * N, p, b);
+  double u[3];
+#pragma unroll
+  for (int a = 0; a < ND; ++a) u[a] = W[a * N + idx];
+  const double pr = W[d.w_p * N + idx];
+  const double mu = W[d.w_mu * N + idx];
+  double rho, rs[NS], Y[NS];
+  if (GAS == CPG) {
+    rho = Q[idx];
+  } else {
+    rho = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      rs[s] = Q[s * N + idx];
+      rho += rs[s];
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Y[s] = rs[s] / rho;
+  }
+  double theta = 0.0;
+#pragma unroll
+  for (int a = 0; a < ND; ++a) theta += G[a][a];
+  const double kap = (GAS == CPG) ? mu : W[d.w_kap * N + idx];
+  double mu_eff = mu / d.Re;
+  double kap_eff = kap / (d.Re * d.Pr);
+  double beta = 0.0, cs = 0.0;
+  if (AD) {
+    const double T = W[ND * N + idx];
+    cs = W[d.w_c * N + idx];
+    double w2;
+    if (ND == 2) {
+      w2 = (G[1][0] - G[0][1]) * (G[1][0] - G[0][1]);
+    } else {
+      w2 = (G[2][1] - G[1][2]) * (G[2][1] - G[1][2]) + (G[0][2] - G[2][0]) * (G[0][2] - G[2][0]) +
+           (G[1][0] - G[0][1]) * (G[1][0] - G[0][1]);
+    }
+    const double fsw = theta < 0.0 ? theta * theta / (theta * theta + w2 + 1e-32) : 0.0;
+    mu_eff = mu_eff + d.Cmu * rho * Gad[0 * N + idx];
+    beta = d.Cbeta * rho * fsw * Gad[1 * N + idx];
+    kap_eff = kap_eff + d.Ckap * rho * cs / T * Gad[2 * N + idx];
+  }
+  const double rhoE = Q[(ns + ND) * N + idx];
+  // species diffusion (Eq. 18 read with grad X_s)
+  double a_s[NS], h[NS];
+  double dX[NS][3];
+  if (GAS == AIR5) {
+    double nsum = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) nsum += Y[s] / molar_mass(s);
+    const double Mbar = 1.0 / nsum;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      double Ds = W[(d.w_D + s) * N + idx];
+      if (AD) Ds = Ds + cs * Gad[(3 + s) * N + idx];
+      a_s[s] = rho * (molar_mass(s) / Mbar) * Ds;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int b = 0; b < ND; ++b) dX[s][b] = dphys<ORDER>(d, W + (ND + 1 + s) * N, p, b);
+    const double Tk = W[ND * N + idx] * d.T_ref;
+    species_h(Tk, h);
+    const double c2 = d.c_inf * d.c_inf;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) h[s] = h[s] / c2;
+  }
+#pragma unroll
+  for (int j = 0; j < ND; ++j) {
+    double* Fj = F + (long)j * nvar * N;
+    double J[NS];
+    if (GAS == AIR5) {
+      double corr = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) corr += a_s[s] * dX[s][j];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        J[s] = -a_s[s] * dX[s][j] + Y[s] * corr;
+        Fj[s * N + idx] = rs[s] * u[j] + J[s];
+      }
+    } else {
+      Fj[idx] = rho * u[j];
+    }
+    double tau[3];
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+      double t = mu_eff * (G[a][j] + G[j][a]);
+      if (a == j) {
+        t = t - mu_eff * (2.0 / 3.0) * theta;
+        if (AD) t = t + beta * theta;
+      }
+      tau[a] = t;
+      double conv = Q[(ns + a) * N + idx] * u[j];
+      if (a == j) conv = conv + pr;
+      Fj[(ns + a) * N + idx] = conv - t;
+    }
+    double q = -kap_eff * dT[j];
+    if (GAS == AIR5) {
+      double hJ = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) hJ += h[s] * J[s];
+      q = q + hJ;
+    }
+    double work = 0.0;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) work += tau[a] * u[a];
+    Fj[(ns + ND) * N + idx] = (rhoE + pr) * u[j] - (work - q);
+  }
+}
+
+// ------------------------------------------------------------------ k_div (+ RK)
+template <int GAS, int ND, int ORDER, int MODE>
+__global__ __launch_bounds__(128) void k_div(Dev d, const double* __restrict__ F,
+                                             const double* __restrict__ W,
+                                             const double* Qin, const double* __restrict__ Qref,
+                                             double* Rout, double* Qio, double* dQio,
+                                             double A, double B, double dt) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.N) return;
+  const long N = d.N;
+  const Pt p = point_of(d, idx);
+  constexpr int ns = (GAS == CPG) ? 1 : NS;
+  constexpr int nvar = ns + ND + 1;
+  const double sig = fmax(d.sx[p.i], d.sy[p.j]);
+  bool held = (p.i == 0);
+  if (d.hold && p.j < 3) held = held || d.hold[((long)p.k * 3 + p.j) * d.nx + p.i];
+#pragma unroll
+  for (int k = 0; k < nvar; ++k) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) acc += dphys<ORDER>(d, F + ((long)j * nvar + k) * N, p, j);
+    double R = -acc;
+    if (GAS == AIR5 && k < NS) R = R + W[(d.w_wdot + k) * N + idx];
+    const double qv = (MODE == MODE_RK) ? Qio[k * N + idx] : Qin[k * N + idx];
+    if (Qref != nullptr && sig != 0.0) R = R - sig * (qv - Qref[k * N + idx]);
+    if (held || (p.j == 0 && k >= ns && k < ns + ND)) R = 0.0;
+    if (MODE == MODE_RHS) {
+      Rout[k * N + idx] = R;
+    } else {
+      const double dq = A * dQio[k * N + idx] + dt * R;
+      dQio[k * N + idx] = dq;
+      Qio[k * N + idx] = qv + B * dq;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ k_bc (wall row)
+__constant__ double c_wall[4] = {48.0 / 25.0, -36.0 / 25.0, 16.0 / 25.0, -3.0 / 25.0};
+
+template <int GAS, int ND>
+__global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nw = (long)(d.nx - 1) * d.nz;
+  if (t >= nw) return;
+  const int i = 1 + (int)(t % (d.nx - 1));
+  const int k = (int)(t / (d.nx - 1));
+  if (d.hold && d.hold[((long)k * 3 + 0) * d.nx + i]) return;
+  const long N = d.N;
+  const long idx0 = (long)k * d.ny * d.nx + i;
+  const long sy = d.nx;
+  constexpr int ns = (GAS == CPG) ? 1 : NS;
+  if (GAS == CPG) {
+    const double rho_w = Q[idx0];
+    double Tw;
+    if (d.wall == HRX_WALL_ISOTHERMAL) {
+      Tw = d.T_wall / d.T_ref;
+    } else {
+      Tw = 0.0;
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) {
+        const long im = idx0 + m * sy;
+        const double rho = Q[im];
+        double ke = 0.0;
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+          const double ua = Q[(1 + a) * N + im] / rho;
+          ke += ua * ua;
+        }
+        const double e = Q[(1 + ND) * N + im] / rho - 0.5 * ke;
+        Tw += c_wall[m - 1] * (d.gamma * e);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < ND; ++a) Q[(1 + a) * N + idx0] = 0.0;
+    Q[(1 + ND) * N + idx0] = rho_w * Tw / d.gamma;
+    return;
+  }
+  double rho_w = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rho_w += Q[s * N + idx0];
+  double Yw[NS] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double Tw = 0.0;
+  const double c2 = d.c_inf * d.c_inf;
+#pragma unroll
+  for (int m = 1; m <= 4; ++m) {
+    const long im = idx0 + m * sy;
+    double rho = 0.0, Y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) rho += Q[s * N + im];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      Y[s] = Q[s * N + im] / rho;
+      Yw[s] += c_wall[m - 1] * Y[s];
+    }
+    if (d.wall != HRX_WALL_ISOTHERMAL) {
+      double ke = 0.0;
+#pragma unroll
+      for (int a = 0; a < ND; ++a) {
+        const double ua = Q[(NS + a) * N + im] / rho;
+        ke += ua * ua;
+      }
+      const double e = Q[(NS + ND) * N + im] / rho - 0.5 * ke;
+      int status, iters;
+      const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
+                                                &iters, nullptr);
+      Tw += c_wall[m - 1] * (Tk / d.T_ref);
+    }
+  }
+  if (d.wall == HRX_WALL_ISOTHERMAL) Tw = d.T_wall / d.T_ref;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Q[s * N + idx0] = rho_w * Yw[s];
+#pragma unroll
+  for (int a = 0; a < ND; ++a) Q[(ns + a) * N + idx0] = 0.0;
+  const double ew = mixture_e(Tw * d.T_ref, Yw) / c2;
+  Q[(ns + ND) * N + idx0] = rho_w * ew;
+}
+
+// ------------------------------------------------------------------ pointwise SI calls
+__global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int max_iter,
+                                                     const double* __restrict__ rho,
+                                                     const double* __restrict__ e,
+                                                     const double* __restrict__ Yin,
+                                                     double* __restrict__ Tout,
+                                                     double* __restrict__ pout,
+                                                     double* __restrict__ hout,
+                                                     double* __restrict__ muout,
+                                                     double* __restrict__ kout,
+                                                     double* __restrict__ Dout,
+                                                     int32_t* __restrict__ stout,
+                                                     unsigned long long* counters) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double Y[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + i];
+  int status, iters;
+  const double T = temperature_from_energy(e[i], Y, rtol, max_iter, &status, &iters, nullptr);
+  if (status == 1) atomicAdd(&counters[0], 1ull);
+  if (status == 2) atomicAdd(&counters[1], 1ull);
+  Tout[i] = T;
+  if (stout) stout[i] = status;
+  const double p = rho[i] * mixture_R(Y) * T;
+  if (pout) pout[i] = p;
+  if (hout) {
+    double h[NS];
+    species_h(T, h);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) hout[s * n + i] = h[s];
+  }
+  if (muout || kout || Dout) {
+    double X[NS], nsum = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      X[s] = Y[s] / molar_mass(s);
+      nsum += X[s];
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) X[s] = X[s] / nsum;
+    SpeciesThermo st;
+    species_e_cv(T, st);
+    Transport<double> tr;
+    mixture_transport<double>(T, p, X, st.cv, tr);
+    if (muout) muout[i] = tr.mu;
+    if (kout) kout[i] = tr.kappa;
+    if (Dout) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) Dout[s * n + i] = tr.D[s];
+    }
+  }
+}
+
+__global__ __launch_bounds__(128) void k_chem_source(long n, const double* __restrict__ rho_s,
+                                                     const double* __restrict__ T,
+                                                     double* __restrict__ wdot) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double rs[NS], w[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rs[s] = rho_s[s * n + i];
+  production_rates<double>(rs, T[i], w);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) wdot[s * n + i] = w[s];
+}
+
+}  // namespace hrx
+
+// ====================================================================== host side
+using namespace hrx;
+
+struct hrx_ctx {
+  hrx_config cfg;
+  Dev dev;
+  hrx_reference ref;
+  int nW, nF;
+  double *W = nullptr, *F = nullptr, *R = nullptr, *AD = nullptr;
+  double *metrics = nullptr;   // mx, my, mz, sx, sy, dlx, dly, dlz
+  unsigned char *hold = nullptr;
+  unsigned long long *counters = nullptr;
+  hipStream_t last_stream = nullptr;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  struct Pending { int kid; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double ms[HRX_NKERNELS] = {0};
+  int64_t launches[HRX_NKERNELS] = {0};
+};
+
+namespace {
+
+enum { K_PRIM = 0, K_AD_SRC, K_AD_D4, K_AD_FX, K_AD_FY, K_AD_FZ, K_FLUX, K_DIV, K_BC, K_THERMO,
+       K_CHEM };
+
+int flush_timing(hrx_ctx* c) {
+  for (auto& p : c->pending) {
+    if (hipEventSynchronize(p.b) != hipSuccess) return HRX_EHIP;
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, p.a, p.b) != hipSuccess) return HRX_EHIP;
+    c->ms[p.kid] += t;
+    c->launches[p.kid] += 1;
+    c->ev_free.push_back(p.a);
+    c->ev_free.push_back(p.b);
+  }
+  c->pending.clear();
+  return HRX_OK;
+}
+
+// Launch f() on stream st, bracketed by events when timing is on.
+template <class Fn>
+void timed(hrx_ctx* c, int kid, hipStream_t st, Fn&& f) {
+  if (!c->timing) {
+    f();
+    return;
+  }
+  if (c->ev_free.size() < 2) flush_timing(c);
+  if (c->ev_free.size() < 2) {
+    f();
+    return;
+  }
+  hipEvent_t a = c->ev_free.back(); c->ev_free.pop_back();
+  hipEvent_t b = c->ev_free.back(); c->ev_free.pop_back();
+  (void)hipEventRecord(a, st);
+  f();
+  (void)hipEventRecord(b, st);
+  c->pending.push_back({kid, a, b});
+}
+
+}  // namespace
+
+namespace {
+
+// index-space first derivative of a host array (same operator as the kernels)
+void host_deriv(const std::vector<double>& f, int order, std::vector<double>& out) {
+  const int n = (int)f.size();
+  out.assign(n, 0.0);
+  const int h = order == 6 ? 3 : 2;
+  for (int i = h; i < n - h; ++i) {
+    double acc;
+    if (order == 6) {
+      acc = 0.75 * (f[i + 1] - f[i - 1]);
+      acc += -0.15 * (f[i + 2] - f[i - 2]);
+      acc += (1.0 / 60.0) * (f[i + 3] - f[i - 3]);
+    } else {
+      acc = (2.0 / 3.0) * (f[i + 1] - f[i - 1]);
+      acc += (-1.0 / 12.0) * (f[i + 2] - f[i - 2]);
+    }
+    out[i] = acc;
+  }
+  const double b0[5] = {-25.0 / 12.0, 4.0, -3.0, 4.0 / 3.0, -0.25};
+  const double b1[5] = {-0.25, -5.0 / 6.0, 1.5, -0.5, 1.0 / 12.0};
+  double s0 = 0, s1 = 0, e0 = 0, e1 = 0;
+  for (int m = 0; m < 5; ++m) {
+    s0 += b0[m] * f[m];
+    s1 += b1[m] * f[m];
+    e0 += b0[m] * f[n - 1 - m];
+    e1 += b1[m] * f[n - 1 - m];
+  }
+  out[0] = s0;
+  out[1] = s1;
+  out[n - 1] = -e0;
+  out[n - 2] = -e1;
+  if (order == 6) {
+    for (int i : {2, n - 3}) {
+      double acc = (2.0 / 3.0) * (f[i + 1] - f[i - 1]);
+      acc += (-1.0 / 12.0) * (f[i + 2] - f[i - 2]);
+      out[i] = acc;
+    }
+  }
+}
+
+int check(hipError_t e) { return e == hipSuccess ? HRX_OK : HRX_EHIP; }
+
+inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+extern "C" {
+
+const char* hrx_strerror(int code) {
+  switch (code) {
+    case HRX_OK: return "ok";
+    case HRX_EINVAL: return "invalid argument or configuration";
+    case HRX_EHIP: return "HIP runtime error";
+    case HRX_ENOMEM: return "device memory allocation failed";
+    case HRX_EUNSUP: return "not supported by this build";
+    default: return "unknown error";
+  }
+}
+
+void hrx_destroy(hrx_ctx* c) {
+  if (!c) return;
+  if (c->timing) hrx_timing_enable(c, 0);
+  (void)hipFree(c->W);
+  (void)hipFree(c->F);
+  (void)hipFree(c->R);
+  (void)hipFree(c->AD);
+  (void)hipFree(c->metrics);
+  (void)hipFree(c->hold);
+  (void)hipFree(c->counters);
+  delete c;
+}
+
+int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
+  if (!cfg || !out) return HRX_EINVAL;
+  *out = nullptr;
+  const hrx_config& c = *cfg;
+  if (c.gas != HRX_GAS_CPG && c.gas != HRX_GAS_AIR5) return HRX_EINVAL;
+  if (c.nx < 8 || c.ny < 8 || c.nz < 1 || (c.nz > 1 && c.nz < 8)) return HRX_EINVAL;
+  if (c.fd_order != 4 && c.fd_order != 6) return HRX_EINVAL;
+  if (c.rk_scheme != HRX_RK3_2N && c.rk_scheme != HRX_RK45_2N) return HRX_EINVAL;
+  if (c.precision != HRX_PREC_FP64) return HRX_EUNSUP;
+  if (!c.x || !c.y || (c.nz > 1 && !c.z)) return HRX_EINVAL;
+  if (c.sponge_in < 0 || c.sponge_out < 0 || c.sponge_top < 0 || c.sponge_in >= c.nx - 1 ||
+      c.sponge_out >= c.nx - 1 || c.sponge_top >= c.ny - 1)
+    return HRX_EINVAL;
+  if (c.wall == HRX_WALL_ISOTHERMAL && !(c.T_wall > 0.0)) return HRX_EINVAL;
+  if (!(c.T_inf > 0.0)) return HRX_EINVAL;
+  const long N = (long)c.nx * c.ny * c.nz;
+  for (int64_t h = 0; h < c.n_hold; ++h) {
+    if (!c.hold || c.hold[h] < 0 || c.hold[h] >= N) return HRX_EINVAL;
+    const long r = c.hold[h] / c.nx;
+    if (r % c.ny >= 3) return HRX_EINVAL;
+  }
+  hrx_ctx* ctx = new (std::nothrow) hrx_ctx();
+  if (!ctx) return HRX_ENOMEM;
+  ctx->cfg = c;
+  ctx->cfg.hold = nullptr;
+  Dev& d = ctx->dev;
+  std::memset(&d, 0, sizeof(d));
+  const int nd = c.nz > 1 ? 3 : 2;
+  const int ns = c.gas == HRX_GAS_AIR5 ? NS : 1;
+  d.nx = c.nx; d.ny = c.ny; d.nz = c.nz; d.ndim = nd; d.ns = ns; d.nvar = ns + nd + 1;
+  d.fd_order = c.fd_order; d.N = N;
+  d.newton_rtol = c.newton_rtol > 0.0 ? c.newton_rtol : 1e-13;
+  d.newton_max = c.newton_max_iter > 0 ? c.newton_max_iter : 50;
+  d.wall = c.wall; d.T_wall = c.T_wall;
+  d.ad_on = c.ad_on ? 1 : 0;
+  d.Cmu = c.ad_coef[0]; d.Cbeta = c.ad_coef[1]; d.Ckap = c.ad_coef[2]; d.CD = c.ad_coef[3];
+  d.CY = c.ad_coef[4];
+  // ---------------------------------------------------------- reference state (Eq. 7, 11)
+  hrx_reference& ref = ctx->ref;
+  std::memset(&ref, 0, sizeof(ref));
+  if (c.gas == HRX_GAS_CPG) {
+    if (!(c.gamma > 1.0) || !(c.Pr > 0.0) || !(c.Re > 0.0)) { delete ctx; return HRX_EINVAL; }
+    ref.gamma = c.gamma; ref.Re = c.Re; ref.Pr = c.Pr; ref.Ec = 1.0;
+    ref.T_ref = (c.gamma - 1.0) * c.T_inf;
+    ref.mu_inf = sutherland<double>(c.T_inf);
+  } else {
+    double Y[NS], ysum = 0.0;
+    for (int s = 0; s < NS; ++s) { Y[s] = c.Y_inf[s]; ysum += Y[s]; }
+    if (!(c.p_inf > 0.0) || fabs(ysum - 1.0) > 1e-9) { delete ctx; return HRX_EINVAL; }
+    const double R = mixture_R(Y);
+    SpeciesThermo st;
+    species_e_cv(c.T_inf, st);
+    double cv = 0.0;
+    for (int s = 0; s < NS; ++s) cv += Y[s] * st.cv[s];
+    const double cp = cv + R, g = cp / cv;
+    const double rho = c.p_inf / (R * c.T_inf);
+    const double cs = sqrt(g * R * c.T_inf);
+    double X[NS], nsum = 0.0;
+    for (int s = 0; s < NS; ++s) { X[s] = Y[s] / molar_mass(s); nsum += X[s]; }
+    for (int s = 0; s < NS; ++s) X[s] = X[s] / nsum;
+    Transport<double> tr;
+    mixture_transport<double>(c.T_inf, c.p_inf, X, st.cv, tr);
+    double L = c.L_ref, Re = c.Re;
+    if (L > 0.0) Re = rho * cs * L / tr.mu;
+    else {
+      if (!(Re > 0.0)) { delete ctx; return HRX_EINVAL; }
+      L = Re * tr.mu / (rho * cs);
+    }
+    ref.gamma = g; ref.Re = Re; ref.Pr = tr.mu * cp / tr.kappa;
+    ref.T_ref = (g - 1.0) * c.T_inf; ref.Ec = cs * cs / (cp * ref.T_ref);
+    ref.rho_inf = rho; ref.c_inf = cs; ref.mu_inf = tr.mu; ref.kappa_inf = tr.kappa;
+    ref.R_inf = R; ref.L_ref = L;
+  }
+  d.gamma = ref.gamma; d.Re = ref.Re; d.Pr = ref.Pr; d.T_ref = ref.T_ref;
+  d.mu_inf = ref.mu_inf; d.kappa_inf = ref.kappa_inf; d.c_inf = ref.c_inf;
+  d.rho_inf = ref.rho_inf; d.L_ref = ref.L_ref; d.R_inf = ref.R_inf;
+  // ---------------------------------------------------------- metrics, spacing, sponge
+  std::vector<double> x(c.x, c.x + c.nx), y(c.y, c.y + c.ny), Dx, Dy, Dx6, Dy6;
+  host_deriv(x, c.fd_order, Dx);
+  host_deriv(y, c.fd_order, Dy);
+  host_deriv(x, 6, Dx6);
+  host_deriv(y, 6, Dy6);
+  const int nz = c.nz;
+  std::vector<double> hm(2 * c.nx + 2 * c.ny + 2 * nz + c.nx + c.ny + nz, 0.0);
+  double* mx = hm.data();
+  double* sxv = mx + c.nx;
+  double* dlx = sxv + c.nx;
+  double* my = dlx + c.nx;
+  double* syv = my + c.ny;
+  double* dly = syv + c.ny;
+  double* mz = dly + c.ny;
+  double* dlz = mz + nz;
+  for (int i = 0; i < c.nx; ++i) {
+    mx[i] = 1.0 / Dx[i];
+    if (!(Dx[i] > 0.0)) { delete ctx; return HRX_EINVAL; }
+    dlx[i] = 1.0 / (1.0 / Dx6[i]);
+  }
+  for (int j = 0; j < c.ny; ++j) {
+    my[j] = 1.0 / Dy[j];
+    if (!(Dy[j] > 0.0)) { delete ctx; return HRX_EINVAL; }
+    dly[j] = 1.0 / (1.0 / Dy6[j]);
+  }
+  for (int k = 0; k < nz; ++k) {
+    if (nz > 1) {
+      const double dz = c.z[1] - c.z[0];
+      mz[k] = 1.0 / dz;
+      dlz[k] = dz;
+    } else {
+      mz[k] = 0.0;
+      dlz[k] = 1.0;
+    }
+  }
+  // sponge: sigma_max s^3 with s the normalised depth (Eq. 26, cubic profile)
+  if (c.sponge_in > 0) {
+    const int i1 = c.sponge_in;
+    for (int i = 0; i < i1; ++i) {
+      const double s = (x[i1] - x[i]) / (x[i1] - x[0]);
+      sxv[i] = fmax(sxv[i], c.sigma_max * (s * s * s));
+    }
+  }
+  if (c.sponge_out > 0) {
+    const int i0 = c.nx - 1 - c.sponge_out;
+    for (int i = i0 + 1; i < c.nx; ++i) {
+      const double s = (x[i] - x[i0]) / (x[c.nx - 1] - x[i0]);
+      sxv[i] = fmax(sxv[i], c.sigma_max * (s * s * s));
+    }
+  }
+  if (c.sponge_top > 0) {
+    const int j0 = c.ny - 1 - c.sponge_top;
+    for (int j = j0 + 1; j < c.ny; ++j) {
+      const double s = (y[j] - y[j0]) / (y[c.ny - 1] - y[j0]);
+      syv[j] = fmax(syv[j], c.sigma_max * (s * s * s));
+    }
+  }
+  int rc = HRX_OK;
+  auto fail = [&](int code) { hrx_destroy(ctx); return code; };
+  if (hipMalloc(&ctx->metrics, hm.size() * sizeof(double)) != hipSuccess) return fail(HRX_ENOMEM);
+  if ((rc = check(hipMemcpy(ctx->metrics, hm.data(), hm.size() * sizeof(double),
+                            hipMemcpyHostToDevice))))
+    return fail(rc);
+  double* dm = ctx->metrics;
+  d.mx = dm; d.sx = dm + c.nx; d.dlx = dm + 2 * c.nx;
+  d.my = dm + 3 * c.nx; d.sy = d.my + c.ny; d.dly = d.my + 2 * c.ny;
+  d.mz = d.my + 3 * c.ny; d.dlz = d.mz + nz;
+  if (c.n_hold > 0) {
+    std::vector<unsigned char> hm8((size_t)nz * 3 * c.nx, 0);
+    for (int64_t h = 0; h < c.n_hold; ++h) {
+      const long q = c.hold[h];
+      const int i = (int)(q % c.nx);
+      const long r = q / c.nx;
+      const int j = (int)(r % c.ny);
+      const int k = (int)(r / c.ny);
+      hm8[((size_t)k * 3 + j) * c.nx + i] = 1;
+    }
+    if (hipMalloc(&ctx->hold, hm8.size()) != hipSuccess) return fail(HRX_ENOMEM);
+    if ((rc = check(hipMemcpy(ctx->hold, hm8.data(), hm8.size(), hipMemcpyHostToDevice))))
+      return fail(rc);
+    d.hold = ctx->hold;
+  }
+  // ---------------------------------------------------------- scratch planes
+  d.nsrc = nd + 1 + (c.gas == HRX_GAS_AIR5 ? NS : 0);
+  int w = d.nsrc;
+  d.w_p = w++;
+  d.w_mu = w++;
+  if (c.gas == HRX_GAS_AIR5) {
+    d.w_kap = w++;
+    d.w_D = w; w += NS;
+    d.w_wdot = w; w += NS;
+  }
+  if (d.ad_on) d.w_c = w++;
+  ctx->nW = w;
+  ctx->nF = nd * d.nvar;
+  d.nad = 3 + (c.gas == HRX_GAS_AIR5 ? NS : 0);
+  if (hipMalloc(&ctx->W, sizeof(double) * N * ctx->nW) != hipSuccess) return fail(HRX_ENOMEM);
+  if (hipMalloc(&ctx->F, sizeof(double) * N * ctx->nF) != hipSuccess) return fail(HRX_ENOMEM);
+  if (hipMalloc(&ctx->R, sizeof(double) * N * d.nvar) != hipSuccess) return fail(HRX_ENOMEM);
+  if (d.ad_on && hipMalloc(&ctx->AD, sizeof(double) * N * d.nad * 2) != hipSuccess)
+    return fail(HRX_ENOMEM);
+  if (hipMalloc(&ctx->counters, 4 * sizeof(unsigned long long)) != hipSuccess)
+    return fail(HRX_ENOMEM);
+  if ((rc = check(hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long))))) return fail(rc);
+  d.counters = ctx->counters;
+  *out = ctx;
+  return HRX_OK;
+}
+
+int hrx_get_reference(const hrx_ctx* ctx, hrx_reference* out) {
+  if (!ctx || !out) return HRX_EINVAL;
+  *out = ctx->ref;
+  return HRX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <int GAS, int ND, int ORDER>
+int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
+  const Dev& d = ctx->dev;
+  const long N = d.N;
+  const int bs = 128;
+  const unsigned nb = blocks_for(N, bs);
+  timed(ctx, K_PRIM, st, [&] { k_prim<GAS, ND><<<nb, bs, 0, st>>>(d, Q, ctx->W); });
+  const double* Gad = nullptr;
+  if (d.ad_on) {
+    double* A = ctx->AD;
+    double* B = ctx->AD + (long)d.nad * N;
+    timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER><<<nb, bs, 0, st>>>(d, Q, ctx->W, A); });
+    timed(ctx, K_AD_D4, st, [&] { k_ad_d4<GAS, ND><<<nb, bs, 0, st>>>(d, A, B); });
+    timed(ctx, K_AD_FX, st, [&] { k_ad_filter<0><<<nb, bs, 0, st>>>(d, B, A); });
+    timed(ctx, K_AD_FY, st, [&] { k_ad_filter<1><<<nb, bs, 0, st>>>(d, A, B); });
+    if (ND == 3) {
+      timed(ctx, K_AD_FZ, st, [&] { k_ad_filter<2><<<nb, bs, 0, st>>>(d, B, A); });
+      Gad = A;
+    } else {
+      Gad = B;
+    }
+    timed(ctx, K_FLUX, st, [&] { k_flux<GAS, ND, ORDER, true><<<nb, bs, 0, st>>>(d, Q, ctx->W, Gad, ctx->F); });
+  } else {
+    timed(ctx, K_FLUX, st, [&] { k_flux<GAS, ND, ORDER, false><<<nb, bs, 0, st>>>(d, Q, ctx->W, nullptr, ctx->F); });
+  }
+  return check(hipGetLastError());
+}
+
+template <int GAS, int ND, int ORDER>
+int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, double* Qio,
+        double* dQ, double A, double B, double dt, hipStream_t st) {
+  const Dev& d = ctx->dev;
+  int rc = launch_rhs_chain<GAS, ND, ORDER>(ctx, mode == MODE_RHS ? Q : Qio, st);
+  if (rc) return rc;
+  const unsigned nb = blocks_for(d.N, 128);
+  if (mode == MODE_RHS) {
+    timed(ctx, K_DIV, st, [&] {
+      k_div<GAS, ND, ORDER, MODE_RHS><<<nb, 128, 0, st>>>(d, ctx->F, ctx->W, Q, Qref, R, nullptr,
+                                                           nullptr, 0.0, 0.0, 0.0);
+    });
+  } else {
+    timed(ctx, K_DIV, st, [&] {
+      k_div<GAS, ND, ORDER, MODE_RK><<<nb, 128, 0, st>>>(d, ctx->F, ctx->W, nullptr, Qref,
+                                                          nullptr, Qio, dQ, A, B, dt);
+    });
+    const long nw = (long)(d.nx - 1) * d.nz;
+    timed(ctx, K_BC, st, [&] { k_bc<GAS, ND><<<blocks_for(nw, 128), 128, 0, st>>>(d, Qio); });
+  }
+  return check(hipGetLastError());
+}
+
+int dispatch(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, double* Qio,
+             double* dQ, double A, double B, double dt, hipStream_t st) {
+  const Dev& d = ctx->dev;
+  const bool air = ctx->cfg.gas == HRX_GAS_AIR5;
+  const bool o6 = d.fd_order == 6;
+#define HRX_RUN(G, NDV, O) return run<G, NDV, O>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, st)
+  if (d.ndim == 2) {
+    if (air) { if (o6) HRX_RUN(AIR5, 2, 6); else HRX_RUN(AIR5, 2, 4); }
+    else { if (o6) HRX_RUN(CPG, 2, 6); else HRX_RUN(CPG, 2, 4); }
+  } else {
+    if (air) { if (o6) HRX_RUN(AIR5, 3, 6); else HRX_RUN(AIR5, 3, 4); }
+    else { if (o6) HRX_RUN(CPG, 3, 6); else HRX_RUN(CPG, 3, 4); }
+  }
+#undef HRX_RUN
+}
+
+// Williamson 2N-RK3 and Carpenter-Kennedy 2N-RK4(3)5 coefficients
+const double RK3A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+const double RK3B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+const double RK4A[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                        -2404267990393.0 / 2016746695238.0, -3550918686646.0 / 2091501179385.0,
+                        -1275806237668.0 / 842570457699.0};
+const double RK4B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+}  // namespace
+
+extern "C" {
+
+int hrx_rhs_eval(hrx_ctx* ctx, const double* Q, const double* Q_ref, double* R,
+                 void* hip_stream) {
+  if (!ctx || !Q || !R || R == Q) return HRX_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  return dispatch(ctx, MODE_RHS, Q, Q_ref, R, nullptr, nullptr, 0.0, 0.0, 0.0, st);
+}
+
+int hrx_rk_stage(hrx_ctx* ctx, int stage, double dt, double* Q, double* dQ, const double* Q_ref,
+                 void* hip_stream) {
+  if (!ctx || !Q || !dQ || Q == dQ || stage < 0 || !std::isfinite(dt)) return HRX_EINVAL;
+  const bool rk3 = ctx->cfg.rk_scheme == HRX_RK3_2N;
+  const int ns = rk3 ? 3 : 5;
+  const int k = stage % ns;
+  const double A = rk3 ? RK3A[k] : RK4A[k];
+  const double B = rk3 ? RK3B[k] : RK4B[k];
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  return dispatch(ctx, MODE_RK, nullptr, Q_ref, nullptr, Q, dQ, A, B, dt, st);
+}
+
+int hrx_thermo_eval(hrx_ctx* ctx, int64_t n, const double* rho, const double* e, const double* Y,
+                    double* T, double* p, double* h, double* mu, double* kappa, double* D,
+                    int32_t* status, void* hip_stream) {
+  if (!ctx || n < 0 || (n > 0 && (!rho || !e || !Y || !T))) return HRX_EINVAL;
+  if (ctx->cfg.gas != HRX_GAS_AIR5) return HRX_EINVAL;
+  if (n == 0) return HRX_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  timed(ctx, K_THERMO, st, [&] {
+    k_thermo_eval<<<blocks_for(n, 128), 128, 0, st>>>(n, ctx->dev.newton_rtol,
+                                                       ctx->dev.newton_max, rho, e, Y, T, p, h,
+                                                       mu, kappa, D, status, ctx->counters);
+  });
+  return check(hipGetLastError());
+}
+
+int hrx_chem_source(hrx_ctx* ctx, int64_t n, const double* rho_s, const double* T, double* wdot,
+                    void* hip_stream) {
+  if (!ctx || n < 0 || (n > 0 && (!rho_s || !T || !wdot))) return HRX_EINVAL;
+  if (ctx->cfg.gas != HRX_GAS_AIR5) return HRX_EINVAL;
+  if (n == 0) return HRX_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  timed(ctx, K_CHEM, st, [&] { k_chem_source<<<blocks_for(n, 128), 128, 0, st>>>(n, rho_s, T, wdot); });
+  return check(hipGetLastError());
+}
+
+int hrx_timing_enable(hrx_ctx* ctx, int on) {
+  if (!ctx) return HRX_EINVAL;
+  if (on) {
+    if (!ctx->timing) {
+      for (int i = 0; i < 8192; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return HRX_EHIP;
+        ctx->ev_free.push_back(e);
+      }
+      for (int k = 0; k < HRX_NKERNELS; ++k) { ctx->ms[k] = 0.0; ctx->launches[k] = 0; }
+      ctx->timing = true;
+    }
+    return HRX_OK;
+  }
+  int rc = flush_timing(ctx);
+  for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
+  ctx->ev_free.clear();
+  ctx->timing = false;
+  return rc;
+}
+
+int hrx_timing_read(hrx_ctx* ctx, double* ms, int64_t* launches) {
+  if (!ctx || !ms || !launches) return HRX_EINVAL;
+  int rc = flush_timing(ctx);
+  for (int k = 0; k < HRX_NKERNELS; ++k) { ms[k] = ctx->ms[k]; launches[k] = ctx->launches[k]; }
+  return rc;
+}
+
+int hrx_get_counters(hrx_ctx* ctx, hrx_counters* out, int reset) {
+  if (!ctx || !out) return HRX_EINVAL;
+  unsigned long long h[4] = {0, 0, 0, 0};
+  int rc = check(hipStreamSynchronize(ctx->last_stream));
+  if (rc) return rc;
+  rc = check(hipMemcpy(h, ctx->counters, sizeof(h), hipMemcpyDeviceToHost));
+  if (rc) return rc;
+  out->newton_nonconverged = (int64_t)h[0];
+  out->energy_below_min = (int64_t)h[1];
+  out->surrogate_fallbacks = (int64_t)h[2];
+  if (reset) rc = check(hipMemset(ctx->counters, 0, sizeof(h)));
+  return rc;
+}
+
+}  // extern "C"

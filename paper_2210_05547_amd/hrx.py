@@ -1,0 +1,211 @@
+"""ctypes binding of the hrx C-ABI (include/hrx.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libhrx.so``.  Device buffers are
+torch tensors on a ROCm device (PyTorch supplies memory and streams); the binding
+passes their raw pointers and the current HIP stream.  A missing library is an
+error: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhrx.so")
+
+GAS_CPG, GAS_AIR5 = 0, 1
+WALL_ADIABATIC, WALL_ISOTHERMAL = 0, 1
+RK3_2N, RK45_2N = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+
+HRX_OK = 0
+
+
+class HrxError(RuntimeError):
+    pass
+
+
+class _Config(C.Structure):
+    _fields_ = [
+        ("gas", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)), ("z", C.POINTER(C.c_double)),
+        ("fd_order", C.c_int), ("rk_scheme", C.c_int), ("precision", C.c_int), ("ad_on", C.c_int),
+        ("ad_coef", C.c_double * 5),
+        ("gamma", C.c_double), ("Pr", C.c_double), ("mach", C.c_double), ("T_inf", C.c_double),
+        ("p_inf", C.c_double), ("Re", C.c_double), ("L_ref", C.c_double),
+        ("Y_inf", C.c_double * 5),
+        ("wall", C.c_int), ("T_wall", C.c_double),
+        ("sponge_in", C.c_int), ("sponge_out", C.c_int), ("sponge_top", C.c_int),
+        ("sigma_max", C.c_double),
+        ("hold", C.POINTER(C.c_int64)), ("n_hold", C.c_int64),
+        ("newton_max_iter", C.c_int), ("newton_rtol", C.c_double),
+    ]
+
+
+class Reference(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "gamma", "Re", "Pr", "Ec", "T_ref", "rho_inf", "c_inf", "mu_inf", "kappa_inf", "R_inf",
+        "L_ref")]
+
+
+class Counters(C.Structure):
+    _fields_ = [("newton_nonconverged", C.c_int64), ("energy_below_min", C.c_int64),
+                ("surrogate_fallbacks", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhrx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise HrxError(f"{path} not found: build it with __graft_entry__.build()")
+    lib = C.CDLL(path)
+    vp, dp, i64 = C.c_void_p, C.c_void_p, C.c_int64
+    lib.hrx_create.argtypes = [C.POINTER(_Config), C.POINTER(vp)]
+    lib.hrx_create.restype = C.c_int
+    lib.hrx_destroy.argtypes = [vp]
+    lib.hrx_destroy.restype = None
+    lib.hrx_get_reference.argtypes = [vp, C.POINTER(Reference)]
+    lib.hrx_get_reference.restype = C.c_int
+    lib.hrx_rhs_eval.argtypes = [vp, dp, dp, dp, vp]
+    lib.hrx_rhs_eval.restype = C.c_int
+    lib.hrx_rk_stage.argtypes = [vp, C.c_int, C.c_double, dp, dp, dp, vp]
+    lib.hrx_rk_stage.restype = C.c_int
+    lib.hrx_thermo_eval.argtypes = [vp, i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
+    lib.hrx_thermo_eval.restype = C.c_int
+    lib.hrx_chem_source.argtypes = [vp, i64, dp, dp, dp, vp]
+    lib.hrx_chem_source.restype = C.c_int
+    lib.hrx_get_counters.argtypes = [vp, C.POINTER(Counters), C.c_int]
+    lib.hrx_get_counters.restype = C.c_int
+    lib.hrx_timing_enable.argtypes = [vp, C.c_int]
+    lib.hrx_timing_enable.restype = C.c_int
+    lib.hrx_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.hrx_timing_read.restype = C.c_int
+    lib.hrx_strerror.argtypes = [C.c_int]
+    lib.hrx_strerror.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != HRX_OK:
+        raise HrxError(f"hrx error {rc}: {_lib.hrx_strerror(rc).decode()}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """Owns one hrx_ctx.  Built from a workload description (fields.FlowConfig)."""
+
+    def __init__(self, cfg, x, y, z=None, hold=None, precision=PREC_FP64):
+        lib = load()
+        self._keep = []
+        c = _Config()
+        c.gas = cfg.gas
+        c.nx, c.ny, c.nz = cfg.nx, cfg.ny, cfg.nz
+
+        def arr(a):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            self._keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_double))
+
+        c.x, c.y = arr(x), arr(y)
+        c.z = arr(z) if (z is not None and cfg.nz > 1) else None
+        c.fd_order, c.rk_scheme, c.precision = cfg.fd_order, cfg.rk, precision
+        c.ad_on = 1 if cfg.ad else 0
+        c.ad_coef[:] = list(cfg.ad_coef)
+        c.gamma, c.Pr, c.mach, c.T_inf = cfg.gamma, cfg.Pr, cfg.mach, cfg.T_inf
+        c.p_inf, c.Re, c.L_ref = cfg.p_inf, cfg.Re, cfg.L_ref
+        c.Y_inf[:] = list(cfg.Y_inf)
+        c.wall, c.T_wall = cfg.wall, cfg.T_wall
+        c.sponge_in, c.sponge_out, c.sponge_top = cfg.sponge_in, cfg.sponge_out, cfg.sponge_top
+        c.sigma_max = cfg.sigma_max
+        if hold is not None and len(hold):
+            h = np.ascontiguousarray(hold, dtype=np.int64)
+            self._keep.append(h)
+            c.hold = h.ctypes.data_as(C.POINTER(C.c_int64))
+            c.n_hold = len(h)
+        else:
+            c.hold, c.n_hold = None, 0
+        c.newton_max_iter, c.newton_rtol = 0, 0.0
+        h = C.c_void_p()
+        _check(lib.hrx_create(C.byref(c), C.byref(h)))
+        self._h = h
+        self.cfg = cfg
+        self.nvar = cfg.nvar
+        self.N = cfg.npts
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hrx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reference(self):
+        r = Reference()
+        _check(_lib.hrx_get_reference(self._h, C.byref(r)))
+        return {n: getattr(r, n) for n, _ in Reference._fields_}
+
+    def counters(self, reset=False):
+        c = Counters()
+        _check(_lib.hrx_get_counters(self._h, C.byref(c), 1 if reset else 0))
+        return {n: getattr(c, n) for n, _ in Counters._fields_}
+
+
+KERNEL_NAMES = ("prim", "ad_src", "ad_d4", "ad_filter_x", "ad_filter_y", "ad_filter_z", "flux",
+                "div", "bc", "thermo_eval", "chem_source")
+
+
+def timing_enable(ctx, on=True):
+    _check(_lib.hrx_timing_enable(ctx._h, 1 if on else 0))
+
+
+def timing_read(ctx):
+    """{kernel: (total ms, launches)} since timing was enabled (synchronises)."""
+    n = len(KERNEL_NAMES)
+    ms = (C.c_double * n)()
+    cnt = (C.c_int64 * n)()
+    _check(_lib.hrx_timing_read(ctx._h, ms, cnt))
+    return {KERNEL_NAMES[k]: (ms[k], cnt[k]) for k in range(n)}
+
+
+def rhs_eval(ctx, Q, Q_ref, R, stream=None):
+    _check(_lib.hrx_rhs_eval(ctx._h, _ptr(Q), _ptr(Q_ref), _ptr(R), _stream(stream)))
+
+
+def rk_stage(ctx, stage, dt, Q, dQ, Q_ref, stream=None):
+    _check(_lib.hrx_rk_stage(ctx._h, int(stage), float(dt), _ptr(Q), _ptr(dQ), _ptr(Q_ref),
+                             _stream(stream)))
+
+
+def thermo_eval(ctx, n, rho, e, Y, T, p=None, h=None, mu=None, kappa=None, D=None, status=None,
+                stream=None):
+    _check(_lib.hrx_thermo_eval(ctx._h, int(n), _ptr(rho), _ptr(e), _ptr(Y), _ptr(T), _ptr(p),
+                                _ptr(h), _ptr(mu), _ptr(kappa), _ptr(D), _ptr(status),
+                                _stream(stream)))
+
+
+def chem_source(ctx, n, rho_s, T, wdot, stream=None):
+    _check(_lib.hrx_chem_source(ctx._h, int(n), _ptr(rho_s), _ptr(T), _ptr(wdot), _stream(stream)))
