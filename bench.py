@@ -73,7 +73,19 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 10 times (counter scaling)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "reps": 10}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path's multi-GPU sharding is described in DESIGN.md, not built)",
@@ -96,9 +108,6 @@ def main():
         hrx.rk_stage(ctx, stage, info["dt"], Qd, dQd, Qrd)
         stage += 1
     torch.cuda.synchronize()
-    hrx.timing_enable(ctx, True)
-    hrx.timing_read(ctx)
-    hrx.timing_enable(ctx, False)
     hrx.timing_enable(ctx, True)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
