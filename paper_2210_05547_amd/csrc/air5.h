@@ -74,9 +74,11 @@ HRX_HD double gas_const(int s) { return RU / molar_mass(s); }
 // Species energy and heat capacity per unit mass at one temperature:
 //   e_s = R_s [(3/2 + r_s) T + r_s theta_s / (exp(theta_s/T) - 1)] + h_f,s(0 K)/M_s
 // with r_s = 1 for the diatomics (one rotational and one vibrational mode), 0 for atoms.
+// em1[s] = exp(theta_s/T) - 1 of the three diatomics is kept for reuse (Gibbs energies).
 struct SpeciesThermo {
   double e[NS];    // J/kg
   double cv[NS];   // J/(kg K)
+  double em1[3];
 };
 
 HRX_HD void species_e_cv(double T, SpeciesThermo& st) {
@@ -88,6 +90,7 @@ HRX_HD void species_e_cv(double T, SpeciesThermo& st) {
       const double x = theta_vib(s) / T;
       const double em1 = expm1(x);
       const double ex = em1 + 1.0;
+      st.em1[s] = em1;
       st.e[s] = Rs * (2.5 * T + theta_vib(s) / em1) + hf;
       st.cv[s] = Rs * (2.5 + x * x * ex / (em1 * em1));
     } else {
@@ -128,31 +131,37 @@ HRX_HD double mixture_R(const double* Y) {
 }
 
 constexpr double T_MIN = 50.0;
+constexpr double T_GUESS_MAX = 1.0e5;
 
-// Newton inversion of e = sum_s Y_s e_s(T) (Sec. 3.4).  The start T0 solves the
-// energy equation with fully excited vibration, which over-estimates e_s(T), so T0
-// lies below the root; e(T) is increasing and convex, so the iterates approach the
-// root from above after the first step.  status: 0 converged, 1 no convergence in
-// max_iter, 2 energy below e(T_MIN).
+// Newton inversion of e = sum_s Y_s e_s(T) (Sec. 3.4).  e(T) is increasing and
+// convex (c_v rises with T), so Newton's method converges from any start: from below
+// the root the first step lands above it, and from above the iterates decrease
+// monotonically.  Cold start: the temperature that solves the energy equation with
+// fully excited vibration (a lower bound of the root).  Warm start: a previous
+// temperature T_guess in (T_MIN, T_GUESS_MAX), which the caller may pass to save
+// iterations; the root is the same.  Stops when |dT| <= rtol T.  status: 0 converged,
+// 1 no convergence in max_iter, 2 energy below e(T_MIN).
 HRX_HD double temperature_from_energy(double e, const double* Y, double rtol, int max_iter,
-                                      int* status, int* iters, double* cv_out) {
+                                      int* status, int* iters, double T_guess = 0.0) {
   double ef = 0.0, cfull = 0.0, emin = 0.0;
-  SpeciesThermo st;
-  species_e_cv(T_MIN, st);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
+    const double Rs = gas_const(s);
     ef += Y[s] * (hf0_molar(s) / molar_mass(s));
-    cfull += Y[s] * gas_const(s) * (is_diatomic(s) ? 3.5 : 1.5);
-    emin += Y[s] * st.e[s];
+    cfull += Y[s] * Rs * (is_diatomic(s) ? 3.5 : 1.5);
+    // e_s(T_MIN): at 50 K the vibrational energy theta/(exp(theta/T) - 1) is below
+    // 1e-18 of the translational-rotational part for every species, so it vanishes in
+    // double precision and is left out
+    emin += Y[s] * (Rs * ((is_diatomic(s) ? 2.5 : 1.5) * T_MIN) + hf0_molar(s) / molar_mass(s));
   }
-  double T = (e - ef) / cfull;
   *iters = 0;
   if (!(e >= emin)) {
     *status = 2;
-    if (cv_out) *cv_out = 0.0;
     return T_MIN;
   }
+  double T = (T_guess > T_MIN && T_guess < T_GUESS_MAX) ? T_guess : (e - ef) / cfull;
   if (T < T_MIN) T = T_MIN;
+  SpeciesThermo st;
   for (int it = 0; it < max_iter; ++it) {
     species_e_cv(T, st);
     double f = 0.0, cv = 0.0;
@@ -165,7 +174,6 @@ HRX_HD double temperature_from_energy(double e, const double* Y, double rtol, in
     const double dT = f / cv;
     T = T - dT;
     *iters = it + 1;
-    if (cv_out) *cv_out = cv;
     if (fabs(dT) <= rtol * T) {
       *status = 0;
       return T;
@@ -175,28 +183,7 @@ HRX_HD double temperature_from_energy(double e, const double* Y, double rtol, in
   return T;
 }
 
-// Frozen c_v at T (one more evaluation; used where the sound speed is needed).
-HRX_HD double mixture_cv(double T, const double* Y) {
-  SpeciesThermo st;
-  species_e_cv(T, st);
-  double cv = 0.0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) cv += Y[s] * st.cv[s];
-  return cv;
-}
-
 // ----------------------------------------------------------------- transport
-template <class R>
-HRX_HD R omega22(R Ts) {
-  return R(1.16145) * pow(Ts, R(-0.14874)) + R(0.52487) * exp(R(-0.77320) * Ts) +
-         R(2.16178) * exp(R(-2.43787) * Ts);
-}
-template <class R>
-HRX_HD R omega11(R Ts) {
-  return R(1.06036) * pow(Ts, R(-0.15610)) + R(0.19300) * exp(R(-0.47635) * Ts) +
-         R(1.03587) * exp(R(-1.52996) * Ts) + R(1.76474) * exp(R(-3.89411) * Ts);
-}
-
 constexpr double X_CLIP = 1e-12;
 
 template <class R>
@@ -209,28 +196,37 @@ struct Transport {
 // coefficients at (T, p, X).  cv[s] is the species c_v at T (J/(kg K)).
 //   mu_s  = (5/16) sqrt(pi m_s k T) / (pi sigma_s^2 Omega22*(T/eps_s))
 //   D_sr  = (3/16) sqrt(2 pi k^3 T^3 / m_sr) / (p pi sigma_sr^2 Omega11*(T/eps_sr))
+//   Omega22*(x) = 1.16145 x^-0.14874 + 0.52487 e^-0.77320x + 2.16178 e^-2.43787x
+//   Omega11*(x) = 1.06036 x^-0.15610 + 0.19300 e^-0.47635x + 1.03587 e^-1.52996x
+//                 + 1.76474 e^-3.89411x                        (Neufeld et al. 1972)
 //   kappa_s = mu_s (15/4 R_s + c_v,int,s)   (Eucken; c_v,int = c_v - 3/2 R_s)
 //   phi_sr = [1 + sqrt(mu_s/mu_r) (M_r/M_s)^(1/4)]^2 / sqrt(8 (1 + M_s/M_r))
 //   mu = sum_s X_s mu_s / sum_r X_r phi_sr, kappa likewise;
 //   D_s = (1 - X_s) / sum_{r != s} X_r / D_sr (Eq. 19) with 1 - X_s formed as
 //   sum_{r != s} X_r and every X_r clipped below at 1e-12 in this formula only.
 // The molecular constants are folded in double precision so that the float
-// instantiation sees only well-scaled numbers.
+// instantiation sees only well-scaled numbers; powers x^a are exp(a (ln T - ln eps)).
 template <class R>
 HRX_HD void mixture_transport(double T, double p, const double* X, const double* cv,
                               Transport<R>& out) {
-  R mu_s[NS], k_s[NS];
+  R mu_s[NS], k_s[NS], smu[NS], ismu[NS];
   const R Tr = R(T);
   const R sqT = sqrt(Tr);
+  const R lnT = log(Tr);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const double m = molar_mass(s) / NAV;
     const double sig = lj_sigma(s);
     const R A = R((5.0 / 16.0) * sqrt(PI * m * KB) / (PI * sig * sig));
-    mu_s[s] = A * sqT / omega22<R>(Tr / R(lj_eps(s)));
+    const R Ts = Tr * R(1.0 / lj_eps(s));
+    const R om = R(1.16145) * exp(R(-0.14874) * (lnT - R(log(lj_eps(s))))) +
+                 R(0.52487) * exp(R(-0.77320) * Ts) + R(2.16178) * exp(R(-2.43787) * Ts);
+    mu_s[s] = A * sqT / om;
     const R Rs = R(gas_const(s));
     const R cv_int = R(cv[s]) - R(1.5) * Rs;
     k_s[s] = mu_s[s] * (R(3.75) * Rs + cv_int);
+    smu[s] = sqrt(mu_s[s]);
+    ismu[s] = R(1) / smu[s];
   }
   R mu = R(0), kap = R(0);
 #pragma unroll
@@ -238,8 +234,13 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
     R den = R(0);
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
-      const R a = R(1) + sqrt(mu_s[s] / mu_s[r]) * R(pow(molar_mass(r) / molar_mass(s), 0.25));
-      const R phi = a * a / R(sqrt(8.0 * (1.0 + molar_mass(s) / molar_mass(r))));
+      R phi;
+      if (r == s) {
+        phi = R(1);
+      } else {
+        const R a = R(1) + smu[s] * ismu[r] * R(pow(molar_mass(r) / molar_mass(s), 0.25));
+        phi = a * a * R(1.0 / sqrt(8.0 * (1.0 + molar_mass(s) / molar_mass(r))));
+      }
       den += R(X[r]) * phi;
     }
     mu += R(X[s]) * mu_s[s] / den;
@@ -247,9 +248,9 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
   }
   out.mu = mu;
   out.kappa = kap;
-  R Dsr[NS][NS];
-  const R T15 = Tr * sqT;
-  const R pr = R(p);
+  // reciprocal binary coefficients 1/D_sr = p Omega11 / (B_sr T^(3/2))
+  R iD[NS][NS];
+  const R pr_iT15 = R(p) / (Tr * sqT);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
 #pragma unroll
@@ -257,11 +258,15 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
       const double ms = molar_mass(s) / NAV, mr = molar_mass(r) / NAV;
       const double msr = ms * mr / (ms + mr);
       const double sig = 0.5 * (lj_sigma(s) + lj_sigma(r));
-      const R B = R((3.0 / 16.0) * sqrt(2.0 * PI * KB * KB * KB / msr) / (PI * sig * sig));
-      const R eps = R(sqrt(lj_eps(s) * lj_eps(r)));
-      const R d = B * T15 / (pr * omega11<R>(Tr / eps));
-      Dsr[s][r] = d;
-      Dsr[r][s] = d;
+      const double eps = sqrt(lj_eps(s) * lj_eps(r));
+      const R iB = R((PI * sig * sig) / ((3.0 / 16.0) * sqrt(2.0 * PI * KB * KB * KB / msr)));
+      const R Ts = Tr * R(1.0 / eps);
+      const R om = R(1.06036) * exp(R(-0.15610) * (lnT - R(log(eps)))) +
+                   R(0.19300) * exp(R(-0.47635) * Ts) + R(1.03587) * exp(R(-1.52996) * Ts) +
+                   R(1.76474) * exp(R(-3.89411) * Ts);
+      const R v = pr_iT15 * om * iB;
+      iD[s][r] = v;
+      iD[r][s] = v;
     }
   }
   R Xc[NS];
@@ -274,7 +279,7 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
     for (int r = 0; r < NS; ++r) {
       if (r == s) continue;
       num += Xc[r];
-      den += Xc[r] / Dsr[s][r];
+      den += Xc[r] * iD[s][r];
     }
     out.D[s] = num / den;
   }
@@ -287,18 +292,19 @@ HRX_HD R sutherland(R T) {
 }
 
 // ----------------------------------------------------------------- chemistry
-// Standard-state molar Gibbs energy g_s/(R_u T) at p0 (statistical mechanics).
-HRX_HD void gibbs_over_RT(double T, double* g) {
-  const double lnT = log(T);
+// Standard-state molar Gibbs energy g_s/(R_u T) at p0 (statistical mechanics):
+//   g_s/(R_u T) = h_f,s/(R_u T) - ln[(2 pi m_s k T/h^2)^(3/2) k T/p0] - ln g_el,s
+//                 - r_s ln(T/(sigma_s theta_r,s)) + r_s ln(1 - exp(-theta_s/T))
+// em1[s] = exp(theta_s/T) - 1 of the diatomics (1 - exp(-x) = em1/(em1 + 1)).
+HRX_HD void gibbs_over_RT(double T, double lnT, const double* em1, double* g) {
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const double m = molar_mass(s) / NAV;
-    // ln[(2 pi m k T / h^2)^(3/2) k T / p0]
     const double ltr = 1.5 * log(2.0 * PI * m * KB / (HPL * HPL)) + 2.5 * lnT + log(KB / P0);
     double gs = hf0_molar(s) / (RU * T) - ltr - log(g_elec(s));
     if (is_diatomic(s)) {
       gs -= lnT - log(sym_number(s) * theta_rot(s));
-      gs += log(-expm1(-theta_vib(s) / T));
+      gs += log(em1[s] / (em1[s] + 1.0));
     }
     g[s] = gs;
   }
@@ -327,44 +333,64 @@ HRX_HD double tb_eff(int r, int s) {
   return z[r][s];
 }
 
+// exp in the precision of the rate arithmetic: FP64 for R = double, and for R = float
+// FP64 at and above T_hi (where the rates matter), FP32 below with the argument
+// clamped to the float range.  The argument itself is always formed in FP64.
+template <class R>
+HRX_HD R rate_exp(double x, bool hi) {
+  if (sizeof(R) == sizeof(double) || hi) return R(exp(x));
+  const float xf = (float)(x < -87.0 ? -87.0 : (x > 88.0 ? 88.0 : x));
+  return R(expf(xf));
+}
+
 // Net mass production rates wdot_s [kg/(m^3 s)] from partial densities [kg/m^3] and T.
 // Rates of progress R_r = (k_f prod c^nu' - k_b prod c^nu'') * (sum Z c) (Eq. 14),
 // k_f = C T^n exp(-theta/T) (the printed exponent read with a minus sign), k_b = k_f/K_c,
 // K_c = (p0/(R_u T))^dnu exp(-sum dnu g/(R_u T)); wdot_s = M_s sum_r (nu'' - nu') R_r (Eq. 15).
+// Both k_f and k_b are formed as one exponential of a log-sum (C T^n exp(-theta/T)
+// = C exp(n ln T - theta/T)); em1 as for gibbs_over_RT.
 template <class R>
-HRX_HD void production_rates(const double* rho_s, double T, R* wdot) {
+HRX_HD void production_rates(const double* rho_s, double T, const double* em1, R* wdot,
+                             double T_hi = 0.0) {
+  const double lnT = log(T);
+  const double iT = 1.0 / T;
   double g[NS];
-  gibbs_over_RT(T, g);
-  double c[NS];
+  gibbs_over_RT(T, lnT, em1, g);
+  R c[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) c[s] = rho_s[s] / molar_mass(s);
-  const double c0 = P0 / (RU * T);
-  double Rr[5];
-  // delta g of each reaction and its sum of stoichiometric changes
+  for (int s = 0; s < NS; ++s) c[s] = R(rho_s[s] / molar_mass(s));
+  const double ln_c0 = log(P0 / RU) - lnT;     // ln(p0/(R_u T))
   const double dG[5] = {2.0 * g[3] - g[0], 2.0 * g[4] - g[1], g[3] + g[4] - g[2],
                         g[2] + g[3] - g[0] - g[4], g[1] + g[3] - g[2] - g[4]};
   const double dnu[5] = {1.0, 1.0, 1.0, 0.0, 0.0};
-  double fwdp[5] = {c[0], c[1], c[2], c[0] * c[4], c[2] * c[4]};
-  double bwdp[5] = {c[3] * c[3], c[4] * c[4], c[3] * c[4], c[2] * c[3], c[1] * c[3]};
+  const R fwdp[5] = {c[0], c[1], c[2], c[0] * c[4], c[2] * c[4]};
+  const R bwdp[5] = {c[3] * c[3], c[4] * c[4], c[3] * c[4], c[2] * c[3], c[1] * c[3]};
+  const bool hi = T >= T_hi;
+  R Rr[5];
 #pragma unroll
   for (int r = 0; r < 5; ++r) {
     const Reaction re = reaction(r);
-    const double kf = re.C * 1e-6 * pow(T, re.n) * exp(-re.theta / T);
-    const double Kc = pow(c0, dnu[r]) * exp(-dG[r]);
-    const double kb = kf / Kc;
-    double tb = 1.0;
+    const double lkf = log(re.C * 1e-6) + re.n * lnT - re.theta * iT;
+    const R kf = rate_exp<R>(lkf, hi);
+    const R kb = rate_exp<R>(lkf + dG[r] - dnu[r] * ln_c0, hi);
+    R tb = R(1);
     if (r < 3) {
-      tb = 0.0;
+      tb = R(0);
 #pragma unroll
-      for (int s = 0; s < NS; ++s) tb += tb_eff(r, s) * c[s];
+      for (int s = 0; s < NS; ++s) tb += R(tb_eff(r, s)) * c[s];
     }
     Rr[r] = (kf * fwdp[r] - kb * bwdp[r]) * tb;
   }
-  wdot[0] = R(molar_mass(0) * (-Rr[0] - Rr[3]));
-  wdot[1] = R(molar_mass(1) * (-Rr[1] + Rr[4]));
-  wdot[2] = R(molar_mass(2) * (-Rr[2] + Rr[3] - Rr[4]));
-  wdot[3] = R(molar_mass(3) * (2.0 * Rr[0] + Rr[2] + Rr[3] + Rr[4]));
-  wdot[4] = R(molar_mass(4) * (2.0 * Rr[1] + Rr[2] - Rr[3] - Rr[4]));
+  wdot[0] = R(molar_mass(0)) * (-Rr[0] - Rr[3]);
+  wdot[1] = R(molar_mass(1)) * (-Rr[1] + Rr[4]);
+  wdot[2] = R(molar_mass(2)) * (-Rr[2] + Rr[3] - Rr[4]);
+  wdot[3] = R(molar_mass(3)) * (R(2) * Rr[0] + Rr[2] + Rr[3] + Rr[4]);
+  wdot[4] = R(molar_mass(4)) * (R(2) * Rr[1] + Rr[2] - Rr[3] - Rr[4]);
+}
+
+HRX_HD void vib_em1(double T, double* em1) {
+#pragma unroll
+  for (int s = 0; s < 3; ++s) em1[s] = expm1(theta_vib(s) / T);
 }
 
 }  // namespace hrx

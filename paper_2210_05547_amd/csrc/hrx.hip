@@ -46,6 +46,7 @@ struct Dev {
   // W plane offsets
   int nsrc, w_p, w_mu, w_kap, w_D, w_wdot, w_c;
   int nad;                        // artificial-diffusivity planes (3 + ns)
+  int warm;                       // W holds a previous temperature field (Newton warm start)
 };
 
 // ------------------------------------------------------------------ stencils
@@ -189,8 +190,9 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   const double e = E - 0.5 * ke;
   const double c2 = d.c_inf * d.c_inf;
   int status, iters;
+  const double Tguess = d.warm ? W[ND * N + idx] * d.T_ref : 0.0;
   const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
-                                            &iters, nullptr);
+                                            &iters, Tguess);
   if (status) count(d, status);
   const double T = Tk / d.T_ref;
   const double Rmix = mixture_R(Y);
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   double rsd[NS], wd[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) rsd[s] = rs[s] * d.rho_inf;
-  production_rates<double>(rsd, Tk, wd);
+  production_rates<double>(rsd, Tk, st.em1, wd);
   const double wscale = d.L_ref / (d.rho_inf * d.c_inf);
 #pragma unroll
   for (int a = 0; a < ND; ++a) W[a * N + idx] = u[a];
@@ -622,7 +624,7 @@ __global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
       const double e = Q[(NS + ND) * N + im] / rho - 0.5 * ke;
       int status, iters;
       const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
-                                                &iters, nullptr);
+                                                &iters);
       Tw += c_wall[m - 1] * (Tk / d.T_ref);
     }
   }
@@ -654,7 +656,7 @@ __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int ma
 #pragma unroll
   for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + i];
   int status, iters;
-  const double T = temperature_from_energy(e[i], Y, rtol, max_iter, &status, &iters, nullptr);
+  const double T = temperature_from_energy(e[i], Y, rtol, max_iter, &status, &iters);
   if (status == 1) atomicAdd(&counters[0], 1ull);
   if (status == 2) atomicAdd(&counters[1], 1ull);
   Tout[i] = T;
@@ -697,7 +699,9 @@ __global__ __launch_bounds__(128) void k_chem_source(long n, const double* __res
   double rs[NS], w[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) rs[s] = rho_s[s * n + i];
-  production_rates<double>(rs, T[i], w);
+  double em1[3];
+  vib_em1(T[i], em1);
+  production_rates<double>(rs, T[i], em1, w);
 #pragma unroll
   for (int s = 0; s < NS; ++s) wdot[s * n + i] = w[s];
 }
@@ -1022,6 +1026,8 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     return fail(HRX_ENOMEM);
   if ((rc = check(hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long))))) return fail(rc);
   d.counters = ctx->counters;
+  // zeroed temperature plane: the first energy inversion starts cold
+  if ((rc = check(hipMemset(ctx->W, 0, sizeof(double) * N * ctx->nW)))) return fail(rc);
   *out = ctx;
   return HRX_OK;
 }
@@ -1070,6 +1076,7 @@ int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, 
   const Dev& d = ctx->dev;
   int rc = launch_rhs_chain<GAS, ND, ORDER>(ctx, mode == MODE_RHS ? Q : Qio, st);
   if (rc) return rc;
+  ctx->dev.warm = 1;
   const unsigned nb = blocks_for(d.N, 128);
   if (mode == MODE_RHS) {
     timed(ctx, K_DIV, st, [&] {
