@@ -52,48 +52,43 @@ struct Dev {
 // ------------------------------------------------------------------ stencils
 // First derivative in index space along a line of n points with stride s, at
 // position i of the line (flat index idx).  Interior: explicit central 6th (or 4th)
-// order; ends: one-sided 4th-order closures and their mirror images.
-template <int ORDER>
-__device__ __forceinline__ double dline(const double* __restrict__ f, long idx, long s, int i,
-                                        int n) {
+// order; ends: one-sided 4th-order closures and their mirror images.  RT is the
+// type of the stored plane and of the arithmetic (double, or float in the mixed form).
+template <int ORDER, class TA, class TD>
+__device__ __forceinline__ TA dline(const TD* __restrict__ f, long idx, long s, int i, int n) {
+  // differences are formed in the storage type TD, weighted sums in the arithmetic type TA
   if (ORDER == 6) {
     if (i >= 3 && i <= n - 4) {
-      double acc = 0.75 * (f[idx + s] - f[idx - s]);
-      acc += -0.15 * (f[idx + 2 * s] - f[idx - 2 * s]);
-      acc += (1.0 / 60.0) * (f[idx + 3 * s] - f[idx - 3 * s]);
+      TA acc = TA(0.75) * TA(f[idx + s] - f[idx - s]);
+      acc += TA(-0.15) * TA(f[idx + 2 * s] - f[idx - 2 * s]);
+      acc += TA(1.0 / 60.0) * TA(f[idx + 3 * s] - f[idx - 3 * s]);
       return acc;
     }
   } else {
     if (i >= 2 && i <= n - 3) {
-      double acc = (2.0 / 3.0) * (f[idx + s] - f[idx - s]);
-      acc += (-1.0 / 12.0) * (f[idx + 2 * s] - f[idx - 2 * s]);
+      TA acc = TA(2.0 / 3.0) * TA(f[idx + s] - f[idx - s]);
+      acc += TA(-1.0 / 12.0) * TA(f[idx + 2 * s] - f[idx - 2 * s]);
       return acc;
     }
   }
-  constexpr double b00 = -25.0 / 12.0, b01 = 4.0, b02 = -3.0, b03 = 4.0 / 3.0, b04 = -0.25;
-  constexpr double b10 = -0.25, b11 = -5.0 / 6.0, b12 = 1.5, b13 = -0.5, b14 = 1.0 / 12.0;
-  if (i == 0)
-    return b00 * f[idx] + b01 * f[idx + s] + b02 * f[idx + 2 * s] + b03 * f[idx + 3 * s] +
-           b04 * f[idx + 4 * s];
-  if (i == 1)
-    return b10 * f[idx - s] + b11 * f[idx] + b12 * f[idx + s] + b13 * f[idx + 2 * s] +
-           b14 * f[idx + 3 * s];
-  if (i == n - 1)
-    return -(b00 * f[idx] + b01 * f[idx - s] + b02 * f[idx - 2 * s] + b03 * f[idx - 3 * s] +
-             b04 * f[idx - 4 * s]);
-  if (i == n - 2)
-    return -(b10 * f[idx + s] + b11 * f[idx] + b12 * f[idx - s] + b13 * f[idx - 2 * s] +
-             b14 * f[idx - 3 * s]);
+  // one-sided closures: the weights sum to zero, so subtract the centre value first
+  const TD c = f[idx];
+  auto df = [&](long o) { return TA(f[idx + o] - c); };
+  const TA b01 = TA(4.0), b02 = TA(-3.0), b03 = TA(4.0 / 3.0), b04 = TA(-0.25);
+  const TA b10 = TA(-0.25), b12 = TA(1.5), b13 = TA(-0.5), b14 = TA(1.0 / 12.0);
+  if (i == 0) return b01 * df(s) + b02 * df(2 * s) + b03 * df(3 * s) + b04 * df(4 * s);
+  if (i == 1) return b10 * df(-s) + b12 * df(s) + b13 * df(2 * s) + b14 * df(3 * s);
+  if (i == n - 1) return -(b01 * df(-s) + b02 * df(-2 * s) + b03 * df(-3 * s) + b04 * df(-4 * s));
+  if (i == n - 2) return -(b10 * df(s) + b12 * df(-s) + b13 * df(-2 * s) + b14 * df(-3 * s));
   // 6th order only: points 2 and n-3 use the central 4th-order stencil
-  double acc = (2.0 / 3.0) * (f[idx + s] - f[idx - s]);
-  acc += (-1.0 / 12.0) * (f[idx + 2 * s] - f[idx - 2 * s]);
+  TA acc = TA(2.0 / 3.0) * TA(f[idx + s] - f[idx - s]);
+  acc += TA(-1.0 / 12.0) * TA(f[idx + 2 * s] - f[idx - 2 * s]);
   return acc;
 }
 
 // Periodic central first derivative (z direction).
-template <int ORDER>
-__device__ __forceinline__ double dper(const double* __restrict__ f, long idx, long s, int i,
-                                       int n) {
+template <int ORDER, class TA, class TD>
+__device__ __forceinline__ TA dper(const TD* __restrict__ f, long idx, long s, int i, int n) {
   const long base = idx - (long)i * s;
   auto at = [&](int m) {
     int q = i + m;
@@ -101,13 +96,13 @@ __device__ __forceinline__ double dper(const double* __restrict__ f, long idx, l
     return f[base + (long)q * s];
   };
   if (ORDER == 6) {
-    double acc = 0.75 * (at(1) - at(-1));
-    acc += -0.15 * (at(2) - at(-2));
-    acc += (1.0 / 60.0) * (at(3) - at(-3));
+    TA acc = TA(0.75) * TA(at(1) - at(-1));
+    acc += TA(-0.15) * TA(at(2) - at(-2));
+    acc += TA(1.0 / 60.0) * TA(at(3) - at(-3));
     return acc;
   }
-  double acc = (2.0 / 3.0) * (at(1) - at(-1));
-  acc += (-1.0 / 12.0) * (at(2) - at(-2));
+  TA acc = TA(2.0 / 3.0) * TA(at(1) - at(-1));
+  acc += TA(-1.0 / 12.0) * TA(at(2) - at(-2));
   return acc;
 }
 
@@ -127,12 +122,11 @@ __device__ __forceinline__ Pt point_of(const Dev& d, long idx) {
 }
 
 // physical derivative of plane f along direction dir at point p
-template <int ORDER>
-__device__ __forceinline__ double dphys(const Dev& d, const double* __restrict__ f, const Pt& p,
-                                        int dir) {
-  if (dir == 0) return dline<ORDER>(f, p.idx, 1, p.i, d.nx) * d.mx[p.i];
-  if (dir == 1) return dline<ORDER>(f, p.idx, d.nx, p.j, d.ny) * d.my[p.j];
-  return dper<ORDER>(f, p.idx, (long)d.nx * d.ny, p.k, d.nz) * d.mz[p.k];
+template <int ORDER, class TA, class TD>
+__device__ __forceinline__ TA dphys(const Dev& d, const TD* __restrict__ f, const Pt& p, int dir) {
+  if (dir == 0) return dline<ORDER, TA, TD>(f, p.idx, 1, p.i, d.nx) * TA(d.mx[p.i]);
+  if (dir == 1) return dline<ORDER, TA, TD>(f, p.idx, d.nx, p.j, d.ny) * TA(d.my[p.j]);
+  return dper<ORDER, TA, TD>(f, p.idx, (long)d.nx * d.ny, p.k, d.nz) * TA(d.mz[p.k]);
 }
 
 __device__ __forceinline__ void count(const Dev& d, int status) {
@@ -140,10 +134,15 @@ __device__ __forceinline__ void count(const Dev& d, int status) {
   if (status == 2) atomicAdd(&d.counters[1], 1ull);
 }
 
+// Temperature above which the mixed form keeps the Arrhenius exponentials in FP64.
+constexpr double T_HI_MIXED = 2000.0;
+
 // ------------------------------------------------------------------ k_prim
-template <int GAS, int ND>
+// Wd planes (double): [u, v, (w), T, X_1..X_5 (air5), p]   -- differentiated or convective
+// Wp planes (RT):     [mu, kappa, D_1..D_5, wdot_1..wdot_5, (c)] (air5), [mu, (c)] (CPG)
+template <int GAS, int ND, class RT>
 __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ Q,
-                                              double* __restrict__ W) {
+                                              double* __restrict__ Wd, RT* __restrict__ Wp) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d.N) return;
   const long N = d.N;
@@ -161,13 +160,13 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
     const double g = d.gamma;
     const double T = g * e;
     const double p = rho * (g - 1.0) * T / g;
-    const double mu = sutherland<double>(T * d.T_ref) / d.mu_inf;
+    const RT mu = sutherland<RT>(RT(T * d.T_ref)) / RT(d.mu_inf);
 #pragma unroll
-    for (int a = 0; a < ND; ++a) W[a * N + idx] = u[a];
-    W[ND * N + idx] = T;
-    W[d.w_p * N + idx] = p;
-    W[d.w_mu * N + idx] = mu;
-    if (d.ad_on) W[d.w_c * N + idx] = sqrt(g * p / rho);
+    for (int a = 0; a < ND; ++a) Wd[a * N + idx] = u[a];
+    Wd[ND * N + idx] = T;
+    Wd[d.w_p * N + idx] = p;
+    Wp[d.w_mu * N + idx] = mu;
+    if (d.ad_on) Wp[d.w_c * N + idx] = RT(sqrt(g * p / rho));
     return;
   }
   double rs[NS], Y[NS];
@@ -190,7 +189,7 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   const double e = E - 0.5 * ke;
   const double c2 = d.c_inf * d.c_inf;
   int status, iters;
-  const double Tguess = d.warm ? W[ND * N + idx] * d.T_ref : 0.0;
+  const double Tguess = d.warm ? Wd[ND * N + idx] * d.T_ref : 0.0;
   const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
                                             &iters, Tguess);
   if (status) count(d, status);
@@ -209,60 +208,60 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   for (int s = 0; s < NS; ++s) X[s] = X[s] / n;
   SpeciesThermo st;
   species_e_cv(Tk, st);
-  Transport<double> tr;
-  mixture_transport<double>(Tk, p_d, X, st.cv, tr);
-  double rsd[NS], wd[NS];
+  Transport<RT> tr;
+  mixture_transport<RT>(Tk, p_d, X, st.cv, tr);
+  double rsd[NS];
+  RT wd[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) rsd[s] = rs[s] * d.rho_inf;
-  production_rates<double>(rsd, Tk, st.em1, wd);
+  production_rates<RT>(rsd, Tk, st.em1, wd, T_HI_MIXED);
+#pragma unroll
+  for (int a = 0; a < ND; ++a) Wd[a * N + idx] = u[a];
+  Wd[ND * N + idx] = T;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Wd[(ND + 1 + s) * N + idx] = X[s];
+  Wd[d.w_p * N + idx] = p;
+  Wp[d.w_mu * N + idx] = tr.mu / RT(d.mu_inf);
+  Wp[d.w_kap * N + idx] = tr.kappa / RT(d.kappa_inf);
+  const RT Dscale = RT(d.c_inf * d.L_ref);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * N + idx] = tr.D[s] / Dscale;
   const double wscale = d.L_ref / (d.rho_inf * d.c_inf);
 #pragma unroll
-  for (int a = 0; a < ND; ++a) W[a * N + idx] = u[a];
-  W[ND * N + idx] = T;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) W[(ND + 1 + s) * N + idx] = X[s];
-  W[d.w_p * N + idx] = p;
-  W[d.w_mu * N + idx] = tr.mu / d.mu_inf;
-  W[d.w_kap * N + idx] = tr.kappa / d.kappa_inf;
-  const double Dscale = d.c_inf * d.L_ref;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) W[(d.w_D + s) * N + idx] = tr.D[s] / Dscale;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) W[(d.w_wdot + s) * N + idx] = wd[s] * d.L_ref / (d.rho_inf * d.c_inf);
-  (void)wscale;
+  for (int s = 0; s < NS; ++s) Wp[(d.w_wdot + s) * N + idx] = RT(double(wd[s]) * wscale);
   if (d.ad_on) {
     double cv = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) cv += Y[s] * st.cv[s];
     const double gf = (cv + Rmix) / cv;
-    W[d.w_c * N + idx] = sqrt(gf * Rmix * Tk) / d.c_inf;
+    Wp[d.w_c * N + idx] = RT(sqrt(gf * Rmix * Tk) / d.c_inf);
   }
 }
 
 // ------------------------------------------------------------------ artificial diffusivity
-// A planes: [|S|, theta, e, Y_1..Y_ns]
-template <int GAS, int ND, int ORDER>
+// A planes (RT): [|S|, theta, e, Y_1..Y_ns]
+template <int GAS, int ND, int ORDER, class RT>
 __global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict__ Q,
-                                                const double* __restrict__ W,
-                                                double* __restrict__ A) {
+                                                const double* __restrict__ Wd,
+                                                RT* __restrict__ A) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d.N) return;
   const long N = d.N;
   const Pt p = point_of(d, idx);
-  double G[3][3];
+  RT G[3][3];
 #pragma unroll
   for (int a = 0; a < ND; ++a)
 #pragma unroll
-    for (int b = 0; b < ND; ++b) G[a][b] = dphys<ORDER>(d, W + a * N, p, b);
-  double s2 = 0.0;
+    for (int b = 0; b < ND; ++b) G[a][b] = dphys<ORDER, RT>(d, Wd + a * N, p, b);
+  RT s2 = RT(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a)
 #pragma unroll
     for (int b = 0; b < ND; ++b) {
-      const double sab = 0.5 * (G[a][b] + G[b][a]);
+      const RT sab = RT(0.5) * (G[a][b] + G[b][a]);
       s2 += sab * sab;
     }
-  double theta = 0.0;
+  RT theta = RT(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a) theta += G[a][a];
   const int ns = (GAS == CPG) ? 1 : NS;
@@ -282,67 +281,67 @@ __global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict_
   const double e = Q[(ns + ND) * N + idx] / rho - 0.5 * ke;
   A[0 * N + idx] = sqrt(s2);
   A[1 * N + idx] = theta;
-  A[2 * N + idx] = e;
+  A[2 * N + idx] = RT(e);
   if (GAS == AIR5) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) A[(3 + s) * N + idx] = Q[s * N + idx] / rho;
+    for (int s = 0; s < NS; ++s) A[(3 + s) * N + idx] = RT(Q[s * N + idx] / rho);
   }
 }
 
 // fourth difference along a line, copying the nearest interior value at the two
 // first and last points of a non-periodic line
-__device__ __forceinline__ double d4line(const double* __restrict__ f, long idx, long s, int i,
-                                         int n) {
+template <class RT>
+__device__ __forceinline__ RT d4line(const RT* __restrict__ f, long idx, long s, int i, int n) {
   int ic = i < 2 ? 2 : (i > n - 3 ? n - 3 : i);
   const long c = idx + (long)(ic - i) * s;
-  return f[c - 2 * s] - 4.0 * f[c - s] + 6.0 * f[c] - 4.0 * f[c + s] + f[c + 2 * s];
+  return f[c - 2 * s] - RT(4) * f[c - s] + RT(6) * f[c] - RT(4) * f[c + s] + f[c + 2 * s];
 }
-__device__ __forceinline__ double d4per(const double* __restrict__ f, long idx, long s, int i,
-                                        int n) {
+template <class RT>
+__device__ __forceinline__ RT d4per(const RT* __restrict__ f, long idx, long s, int i, int n) {
   const long base = idx - (long)i * s;
   auto at = [&](int m) {
     int q = i + m;
     q = q < 0 ? q + n : (q >= n ? q - n : q);
     return f[base + (long)q * s];
   };
-  return at(-2) - 4.0 * at(-1) + 6.0 * f[idx] - 4.0 * at(1) + at(2);
+  return at(-2) - RT(4) * at(-1) + RT(6) * f[idx] - RT(4) * at(1) + at(2);
 }
 
 // B planes: [a_mu, a_beta, a_kappa, a_D,1..ns] before filtering
-template <int GAS, int ND>
-__global__ __launch_bounds__(128) void k_ad_d4(Dev d, const double* __restrict__ A,
-                                               double* __restrict__ B) {
+template <int GAS, int ND, class RT>
+__global__ __launch_bounds__(128) void k_ad_d4(Dev d, const RT* __restrict__ A,
+                                               RT* __restrict__ B) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d.N) return;
   const long N = d.N;
   const Pt p = point_of(d, idx);
-  const double dl[3] = {d.dlx[p.i], d.dly[p.j], ND == 3 ? d.dlz[p.k] : 1.0};
-  double dbar;
+  const RT dl[3] = {RT(d.dlx[p.i]), RT(d.dly[p.j]), ND == 3 ? RT(d.dlz[p.k]) : RT(1)};
+  RT dbar;
   if (ND == 2)
-    dbar = pow(dl[0] * dl[1], 0.5);
+    dbar = RT(pow(d.dlx[p.i] * d.dly[p.j], 0.5));
   else
-    dbar = pow(dl[0] * dl[1] * dl[2], 1.0 / 3.0);
+    dbar = RT(pow(d.dlx[p.i] * d.dly[p.j] * d.dlz[p.k], 1.0 / 3.0));
   const int nplanes = 3 + ((GAS == AIR5) ? NS : 0);
   for (int v = 0; v < nplanes; ++v) {
-    const double* f = A + (long)v * N;
+    const RT* f = A + (long)v * N;
     const bool sq = v < 2;
-    double acc = 0.0;
+    RT acc = RT(0);
 #pragma unroll
     for (int l = 0; l < ND; ++l) {
-      double q;
+      RT q;
       if (l == 0)
-        q = d4line(f, idx, 1, p.i, d.nx);
+        q = d4line<RT>(f, idx, 1, p.i, d.nx);
       else if (l == 1)
-        q = d4line(f, idx, d.nx, p.j, d.ny);
+        q = d4line<RT>(f, idx, d.nx, p.j, d.ny);
       else
-        q = d4per(f, idx, (long)d.nx * d.ny, p.k, d.nz);
+        q = d4per<RT>(f, idx, (long)d.nx * d.ny, p.k, d.nz);
       acc += q * (sq ? dl[l] * dl[l] : dl[l]);
     }
-    double out = fabs(acc);
+    RT out = fabs(acc);
     if (v >= 3) {
-      const double Ys = f[idx];
-      const double over = 0.5 * (fabs(Ys) - 1.0 + fabs(1.0 - Ys));
-      out = d.CD * out + d.CY * over * dbar;
+      const RT Ys = f[idx];
+      const RT over = RT(0.5) * (fabs(Ys) - RT(1) + fabs(RT(1) - Ys));
+      out = RT(d.CD) * out + RT(d.CY) * over * dbar;
     }
     B[(long)v * N + idx] = out;
   }
@@ -353,9 +352,9 @@ __global__ __launch_bounds__(128) void k_ad_d4(Dev d, const double* __restrict__
 __constant__ double c_gauss9[5] = {3565.0 / 10368.0, 3091.0 / 12960.0, 1997.0 / 25920.0,
                                    149.0 / 12960.0, 107.0 / 103680.0};
 
-template <int DIR>
-__global__ __launch_bounds__(128) void k_ad_filter(Dev d, const double* __restrict__ in,
-                                                   double* __restrict__ out) {
+template <int DIR, class RT>
+__global__ __launch_bounds__(128) void k_ad_filter(Dev d, const RT* __restrict__ in,
+                                                   RT* __restrict__ out) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d.N) return;
   const long N = d.N;
@@ -364,8 +363,8 @@ __global__ __launch_bounds__(128) void k_ad_filter(Dev d, const double* __restri
   const int n = DIR == 0 ? d.nx : (DIR == 1 ? d.ny : d.nz);
   const long s = DIR == 0 ? 1 : (DIR == 1 ? (long)d.nx : (long)d.nx * d.ny);
   for (int v = 0; v < d.nad; ++v) {
-    const double* f = in + (long)v * N;
-    double r;
+    const RT* f = in + (long)v * N;
+    RT r;
     if (DIR == 2) {
       const long base = idx - (long)i * s;
       auto at = [&](int m) {
@@ -373,15 +372,15 @@ __global__ __launch_bounds__(128) void k_ad_filter(Dev d, const double* __restri
         q = q < 0 ? q + n : (q >= n ? q - n : q);
         return f[base + (long)q * s];
       };
-      r = c_gauss9[0] * f[idx];
+      r = RT(c_gauss9[0]) * f[idx];
 #pragma unroll
-      for (int k = 1; k <= 4; ++k) r += c_gauss9[k] * (at(-k) + at(k));
+      for (int k = 1; k <= 4; ++k) r += RT(c_gauss9[k]) * (at(-k) + at(k));
     } else {
-      double acc = 0.0, wsum = 0.0;
+      RT acc = RT(0), wsum = RT(0);
 #pragma unroll
       for (int k = -4; k <= 4; ++k) {
         const int q = i + k;
-        const double w = (q >= 0 && q < n) ? c_gauss9[k < 0 ? -k : k] : 0.0;
+        const RT w = (q >= 0 && q < n) ? RT(c_gauss9[k < 0 ? -k : k]) : RT(0);
         const int qc = q < 0 ? 0 : (q >= n ? n - 1 : q);
         acc += w * f[idx + (long)(qc - i) * s];
         wsum += w;
@@ -393,31 +392,33 @@ __global__ __launch_bounds__(128) void k_ad_filter(Dev d, const double* __restri
 }
 
 // ------------------------------------------------------------------ k_flux
-// F planes: F[j][k] for direction j and conserved component k.
-template <int GAS, int ND, int ORDER, bool AD>
+// F planes (double): F[j][k] for direction j and conserved component k.  Convective
+// fluxes are formed in FP64; stresses, heat and diffusion fluxes in RT.
+template <int GAS, int ND, int ORDER, bool AD, class RT>
 __global__ __launch_bounds__(128) void k_flux(Dev d, const double* __restrict__ Q,
-                                              const double* __restrict__ W,
-                                              const double* __restrict__ Gad,
-                                              double* __restrict__ F) {
+                                              const double* __restrict__ Wd,
+                                              const RT* __restrict__ Wp,
+                                              const RT* __restrict__ Gad, double* __restrict__ F) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d.N) return;
   const long N = d.N;
   const Pt p = point_of(d, idx);
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
-  double G[3][3], dT[3];
+  RT G[3][3], dT[3];
 #pragma unroll
   for (int a = 0; a < ND; ++a)
 #pragma unroll
-    for (int b = 0; b < ND; ++b) G[a][b] = dphys<ORDER>(d, W + a * N, p, b);
+    for (int b = 0; b < ND; ++b) G[a][b] = dphys<ORDER, RT>(d, Wd + a * N, p, b);
 #pragma unroll
-  for (int b = 0; b < ND; ++b) dT[b] = dphys<ORDER>(d, W + ND * N, p, b);
+  for (int b = 0; b < ND; ++b) dT[b] = dphys<ORDER, RT>(d, Wd + ND * N, p, b);
   double u[3];
 #pragma unroll
-  for (int a = 0; a < ND; ++a) u[a] = W[a * N + idx];
-  const double pr = W[d.w_p * N + idx];
-  const double mu = W[d.w_mu * N + idx];
-  double rho, rs[NS], Y[NS];
+  for (int a = 0; a < ND; ++a) u[a] = Wd[a * N + idx];
+  const double pr = Wd[d.w_p * N + idx];
+  const RT mu = Wp[d.w_mu * N + idx];
+  double rho, rs[NS];
+  RT Y[NS];
   if (GAS == CPG) {
     rho = Q[idx];
   } else {
@@ -428,105 +429,110 @@ __global__ __launch_bounds__(128) void k_flux(Dev d, const double* __restrict__ 
       rho += rs[s];
     }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) Y[s] = rs[s] / rho;
+    for (int s = 0; s < NS; ++s) Y[s] = RT(rs[s] / rho);
   }
-  double theta = 0.0;
+  RT theta = RT(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a) theta += G[a][a];
-  const double kap = (GAS == CPG) ? mu : W[d.w_kap * N + idx];
-  double mu_eff = mu / d.Re;
-  double kap_eff = kap / (d.Re * d.Pr);
-  double beta = 0.0, cs = 0.0;
+  const RT kap = (GAS == CPG) ? mu : Wp[d.w_kap * N + idx];
+  RT mu_eff = mu / RT(d.Re);
+  RT kap_eff = kap / RT(d.Re * d.Pr);
+  RT beta = RT(0), cs = RT(0);
+  const RT rho_r = RT(rho);
   if (AD) {
-    const double T = W[ND * N + idx];
-    cs = W[d.w_c * N + idx];
-    double w2;
+    const RT T = RT(Wd[ND * N + idx]);
+    cs = Wp[d.w_c * N + idx];
+    RT w2;
     if (ND == 2) {
       w2 = (G[1][0] - G[0][1]) * (G[1][0] - G[0][1]);
     } else {
       w2 = (G[2][1] - G[1][2]) * (G[2][1] - G[1][2]) + (G[0][2] - G[2][0]) * (G[0][2] - G[2][0]) +
            (G[1][0] - G[0][1]) * (G[1][0] - G[0][1]);
     }
-    const double fsw = theta < 0.0 ? theta * theta / (theta * theta + w2 + 1e-32) : 0.0;
-    mu_eff = mu_eff + d.Cmu * rho * Gad[0 * N + idx];
-    beta = d.Cbeta * rho * fsw * Gad[1 * N + idx];
-    kap_eff = kap_eff + d.Ckap * rho * cs / T * Gad[2 * N + idx];
+    const RT fsw = theta < RT(0) ? theta * theta / (theta * theta + w2 + RT(1e-32)) : RT(0);
+    mu_eff = mu_eff + RT(d.Cmu) * rho_r * Gad[0 * N + idx];
+    beta = RT(d.Cbeta) * rho_r * fsw * Gad[1 * N + idx];
+    kap_eff = kap_eff + RT(d.Ckap) * rho_r * cs / T * Gad[2 * N + idx];
   }
   const double rhoE = Q[(ns + ND) * N + idx];
   // species diffusion (Eq. 18 read with grad X_s)
-  double a_s[NS], h[NS];
-  double dX[NS][3];
+  RT a_s[NS], h[NS];
+  RT dX[NS][3];
   if (GAS == AIR5) {
-    double nsum = 0.0;
+    RT nsum = RT(0);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) nsum += Y[s] / molar_mass(s);
-    const double Mbar = 1.0 / nsum;
+    for (int s = 0; s < NS; ++s) nsum += Y[s] / RT(molar_mass(s));
+    const RT Mbar = RT(1) / nsum;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      double Ds = W[(d.w_D + s) * N + idx];
+      RT Ds = Wp[(d.w_D + s) * N + idx];
       if (AD) Ds = Ds + cs * Gad[(3 + s) * N + idx];
-      a_s[s] = rho * (molar_mass(s) / Mbar) * Ds;
+      a_s[s] = rho_r * (RT(molar_mass(s)) / Mbar) * Ds;
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int b = 0; b < ND; ++b) dX[s][b] = dphys<ORDER>(d, W + (ND + 1 + s) * N, p, b);
-    const double Tk = W[ND * N + idx] * d.T_ref;
-    species_h(Tk, h);
+      for (int b = 0; b < ND; ++b) dX[s][b] = dphys<ORDER, RT>(d, Wd + (ND + 1 + s) * N, p, b);
+    const double Tk = Wd[ND * N + idx] * d.T_ref;
+    double hd[NS];
+    species_h(Tk, hd);
     const double c2 = d.c_inf * d.c_inf;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) h[s] = h[s] / c2;
+    for (int s = 0; s < NS; ++s) h[s] = RT(hd[s] / c2);
   }
 #pragma unroll
   for (int j = 0; j < ND; ++j) {
     double* Fj = F + (long)j * nvar * N;
-    double J[NS];
+    RT J[NS];
     if (GAS == AIR5) {
-      double corr = 0.0;
+      RT corr = RT(0);
 #pragma unroll
       for (int s = 0; s < NS; ++s) corr += a_s[s] * dX[s][j];
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         J[s] = -a_s[s] * dX[s][j] + Y[s] * corr;
-        Fj[s * N + idx] = rs[s] * u[j] + J[s];
+        Fj[s * N + idx] = rs[s] * u[j] + double(J[s]);
       }
     } else {
       Fj[idx] = rho * u[j];
     }
-    double tau[3];
+    RT tau[3];
 #pragma unroll
     for (int a = 0; a < ND; ++a) {
-      double t = mu_eff * (G[a][j] + G[j][a]);
+      RT t = mu_eff * (G[a][j] + G[j][a]);
       if (a == j) {
-        t = t - mu_eff * (2.0 / 3.0) * theta;
+        t = t - mu_eff * RT(2.0 / 3.0) * theta;
         if (AD) t = t + beta * theta;
       }
       tau[a] = t;
       double conv = Q[(ns + a) * N + idx] * u[j];
       if (a == j) conv = conv + pr;
-      Fj[(ns + a) * N + idx] = conv - t;
+      Fj[(ns + a) * N + idx] = conv - double(t);
     }
-    double q = -kap_eff * dT[j];
+    RT q = -kap_eff * dT[j];
     if (GAS == AIR5) {
-      double hJ = 0.0;
+      RT hJ = RT(0);
 #pragma unroll
       for (int s = 0; s < NS; ++s) hJ += h[s] * J[s];
       q = q + hJ;
     }
-    double work = 0.0;
+    RT work = RT(0);
 #pragma unroll
-    for (int a = 0; a < ND; ++a) work += tau[a] * u[a];
-    Fj[(ns + ND) * N + idx] = (rhoE + pr) * u[j] - (work - q);
+    for (int a = 0; a < ND; ++a) work += tau[a] * RT(u[a]);
+    Fj[(ns + ND) * N + idx] = (rhoE + pr) * u[j] - double(work - q);
   }
 }
 
 // ------------------------------------------------------------------ k_div (+ RK)
-template <int GAS, int ND, int ORDER, int MODE>
+// R = -sum_j dF_j/dx_j (FP64 differences, RT weighted sums) + wdot (species)
+//     - sigma (Q - Q_ref) (FP64); boundary rows; then R out, or the low-storage update
+// of Q and dQ in FP64.
+template <int GAS, int ND, int ORDER, int MODE, class RT>
 __global__ __launch_bounds__(128) void k_div(Dev d, const double* __restrict__ F,
-                                             const double* __restrict__ W,
-                                             const double* Qin, const double* __restrict__ Qref,
-                                             double* Rout, double* Qio, double* dQio,
-                                             double A, double B, double dt) {
+                                             const RT* __restrict__ Wp, const double* Qin,
+                                             const double* __restrict__ Qref, double* Rout,
+                                             double* Qio, double* dQio, double A, double B,
+                                             double dt) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d.N) return;
   const long N = d.N;
@@ -538,11 +544,11 @@ __global__ __launch_bounds__(128) void k_div(Dev d, const double* __restrict__ F
   if (d.hold && p.j < 3) held = held || d.hold[((long)p.k * 3 + p.j) * d.nx + p.i];
 #pragma unroll
   for (int k = 0; k < nvar; ++k) {
-    double acc = 0.0;
+    RT acc = RT(0);
 #pragma unroll
-    for (int j = 0; j < ND; ++j) acc += dphys<ORDER>(d, F + ((long)j * nvar + k) * N, p, j);
-    double R = -acc;
-    if (GAS == AIR5 && k < NS) R = R + W[(d.w_wdot + k) * N + idx];
+    for (int j = 0; j < ND; ++j) acc += dphys<ORDER, RT>(d, F + ((long)j * nvar + k) * N, p, j);
+    double R = -double(acc);
+    if (GAS == AIR5 && k < NS) R = R + double(Wp[(d.w_wdot + k) * N + idx]);
     const double qv = (MODE == MODE_RK) ? Qio[k * N + idx] : Qin[k * N + idx];
     if (Qref != nullptr && sig != 0.0) R = R - sig * (qv - Qref[k * N + idx]);
     if (held || (p.j == 0 && k >= ns && k < ns + ND)) R = 0.0;
@@ -638,6 +644,7 @@ __global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
 }
 
 // ------------------------------------------------------------------ pointwise SI calls
+template <class RT>
 __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int max_iter,
                                                      const double* __restrict__ rho,
                                                      const double* __restrict__ e,
@@ -680,30 +687,32 @@ __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int ma
     for (int s = 0; s < NS; ++s) X[s] = X[s] / nsum;
     SpeciesThermo st;
     species_e_cv(T, st);
-    Transport<double> tr;
-    mixture_transport<double>(T, p, X, st.cv, tr);
-    if (muout) muout[i] = tr.mu;
-    if (kout) kout[i] = tr.kappa;
+    Transport<RT> tr;
+    mixture_transport<RT>(T, p, X, st.cv, tr);
+    if (muout) muout[i] = double(tr.mu);
+    if (kout) kout[i] = double(tr.kappa);
     if (Dout) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) Dout[s * n + i] = tr.D[s];
+      for (int s = 0; s < NS; ++s) Dout[s * n + i] = double(tr.D[s]);
     }
   }
 }
 
+template <class RT>
 __global__ __launch_bounds__(128) void k_chem_source(long n, const double* __restrict__ rho_s,
                                                      const double* __restrict__ T,
                                                      double* __restrict__ wdot) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double rs[NS], w[NS];
+  double rs[NS];
+  RT w[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) rs[s] = rho_s[s * n + i];
   double em1[3];
   vib_em1(T[i], em1);
-  production_rates<double>(rs, T[i], em1, w);
+  production_rates<RT>(rs, T[i], em1, w, T_HI_MIXED);
 #pragma unroll
-  for (int s = 0; s < NS; ++s) wdot[s * n + i] = w[s];
+  for (int s = 0; s < NS; ++s) wdot[s * n + i] = double(w[s]);
 }
 
 }  // namespace hrx
@@ -715,8 +724,11 @@ struct hrx_ctx {
   hrx_config cfg;
   Dev dev;
   hrx_reference ref;
-  int nW, nF;
-  double *W = nullptr, *F = nullptr, *R = nullptr, *AD = nullptr;
+  int nF;
+  double *Wd = nullptr, *F = nullptr, *R = nullptr;
+  void *Wp = nullptr, *AD = nullptr;   // RT planes (double, or float in the mixed form)
+  int nWd = 0, nWp = 0;
+  size_t rt_size = sizeof(double);
   double *metrics = nullptr;   // mx, my, mz, sx, sy, dlx, dly, dlz
   unsigned char *hold = nullptr;
   unsigned long long *counters = nullptr;
@@ -834,7 +846,8 @@ const char* hrx_strerror(int code) {
 void hrx_destroy(hrx_ctx* c) {
   if (!c) return;
   if (c->timing) hrx_timing_enable(c, 0);
-  (void)hipFree(c->W);
+  (void)hipFree(c->Wd);
+  (void)hipFree(c->Wp);
   (void)hipFree(c->F);
   (void)hipFree(c->R);
   (void)hipFree(c->AD);
@@ -852,7 +865,7 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   if (c.nx < 8 || c.ny < 8 || c.nz < 1 || (c.nz > 1 && c.nz < 8)) return HRX_EINVAL;
   if (c.fd_order != 4 && c.fd_order != 6) return HRX_EINVAL;
   if (c.rk_scheme != HRX_RK3_2N && c.rk_scheme != HRX_RK45_2N) return HRX_EINVAL;
-  if (c.precision != HRX_PREC_FP64) return HRX_EUNSUP;
+  if (c.precision != HRX_PREC_FP64 && c.precision != HRX_PREC_MIXED) return HRX_EINVAL;
   if (!c.x || !c.y || (c.nz > 1 && !c.z)) return HRX_EINVAL;
   if (c.sponge_in < 0 || c.sponge_out < 0 || c.sponge_top < 0 || c.sponge_in >= c.nx - 1 ||
       c.sponge_out >= c.nx - 1 || c.sponge_top >= c.ny - 1)
@@ -1005,8 +1018,9 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   }
   // ---------------------------------------------------------- scratch planes
   d.nsrc = nd + 1 + (c.gas == HRX_GAS_AIR5 ? NS : 0);
-  int w = d.nsrc;
-  d.w_p = w++;
+  d.w_p = d.nsrc;
+  ctx->nWd = d.nsrc + 1;
+  int w = 0;
   d.w_mu = w++;
   if (c.gas == HRX_GAS_AIR5) {
     d.w_kap = w++;
@@ -1014,20 +1028,22 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     d.w_wdot = w; w += NS;
   }
   if (d.ad_on) d.w_c = w++;
-  ctx->nW = w;
+  ctx->nWp = w;
   ctx->nF = nd * d.nvar;
   d.nad = 3 + (c.gas == HRX_GAS_AIR5 ? NS : 0);
-  if (hipMalloc(&ctx->W, sizeof(double) * N * ctx->nW) != hipSuccess) return fail(HRX_ENOMEM);
+  const size_t rts = c.precision == HRX_PREC_MIXED ? sizeof(float) : sizeof(double);
+  ctx->rt_size = rts;
+  if (hipMalloc(&ctx->Wd, sizeof(double) * N * ctx->nWd) != hipSuccess) return fail(HRX_ENOMEM);
+  if (hipMalloc(&ctx->Wp, rts * N * ctx->nWp) != hipSuccess) return fail(HRX_ENOMEM);
   if (hipMalloc(&ctx->F, sizeof(double) * N * ctx->nF) != hipSuccess) return fail(HRX_ENOMEM);
   if (hipMalloc(&ctx->R, sizeof(double) * N * d.nvar) != hipSuccess) return fail(HRX_ENOMEM);
-  if (d.ad_on && hipMalloc(&ctx->AD, sizeof(double) * N * d.nad * 2) != hipSuccess)
-    return fail(HRX_ENOMEM);
+  if (d.ad_on && hipMalloc(&ctx->AD, rts * N * d.nad * 2) != hipSuccess) return fail(HRX_ENOMEM);
   if (hipMalloc(&ctx->counters, 4 * sizeof(unsigned long long)) != hipSuccess)
     return fail(HRX_ENOMEM);
   if ((rc = check(hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long))))) return fail(rc);
   d.counters = ctx->counters;
   // zeroed temperature plane: the first energy inversion starts cold
-  if ((rc = check(hipMemset(ctx->W, 0, sizeof(double) * N * ctx->nW)))) return fail(rc);
+  if ((rc = check(hipMemset(ctx->Wd, 0, sizeof(double) * N * ctx->nWd)))) return fail(rc);
   *out = ctx;
   return HRX_OK;
 }
@@ -1042,51 +1058,60 @@ int hrx_get_reference(const hrx_ctx* ctx, hrx_reference* out) {
 
 namespace {
 
-template <int GAS, int ND, int ORDER>
+template <int GAS, int ND, int ORDER, class RT>
 int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
   const Dev& d = ctx->dev;
   const long N = d.N;
   const int bs = 128;
   const unsigned nb = blocks_for(N, bs);
-  timed(ctx, K_PRIM, st, [&] { k_prim<GAS, ND><<<nb, bs, 0, st>>>(d, Q, ctx->W); });
-  const double* Gad = nullptr;
+  double* Wd = ctx->Wd;
+  RT* Wp = (RT*)ctx->Wp;
+  double* F = ctx->F;
+  timed(ctx, K_PRIM, st, [&] { k_prim<GAS, ND, RT><<<nb, bs, 0, st>>>(d, Q, Wd, Wp); });
   if (d.ad_on) {
-    double* A = ctx->AD;
-    double* B = ctx->AD + (long)d.nad * N;
-    timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER><<<nb, bs, 0, st>>>(d, Q, ctx->W, A); });
-    timed(ctx, K_AD_D4, st, [&] { k_ad_d4<GAS, ND><<<nb, bs, 0, st>>>(d, A, B); });
-    timed(ctx, K_AD_FX, st, [&] { k_ad_filter<0><<<nb, bs, 0, st>>>(d, B, A); });
-    timed(ctx, K_AD_FY, st, [&] { k_ad_filter<1><<<nb, bs, 0, st>>>(d, A, B); });
+    RT* A = (RT*)ctx->AD;
+    RT* B = A + (long)d.nad * N;
+    const RT* Gad;
+    timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER, RT><<<nb, bs, 0, st>>>(d, Q, Wd, A); });
+    timed(ctx, K_AD_D4, st, [&] { k_ad_d4<GAS, ND, RT><<<nb, bs, 0, st>>>(d, A, B); });
+    timed(ctx, K_AD_FX, st, [&] { k_ad_filter<0, RT><<<nb, bs, 0, st>>>(d, B, A); });
+    timed(ctx, K_AD_FY, st, [&] { k_ad_filter<1, RT><<<nb, bs, 0, st>>>(d, A, B); });
     if (ND == 3) {
-      timed(ctx, K_AD_FZ, st, [&] { k_ad_filter<2><<<nb, bs, 0, st>>>(d, B, A); });
+      timed(ctx, K_AD_FZ, st, [&] { k_ad_filter<2, RT><<<nb, bs, 0, st>>>(d, B, A); });
       Gad = A;
     } else {
       Gad = B;
     }
-    timed(ctx, K_FLUX, st, [&] { k_flux<GAS, ND, ORDER, true><<<nb, bs, 0, st>>>(d, Q, ctx->W, Gad, ctx->F); });
+    timed(ctx, K_FLUX, st, [&] {
+      k_flux<GAS, ND, ORDER, true, RT><<<nb, bs, 0, st>>>(d, Q, Wd, Wp, Gad, F);
+    });
   } else {
-    timed(ctx, K_FLUX, st, [&] { k_flux<GAS, ND, ORDER, false><<<nb, bs, 0, st>>>(d, Q, ctx->W, nullptr, ctx->F); });
+    timed(ctx, K_FLUX, st, [&] {
+      k_flux<GAS, ND, ORDER, false, RT><<<nb, bs, 0, st>>>(d, Q, Wd, Wp, nullptr, F);
+    });
   }
   return check(hipGetLastError());
 }
 
-template <int GAS, int ND, int ORDER>
+template <int GAS, int ND, int ORDER, class RT>
 int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, double* Qio,
         double* dQ, double A, double B, double dt, hipStream_t st) {
   const Dev& d = ctx->dev;
-  int rc = launch_rhs_chain<GAS, ND, ORDER>(ctx, mode == MODE_RHS ? Q : Qio, st);
+  int rc = launch_rhs_chain<GAS, ND, ORDER, RT>(ctx, mode == MODE_RHS ? Q : Qio, st);
   if (rc) return rc;
   ctx->dev.warm = 1;
   const unsigned nb = blocks_for(d.N, 128);
+  const double* F = ctx->F;
+  const RT* Wp = (const RT*)ctx->Wp;
   if (mode == MODE_RHS) {
     timed(ctx, K_DIV, st, [&] {
-      k_div<GAS, ND, ORDER, MODE_RHS><<<nb, 128, 0, st>>>(d, ctx->F, ctx->W, Q, Qref, R, nullptr,
-                                                           nullptr, 0.0, 0.0, 0.0);
+      k_div<GAS, ND, ORDER, MODE_RHS, RT><<<nb, 128, 0, st>>>(d, F, Wp, Q, Qref, R, nullptr,
+                                                               nullptr, 0.0, 0.0, 0.0);
     });
   } else {
     timed(ctx, K_DIV, st, [&] {
-      k_div<GAS, ND, ORDER, MODE_RK><<<nb, 128, 0, st>>>(d, ctx->F, ctx->W, nullptr, Qref,
-                                                          nullptr, Qio, dQ, A, B, dt);
+      k_div<GAS, ND, ORDER, MODE_RK, RT><<<nb, 128, 0, st>>>(d, F, Wp, nullptr, Qref, nullptr,
+                                                              Qio, dQ, A, B, dt);
     });
     const long nw = (long)(d.nx - 1) * d.nz;
     timed(ctx, K_BC, st, [&] { k_bc<GAS, ND><<<blocks_for(nw, 128), 128, 0, st>>>(d, Qio); });
@@ -1099,7 +1124,10 @@ int dispatch(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double
   const Dev& d = ctx->dev;
   const bool air = ctx->cfg.gas == HRX_GAS_AIR5;
   const bool o6 = d.fd_order == 6;
-#define HRX_RUN(G, NDV, O) return run<G, NDV, O>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, st)
+  const bool mixed = ctx->cfg.precision == HRX_PREC_MIXED;
+#define HRX_RUN(G, NDV, O)                                                         \
+  return mixed ? run<G, NDV, O, float>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, st) \
+               : run<G, NDV, O, double>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, st)
   if (d.ndim == 2) {
     if (air) { if (o6) HRX_RUN(AIR5, 2, 6); else HRX_RUN(AIR5, 2, 4); }
     else { if (o6) HRX_RUN(CPG, 2, 6); else HRX_RUN(CPG, 2, 4); }
@@ -1153,10 +1181,16 @@ int hrx_thermo_eval(hrx_ctx* ctx, int64_t n, const double* rho, const double* e,
   if (n == 0) return HRX_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   ctx->last_stream = st;
+  const bool mixed = ctx->cfg.precision == HRX_PREC_MIXED;
   timed(ctx, K_THERMO, st, [&] {
-    k_thermo_eval<<<blocks_for(n, 128), 128, 0, st>>>(n, ctx->dev.newton_rtol,
-                                                       ctx->dev.newton_max, rho, e, Y, T, p, h,
-                                                       mu, kappa, D, status, ctx->counters);
+    if (mixed)
+      k_thermo_eval<float><<<blocks_for(n, 128), 128, 0, st>>>(
+          n, ctx->dev.newton_rtol, ctx->dev.newton_max, rho, e, Y, T, p, h, mu, kappa, D, status,
+          ctx->counters);
+    else
+      k_thermo_eval<double><<<blocks_for(n, 128), 128, 0, st>>>(
+          n, ctx->dev.newton_rtol, ctx->dev.newton_max, rho, e, Y, T, p, h, mu, kappa, D, status,
+          ctx->counters);
   });
   return check(hipGetLastError());
 }
@@ -1168,7 +1202,13 @@ int hrx_chem_source(hrx_ctx* ctx, int64_t n, const double* rho_s, const double* 
   if (n == 0) return HRX_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   ctx->last_stream = st;
-  timed(ctx, K_CHEM, st, [&] { k_chem_source<<<blocks_for(n, 128), 128, 0, st>>>(n, rho_s, T, wdot); });
+  const bool mixed = ctx->cfg.precision == HRX_PREC_MIXED;
+  timed(ctx, K_CHEM, st, [&] {
+    if (mixed)
+      k_chem_source<float><<<blocks_for(n, 128), 128, 0, st>>>(n, rho_s, T, wdot);
+    else
+      k_chem_source<double><<<blocks_for(n, 128), 128, 0, st>>>(n, rho_s, T, wdot);
+  });
   return check(hipGetLastError());
 }
 
