@@ -48,6 +48,7 @@ enum { HRX_GAS_CPG = 0, HRX_GAS_AIR5 = 1 };
 enum { HRX_WALL_ADIABATIC = 0, HRX_WALL_ISOTHERMAL = 1 };
 enum { HRX_RK3_2N = 0, HRX_RK45_2N = 1 };
 enum { HRX_PREC_FP64 = 0, HRX_PREC_MIXED = 1 };
+enum { HRX_THERMO_PLAIN = 0, HRX_THERMO_SURROGATE = 1 };
 
 /* Workload description (host).  Sec. 2.1 (reference scales, Eq. 7 and 11), Sec. 3.2
  * (sponges, wall), Sec. 3.3 (artificial diffusivity), Sec. 4 (case parameters). */
@@ -58,7 +59,11 @@ typedef struct hrx_config {
                                non-periodic, z uniform and periodic (may be NULL if nz = 1) */
   int fd_order;             /* 4 or 6: explicit central differences, one-sided ends */
   int rk_scheme;            /* HRX_RK3_2N or HRX_RK45_2N */
-  int precision;            /* HRX_PREC_FP64 or HRX_PREC_MIXED */
+  int precision;            /* HRX_PREC_FP64, or HRX_PREC_MIXED: FP64 conserved state, RK
+                               update, energy inversion, convective fluxes, stencil
+                               differences and Arrhenius exponentials at T >= 2000 K;
+                               FP32 transport, rate products, viscous/diffusive fluxes,
+                               stencil weighted sums and artificial-diffusivity planes */
   int ad_on;                /* artificial diffusivity on/off */
   double ad_coef[5];        /* C_mu, C_beta, C_kappa, C_D, C_Y */
   double gamma, Pr;         /* calorically perfect gas only */
@@ -91,7 +96,7 @@ typedef struct hrx_reference {
 typedef struct hrx_counters {
   int64_t newton_nonconverged;      /* points with no convergence in newton_max_iter */
   int64_t energy_below_min;         /* points with e < e(50 K) */
-  int64_t surrogate_fallbacks;      /* reserved */
+  int64_t surrogate_fallbacks;      /* points evaluated outside the surrogate's hull */
 } hrx_counters;
 
 /* Validate cfg, derive the reference state (Sec. 2.1, Eqs. 7 and 11), the metrics and
@@ -137,14 +142,58 @@ int hrx_chem_source(hrx_ctx *ctx, int64_t n, const double *rho_s, const double *
  * zeroes them afterwards. */
 int hrx_get_counters(hrx_ctx *ctx, hrx_counters *out /* (host) */, int reset);
 
+/* ---- Learned thermochemistry surrogate (motivated by Sec. 5: replacing the costly
+ * thermochemical-library calls with a learned model).  Network 7 -> 64 -> 64 -> 64 -> 8,
+ * tanh hidden layers, mapping standardised (log10 rho [kg/m^3], e [J/kg], Y_1..Y_5) to
+ * standardised (T [K], ln mu, ln kappa, ln(rho D_1)..ln(rho D_5)) in SI units (the
+ * diffusion coefficients are recovered as D_s = exp(y)/rho).  Parameters: 9352
+ * FP32 values in the order [W1 (64x7, row-major by output), b1, W2 (64x64), b2, W3, b3,
+ * W4 (8x64), b4].  Inference and the training forward pass run on the matrix cores in
+ * BF16 with FP32 accumulation (weights and layer inputs rounded to BF16, nearest even);
+ * the backward pass and Adam run in FP32 on FP32 master parameters. */
+
+/* Allocate the network's parameters, Adam moments and a training workspace for
+ * batches of up to max_batch rows (setup call; once per context). */
+int hrx_mlp_init(hrx_ctx *ctx, int64_t max_batch);
+/* Copy parameters theta [9352] (device, FP32) into the context, zero the Adam moments
+ * and prepare the BF16 matrix-core copy. */
+int hrx_mlp_set_params(hrx_ctx *ctx, const float *theta, void *hip_stream);
+/* Copy the current FP32 parameters to theta_out [9352] (device). */
+int hrx_mlp_get_params(hrx_ctx *ctx, float *theta_out, void *hip_stream);
+/* Standardisation (host arrays: input mean/std [7], output mean/std [8]) and the
+ * training hull: log10 rho in [log10rho_min, log10rho_max], Y_s >= 0 and
+ * sum_s Y_s e_s(T_lo) <= e <= sum_s Y_s e_s(T_hi). */
+int hrx_mlp_set_norm(hrx_ctx *ctx, const float *in_mean, const float *in_std,
+                     const float *out_mean, const float *out_std, double log10rho_min,
+                     double log10rho_max, double T_lo, double T_hi);
+/* HRX_THERMO_SURROGATE makes hrx_thermo_eval, hrx_rhs_eval and hrx_rk_stage (air5) take
+ * mu, kappa, D_s from the network and start the FP64 energy inversion from its T, for
+ * points inside the hull; points outside fall back to the plain evaluation and are
+ * counted.  Requires parameters and normalisation to be set. */
+int hrx_set_thermo_mode(hrx_ctx *ctx, int mode);
+/* Y [n][8] = network(X [n][7]) on standardised rows (device, FP32). */
+int hrx_mlp_forward(hrx_ctx *ctx, int64_t n, const float *X, float *Y, void *hip_stream);
+/* grad [9352] (device) = d(loss)/d(theta) for the batch X [n][7] (n <= max_batch) given
+ * dLdY [n][8] (device). */
+int hrx_mlp_backward(hrx_ctx *ctx, int64_t n, const float *X, const float *dLdY,
+                     float *grad, void *hip_stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; t counts from 1) with gradient grad. */
+int hrx_adam_step(hrx_ctx *ctx, const float *grad, float lr, int t, void *hip_stream);
+/* Forward, mean-squared-error gradient against Yt, backward and Adam for the rows
+ * idx [n] (device, or NULL for rows 0..n-1) of X [.][7] and Yt [.][8]; the batch's
+ * mean squared error is added to *loss (device, may be NULL). */
+int hrx_mlp_train_step(hrx_ctx *ctx, int64_t n, const int32_t *idx, const float *X,
+                       const float *Yt, float lr, int t, float *loss, void *hip_stream);
+
 /* Per-kernel timing with HIP events recorded on the launching stream around every
  * kernel of the calls that follow hrx_timing_enable(ctx, 1).  Kernel ids (index into
  * the arrays of hrx_timing_read): 0 prim, 1 ad_src, 2 ad_d4, 3 ad_filter_x,
- * 4 ad_filter_y, 5 ad_filter_z, 6 flux, 7 div, 8 bc, 9 thermo_eval, 10 chem_source.
+ * 4 ad_filter_y, 5 ad_filter_z, 6 flux, 7 div, 8 bc, 9 thermo_eval, 10 chem_source,
+ * 11 surrogate network pass.
  * hrx_timing_read synchronises, returns the summed milliseconds and launch counts
  * per kernel since enabling (arrays of HRX_NKERNELS, host) and keeps timing on.
  * hrx_timing_enable(ctx, 0) stops and releases the events. */
-#define HRX_NKERNELS 11
+#define HRX_NKERNELS 12
 int hrx_timing_enable(hrx_ctx *ctx, int on);
 int hrx_timing_read(hrx_ctx *ctx, double *ms /* (host) */, int64_t *launches /* (host) */);
 

@@ -11,7 +11,11 @@ of widths 7 -> 64 -> 64 -> 64 -> 8.  Parameters are one flat vector in the order
 [W1 (64x7, row = output unit), b1, W2 (64x64), b2, W3 (64x64), b3, W4 (8x64), b4],
 9352 values.  With ``bf16=True`` every matrix-product operand (weights and layer
 inputs) is first rounded to bfloat16 (round to nearest even, from float32), as the
-matrix-core path does; everything else stays float64.
+matrix-core path does, except the network's own inputs, which enter as the sum of
+two bfloat16 numbers bf16(x) + bf16(x - bf16(x)) (x in float32); everything else
+stays float64.  In the backward pass the
+same rounding applies to the weights and to the saved layer inputs (the operands the
+forward pass consumed); the back-propagated deltas stay unrounded.
 """
 import numpy as np
 
@@ -44,6 +48,14 @@ def to_bf16(a):
     return np.where(np.isnan(f), np.nan, out)
 
 
+def to_split_bf16(a):
+    """bf16(x) + bf16(x - bf16(x)) of float32 x: the two-term input representation."""
+    x = np.asarray(a, dtype=np.float32)
+    hi = to_bf16(x).astype(np.float32)
+    lo = to_bf16((x - hi).astype(np.float32))
+    return hi.astype(np.float64) + lo
+
+
 def init_params(seed=0):
     """Glorot-uniform weights, zero biases."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -62,7 +74,8 @@ def forward(theta, X, bf16=False):
     a = np.asarray(X, dtype=np.float64)
     acts = [a]
     for li, (W, b) in enumerate(layers):
-        z = q(a) @ q(W).T + b
+        qa = (to_split_bf16 if (bf16 and li == 0) else q)(a)
+        z = qa @ q(W).T + b
         a = np.tanh(z) if li < 3 else z
         acts.append(a)
     return a, acts
@@ -77,11 +90,11 @@ def backward(theta, acts, dY, bf16=False):
     for li in range(3, -1, -1):
         W, b = layers[li]
         a_in = acts[li]
-        gW = q(d).T @ q(a_in)
+        gW = d.T @ (to_split_bf16 if (bf16 and li == 0) else q)(a_in)
         gb = d.sum(axis=0)
         grads[li] = (gW, gb)
         if li > 0:
-            da = q(d) @ q(W)
+            da = d @ q(W)
             d = da * (1.0 - acts[li] ** 2)
     return pack(grads)
 

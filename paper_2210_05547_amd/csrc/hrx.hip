@@ -14,6 +14,7 @@
 // loads of a wavefront are contiguous and y/z neighbours are reused through L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -22,6 +23,7 @@
 
 #include "air5.h"
 #include "hrx.h"
+#include "mlp.h"
 
 namespace hrx {
 
@@ -140,7 +142,7 @@ constexpr double T_HI_MIXED = 2000.0;
 // ------------------------------------------------------------------ k_prim
 // Wd planes (double): [u, v, (w), T, X_1..X_5 (air5), p]   -- differentiated or convective
 // Wp planes (RT):     [mu, kappa, D_1..D_5, wdot_1..wdot_5, (c)] (air5), [mu, (c)] (CPG)
-template <int GAS, int ND, class RT>
+template <int GAS, int ND, class RT, bool SUR = false>
 __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ Q,
                                               double* __restrict__ Wd, RT* __restrict__ Wp) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -208,8 +210,14 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   for (int s = 0; s < NS; ++s) X[s] = X[s] / n;
   SpeciesThermo st;
   species_e_cv(Tk, st);
+  // surrogate form: the network already wrote the transport planes, except where it
+  // marked the point as outside its hull (NaN)
+  const bool plain_transport = !SUR || isnan(Wp[d.w_mu * N + idx]);
   Transport<RT> tr;
-  mixture_transport<RT>(Tk, p_d, X, st.cv, tr);
+  if (plain_transport) {
+    if (SUR) atomicAdd(&d.counters[2], 1ull);
+    mixture_transport<RT>(Tk, p_d, X, st.cv, tr);
+  }
   double rsd[NS];
   RT wd[NS];
 #pragma unroll
@@ -221,11 +229,13 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
 #pragma unroll
   for (int s = 0; s < NS; ++s) Wd[(ND + 1 + s) * N + idx] = X[s];
   Wd[d.w_p * N + idx] = p;
-  Wp[d.w_mu * N + idx] = tr.mu / RT(d.mu_inf);
-  Wp[d.w_kap * N + idx] = tr.kappa / RT(d.kappa_inf);
-  const RT Dscale = RT(d.c_inf * d.L_ref);
+  if (plain_transport) {
+    Wp[d.w_mu * N + idx] = tr.mu / RT(d.mu_inf);
+    Wp[d.w_kap * N + idx] = tr.kappa / RT(d.kappa_inf);
+    const RT Dscale = RT(d.c_inf * d.L_ref);
 #pragma unroll
-  for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * N + idx] = tr.D[s] / Dscale;
+    for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * N + idx] = tr.D[s] / Dscale;
+  }
   const double wscale = d.L_ref / (d.rho_inf * d.c_inf);
 #pragma unroll
   for (int s = 0; s < NS; ++s) Wp[(d.w_wdot + s) * N + idx] = RT(double(wd[s]) * wscale);
@@ -644,7 +654,7 @@ __global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
 }
 
 // ------------------------------------------------------------------ pointwise SI calls
-template <class RT>
+template <class RT, bool SUR = false>
 __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int max_iter,
                                                      const double* __restrict__ rho,
                                                      const double* __restrict__ e,
@@ -663,7 +673,12 @@ __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int ma
 #pragma unroll
   for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + i];
   int status, iters;
-  const double T = temperature_from_energy(e[i], Y, rtol, max_iter, &status, &iters);
+  // surrogate form: Tout holds the network's temperature (NaN outside its hull) and
+  // mu, kappa, D hold ln mu, ln kappa, ln D_s
+  const double Tg = SUR ? Tout[i] : 0.0;
+  const bool in_hull = SUR && !isnan(Tg);
+  const double T = temperature_from_energy(e[i], Y, rtol, max_iter, &status, &iters,
+                                           in_hull ? Tg : 0.0);
   if (status == 1) atomicAdd(&counters[0], 1ull);
   if (status == 2) atomicAdd(&counters[1], 1ull);
   Tout[i] = T;
@@ -676,7 +691,15 @@ __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int ma
 #pragma unroll
     for (int s = 0; s < NS; ++s) hout[s * n + i] = h[s];
   }
-  if (muout || kout || Dout) {
+  if (in_hull) {
+    if (muout) muout[i] = exp(muout[i]);
+    if (kout) kout[i] = exp(kout[i]);
+    if (Dout) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) Dout[s * n + i] = exp(Dout[s * n + i]);
+    }
+  } else if (muout || kout || Dout) {
+    if (SUR) atomicAdd(&counters[2], 1ull);
     double X[NS], nsum = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -715,6 +738,290 @@ __global__ __launch_bounds__(128) void k_chem_source(long n, const double* __res
   for (int s = 0; s < NS; ++s) wdot[s * n + i] = double(w[s]);
 }
 
+// ------------------------------------------------------------------ surrogate network
+// theta (FP32 flat) -> swizzled BF16 weights for the matrix cores, FP32 biases, and a
+// BF16-rounded FP32 copy of the weights in flat order for the backward pass.
+__global__ __launch_bounds__(256) void k_mlp_pack(const float* __restrict__ theta,
+                                                  uint16_t* __restrict__ wsw,
+                                                  float* __restrict__ bias,
+                                                  float* __restrict__ wq) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < MLP_SW_SIZE;
+       i += gridDim.x * blockDim.x) {
+    int L = 3;
+    while (L > 0 && i < MLP_SW_OFF[L]) --L;
+    const int r = i - MLP_SW_OFF[L];
+    const int q = r & 7, lane = (r >> 3) & 63, mt = r >> 9;
+    const int m = mt / MLP_KS[L], t = mt % MLP_KS[L];
+    const int o = 32 * m + (lane & 31), k = 16 * t + 8 * (lane >> 5) + q;
+    // first layer: columns k and 7 + k both carry W1[o][k] (hi/lo input pairs)
+    const int kk = (L == 0 && k >= MLP_NIN && k < 2 * MLP_NIN) ? k - MLP_NIN : k;
+    float v = 0.0f;
+    if (o < MLP_NOUT_L[L] && kk < MLP_NIN_L[L]) v = theta[MLP_OFF_W[L] + o * MLP_NIN_L[L] + kk];
+    wsw[i] = f2bf(v);
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < MLP_NPARAM;
+       i += gridDim.x * blockDim.x) {
+    bool is_b = false;
+    int bo = 0;
+    for (int L = 0; L < 4; ++L)
+      if (i >= MLP_OFF_B[L] && i < MLP_OFF_B[L] + MLP_NOUT_L[L]) {
+        is_b = true;
+        bo = (L == 0 ? 0 : (L == 1 ? 64 : (L == 2 ? 128 : 192))) + (i - MLP_OFF_B[L]);
+      }
+    wq[i] = is_b ? theta[i] : bf2f(f2bf(theta[i]));
+    if (is_b) bias[bo] = theta[i];
+  }
+}
+
+// Forward pass of n standardised inputs X [n][7] (rows gathered through idx when
+// given) -> Y [n][8]; save != null keeps the hidden activations [3][n][64] (FP32).
+__global__ __launch_bounds__(256) void k_mlp_fwd(long n, const float* __restrict__ X,
+                                                 const int32_t* __restrict__ idx,
+                                                 float* __restrict__ Y, float* save,
+                                                 const uint16_t* __restrict__ gW,
+                                                 const float* __restrict__ gB) {
+  __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_SW_SIZE];
+  __shared__ float sB[MLP_NBIAS];
+  __shared__ __attribute__((aligned(16))) uint16_t sH[4][64 * MLP_HPITCH];
+  mlp_load_lds(gW, gB, sW, sB);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (long base = (long)blockIdx.x * 256 + wave * 64; base < n; base += (long)gridDim.x * 256) {
+    const long p = base + lane;
+    const bool valid = p < n;
+    float x[MLP_NIN], y[MLP_NOUT];
+    const long row = valid ? (idx ? (long)idx[p] : p) : 0;
+#pragma unroll
+    for (int k = 0; k < MLP_NIN; ++k) x[k] = valid ? X[row * MLP_NIN + k] : 0.0f;
+    mlp_wave64(sW, sB, sH[wave], x, y, save, base, n, valid);
+    if (valid) {
+#pragma unroll
+      for (int o = 0; o < MLP_NOUT; ++o) Y[p * MLP_NOUT + o] = y[o];
+    }
+  }
+}
+
+// MSE over n x 8 outputs: dY = 2 (Y - T) / (8 n); loss += mean squared error.
+__global__ __launch_bounds__(256) void k_mlp_mse(long n, const float* __restrict__ Y,
+                                                 const float* __restrict__ T,
+                                                 const int32_t* __restrict__ idx,
+                                                 float* __restrict__ dY, float* loss) {
+  __shared__ float red[256];
+  const long m = n * MLP_NOUT;
+  float acc = 0.0f;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (long)gridDim.x * blockDim.x) {
+    const long b = i / MLP_NOUT;
+    const int o = (int)(i % MLP_NOUT);
+    const long tb = idx ? (long)idx[b] : b;
+    const float r = Y[i] - T[tb * MLP_NOUT + o];
+    dY[i] = 2.0f * r / (float)m;
+    acc += r * r;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) atomicAdd(loss, red[0] / (float)m);
+}
+
+// Back-propagated deltas, one sample per thread: delta [n][200] = (d1, d2, d3, d4).
+__global__ __launch_bounds__(128) void k_mlp_bwd_delta(long n, const float* __restrict__ dY,
+                                                       const float* __restrict__ save,
+                                                       const float* __restrict__ wq,
+                                                       float* __restrict__ delta) {
+  const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  float* db = delta + b * 200;
+  float d4[MLP_NOUT];
+#pragma unroll
+  for (int o = 0; o < MLP_NOUT; ++o) {
+    d4[o] = dY[b * MLP_NOUT + o];
+    db[192 + o] = d4[o];
+  }
+  float d3[64], d2[64];
+  const float* W4 = wq + MLP_OFF_W[3];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    float sacc = 0.0f;
+#pragma unroll
+    for (int o = 0; o < MLP_NOUT; ++o) sacc += d4[o] * W4[o * 64 + k];
+    const float a = save[(2 * n + b) * 64 + k];
+    d3[k] = sacc * (1.0f - a * a);
+    db[128 + k] = d3[k];
+  }
+  const float* W3 = wq + MLP_OFF_W[2];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    float sacc = 0.0f;
+#pragma unroll
+    for (int o = 0; o < 64; ++o) sacc += d3[o] * W3[o * 64 + k];
+    const float a = save[(1 * n + b) * 64 + k];
+    d2[k] = sacc * (1.0f - a * a);
+    db[64 + k] = d2[k];
+  }
+  const float* W2 = wq + MLP_OFF_W[1];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    float sacc = 0.0f;
+#pragma unroll
+    for (int o = 0; o < 64; ++o) sacc += d2[o] * W2[o * 64 + k];
+    const float a = save[(0 * n + b) * 64 + k];
+    db[k] = sacc * (1.0f - a * a);
+  }
+}
+
+// Weight and bias gradients: one block per (layer, output unit); the batch sum runs
+// in four interleaved partial sums combined in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_mlp_wgrad(long n, const float* __restrict__ X,
+                                                   const int32_t* __restrict__ idx,
+                                                   const float* __restrict__ save,
+                                                   const float* __restrict__ delta,
+                                                   float* __restrict__ grad) {
+  __shared__ float redw[4][64];
+  __shared__ float redb[4];
+  int bid = blockIdx.x, L = 0;
+  while (L < 3 && bid >= MLP_NOUT_L[L]) {
+    bid -= MLP_NOUT_L[L];
+    ++L;
+  }
+  const int o = bid;
+  const int nin = MLP_NIN_L[L];
+  const int k = threadIdx.x & 63, part = threadIdx.x >> 6;
+  const int doff = L == 0 ? 0 : (L == 1 ? 64 : (L == 2 ? 128 : 192));
+  float acc = 0.0f, bsum = 0.0f;
+  for (long b = part; b < n; b += 4) {
+    const float dl = delta[b * 200 + doff + o];
+    if (k < nin) {
+      const float ain = (L == 0) ? split_bf(X[(idx ? (long)idx[b] : b) * MLP_NIN + k])
+                                 : bf2f(f2bf(save[((long)(L - 1) * n + b) * 64 + k]));
+      acc += dl * ain;
+    }
+    if (k == 0) bsum += dl;
+  }
+  redw[part][k] = acc;
+  if (k == 0) redb[part] = bsum;
+  __syncthreads();
+  if (part == 0 && k < nin)
+    grad[MLP_OFF_W[L] + o * nin + k] = ((redw[0][k] + redw[1][k]) + redw[2][k]) + redw[3][k];
+  if (threadIdx.x == 0) grad[MLP_OFF_B[L] + o] = ((redb[0] + redb[1]) + redb[2]) + redb[3];
+}
+
+// Adam (beta1 = 0.9, beta2 = 0.999, eps = 1e-8) on the FP32 master parameters.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, float* __restrict__ m,
+                                              float* __restrict__ v,
+                                              const float* __restrict__ g, float lr, float bc1,
+                                              float bc2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MLP_NPARAM) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  theta[i] = theta[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+}
+
+// Inputs of the network from an SI state; returns false outside the training hull
+// (log10 rho outside [min, max], a negative mass fraction, or e outside
+// [sum Y e_s(T_lo), sum Y e_s(T_hi)]).
+__device__ __forceinline__ bool surrogate_inputs(const MlpNorm& nm, double rho, double e,
+                                                 const double* Y, float* x) {
+  const double lr = log10(rho);
+  double elo = 0.0, ehi = 0.0;
+  bool ok = lr >= nm.log10rho_min && lr <= nm.log10rho_max;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    elo += Y[s] * nm.e_lo[s];
+    ehi += Y[s] * nm.e_hi[s];
+    ok = ok && Y[s] >= 0.0;
+  }
+  ok = ok && e >= elo && e <= ehi;
+  const double raw[MLP_NIN] = {lr, e, Y[0], Y[1], Y[2], Y[3], Y[4]};
+#pragma unroll
+  for (int k = 0; k < MLP_NIN; ++k)
+    x[k] = ok ? (float)((raw[k] - nm.in_mean[k]) / nm.in_std[k]) : 0.0f;
+  return ok;
+}
+
+// Network evaluation on physical states (the surrogate's first pass).  MODE_STATE_SI:
+// inputs rho [n], e [n], Y [5][n] (SI); outputs (de-standardised) written in place of
+// the caller's outputs: T guess into Tg [n] (NaN outside the hull), ln mu, ln kappa,
+// ln D_s into mu, kappa, D when given.  MODE_STATE_Q: inputs from the nondimensional
+// conserved state Q; outputs mu/mu_inf, kappa/kappa_inf, D_s/(c_inf L_ref) into the
+// transport planes of Wp, with NaN in the mu plane outside the hull.
+enum { MODE_STATE_SI = 0, MODE_STATE_Q = 1 };
+template <int MODE, int ND, class RT>
+__global__ __launch_bounds__(256) void k_mlp_state(
+    Dev d, MlpNorm nm, long n, const double* __restrict__ rho, const double* __restrict__ e,
+    const double* __restrict__ Yin, double* __restrict__ Tg, double* __restrict__ mu,
+    double* __restrict__ kap, double* __restrict__ D, const double* __restrict__ Q,
+    RT* __restrict__ Wp, const uint16_t* __restrict__ gW, const float* __restrict__ gB) {
+  __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_SW_SIZE];
+  __shared__ float sB[MLP_NBIAS];
+  __shared__ __attribute__((aligned(16))) uint16_t sH[4][64 * MLP_HPITCH];
+  mlp_load_lds(gW, gB, sW, sB);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (long base = (long)blockIdx.x * 256 + wave * 64; base < n; base += (long)gridDim.x * 256) {
+    const long i = base + lane;
+    const bool valid = i < n;
+    const long ix = valid ? i : 0;
+    double Y[NS], r, ee;
+    if (MODE == MODE_STATE_SI) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + ix];
+      r = rho[ix];
+      ee = e[ix];
+    } else {
+      double rs = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        Y[s] = Q[s * n + ix];
+        rs += Y[s];
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s) Y[s] = Y[s] / rs;
+      double ke = 0.0;
+#pragma unroll
+      for (int a = 0; a < ND; ++a) {
+        const double ua = Q[(NS + a) * n + ix] / rs;
+        ke += ua * ua;
+      }
+      r = rs * d.rho_inf;
+      ee = (Q[(NS + ND) * n + ix] / rs - 0.5 * ke) * (d.c_inf * d.c_inf);
+    }
+    float x[MLP_NIN], y[MLP_NOUT];
+    const bool in_hull = surrogate_inputs(nm, r, ee, Y, x) && valid;
+    mlp_wave64(sW, sB, sH[wave], x, y, nullptr, 0, 0, valid);
+    if (!valid) continue;
+    double ys[MLP_NOUT];
+#pragma unroll
+    for (int o = 0; o < MLP_NOUT; ++o) ys[o] = (double)y[o] * nm.out_std[o] + nm.out_mean[o];
+    if (MODE == MODE_STATE_SI) {
+      Tg[i] = in_hull ? ys[0] : __builtin_nan("");
+      if (mu) mu[i] = ys[1];
+      if (kap) kap[i] = ys[2];
+      if (D) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) D[s * n + i] = ys[3 + s] - log(r);   // ln D_s
+      }
+    } else {
+      if (in_hull) {
+        Wp[d.w_mu * n + i] = RT(exp(ys[1]) / d.mu_inf);
+        Wp[d.w_kap * n + i] = RT(exp(ys[2]) / d.kappa_inf);
+        const double Dscale = d.c_inf * d.L_ref;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * n + i] = RT(exp(ys[3 + s]) / (r * Dscale));
+      } else {
+        Wp[d.w_mu * n + i] = RT(__builtin_nan(""));
+      }
+    }
+  }
+}
+
 }  // namespace hrx
 
 // ====================================================================== host side
@@ -740,12 +1047,21 @@ struct hrx_ctx {
   std::vector<Pending> pending;
   double ms[HRX_NKERNELS] = {0};
   int64_t launches[HRX_NKERNELS] = {0};
+  // surrogate network
+  int thermo_mode = HRX_THERMO_PLAIN;
+  bool mlp_params = false, mlp_norm = false;
+  int64_t mlp_maxb = 0;
+  float *theta = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
+  float *bias = nullptr, *wq = nullptr, *save = nullptr, *ybuf = nullptr, *dybuf = nullptr,
+        *delta = nullptr;
+  uint16_t* wsw = nullptr;
+  MlpNorm norm;
 };
 
 namespace {
 
 enum { K_PRIM = 0, K_AD_SRC, K_AD_D4, K_AD_FX, K_AD_FY, K_AD_FZ, K_FLUX, K_DIV, K_BC, K_THERMO,
-       K_CHEM };
+       K_CHEM, K_MLP };
 
 int flush_timing(hrx_ctx* c) {
   for (auto& p : c->pending) {
@@ -854,6 +1170,10 @@ void hrx_destroy(hrx_ctx* c) {
   (void)hipFree(c->metrics);
   (void)hipFree(c->hold);
   (void)hipFree(c->counters);
+  for (void* q : {(void*)c->theta, (void*)c->adam_m, (void*)c->adam_v, (void*)c->grad,
+                  (void*)c->bias, (void*)c->wq, (void*)c->save, (void*)c->ybuf, (void*)c->dybuf,
+                  (void*)c->delta, (void*)c->wsw})
+    (void)hipFree(q);
   delete c;
 }
 
@@ -1067,7 +1387,17 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
   double* Wd = ctx->Wd;
   RT* Wp = (RT*)ctx->Wp;
   double* F = ctx->F;
-  timed(ctx, K_PRIM, st, [&] { k_prim<GAS, ND, RT><<<nb, bs, 0, st>>>(d, Q, Wd, Wp); });
+  if (GAS == AIR5 && ctx->thermo_mode == HRX_THERMO_SURROGATE) {
+    const unsigned nbs = (unsigned)std::min<long>((N + 255) / 256, 2048);
+    timed(ctx, K_MLP, st, [&] {
+      k_mlp_state<MODE_STATE_Q, ND, RT><<<nbs, 256, 0, st>>>(
+          d, ctx->norm, N, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, Q, Wp,
+          ctx->wsw, ctx->bias);
+    });
+    timed(ctx, K_PRIM, st, [&] { k_prim<GAS, ND, RT, true><<<nb, bs, 0, st>>>(d, Q, Wd, Wp); });
+  } else {
+    timed(ctx, K_PRIM, st, [&] { k_prim<GAS, ND, RT><<<nb, bs, 0, st>>>(d, Q, Wd, Wp); });
+  }
   if (d.ad_on) {
     RT* A = (RT*)ctx->AD;
     RT* B = A + (long)d.nad * N;
@@ -1183,7 +1513,15 @@ int hrx_thermo_eval(hrx_ctx* ctx, int64_t n, const double* rho, const double* e,
   ctx->last_stream = st;
   const bool mixed = ctx->cfg.precision == HRX_PREC_MIXED;
   timed(ctx, K_THERMO, st, [&] {
-    if (mixed)
+    if (ctx->thermo_mode == HRX_THERMO_SURROGATE) {
+      const unsigned nbs = (unsigned)std::min<long>((n + 255) / 256, 2048);
+      k_mlp_state<MODE_STATE_SI, 2, double><<<nbs, 256, 0, st>>>(
+          ctx->dev, ctx->norm, n, rho, e, Y, T, mu, kappa, D, nullptr, nullptr, ctx->wsw,
+          ctx->bias);
+      k_thermo_eval<double, true><<<blocks_for(n, 128), 128, 0, st>>>(
+          n, ctx->dev.newton_rtol, ctx->dev.newton_max, rho, e, Y, T, p, h, mu, kappa, D, status,
+          ctx->counters);
+    } else if (mixed)
       k_thermo_eval<float><<<blocks_for(n, 128), 128, 0, st>>>(
           n, ctx->dev.newton_rtol, ctx->dev.newton_max, rho, e, Y, T, p, h, mu, kappa, D, status,
           ctx->counters);
@@ -1252,6 +1590,152 @@ int hrx_get_counters(hrx_ctx* ctx, hrx_counters* out, int reset) {
   out->surrogate_fallbacks = (int64_t)h[2];
   if (reset) rc = check(hipMemset(ctx->counters, 0, sizeof(h)));
   return rc;
+}
+
+}  // extern "C"
+
+// ====================================================================== surrogate API
+extern "C" {
+
+int hrx_mlp_init(hrx_ctx* ctx, int64_t max_batch) {
+  if (!ctx || max_batch < 1 || max_batch > (int64_t)1 << 24) return HRX_EINVAL;
+  if (ctx->theta) return HRX_EINVAL;  // once per context
+  const size_t P = MLP_NPARAM * sizeof(float);
+  const size_t B = (size_t)max_batch;
+  if (hipMalloc(&ctx->theta, P) != hipSuccess || hipMalloc(&ctx->adam_m, P) != hipSuccess ||
+      hipMalloc(&ctx->adam_v, P) != hipSuccess || hipMalloc(&ctx->grad, P) != hipSuccess ||
+      hipMalloc(&ctx->wq, P) != hipSuccess ||
+      hipMalloc(&ctx->bias, MLP_NBIAS * sizeof(float)) != hipSuccess ||
+      hipMalloc(&ctx->wsw, MLP_SW_SIZE * sizeof(uint16_t)) != hipSuccess ||
+      hipMalloc(&ctx->save, 3 * B * 64 * sizeof(float)) != hipSuccess ||
+      hipMalloc(&ctx->ybuf, B * MLP_NOUT * sizeof(float)) != hipSuccess ||
+      hipMalloc(&ctx->dybuf, B * MLP_NOUT * sizeof(float)) != hipSuccess ||
+      hipMalloc(&ctx->delta, B * 200 * sizeof(float)) != hipSuccess)
+    return HRX_ENOMEM;
+  if (hipMemset(ctx->adam_m, 0, P) != hipSuccess || hipMemset(ctx->adam_v, 0, P) != hipSuccess)
+    return HRX_EHIP;
+  ctx->mlp_maxb = max_batch;
+  return HRX_OK;
+}
+
+int hrx_mlp_set_params(hrx_ctx* ctx, const float* theta, void* hip_stream) {
+  if (!ctx || !theta || !ctx->theta) return HRX_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  const size_t P = MLP_NPARAM * sizeof(float);
+  if (hipMemcpyAsync(ctx->theta, theta, P, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemsetAsync(ctx->adam_m, 0, P, st) != hipSuccess ||
+      hipMemsetAsync(ctx->adam_v, 0, P, st) != hipSuccess)
+    return HRX_EHIP;
+  k_mlp_pack<<<48, 256, 0, st>>>(ctx->theta, ctx->wsw, ctx->bias, ctx->wq);
+  ctx->mlp_params = true;
+  return check(hipGetLastError());
+}
+
+int hrx_mlp_get_params(hrx_ctx* ctx, float* theta_out, void* hip_stream) {
+  if (!ctx || !theta_out || !ctx->theta) return HRX_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  return check(hipMemcpyAsync(theta_out, ctx->theta, MLP_NPARAM * sizeof(float),
+                              hipMemcpyDeviceToDevice, st));
+}
+
+int hrx_mlp_set_norm(hrx_ctx* ctx, const float* in_mean, const float* in_std,
+                     const float* out_mean, const float* out_std, double log10rho_min,
+                     double log10rho_max, double T_lo, double T_hi) {
+  if (!ctx || !in_mean || !in_std || !out_mean || !out_std) return HRX_EINVAL;
+  if (!(log10rho_min < log10rho_max) || !(T_lo > T_MIN) || !(T_lo < T_hi)) return HRX_EINVAL;
+  MlpNorm& nm = ctx->norm;
+  for (int k = 0; k < MLP_NIN; ++k) {
+    if (!(in_std[k] > 0.0f)) return HRX_EINVAL;
+    nm.in_mean[k] = in_mean[k];
+    nm.in_std[k] = in_std[k];
+  }
+  for (int k = 0; k < MLP_NOUT; ++k) {
+    if (!(out_std[k] > 0.0f)) return HRX_EINVAL;
+    nm.out_mean[k] = out_mean[k];
+    nm.out_std[k] = out_std[k];
+  }
+  nm.log10rho_min = log10rho_min;
+  nm.log10rho_max = log10rho_max;
+  SpeciesThermo lo, hi;
+  species_e_cv(T_lo, lo);
+  species_e_cv(T_hi, hi);
+  for (int s = 0; s < NS; ++s) {
+    nm.e_lo[s] = lo.e[s];
+    nm.e_hi[s] = hi.e[s];
+  }
+  ctx->mlp_norm = true;
+  return HRX_OK;
+}
+
+int hrx_set_thermo_mode(hrx_ctx* ctx, int mode) {
+  if (!ctx) return HRX_EINVAL;
+  if (mode == HRX_THERMO_PLAIN) {
+    ctx->thermo_mode = mode;
+    return HRX_OK;
+  }
+  if (mode != HRX_THERMO_SURROGATE || ctx->cfg.gas != HRX_GAS_AIR5) return HRX_EINVAL;
+  if (!ctx->mlp_params || !ctx->mlp_norm) return HRX_EINVAL;
+  ctx->thermo_mode = mode;
+  return HRX_OK;
+}
+
+int hrx_mlp_forward(hrx_ctx* ctx, int64_t n, const float* X, float* Y, void* hip_stream) {
+  if (!ctx || n < 0 || (n > 0 && (!X || !Y)) || !ctx->mlp_params) return HRX_EINVAL;
+  if (n == 0) return HRX_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+  k_mlp_fwd<<<nb, 256, 0, st>>>(n, X, nullptr, Y, nullptr, ctx->wsw, ctx->bias);
+  return check(hipGetLastError());
+}
+
+static int mlp_backward_impl(hrx_ctx* ctx, int64_t n, const int32_t* idx, const float* X,
+                             const float* dY, float* grad, hipStream_t st) {
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+  k_mlp_fwd<<<nb, 256, 0, st>>>(n, X, idx, ctx->ybuf, ctx->save, ctx->wsw, ctx->bias);
+  k_mlp_bwd_delta<<<blocks_for(n, 128), 128, 0, st>>>(n, dY, ctx->save, ctx->wq, ctx->delta);
+  k_mlp_wgrad<<<200, 256, 0, st>>>(n, X, idx, ctx->save, ctx->delta, grad);
+  return check(hipGetLastError());
+}
+
+int hrx_mlp_backward(hrx_ctx* ctx, int64_t n, const float* X, const float* dLdY, float* grad,
+                     void* hip_stream) {
+  if (!ctx || !ctx->mlp_params || n < 1 || n > ctx->mlp_maxb || !X || !dLdY || !grad)
+    return HRX_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  return mlp_backward_impl(ctx, n, nullptr, X, dLdY, grad, st);
+}
+
+int hrx_adam_step(hrx_ctx* ctx, const float* grad, float lr, int t, void* hip_stream) {
+  if (!ctx || !ctx->mlp_params || !grad || t < 1 || !(lr >= 0.0f)) return HRX_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  const float bc1 = (float)(1.0 - pow(0.9, t)), bc2 = (float)(1.0 - pow(0.999, t));
+  k_adam<<<blocks_for(MLP_NPARAM, 256), 256, 0, st>>>(ctx->theta, ctx->adam_m, ctx->adam_v, grad,
+                                                      lr, bc1, bc2);
+  k_mlp_pack<<<48, 256, 0, st>>>(ctx->theta, ctx->wsw, ctx->bias, ctx->wq);
+  return check(hipGetLastError());
+}
+
+int hrx_mlp_train_step(hrx_ctx* ctx, int64_t n, const int32_t* idx, const float* X,
+                       const float* Yt, float lr, int t, float* loss, void* hip_stream) {
+  if (!ctx || !ctx->mlp_params || n < 1 || n > ctx->mlp_maxb || !X || !Yt || t < 1)
+    return HRX_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+  k_mlp_fwd<<<nb, 256, 0, st>>>(n, X, idx, ctx->ybuf, ctx->save, ctx->wsw, ctx->bias);
+  k_mlp_mse<<<(unsigned)std::min<int64_t>((n * MLP_NOUT + 255) / 256, 1024), 256, 0, st>>>(
+      n, ctx->ybuf, Yt, idx, ctx->dybuf, loss);
+  k_mlp_bwd_delta<<<blocks_for(n, 128), 128, 0, st>>>(n, ctx->dybuf, ctx->save, ctx->wq,
+                                                      ctx->delta);
+  k_mlp_wgrad<<<200, 256, 0, st>>>(n, X, idx, ctx->save, ctx->delta, ctx->grad);
+  int rc = check(hipGetLastError());
+  if (rc) return rc;
+  return hrx_adam_step(ctx, ctx->grad, lr, t, hip_stream);
 }
 
 }  // extern "C"

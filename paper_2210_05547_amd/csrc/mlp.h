@@ -1,0 +1,195 @@
+// Thermochemistry surrogate network for gfx950: BF16 matrix-core (MFMA) inference with
+// FP32 accumulation, FP32 backward pass and Adam.
+//
+// The paper closes (Sec. 5) by pointing at machine learning as a way to replace the
+// expensive calls of its thermochemical library.  The network maps
+//   x = standardised (log10 rho, e, Y_1..Y_5)  ->  y = standardised (T, ln mu, ln kappa,
+//                                                     ln D_1..ln D_5)
+// with three tanh hidden layers of 64 units: 7 -> 64 -> 64 -> 64 -> 8, 9352 parameters,
+// flat order [W1 (64x7, row = output), b1, W2, b2, W3, b3, W4 (8x64), b4].
+//
+// Matrix-core mapping (v_mfma_f32_32x32x16_bf16, one wavefront of 64 lanes):
+//   A (32x16, weights):     lane l holds A[l%32][8(l/32) + q], q = 0..7
+//   B (16x32, activations): lane l holds B[8(l/32) + q][l%32]
+//   D (32x32, FP32):        lane l, register r holds D[(r%4) + 8(r/4) + 4(l/32)][l%32]
+// A wavefront evaluates 64 points as two 32-point column tiles; hidden activations
+// pass between layers through a per-wave LDS buffer in BF16.  Weights are stored
+// once, pre-swizzled so that each lane's A operand is 16 contiguous bytes.
+// The network's inputs enter the first layer as hi + lo BF16 pairs (see mlp_wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hrx {
+
+constexpr int MLP_NIN = 7, MLP_NH = 64, MLP_NOUT = 8;
+constexpr int MLP_NPARAM = 64 * 7 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 8 * 64 + 8;  // 9352
+// offsets of each layer's W and b in the flat parameter vector
+constexpr int MLP_OFF_W[4] = {0, 64 * 7 + 64, 64 * 7 + 64 + 64 * 64 + 64,
+                              64 * 7 + 64 + 2 * (64 * 64 + 64)};
+constexpr int MLP_OFF_B[4] = {64 * 7, 64 * 7 + 64 + 64 * 64, 64 * 7 + 64 + 2 * 64 * 64 + 64,
+                              64 * 7 + 64 + 2 * (64 * 64 + 64) + 8 * 64};
+constexpr int MLP_NIN_L[4] = {7, 64, 64, 64};
+constexpr int MLP_NOUT_L[4] = {64, 64, 64, 8};
+// MFMA tiling per layer: M tiles of 32 outputs, K steps of 16 inputs
+constexpr int MLP_MT[4] = {2, 2, 2, 1};
+constexpr int MLP_KS[4] = {1, 4, 4, 4};
+// offsets (in BF16 elements) of each layer's swizzled weights
+constexpr int MLP_SW_OFF[4] = {0, 1024, 1024 + 4096, 1024 + 2 * 4096};
+constexpr int MLP_SW_SIZE = 1024 + 2 * 4096 + 2048;  // 11264
+constexpr int MLP_NBIAS = 64 + 64 + 64 + 8;
+constexpr int MLP_HPITCH = 72;  // BF16 elements per point row of the activation buffer
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+
+// float -> bfloat16 bits, round to nearest even (the gfx950 conversion instruction)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) {
+  return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+// value of an input as the first layer sees it: bf16(x) + bf16(x - bf16(x))
+__device__ __forceinline__ float split_bf(float x) {
+  const float hi = bf2f(f2bf(x));
+  return hi + bf2f(f2bf(x - hi));
+}
+
+__device__ __forceinline__ float fast_tanh(float z) {
+  // tanh z = 1 - 2 / (2^(2 z log2 e) + 1) with the hardware exp2 and reciprocal;
+  // saturates to +-1 for large |z|.  Error about 1e-7, far below the BF16 rounding
+  // the activation receives next.
+  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * z);
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+// Swizzled weight index of element (row o, column k) of layer L (padded with zeros).
+__host__ __device__ __forceinline__ int mlp_sw_index(int L, int m, int t, int lane, int q) {
+  return MLP_SW_OFF[L] + ((m * MLP_KS[L] + t) * 64 + lane) * 8 + q;
+}
+
+// Evaluate the network for the 64 points of one wavefront.  Lane l owns point l:
+// x[7] standardised inputs in, y[8] standardised outputs out.  sW: swizzled BF16
+// weights (LDS), sB: biases (LDS), sH: this wave's activation buffer (LDS,
+// 64 x MLP_HPITCH BF16).  If save != nullptr the FP32 post-activations of the three
+// hidden layers are written to save[(L*ldn + point)*64 + unit] for training, with
+// point = base + lane and only for lanes with valid != 0.
+__device__ __forceinline__ void mlp_wave64(const uint16_t* __restrict__ sW,
+                                           const float* __restrict__ sB, uint16_t* sH,
+                                           const float* x, float* y, float* save, long base,
+                                           long ldn, bool valid) {
+  const int lane = threadIdx.x & 63;
+  const int hl = lane >> 5;    // which half of the wave
+  const int col = lane & 31;   // column (point) within a 32-point tile
+  // inputs -> BF16 row of this lane's point as hi/lo pairs: columns 0..6 hold
+  // bf16(x), columns 7..13 hold bf16(x - bf16(x)) (the first layer's weights are
+  // repeated for both halves), 14..15 are zero: the first layer sees its inputs to
+  // about 16 significant bits at no extra matrix-core work (K is padded to 16 anyway)
+  {
+    uint16_t* row = sH + lane * MLP_HPITCH;
+#pragma unroll
+    for (int k = 0; k < MLP_NIN; ++k) {
+      const uint16_t hi = f2bf(x[k]);
+      row[k] = hi;
+      row[MLP_NIN + k] = f2bf(x[k] - bf2f(hi));
+    }
+    row[14] = 0;
+    row[15] = 0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int L = 0; L < 4; ++L) {
+    const int MT = MLP_MT[L], KS = MLP_KS[L];
+    f32x16_t acc[2][2];  // [point tile][M tile]
+#pragma unroll
+    for (int pt = 0; pt < 2; ++pt) {
+      bf16x8_t b[4];
+#pragma unroll
+      for (int t = 0; t < KS; ++t)
+        b[t] = *reinterpret_cast<const bf16x8_t*>(sH + (32 * pt + col) * MLP_HPITCH + 16 * t +
+                                                  8 * hl);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        f32x16_t c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                      0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < KS; ++t) {
+          const bf16x8_t a =
+              *reinterpret_cast<const bf16x8_t*>(sW + mlp_sw_index(L, m, t, lane, 0));
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[t], c, 0, 0, 0);
+        }
+        acc[pt][m] = c;
+      }
+    }
+    // all B reads of this layer are complete (their data fed the MFMAs); overwrite
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float* bias = sB + (L == 0 ? 0 : (L == 1 ? 64 : (L == 2 ? 128 : 192)));
+    if (L < 3) {
+#pragma unroll
+      for (int pt = 0; pt < 2; ++pt)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            // registers 4g..4g+3 hold four consecutive units i0..i0+3 of one point
+            const int i0 = 32 * m + 8 * g + 4 * hl;
+            const int pnt = 32 * pt + col;
+            float a[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = fast_tanh(acc[pt][m][4 * g + q] + bias[i0 + q]);
+            const uint32_t lo = (uint32_t)f2bf(a[0]) | ((uint32_t)f2bf(a[1]) << 16);
+            const uint32_t hi = (uint32_t)f2bf(a[2]) | ((uint32_t)f2bf(a[3]) << 16);
+            *reinterpret_cast<uint2*>(sH + pnt * MLP_HPITCH + i0) = make_uint2(lo, hi);
+            if (save) {
+              const long gp = base + pnt;
+              if (gp < ldn) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) save[((long)L * ldn + gp) * 64 + i0 + q] = a[q];
+              }
+            }
+          }
+    } else {
+      // outputs 0..7 live in registers r = 0..3 of both halves; stage through LDS as FP32
+      float* sO = reinterpret_cast<float*>(sH);
+#pragma unroll
+      for (int pt = 0; pt < 2; ++pt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = r + 4 * hl;
+          sO[(32 * pt + col) * 8 + i] = acc[pt][0][r] + bias[i];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  const float* sO = reinterpret_cast<const float*>(sH);
+#pragma unroll
+  for (int o = 0; o < MLP_NOUT; ++o) y[o] = sO[lane * 8 + o];
+  (void)valid;
+}
+
+// Cooperative copy of the swizzled weights and biases into LDS (whole block).
+__device__ __forceinline__ void mlp_load_lds(const uint16_t* __restrict__ gW,
+                                             const float* __restrict__ gB, uint16_t* sW,
+                                             float* sB) {
+  const uint4* src = reinterpret_cast<const uint4*>(gW);
+  uint4* dst = reinterpret_cast<uint4*>(sW);
+  for (int i = threadIdx.x; i < MLP_SW_SIZE / 8; i += blockDim.x) dst[i] = src[i];
+  for (int i = threadIdx.x; i < MLP_NBIAS; i += blockDim.x) sB[i] = gB[i];
+}
+
+// Standardisation statistics and training-domain bounds of the surrogate (device).
+struct MlpNorm {
+  float in_mean[MLP_NIN], in_std[MLP_NIN];
+  float out_mean[MLP_NOUT], out_std[MLP_NOUT];
+  double log10rho_min, log10rho_max;   // kg/m^3
+  double e_lo[5], e_hi[5];             // species energies at the T bounds (J/kg)
+};
+
+}  // namespace hrx

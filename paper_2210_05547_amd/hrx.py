@@ -19,6 +19,8 @@ GAS_CPG, GAS_AIR5 = 0, 1
 WALL_ADIABATIC, WALL_ISOTHERMAL = 0, 1
 RK3_2N, RK45_2N = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
+THERMO_PLAIN, THERMO_SURROGATE = 0, 1
+MLP_NPARAM = 9352
 
 HRX_OK = 0
 
@@ -87,6 +89,22 @@ def load(path: str = LIB_PATH):
     lib.hrx_timing_enable.restype = C.c_int
     lib.hrx_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.hrx_timing_read.restype = C.c_int
+    f32 = C.c_float
+    lib.hrx_mlp_init.argtypes = [vp, i64]
+    lib.hrx_mlp_set_params.argtypes = [vp, dp, vp]
+    lib.hrx_mlp_get_params.argtypes = [vp, dp, vp]
+    lib.hrx_mlp_set_norm.argtypes = [vp, C.POINTER(f32), C.POINTER(f32), C.POINTER(f32),
+                                     C.POINTER(f32), C.c_double, C.c_double, C.c_double,
+                                     C.c_double]
+    lib.hrx_set_thermo_mode.argtypes = [vp, C.c_int]
+    lib.hrx_mlp_forward.argtypes = [vp, i64, dp, dp, vp]
+    lib.hrx_mlp_backward.argtypes = [vp, i64, dp, dp, dp, vp]
+    lib.hrx_adam_step.argtypes = [vp, dp, f32, C.c_int, vp]
+    lib.hrx_mlp_train_step.argtypes = [vp, i64, dp, dp, dp, f32, C.c_int, dp, vp]
+    for fn in ("hrx_mlp_init", "hrx_mlp_set_params", "hrx_mlp_get_params", "hrx_mlp_set_norm",
+               "hrx_set_thermo_mode", "hrx_mlp_forward", "hrx_mlp_backward", "hrx_adam_step",
+               "hrx_mlp_train_step"):
+        getattr(lib, fn).restype = C.c_int
     lib.hrx_strerror.argtypes = [C.c_int]
     lib.hrx_strerror.restype = C.c_char_p
     _lib = lib
@@ -99,8 +117,11 @@ def _check(rc):
 
 
 def _ptr(t):
+    """Raw device pointer of a tensor; the C-ABI takes dense row-major arrays only."""
     if t is None:
         return None
+    if not t.is_contiguous():
+        raise HrxError("hrx arrays must be contiguous (row-major) tensors")
     return C.c_void_p(t.data_ptr())
 
 
@@ -175,7 +196,7 @@ class Context:
 
 
 KERNEL_NAMES = ("prim", "ad_src", "ad_d4", "ad_filter_x", "ad_filter_y", "ad_filter_z", "flux",
-                "div", "bc", "thermo_eval", "chem_source")
+                "div", "bc", "thermo_eval", "chem_source", "surrogate_net")
 
 
 def timing_enable(ctx, on=True):
@@ -209,3 +230,48 @@ def thermo_eval(ctx, n, rho, e, Y, T, p=None, h=None, mu=None, kappa=None, D=Non
 
 def chem_source(ctx, n, rho_s, T, wdot, stream=None):
     _check(_lib.hrx_chem_source(ctx._h, int(n), _ptr(rho_s), _ptr(T), _ptr(wdot), _stream(stream)))
+
+
+# ---------------------------------------------------------------- surrogate network
+def mlp_init(ctx, max_batch):
+    _check(_lib.hrx_mlp_init(ctx._h, int(max_batch)))
+
+
+def mlp_set_params(ctx, theta, stream=None):
+    _check(_lib.hrx_mlp_set_params(ctx._h, _ptr(theta), _stream(stream)))
+
+
+def mlp_get_params(ctx, theta_out, stream=None):
+    _check(_lib.hrx_mlp_get_params(ctx._h, _ptr(theta_out), _stream(stream)))
+
+
+def mlp_set_norm(ctx, in_mean, in_std, out_mean, out_std, log10rho_range, T_range):
+    def f(a, n):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        assert a.shape == (n,)
+        return a
+    arrs = [f(in_mean, 7), f(in_std, 7), f(out_mean, 8), f(out_std, 8)]
+    ptrs = [a.ctypes.data_as(C.POINTER(C.c_float)) for a in arrs]
+    _check(_lib.hrx_mlp_set_norm(ctx._h, *ptrs, float(log10rho_range[0]), float(log10rho_range[1]),
+                                 float(T_range[0]), float(T_range[1])))
+
+
+def set_thermo_mode(ctx, mode):
+    _check(_lib.hrx_set_thermo_mode(ctx._h, int(mode)))
+
+
+def mlp_forward(ctx, n, X, Y, stream=None):
+    _check(_lib.hrx_mlp_forward(ctx._h, int(n), _ptr(X), _ptr(Y), _stream(stream)))
+
+
+def mlp_backward(ctx, n, X, dLdY, grad, stream=None):
+    _check(_lib.hrx_mlp_backward(ctx._h, int(n), _ptr(X), _ptr(dLdY), _ptr(grad), _stream(stream)))
+
+
+def adam_step(ctx, grad, lr, t, stream=None):
+    _check(_lib.hrx_adam_step(ctx._h, _ptr(grad), float(lr), int(t), _stream(stream)))
+
+
+def mlp_train_step(ctx, n, idx, X, Yt, lr, t, loss=None, stream=None):
+    _check(_lib.hrx_mlp_train_step(ctx._h, int(n), _ptr(idx), _ptr(X), _ptr(Yt), float(lr), int(t),
+                                   _ptr(loss), _stream(stream)))

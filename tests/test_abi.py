@@ -46,3 +46,12 @@ def test_binding_refuses_missing_library(tmp_path):
             hrx.load(str(tmp_path / "missing.so"))
         finally:
             hrx._lib = hrx._lib_backup
+
+
+def test_binding_refuses_non_contiguous_arrays():
+    import torch
+    from paper_2210_05547_amd import hrx
+    t = torch.zeros((4, 3), dtype=torch.float64).t()
+    with pytest.raises(hrx.HrxError):
+        hrx._ptr(t)
+    assert hrx._ptr(None) is None

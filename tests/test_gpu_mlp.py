@@ -1,0 +1,121 @@
+"""Surrogate-network kernels through the C-ABI against the oracle's FP64 network.
+
+Forward: BF16 matrix-core inference vs the oracle forward with the same BF16-rounded
+weights and layer inputs.  Backward: FP32 gradient kernels vs the oracle backward on
+the same rounded operands.  Differences come from FP32 accumulation order and the
+fast tanh (~1e-7) and from the rare BF16 rounding decisions they flip (one BF16 ulp,
+0.4 %, of a hidden activation); the bars below leave room for those and nothing
+else.  Adam: one step vs the oracle's closed form.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2210_05547_amd import fields, hrx  # noqa: E402
+from oracle import mlp as omlp  # noqa: E402
+from gpu_util import normwise  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def ctx_with_params(theta, maxb=4096):
+    cfg = fields.get_config("c2").scaled(16, 16)
+    x, y, z = fields.grid(cfg)
+    ctx = hrx.Context(cfg, x, y, z)
+    hrx.mlp_init(ctx, maxb)
+    hrx.mlp_set_params(ctx, torch.from_numpy(theta.astype(np.float32)).to(DEV))
+    return ctx
+
+
+def params(seed=3):
+    th = omlp.init_params(seed) + 0.05 * np.random.default_rng(seed).standard_normal(omlp.NPARAM)
+    return th.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 1000, 20000])
+def test_forward_parity(n):
+    print("mlp forward n =", n, flush=True)
+    th = params()
+    ctx = ctx_with_params(th)
+    X = np.random.default_rng(n).standard_normal((n, 7)).astype(np.float32)
+    Yd = torch.empty((n, 8), dtype=torch.float32, device=DEV)
+    hrx.mlp_forward(ctx, n, torch.from_numpy(X).to(DEV), Yd)
+    torch.cuda.synchronize()
+    ref, _ = omlp.forward(th, X.astype(np.float64), bf16=True)
+    err = normwise(Yd.cpu().numpy(), ref)
+    print("  forward normwise error %.2e" % err, flush=True)
+    assert err <= 2e-3
+
+
+@pytest.mark.parametrize("n", [7, 256, 4096])
+def test_backward_parity(n):
+    print("mlp backward n =", n, flush=True)
+    th = params(5)
+    ctx = ctx_with_params(th)
+    rng = np.random.default_rng(n + 1)
+    X = rng.standard_normal((n, 7)).astype(np.float32)
+    dY = (rng.standard_normal((n, 8)) / n).astype(np.float32)
+    g = torch.empty(omlp.NPARAM, dtype=torch.float32, device=DEV)
+    hrx.mlp_backward(ctx, n, torch.from_numpy(X).to(DEV), torch.from_numpy(dY).to(DEV), g)
+    torch.cuda.synchronize()
+    _, acts = omlp.forward(th, X.astype(np.float64), bf16=True)
+    ref = omlp.backward(th, acts, dY.astype(np.float64), bf16=True)
+    gg = g.cpu().numpy()
+    err = normwise(gg, ref)
+    errs = [normwise(gg[a:b], ref[a:b]) for a, b in
+            [(0, 448), (512, 512 + 4096), (4672, 4672 + 4096), (8832, 8832 + 512)]]
+    print("  gradient normwise error %.2e per layer" % err, ["%.1e" % e for e in errs], flush=True)
+    assert err <= 2e-3
+
+
+def test_adam_step_parity():
+    th = params(7)
+    ctx = ctx_with_params(th)
+    g = np.random.default_rng(1).standard_normal(omlp.NPARAM).astype(np.float32)
+    gd = torch.from_numpy(g).to(DEV)
+    for t in (1, 2):
+        hrx.adam_step(ctx, gd, 1e-3, t)
+    out = torch.empty(omlp.NPARAM, dtype=torch.float32, device=DEV)
+    hrx.mlp_get_params(ctx, out)
+    torch.cuda.synchronize()
+    m = np.zeros(omlp.NPARAM)
+    v = np.zeros(omlp.NPARAM)
+    ref = th.copy()
+    for t in (1, 2):
+        ref, m, v = omlp.adam(ref, g.astype(np.float64), m, v, t, 1e-3)
+    # the FP32 master parameters (|theta| < 0.5) resolve the 2e-3 step to about
+    # 2^-24 * 0.5 / 2e-3 = 1.5e-5 relative
+    assert normwise(out.cpu().numpy() - th, ref - th) <= 5e-5
+
+
+def test_train_step_parity():
+    """One fused train step (forward, MSE gradient, backward, Adam) on gathered rows
+    equals the oracle's sequence of the same operations."""
+    th = params(9)
+    ctx = ctx_with_params(th)
+    rng = np.random.default_rng(4)
+    n_all, n = 5000, 512
+    X = rng.standard_normal((n_all, 7)).astype(np.float32)
+    Yt = rng.standard_normal((n_all, 8)).astype(np.float32)
+    idx = rng.permutation(n_all)[:n].astype(np.int32)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    hrx.mlp_train_step(ctx, n, torch.from_numpy(idx).to(DEV), torch.from_numpy(X).to(DEV),
+                       torch.from_numpy(Yt).to(DEV), 1e-3, 1, loss)
+    out = torch.empty(omlp.NPARAM, dtype=torch.float32, device=DEV)
+    hrx.mlp_get_params(ctx, out)
+    torch.cuda.synchronize()
+    Xb = X[idx].astype(np.float64)
+    Yh, acts = omlp.forward(th, Xb, bf16=True)
+    L, dY = omlp.mse_grad(Yh, Yt[idx].astype(np.float64))
+    g = omlp.backward(th, acts, dY, bf16=True)
+    ref, _, _ = omlp.adam(th, g, np.zeros_like(th), np.zeros_like(th), 1, 1e-3)
+    print("  loss gpu %.6f oracle %.6f" % (float(loss.item()), L), flush=True)
+    assert abs(float(loss.item()) - L) <= 1e-3 * L
+    step_err = normwise(out.cpu().numpy() - th, ref - th)
+    print("  step error %.2e" % step_err, flush=True)
+    # Adam's first step is lr * sign(g) except where |g| is tiny: compare where |g| is
+    # well above the rounding noise of the gradient
+    big = np.abs(g) > 1e-3 * np.max(np.abs(g))
+    assert normwise((out.cpu().numpy() - th)[big], (ref - th)[big]) <= 1e-3

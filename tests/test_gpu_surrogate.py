@@ -1,0 +1,231 @@
+"""Learned thermochemistry surrogate: training on the GPU with the library's own
+kernels, accuracy against the plain evaluation, hull fallback, the right-hand side
+with the surrogate, and what the network gains over the plain evaluation.
+
+Data: 10^6 oracle states (T ~ U(200, 8000) K, rho ~ 10^U(-4, 0) kg/m^3, Y ~
+Dirichlet(1,...,1)); 90 % train, 10 % held out.  Bars: the FP64 energy inversion
+keeps T at 1e-12; network transport within 1e-2 relative per point on held-out
+states (max) and the RHS with surrogate transport within 1e-3 normwise per field of
+the plain FP64 RHS; out-of-hull points reproduce the plain evaluation to 1e-12.
+"""
+import json
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2210_05547_amd import fields, hrx  # noqa: E402
+from oracle import mlp as omlp  # noqa: E402
+from oracle import rhs as orhs  # noqa: E402
+from oracle import thermo as oth  # noqa: E402
+from oracle import transport as otr  # noqa: E402
+from gpu_util import field_errors, normwise  # noqa: E402
+from surrogate_util import LOGRHO_RANGE, T_RANGE, raw_dataset, standardise  # noqa: E402
+
+DEV = "cuda:0"
+NTOT = 1_000_000
+BATCH = 4096
+EPOCHS = int(os.environ.get("HRX_SURROGATE_EPOCHS", "100"))
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+REPORT = {}
+
+
+def report(k, v):
+    REPORT[k] = v
+    print(" ", k, v, flush=True)
+    if os.path.isdir(OUT):
+        with open(os.path.join(OUT, "surrogate_report.json"), "w") as f:
+            json.dump(REPORT, f, indent=1)
+
+
+def air_ctx(cfg=None, hold=None):
+    cfg = cfg or fields.get_config("c2").scaled(16, 16)
+    x, y, z = fields.grid(cfg)
+    return hrx.Context(cfg, x, y, z, hold)
+
+
+@pytest.fixture(scope="module")
+def trained():
+    t0 = time.time()
+    X, Yt, raw = raw_dataset(NTOT, seed=20221011 + 5)
+    ntr = int(0.9 * NTOT)
+    xm, xs, ym, ys = standardise(X[:ntr], Yt[:ntr])
+    Xs = ((X - xm) / xs).astype(np.float32)
+    Ys = ((Yt - ym) / ys).astype(np.float32)
+    report("oracle_dataset_seconds", round(time.time() - t0, 1))
+    ctx = air_ctx()
+    hrx.mlp_init(ctx, BATCH)
+    theta0 = omlp.init_params(11).astype(np.float32)
+    hrx.mlp_set_params(ctx, torch.from_numpy(theta0).to(DEV))
+    Xd = torch.from_numpy(Xs).to(DEV)
+    Yd = torch.from_numpy(Ys).to(DEV)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    rng = np.random.default_rng(0)
+    steps_per_epoch = ntr // BATCH
+    total = EPOCHS * steps_per_epoch
+    lr0, t = 2e-3, 0
+    hist = []
+    torch.cuda.synchronize()
+    t1 = time.time()
+    for ep in range(EPOCHS):
+        perm = torch.from_numpy(rng.permutation(ntr).astype(np.int32)).to(DEV)
+        loss.zero_()
+        for b in range(steps_per_epoch):
+            t += 1
+            lr = lr0 * 0.5 * (1.0 + math.cos(math.pi * t / total)) + 1e-6
+            hrx.mlp_train_step(ctx, BATCH, perm[b * BATCH:(b + 1) * BATCH], Xd, Yd, lr, t, loss)
+        hist.append(float(loss.item()) / steps_per_epoch)
+    torch.cuda.synchronize()
+    report("train_seconds_gpu", round(time.time() - t1, 2))
+    report("train_loss_first_last", [hist[0], hist[-1]])
+    hrx.mlp_set_norm(ctx, xm, xs, ym, ys, LOGRHO_RANGE, T_RANGE)
+    theta = torch.empty(hrx.MLP_NPARAM, dtype=torch.float32, device=DEV)
+    hrx.mlp_get_params(ctx, theta)
+    held = slice(ntr, NTOT)
+    return dict(ctx=ctx, theta=theta, norm=(xm, xs, ym, ys), hist=hist, Xs=Xs, Ys=Ys, raw=raw,
+                held=held, ntr=ntr)
+
+
+def with_surrogate(ctx, tr):
+    hrx.mlp_init(ctx, 16)
+    hrx.mlp_set_params(ctx, tr["theta"])
+    xm, xs, ym, ys = tr["norm"]
+    hrx.mlp_set_norm(ctx, xm, xs, ym, ys, LOGRHO_RANGE, T_RANGE)
+    hrx.set_thermo_mode(ctx, hrx.THERMO_SURROGATE)
+    return ctx
+
+
+def test_training_reduces_loss(trained):
+    h = trained["hist"]
+    assert h[-1] < 0.05 * h[0]
+    # where the remaining error sits: the trained weights in FP64 without BF16 rounding
+    th = trained["theta"].cpu().numpy().astype(np.float64)
+    Xh, Yh = trained["Xs"][trained["held"]][:50000], trained["Ys"][trained["held"]][:50000]
+    for bf in (False, True):
+        out, _ = omlp.forward(th, Xh.astype(np.float64), bf16=bf)
+        report("held_out_rms_standardised_bf16_%s" % bf,
+               [float(v) for v in np.sqrt(np.mean((out - Yh) ** 2, axis=0))])
+
+
+def test_network_matches_oracle_network(trained):
+    """The trained parameters give the same outputs through the matrix cores as
+    through the oracle's network (BF16 operands) on held-out inputs."""
+    Xh = trained["Xs"][trained["held"]][:20000]
+    Yd = torch.empty((len(Xh), 8), dtype=torch.float32, device=DEV)
+    hrx.mlp_forward(trained["ctx"], len(Xh), torch.from_numpy(Xh).to(DEV), Yd)
+    ref, _ = omlp.forward(trained["theta"].cpu().numpy().astype(np.float64), Xh.astype(np.float64),
+                          bf16=True)
+    assert normwise(Yd.cpu().numpy(), ref) <= 2e-3
+
+
+def _thermo(ctx, raw, sel):
+    n = len(raw["rho"][sel])
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)  # noqa: E731
+    T = torch.empty(n, dtype=torch.float64, device=DEV)
+    mu, ka = torch.empty_like(T), torch.empty_like(T)
+    D = torch.empty((5, n), dtype=torch.float64, device=DEV)
+    st = torch.empty(n, dtype=torch.int32, device=DEV)
+    hrx.thermo_eval(ctx, n, d(raw["rho"][sel]), d(raw["e"][sel]), d(raw["Y"][:, sel]), T,
+                    mu=mu, kappa=ka, D=D, status=st)
+    torch.cuda.synchronize()
+    return T.cpu().numpy(), mu.cpu().numpy(), ka.cpu().numpy(), D.cpu().numpy(), st.cpu().numpy()
+
+
+def test_surrogate_thermo_accuracy_held_out(trained):
+    raw = trained["raw"]
+    sel = np.arange(trained["ntr"], NTOT)
+    ctx = trained["ctx"]
+    hrx.set_thermo_mode(ctx, hrx.THERMO_SURROGATE)
+    ctx.counters(reset=True)
+    T, mu, ka, D, st = _thermo(ctx, raw, sel)
+    c = ctx.counters(reset=True)
+    hrx.set_thermo_mode(ctx, hrx.THERMO_PLAIN)
+    rel = lambda a, b: np.abs(a / b - 1.0)  # noqa: E731
+    e_mu, e_ka = rel(mu, raw["mu"][sel]), rel(ka, raw["kappa"][sel])
+    e_D = rel(D, raw["D"][:, sel])
+    report("held_out_T_normwise", normwise(T, raw["T"][sel]))
+    report("held_out_rel_err_max", dict(mu=float(e_mu.max()), kappa=float(e_ka.max()),
+                                        D=float(e_D.max())))
+    report("held_out_rel_err_rms", dict(mu=float(np.sqrt(np.mean(e_mu ** 2))),
+                                        kappa=float(np.sqrt(np.mean(e_ka ** 2))),
+                                        D=float(np.sqrt(np.mean(e_D ** 2)))))
+    report("held_out_fallbacks", int(c["surrogate_fallbacks"]))
+    assert np.all(st == 0)
+    assert normwise(T, raw["T"][sel]) <= 1e-12
+    assert max(e_mu.max(), e_ka.max(), e_D.max()) <= 1e-2
+
+
+def test_out_of_hull_falls_back_to_plain(trained):
+    ctx = trained["ctx"]
+    n = 1000
+    rho, T0, Y, _ = fields.thermo_states(n, seed=99, T_range=(9000.0, 12000.0))
+    rho = rho * 3.0          # part of them also above the density range
+    e = oth.mixture_e(T0, Y)
+    raw = dict(rho=rho, e=e, Y=Y)
+    hrx.set_thermo_mode(ctx, hrx.THERMO_SURROGATE)
+    ctx.counters(reset=True)
+    T, mu, ka, D, st = _thermo(ctx, raw, slice(0, n))
+    c = ctx.counters(reset=True)
+    hrx.set_thermo_mode(ctx, hrx.THERMO_PLAIN)
+    assert c["surrogate_fallbacks"] == n
+    Tr, _, _ = oth.temperature_from_energy(e, Y)
+    p, mur, kr, Dr = otr.air5_properties(rho, Tr, Y)
+    assert normwise(T, Tr) <= 1e-12 and normwise(mu, mur) <= 1e-12 and normwise(ka, kr) <= 1e-12
+    for s in range(5):
+        assert normwise(D[s], Dr[s]) <= 1e-12
+
+
+def test_rhs_with_surrogate_on_sbli_field(trained):
+    cfg = fields.get_config("c3").scaled(512, 128)
+    Q, Qr, info = fields.initial_field(cfg)
+    ctx = with_surrogate(air_ctx(cfg, info["hold"]), trained)
+    Qd = torch.from_numpy(Q).to(DEV)
+    Rd = torch.empty_like(Qd)
+    ctx.counters(reset=True)
+    hrx.rhs_eval(ctx, Qd, torch.from_numpy(Qr).to(DEV), Rd)
+    c = ctx.counters(reset=True)
+    case = orhs.Case(cfg, info["x"], info["y"], info["z"], info["hold"])
+    R = orhs.rhs(Q, Qr, case)
+    errs = field_errors(Rd.cpu().numpy(), R)
+    report("sbli_512x128_rhs_errors_surrogate", [float(e) for e in errs])
+    report("sbli_512x128_in_hull_fraction", 1.0 - c["surrogate_fallbacks"] / cfg.npts)
+    assert max(errs) <= 1e-3
+
+
+def test_surrogate_gain_over_plain(trained):
+    """Throughput of the pointwise thermochemistry (T, p, h, mu, kappa, D) on 2^21
+    held-out-like states: plain FP64 evaluation vs the network, at the errors above."""
+    n = 1 << 21
+    rho, T0, Y, _ = fields.thermo_states(n, seed=123, T_range=T_RANGE, logrho_range=LOGRHO_RANGE)
+    e = oth.mixture_e(T0, Y)
+    ctx = trained["ctx"]
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)  # noqa: E731
+    rd, ed, Yd = d(rho), d(e), d(Y)
+    T = torch.empty(n, dtype=torch.float64, device=DEV)
+    p, mu, ka = torch.empty_like(T), torch.empty_like(T), torch.empty_like(T)
+    h = torch.empty((5, n), dtype=torch.float64, device=DEV)
+    D = torch.empty((5, n), dtype=torch.float64, device=DEV)
+    res = {}
+    for mode in (hrx.THERMO_PLAIN, hrx.THERMO_SURROGATE):
+        hrx.set_thermo_mode(ctx, mode)
+        for _ in range(2):
+            hrx.thermo_eval(ctx, n, rd, ed, Yd, T, p, h, mu, ka, D)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(10):
+            hrx.thermo_eval(ctx, n, rd, ed, Yd, T, p, h, mu, ka, D)
+        b.record()
+        torch.cuda.synchronize()
+        res[mode] = a.elapsed_time(b) / 10
+    hrx.set_thermo_mode(ctx, hrx.THERMO_PLAIN)
+    gain = res[hrx.THERMO_PLAIN] / res[hrx.THERMO_SURROGATE]
+    report("thermo_eval_ms_plain_fp64", res[hrx.THERMO_PLAIN])
+    report("thermo_eval_ms_surrogate", res[hrx.THERMO_SURROGATE])
+    report("thermo_eval_Mpts_per_s", dict(plain=n / res[0] / 1e3, surrogate=n / res[1] / 1e3))
+    report("surrogate_gain", gain)
+    assert gain > 1.0

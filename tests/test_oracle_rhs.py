@@ -280,3 +280,11 @@ def test_bf16_rounding_and_adam():
     g = np.array([0.5, -4.0])
     t1, m, vv = mlp.adam(th, g, np.zeros(2), np.zeros(2), 1, 0.1)
     assert np.allclose(t1, th - 0.1 * g / (np.abs(g) + 1e-8), rtol=1e-14)
+
+
+def test_split_bf16_inputs():
+    x = np.array([1.0 + 2 ** -9, 3.14159265, -2.5e6, 1e-3], dtype=np.float32)
+    s = mlp.to_split_bf16(x)
+    # two bfloat16 terms carry 16 significand bits
+    assert np.all(np.abs(s - x.astype(np.float64)) <= 2.0 ** -16 * np.abs(x.astype(np.float64)))
+    assert np.all(s == mlp.to_bf16(x) + mlp.to_bf16(x - mlp.to_bf16(x).astype(np.float32)))
