@@ -103,24 +103,32 @@ def main():
     Qd = torch.from_numpy(Q).to(dev)
     Qrd = torch.from_numpy(Qr).to(dev)
     dQd = torch.zeros_like(Qd)
+    # a non-null stream lets the library replay each stage as a captured HIP graph
+    stream = torch.cuda.Stream()
     stage = 0
-    for _ in range(args.warmup):
-        hrx.rk_stage(ctx, stage, info["dt"], Qd, dQd, Qrd)
-        stage += 1
-    torch.cuda.synchronize()
-    hrx.timing_enable(ctx, True)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(args.steps):
-        hrx.rk_stage(ctx, stage, info["dt"], Qd, dQd, Qrd)
-        stage += 1
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
-    kt = hrx.timing_read(ctx)
-    hrx.timing_enable(ctx, False)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            hrx.rk_stage(ctx, stage, info["dt"], Qd, dQd, Qrd)
+            stage += 1
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(args.steps):
+            hrx.rk_stage(ctx, stage, info["dt"], Qd, dQd, Qrd)
+            stage += 1
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        # per-kernel HIP-event durations: the same stages again with direct launches
+        # bracketed by events on this stream (graph replay is off while timing)
+        hrx.timing_enable(ctx, True)
+        for _ in range(args.steps):
+            hrx.rk_stage(ctx, stage, info["dt"], Qd, dQd, Qrd)
+            stage += 1
+        torch.cuda.synchronize()
+        kt = hrx.timing_read(ctx)
+        hrx.timing_enable(ctx, False)
     cnt = ctx.counters()
     finite = bool(torch.isfinite(Qd).all())
     value = cfg.npts * args.steps / (ms * 1e-3) / 1e6

@@ -46,8 +46,10 @@ struct Dev {
   const unsigned char *hold;      // [nz][3][nx] or null
   unsigned long long *counters;   // [0] Newton non-converged, [1] below e(T_min)
   // W plane offsets
-  int nsrc, w_p, w_mu, w_kap, w_D, w_wdot, w_c;
+  int nsrc, w_p, w_mu, w_kap, w_D, w_wdot, w_h, w_c;
   int nad;                        // artificial-diffusivity planes (3 + ns)
+  int gx;                         // x segments of TX points per grid row
+  int tgx, tgy;                   // 2-D LDS tiles per row / column
   int warm;                       // W holds a previous temperature field (Newton warm start)
 };
 
@@ -108,10 +110,170 @@ __device__ __forceinline__ TA dper(const TD* __restrict__ f, long idx, long s, i
   return acc;
 }
 
+// The 8 XCDs of the chip take workgroups round-robin (workgroup b goes to XCD b mod 8).
+// Stencil kernels remap b so that each XCD sweeps one contiguous band of grid rows:
+// the y (and z) neighbours a tile reads are then mostly in that XCD's own L2.
+__device__ __forceinline__ long xcd_block() {
+  const long b = blockIdx.x, nb = gridDim.x;
+  const long per = nb >> 3;
+  if (b >= (per << 3)) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Branch-free form of the same first-derivative operators: D f = sum_m a_m (f[p_m] - f[q_m])
+// over at most four pairs.  The pairs depend only on the position along the line, so
+// one Sten serves every field at a point and all field loads can be issued together.
+//   interior (6th): (i+1,i-1, 3/4), (i+2,i-2, -3/20), (i+3,i-3, 1/60)
+//   interior (4th) and points 2, n-3 of the 6th-order operator: (i+1,i-1, 2/3), (i+2,i-2, -1/12)
+//   point 0: (m, 0, b0_m) for m = 1..4; point 1: (m, 1, b1_m) for m = 0, 2, 3, 4
+//   (the closure weights sum to zero, so they act on differences to the point itself);
+//   points n-1, n-2: mirror images with the sign flipped.
+struct Sten {
+  long p[4], q[4];
+  double a[4];
+};
+
+template <int ORDER>
+__device__ __forceinline__ Sten make_sten(long idx, long s, int i, int n) {
+  Sten t;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    t.p[m] = idx;
+    t.q[m] = idx;
+    t.a[m] = 0.0;
+  }
+  const bool c6 = ORDER == 6 && i >= 3 && i <= n - 4;
+  const bool c4 = (ORDER == 4 && i >= 2 && i <= n - 3) ||
+                  (ORDER == 6 && (i == 2 || i == n - 3));
+  if (c6) {
+    t.p[0] = idx + s; t.q[0] = idx - s; t.a[0] = 0.75;
+    t.p[1] = idx + 2 * s; t.q[1] = idx - 2 * s; t.a[1] = -0.15;
+    t.p[2] = idx + 3 * s; t.q[2] = idx - 3 * s; t.a[2] = 1.0 / 60.0;
+  } else if (c4) {
+    t.p[0] = idx + s; t.q[0] = idx - s; t.a[0] = 2.0 / 3.0;
+    t.p[1] = idx + 2 * s; t.q[1] = idx - 2 * s; t.a[1] = -1.0 / 12.0;
+  } else if (i == 0 || i == n - 1) {
+    const long sg = i == 0 ? s : -s;
+    const double f = i == 0 ? 1.0 : -1.0;
+    t.p[0] = idx + sg; t.a[0] = f * 4.0;
+    t.p[1] = idx + 2 * sg; t.a[1] = f * -3.0;
+    t.p[2] = idx + 3 * sg; t.a[2] = f * (4.0 / 3.0);
+    t.p[3] = idx + 4 * sg; t.a[3] = f * -0.25;
+  } else {  // i == 1 or i == n - 2
+    const long sg = i == 1 ? s : -s;
+    const double f = i == 1 ? 1.0 : -1.0;
+    t.p[0] = idx - sg; t.a[0] = f * -0.25;
+    t.p[1] = idx + sg; t.a[1] = f * 1.5;
+    t.p[2] = idx + 2 * sg; t.a[2] = f * -0.5;
+    t.p[3] = idx + 3 * sg; t.a[3] = f * (1.0 / 12.0);
+  }
+  return t;
+}
+
+template <int ORDER>
+__device__ __forceinline__ Sten make_sten_per(long idx, long s, int i, int n) {
+  Sten t;
+  const long base = idx - (long)i * s;
+  auto at = [&](int m) {
+    int q = i + m;
+    q = q < 0 ? q + n : (q >= n ? q - n : q);
+    return base + (long)q * s;
+  };
+  t.p[3] = idx; t.q[3] = idx; t.a[3] = 0.0;
+  if (ORDER == 6) {
+    t.p[0] = at(1); t.q[0] = at(-1); t.a[0] = 0.75;
+    t.p[1] = at(2); t.q[1] = at(-2); t.a[1] = -0.15;
+    t.p[2] = at(3); t.q[2] = at(-3); t.a[2] = 1.0 / 60.0;
+  } else {
+    t.p[0] = at(1); t.q[0] = at(-1); t.a[0] = 2.0 / 3.0;
+    t.p[1] = at(2); t.q[1] = at(-2); t.a[1] = -1.0 / 12.0;
+    t.p[2] = idx; t.q[2] = idx; t.a[2] = 0.0;
+  }
+  return t;
+}
+
+// differences in the storage type TD, weighted sum in the arithmetic type TA; NP = number
+// of pairs used (interior points of the 6th/4th-order operators need 3/2, closures 4)
+template <class TA, int NP = 4, class TD>
+__device__ __forceinline__ TA sten_apply(const Sten& t, const TD* __restrict__ f) {
+  TD d[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) d[m] = f[t.p[m]] - f[t.q[m]];
+  TA acc = TA(t.a[0]) * TA(d[0]);
+#pragma unroll
+  for (int m = 1; m < NP; ++m) acc += TA(t.a[m]) * TA(d[m]);
+  return acc;
+}
+
+// true when the point is interior to every non-periodic line (central stencil only)
+template <int ORDER>
+__device__ __forceinline__ bool interior_point(const Dev& d, int i, int j) {
+  const int h = ORDER == 6 ? 3 : 2;
+  return i >= h && i <= d.nx - 1 - h && j >= h && j <= d.ny - 1 - h;
+}
+
 struct Pt {
   long idx;
   int i, j, k;
 };
+
+// Stencil kernels run on a grid of gx * ny * nz blocks of 128 threads, block = 128
+// consecutive x points of one grid row (gx = ceil(nx / 128)); blockIdx.y, when used,
+// selects a field component.  The XCD-aware block number is decomposed into
+// (x segment, row j, plane k) with 32-bit arithmetic.
+constexpr int TX = 128;
+
+__device__ __forceinline__ bool grid_point(const Dev& d, Pt& p) {
+  const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
+  const unsigned per = nb >> 3;
+  const unsigned L = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
+  const unsigned gx = (unsigned)d.gx;
+  const unsigned r = L / gx;
+  p.i = (int)((L - r * gx) * TX + threadIdx.x);
+  p.j = (int)(r % (unsigned)d.ny);
+  p.k = (int)(r / (unsigned)d.ny);
+  p.idx = ((long)p.k * d.ny + p.j) * d.nx + p.i;
+  return p.i < d.nx;
+}
+
+// 2-D stencil tiles staged through LDS: a block of 256 threads owns TTX x TTY points
+// and loads its source planes with a halo of 4 on each side (TW x TH values per plane;
+// 4 = the reach of the one-sided closures from an end point) in one pass of
+// independent loads before a single barrier; halo values outside the domain are
+// clamped copies that the closures never use.
+constexpr int TTX = 64, TTY = 4, THALO = 4;
+constexpr int TW = TTX + 2 * THALO, TH = TTY + 2 * THALO, TILE_E = TW * TH;
+constexpr int FXE = TTY * TW, FYE = TH * TTX;   // flux tiles: x halo only, y halo only
+constexpr int KCH = 4;                          // flux components staged per LDS pass
+
+// Stage TOTAL values into LDS: element e comes from src_of(e).  Every thread first issues
+// all of its global loads (held in registers), then writes them, so the loads of a
+// thread are in flight together instead of one round trip per element.
+template <int TOTAL, int NTHREADS, class SrcOf>
+__device__ __forceinline__ void stage_tile(double* __restrict__ dst, SrcOf src_of) {
+  constexpr int PER = (TOTAL + NTHREADS - 1) / NTHREADS;
+  double v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NTHREADS;
+    v[q] = (e < TOTAL) ? src_of(e) : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NTHREADS;
+    if (e < TOTAL) dst[e] = v[q];
+  }
+}
+
+__device__ __forceinline__ void tile_origin(const Dev& d, int& i0, int& j0) {
+  const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
+  const unsigned per = nb >> 3;
+  const unsigned L = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
+  const unsigned tgx = (unsigned)d.tgx;
+  const unsigned by = L / tgx;
+  i0 = (int)(L - by * tgx) * TTX;
+  j0 = (int)by * TTY;
+}
 
 __device__ __forceinline__ Pt point_of(const Dev& d, long idx) {
   Pt p;
@@ -239,6 +401,9 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   const double wscale = d.L_ref / (d.rho_inf * d.c_inf);
 #pragma unroll
   for (int s = 0; s < NS; ++s) Wp[(d.w_wdot + s) * N + idx] = RT(double(wd[s]) * wscale);
+  // species enthalpies h_s = e_s + R_s T (nondimensional) for the diffusive heat flux
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Wp[(d.w_h + s) * N + idx] = RT((st.e[s] + gas_const(s) * Tk) / c2);
   if (d.ad_on) {
     double cv = 0.0;
 #pragma unroll
@@ -254,15 +419,28 @@ template <int GAS, int ND, int ORDER, class RT>
 __global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict__ Q,
                                                 const double* __restrict__ Wd,
                                                 RT* __restrict__ A) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= d.N) return;
+  Pt p;
+  if (!grid_point(d, p)) return;
+  const long idx = p.idx;
   const long N = d.N;
-  const Pt p = point_of(d, idx);
+  Sten sd[3];
+  RT md[3];
+  sd[0] = make_sten<ORDER>(idx, 1, p.i, d.nx);
+  md[0] = RT(d.mx[p.i]);
+  sd[1] = make_sten<ORDER>(idx, d.nx, p.j, d.ny);
+  md[1] = RT(d.my[p.j]);
+  if (ND == 3) {
+    sd[2] = make_sten_per<ORDER>(idx, (long)d.nx * d.ny, p.k, d.nz);
+    md[2] = RT(d.mz[p.k]);
+  }
+  constexpr int NPI = ORDER == 6 ? 3 : 2;
   RT G[3][3];
 #pragma unroll
   for (int a = 0; a < ND; ++a)
 #pragma unroll
-    for (int b = 0; b < ND; ++b) G[a][b] = dphys<ORDER, RT>(d, Wd + a * N, p, b);
+    for (int b = 0; b < ND; ++b)
+      G[a][b] = (b == 2 ? sten_apply<RT, NPI>(sd[b], Wd + a * N)
+                        : sten_apply<RT>(sd[b], Wd + a * N)) * md[b];
   RT s2 = RT(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a)
@@ -321,10 +499,10 @@ __device__ __forceinline__ RT d4per(const RT* __restrict__ f, long idx, long s, 
 template <int GAS, int ND, class RT>
 __global__ __launch_bounds__(128) void k_ad_d4(Dev d, const RT* __restrict__ A,
                                                RT* __restrict__ B) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= d.N) return;
+  Pt p;
+  if (!grid_point(d, p)) return;
+  const long idx = p.idx;
   const long N = d.N;
-  const Pt p = point_of(d, idx);
   const RT dl[3] = {RT(d.dlx[p.i]), RT(d.dly[p.j]), ND == 3 ? RT(d.dlz[p.k]) : RT(1)};
   RT dbar;
   if (ND == 2)
@@ -365,10 +543,10 @@ __constant__ double c_gauss9[5] = {3565.0 / 10368.0, 3091.0 / 12960.0, 1997.0 / 
 template <int DIR, class RT>
 __global__ __launch_bounds__(128) void k_ad_filter(Dev d, const RT* __restrict__ in,
                                                    RT* __restrict__ out) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= d.N) return;
+  Pt p;
+  if (!grid_point(d, p)) return;
+  const long idx = p.idx;
   const long N = d.N;
-  const Pt p = point_of(d, idx);
   const int i = DIR == 0 ? p.i : (DIR == 1 ? p.j : p.k);
   const int n = DIR == 0 ? d.nx : (DIR == 1 ? d.ny : d.nz);
   const long s = DIR == 0 ? 1 : (DIR == 1 ? (long)d.nx : (long)d.nx * d.ny);
@@ -404,24 +582,71 @@ __global__ __launch_bounds__(128) void k_ad_filter(Dev d, const RT* __restrict__
 // ------------------------------------------------------------------ k_flux
 // F planes (double): F[j][k] for direction j and conserved component k.  Convective
 // fluxes are formed in FP64; stresses, heat and diffusion fluxes in RT.
-template <int GAS, int ND, int ORDER, bool AD, class RT>
-__global__ __launch_bounds__(128) void k_flux(Dev d, const double* __restrict__ Q,
+template <int GAS, int ND, int ORDER, bool AD, class RT, bool TILED>
+__global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ Q,
                                               const double* __restrict__ Wd,
                                               const RT* __restrict__ Wp,
                                               const RT* __restrict__ Gad, double* __restrict__ F) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= d.N) return;
-  const long N = d.N;
-  const Pt p = point_of(d, idx);
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
+  constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);   // u, v, (w), T, (X_s)
+  extern __shared__ double smem[];
+  const long N = d.N;
+  Pt p;
+  long sidx;                // index of the point in the source planes (global or tile)
+  const double* src;        // source planes: Wd, or the LDS tile
+  long splane;              // distance between source planes
+  Sten sd[3];
+  if (TILED) {
+    int i0, j0;
+    tile_origin(d, i0, j0);
+    stage_tile<NSRC * TILE_E, TTX * TTY>(smem, [&](int e) {
+      const int v = e / TILE_E, r = e - v * TILE_E;
+      const int ly = r / TW, lx = r - ly * TW;
+      const int gi = min(max(i0 + lx - THALO, 0), d.nx - 1);
+      const int gj = min(max(j0 + ly - THALO, 0), d.ny - 1);
+      return Wd[(long)v * N + (long)gj * d.nx + gi];
+    });
+    __syncthreads();
+    const int tx = threadIdx.x & (TTX - 1), ty = threadIdx.x / TTX;
+    p.i = i0 + tx;
+    p.j = j0 + ty;
+    p.k = 0;
+    if (p.i >= d.nx || p.j >= d.ny) return;
+    p.idx = (long)p.j * d.nx + p.i;
+    sidx = (long)(ty + THALO) * TW + tx + THALO;
+    src = smem;
+    splane = TILE_E;
+    sd[0] = make_sten<ORDER>(sidx, 1, p.i, d.nx);
+    sd[1] = make_sten<ORDER>(sidx, TW, p.j, d.ny);
+  } else {
+    if (!grid_point(d, p)) return;
+    sidx = p.idx;
+    src = Wd;
+    splane = N;
+    sd[0] = make_sten<ORDER>(sidx, 1, p.i, d.nx);
+    sd[1] = make_sten<ORDER>(sidx, d.nx, p.j, d.ny);
+    if (ND == 3) sd[2] = make_sten_per<ORDER>(sidx, (long)d.nx * d.ny, p.k, d.nz);
+  }
+  const long idx = p.idx;
+  RT md[3];
+  md[0] = RT(d.mx[p.i]);
+  md[1] = RT(d.my[p.j]);
+  if (ND == 3) md[2] = RT(d.mz[p.k]);
+  constexpr int NPI = ORDER == 6 ? 3 : 2;
+  // derivative of source plane a along direction b (z is periodic: central pairs only)
+  auto deriv = [&](int a, int b) -> RT {
+    const double* f = src + a * splane;
+    if (b == 2) return sten_apply<RT, NPI>(sd[b], f) * md[b];
+    return sten_apply<RT>(sd[b], f) * md[b];
+  };
   RT G[3][3], dT[3];
 #pragma unroll
   for (int a = 0; a < ND; ++a)
 #pragma unroll
-    for (int b = 0; b < ND; ++b) G[a][b] = dphys<ORDER, RT>(d, Wd + a * N, p, b);
+    for (int b = 0; b < ND; ++b) G[a][b] = deriv(a, b);
 #pragma unroll
-  for (int b = 0; b < ND; ++b) dT[b] = dphys<ORDER, RT>(d, Wd + ND * N, p, b);
+  for (int b = 0; b < ND; ++b) dT[b] = deriv(ND, b);
   double u[3];
 #pragma unroll
   for (int a = 0; a < ND; ++a) u[a] = Wd[a * N + idx];
@@ -482,13 +707,9 @@ __global__ __launch_bounds__(128) void k_flux(Dev d, const double* __restrict__ 
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int b = 0; b < ND; ++b) dX[s][b] = dphys<ORDER, RT>(d, Wd + (ND + 1 + s) * N, p, b);
-    const double Tk = Wd[ND * N + idx] * d.T_ref;
-    double hd[NS];
-    species_h(Tk, hd);
-    const double c2 = d.c_inf * d.c_inf;
+      for (int b = 0; b < ND; ++b) dX[s][b] = deriv(ND + 1 + s, b);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) h[s] = RT(hd[s] / c2);
+    for (int s = 0; s < NS; ++s) h[s] = Wp[(d.w_h + s) * N + idx];
   }
 #pragma unroll
   for (int j = 0; j < ND; ++j) {
@@ -537,37 +758,96 @@ __global__ __launch_bounds__(128) void k_flux(Dev d, const double* __restrict__ 
 // R = -sum_j dF_j/dx_j (FP64 differences, RT weighted sums) + wdot (species)
 //     - sigma (Q - Q_ref) (FP64); boundary rows; then R out, or the low-storage update
 // of Q and dQ in FP64.
-template <int GAS, int ND, int ORDER, int MODE, class RT>
-__global__ __launch_bounds__(128) void k_div(Dev d, const double* __restrict__ F,
+template <int GAS, int ND, int ORDER, int MODE, class RT, bool TILED>
+__global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F,
                                              const RT* __restrict__ Wp, const double* Qin,
                                              const double* __restrict__ Qref, double* Rout,
                                              double* Qio, double* dQio, double A, double B,
                                              double dt) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= d.N) return;
-  const long N = d.N;
-  const Pt p = point_of(d, idx);
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
-  const double sig = fmax(d.sx[p.i], d.sy[p.j]);
+  extern __shared__ double smem[];
+  const long N = d.N;
+  Pt p;
+  Sten sx, sy, sz;
+  int i0 = 0, j0 = 0, tx = 0, ty = 0;
+  bool active = true;
+  if (TILED) {
+    tile_origin(d, i0, j0);
+    tx = threadIdx.x & (TTX - 1);
+    ty = threadIdx.x / TTX;
+    p.i = i0 + tx;
+    p.j = j0 + ty;
+    p.k = 0;
+    active = p.i < d.nx && p.j < d.ny;   // inactive threads still help stage the tiles
+    p.idx = (long)p.j * d.nx + p.i;
+    sx = make_sten<ORDER>((long)ty * TW + tx + THALO, 1, p.i, d.nx);
+    sy = make_sten<ORDER>((long)(ty + THALO) * TTX + tx, TTX, p.j, d.ny);
+  } else {
+    if (!grid_point(d, p)) return;
+    sx = make_sten<ORDER>(p.idx, 1, p.i, d.nx);
+    sy = make_sten<ORDER>(p.idx, d.nx, p.j, d.ny);
+    if (ND == 3) sz = make_sten_per<ORDER>(p.idx, (long)d.nx * d.ny, p.k, d.nz);
+  }
+  const long idx = p.idx;
+  const RT mx = active ? RT(d.mx[p.i]) : RT(0);
+  const RT my = active ? RT(d.my[p.j]) : RT(0);
+  const RT mz = (ND == 3) ? RT(d.mz[p.k]) : RT(0);
+  const double sig = active ? fmax(d.sx[p.i], d.sy[p.j]) : 0.0;
   bool held = (p.i == 0);
-  if (d.hold && p.j < 3) held = held || d.hold[((long)p.k * 3 + p.j) * d.nx + p.i];
-#pragma unroll
-  for (int k = 0; k < nvar; ++k) {
-    RT acc = RT(0);
-#pragma unroll
-    for (int j = 0; j < ND; ++j) acc += dphys<ORDER, RT>(d, F + ((long)j * nvar + k) * N, p, j);
-    double R = -double(acc);
-    if (GAS == AIR5 && k < NS) R = R + double(Wp[(d.w_wdot + k) * N + idx]);
-    const double qv = (MODE == MODE_RK) ? Qio[k * N + idx] : Qin[k * N + idx];
-    if (Qref != nullptr && sig != 0.0) R = R - sig * (qv - Qref[k * N + idx]);
-    if (held || (p.j == 0 && k >= ns && k < ns + ND)) R = 0.0;
-    if (MODE == MODE_RHS) {
-      Rout[k * N + idx] = R;
-    } else {
-      const double dq = A * dQio[k * N + idx] + dt * R;
-      dQio[k * N + idx] = dq;
-      Qio[k * N + idx] = qv + B * dq;
+  if (active && d.hold && p.j < 3) held = held || d.hold[((long)p.k * 3 + p.j) * d.nx + p.i];
+  constexpr int NPI = ORDER == 6 ? 3 : 2;
+  // components in chunks of KCH; the tiled form stages each chunk's flux tiles in LDS
+  for (int k0 = 0; k0 < nvar; k0 += KCH) {
+    const int kn = min(KCH, nvar - k0);
+    if (TILED) {
+      double* tx_ = smem;
+      double* ty_ = smem + KCH * FXE;
+      if (k0 > 0) __syncthreads();   // previous chunk fully consumed
+      // x-flux tiles of the chunk, then y-flux tiles (components past nvar read any
+      // valid plane and are never used)
+      stage_tile<KCH * FXE, TTX * TTY>(tx_, [&](int e) {
+        const int kk = e / FXE, r = e - kk * FXE;
+        const int ly = r / TW, lx = r - ly * TW;
+        const int gi = min(max(i0 + lx - THALO, 0), d.nx - 1);
+        const int gj = min(j0 + ly, d.ny - 1);
+        const int k = min(k0 + kk, nvar - 1);
+        return F[(long)k * N + (long)gj * d.nx + gi];
+      });
+      stage_tile<KCH * FYE, TTX * TTY>(ty_, [&](int e) {
+        const int kk = e / FYE, r = e - kk * FYE;
+        const int ly = r / TTX, lx = r - ly * TTX;
+        const int gi = min(i0 + lx, d.nx - 1);
+        const int gj = min(max(j0 + ly - THALO, 0), d.ny - 1);
+        const int k = min(k0 + kk, nvar - 1);
+        return F[((long)nvar + k) * N + (long)gj * d.nx + gi];
+      });
+      __syncthreads();
+    }
+    if (!active) continue;
+    for (int kk = 0; kk < kn; ++kk) {
+      const int k = k0 + kk;
+      RT acc;
+      if (TILED) {
+        acc = sten_apply<RT>(sx, smem + kk * FXE) * mx;
+        acc += sten_apply<RT>(sy, smem + KCH * FXE + kk * FYE) * my;
+      } else {
+        acc = sten_apply<RT>(sx, F + (long)k * N) * mx;
+        acc += sten_apply<RT>(sy, F + ((long)nvar + k) * N) * my;
+        if (ND == 3) acc += sten_apply<RT, NPI>(sz, F + ((long)2 * nvar + k) * N) * mz;
+      }
+      double R = -double(acc);
+      if (GAS == AIR5 && k < NS) R = R + double(Wp[(d.w_wdot + k) * N + idx]);
+      const double qv = (MODE == MODE_RK) ? Qio[k * N + idx] : Qin[k * N + idx];
+      if (Qref != nullptr && sig != 0.0) R = R - sig * (qv - Qref[k * N + idx]);
+      if (held || (p.j == 0 && k >= ns && k < ns + ND)) R = 0.0;
+      if (MODE == MODE_RHS) {
+        Rout[k * N + idx] = R;
+      } else {
+        const double dq = A * dQio[k * N + idx] + dt * R;
+        dQio[k * N + idx] = dq;
+        Qio[k * N + idx] = qv + B * dq;
+      }
     }
   }
 }
@@ -1056,6 +1336,16 @@ struct hrx_ctx {
         *delta = nullptr;
   uint16_t* wsw = nullptr;
   MlpNorm norm;
+  // replayable graphs of one RK stage, keyed by the call's arguments (non-null streams)
+  struct StageGraph {
+    const double *Q, *dQ, *Qref;
+    double dt;
+    int k;
+    hipStream_t st;
+    hipGraphExec_t exec;
+  };
+  std::vector<StageGraph> graphs;
+  bool use_graphs = true;
 };
 
 namespace {
@@ -1159,8 +1449,14 @@ const char* hrx_strerror(int code) {
   }
 }
 
+static void clear_graphs(hrx_ctx* c) {
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
 void hrx_destroy(hrx_ctx* c) {
   if (!c) return;
+  clear_graphs(c);
   if (c->timing) hrx_timing_enable(c, 0);
   (void)hipFree(c->Wd);
   (void)hipFree(c->Wp);
@@ -1208,6 +1504,9 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   const int ns = c.gas == HRX_GAS_AIR5 ? NS : 1;
   d.nx = c.nx; d.ny = c.ny; d.nz = c.nz; d.ndim = nd; d.ns = ns; d.nvar = ns + nd + 1;
   d.fd_order = c.fd_order; d.N = N;
+  d.gx = (c.nx + TX - 1) / TX;
+  d.tgx = (c.nx + TTX - 1) / TTX;
+  d.tgy = (c.ny + TTY - 1) / TTY;
   d.newton_rtol = c.newton_rtol > 0.0 ? c.newton_rtol : 1e-13;
   d.newton_max = c.newton_max_iter > 0 ? c.newton_max_iter : 50;
   d.wall = c.wall; d.T_wall = c.T_wall;
@@ -1346,6 +1645,7 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     d.w_kap = w++;
     d.w_D = w; w += NS;
     d.w_wdot = w; w += NS;
+    d.w_h = w; w += NS;
   }
   if (d.ad_on) d.w_c = w++;
   ctx->nWp = w;
@@ -1378,12 +1678,54 @@ int hrx_get_reference(const hrx_ctx* ctx, hrx_reference* out) {
 
 namespace {
 
+// 2-D grids use the LDS-tiled stencil kernels; 3-D grids read neighbours from memory.
+template <int GAS, int ND, int ORDER, bool AD, class RT>
+void launch_flux(hrx_ctx* ctx, hipStream_t st, const double* Q, const double* Wd, const RT* Wp,
+                 const RT* Gad, double* F) {
+  const Dev& d = ctx->dev;
+  if (ND == 2) {
+    constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);
+    const unsigned nt = (unsigned)d.tgx * d.tgy;
+    timed(ctx, K_FLUX, st, [&] {
+      k_flux<GAS, ND, ORDER, AD, RT, true>
+          <<<nt, TTX * TTY, NSRC * TILE_E * sizeof(double), st>>>(d, Q, Wd, Wp, Gad, F);
+    });
+  } else {
+    const unsigned ng = (unsigned)d.gx * d.ny * d.nz;
+    timed(ctx, K_FLUX, st, [&] {
+      k_flux<GAS, ND, ORDER, AD, RT, false><<<ng, TX, 0, st>>>(d, Q, Wd, Wp, Gad, F);
+    });
+  }
+}
+
+template <int GAS, int ND, int ORDER, int MODE, class RT>
+void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, const double* Q,
+                const double* Qref, double* R, double* Qio, double* dQ, double A, double B,
+                double dt) {
+  const Dev& d = ctx->dev;
+  if (ND == 2) {
+    const unsigned nt = (unsigned)d.tgx * d.tgy;
+    const size_t sh = (size_t)KCH * (FXE + FYE) * sizeof(double);
+    timed(ctx, K_DIV, st, [&] {
+      k_div<GAS, ND, ORDER, MODE, RT, true>
+          <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
+    });
+  } else {
+    const unsigned ng = (unsigned)d.gx * d.ny * d.nz;
+    timed(ctx, K_DIV, st, [&] {
+      k_div<GAS, ND, ORDER, MODE, RT, false><<<ng, TX, 0, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A,
+                                                               B, dt);
+    });
+  }
+}
+
 template <int GAS, int ND, int ORDER, class RT>
 int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
   const Dev& d = ctx->dev;
   const long N = d.N;
   const int bs = 128;
   const unsigned nb = blocks_for(N, bs);
+  const unsigned ng = (unsigned)d.gx * d.ny * d.nz;   // stencil-kernel grid
   double* Wd = ctx->Wd;
   RT* Wp = (RT*)ctx->Wp;
   double* F = ctx->F;
@@ -1402,23 +1744,19 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
     RT* A = (RT*)ctx->AD;
     RT* B = A + (long)d.nad * N;
     const RT* Gad;
-    timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER, RT><<<nb, bs, 0, st>>>(d, Q, Wd, A); });
-    timed(ctx, K_AD_D4, st, [&] { k_ad_d4<GAS, ND, RT><<<nb, bs, 0, st>>>(d, A, B); });
-    timed(ctx, K_AD_FX, st, [&] { k_ad_filter<0, RT><<<nb, bs, 0, st>>>(d, B, A); });
-    timed(ctx, K_AD_FY, st, [&] { k_ad_filter<1, RT><<<nb, bs, 0, st>>>(d, A, B); });
+    timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER, RT><<<ng, TX, 0, st>>>(d, Q, Wd, A); });
+    timed(ctx, K_AD_D4, st, [&] { k_ad_d4<GAS, ND, RT><<<ng, TX, 0, st>>>(d, A, B); });
+    timed(ctx, K_AD_FX, st, [&] { k_ad_filter<0, RT><<<ng, TX, 0, st>>>(d, B, A); });
+    timed(ctx, K_AD_FY, st, [&] { k_ad_filter<1, RT><<<ng, TX, 0, st>>>(d, A, B); });
     if (ND == 3) {
-      timed(ctx, K_AD_FZ, st, [&] { k_ad_filter<2, RT><<<nb, bs, 0, st>>>(d, B, A); });
+      timed(ctx, K_AD_FZ, st, [&] { k_ad_filter<2, RT><<<ng, TX, 0, st>>>(d, B, A); });
       Gad = A;
     } else {
       Gad = B;
     }
-    timed(ctx, K_FLUX, st, [&] {
-      k_flux<GAS, ND, ORDER, true, RT><<<nb, bs, 0, st>>>(d, Q, Wd, Wp, Gad, F);
-    });
+    launch_flux<GAS, ND, ORDER, true, RT>(ctx, st, Q, Wd, Wp, Gad, F);
   } else {
-    timed(ctx, K_FLUX, st, [&] {
-      k_flux<GAS, ND, ORDER, false, RT><<<nb, bs, 0, st>>>(d, Q, Wd, Wp, nullptr, F);
-    });
+    launch_flux<GAS, ND, ORDER, false, RT>(ctx, st, Q, Wd, Wp, nullptr, F);
   }
   return check(hipGetLastError());
 }
@@ -1430,19 +1768,15 @@ int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, 
   int rc = launch_rhs_chain<GAS, ND, ORDER, RT>(ctx, mode == MODE_RHS ? Q : Qio, st);
   if (rc) return rc;
   ctx->dev.warm = 1;
-  const unsigned nb = blocks_for(d.N, 128);
+  const unsigned ng = (unsigned)d.gx * d.ny * d.nz;
   const double* F = ctx->F;
   const RT* Wp = (const RT*)ctx->Wp;
   if (mode == MODE_RHS) {
-    timed(ctx, K_DIV, st, [&] {
-      k_div<GAS, ND, ORDER, MODE_RHS, RT><<<nb, 128, 0, st>>>(d, F, Wp, Q, Qref, R, nullptr,
-                                                               nullptr, 0.0, 0.0, 0.0);
-    });
+    launch_div<GAS, ND, ORDER, MODE_RHS, RT>(ctx, st, F, Wp, Q, Qref, R, nullptr, nullptr, 0.0,
+                                             0.0, 0.0);
   } else {
-    timed(ctx, K_DIV, st, [&] {
-      k_div<GAS, ND, ORDER, MODE_RK, RT><<<nb, 128, 0, st>>>(d, F, Wp, nullptr, Qref, nullptr,
-                                                              Qio, dQ, A, B, dt);
-    });
+    launch_div<GAS, ND, ORDER, MODE_RK, RT>(ctx, st, F, Wp, nullptr, Qref, nullptr, Qio, dQ, A,
+                                            B, dt);
     const long nw = (long)(d.nx - 1) * d.nz;
     timed(ctx, K_BC, st, [&] { k_bc<GAS, ND><<<blocks_for(nw, 128), 128, 0, st>>>(d, Qio); });
   }
@@ -1500,6 +1834,26 @@ int hrx_rk_stage(hrx_ctx* ctx, int stage, double dt, double* Q, double* dQ, cons
   const double B = rk3 ? RK3B[k] : RK4B[k];
   hipStream_t st = (hipStream_t)hip_stream;
   ctx->last_stream = st;
+  // After the first stage (which switches the energy inversion to warm starts), a
+  // stage's kernel sequence is captured once per argument set into a HIP graph and
+  // replayed: one launch instead of four or more.  Not on the null stream (it cannot
+  // be captured) and not while per-kernel timing is on.
+  if (ctx->use_graphs && st != nullptr && !ctx->timing && ctx->dev.warm) {
+    for (auto& g : ctx->graphs)
+      if (g.Q == Q && g.dQ == dQ && g.Qref == Q_ref && g.dt == dt && g.k == k && g.st == st)
+        return check(hipGraphLaunch(g.exec, st));
+    if (ctx->graphs.size() >= 16) clear_graphs(ctx);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) return HRX_EHIP;
+    const int rc = dispatch(ctx, MODE_RK, nullptr, Q_ref, nullptr, Q, dQ, A, B, dt, st);
+    hipGraph_t graph;
+    if (hipStreamEndCapture(st, &graph) != hipSuccess || rc) return rc ? rc : HRX_EHIP;
+    hipGraphExec_t exec;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return HRX_EHIP;
+    ctx->graphs.push_back({Q, dQ, Q_ref, dt, k, st, exec});
+    return check(hipGraphLaunch(exec, st));
+  }
   return dispatch(ctx, MODE_RK, nullptr, Q_ref, nullptr, Q, dQ, A, B, dt, st);
 }
 
@@ -1656,6 +2010,7 @@ int hrx_mlp_set_norm(hrx_ctx* ctx, const float* in_mean, const float* in_std,
     nm.out_mean[k] = out_mean[k];
     nm.out_std[k] = out_std[k];
   }
+  clear_graphs(ctx);   // the statistics are kernel arguments baked into captured graphs
   nm.log10rho_min = log10rho_min;
   nm.log10rho_max = log10rho_max;
   SpeciesThermo lo, hi;
@@ -1671,6 +2026,7 @@ int hrx_mlp_set_norm(hrx_ctx* ctx, const float* in_mean, const float* in_std,
 
 int hrx_set_thermo_mode(hrx_ctx* ctx, int mode) {
   if (!ctx) return HRX_EINVAL;
+  clear_graphs(ctx);
   if (mode == HRX_THERMO_PLAIN) {
     ctx->thermo_mode = mode;
     return HRX_OK;
