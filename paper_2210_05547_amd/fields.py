@@ -147,7 +147,7 @@ def _cfg_c4():
                       kappa_y=0.15, mach=8.0, T_inf=947.0, p_inf=49800.0, Re=25291.0,
                       wall=WALL_ISOTHERMAL, T_wall=4000.0, sponge_in=16, sponge_out=32,
                       sponge_top=10, ad=True, delta0=0.8, jet=True, jet_x=52.5, jet_z=2.5,
-                      jet_radius_cells=8.0, inflow_noise=0.05, species_noise=1e-3, cfl=0.2,
+                      jet_radius_cells=8.0, inflow_noise=0.05, species_noise=1e-3, cfl=0.1,
                       seed=20221011 + 4)
 
 
@@ -247,11 +247,15 @@ def initial_field(cfg: FlowConfig):
         dxi = (X3 - cfg.jet_x) / hx
         dzi = (Z3 - cfg.jet_z) / hx          # distances in units of the x spacing
         r2 = (dxi ** 2 + dzi ** 2) / cfg.jet_radius_cells ** 2
-        wj = np.exp(-r2)
+        wxz = np.exp(-r2)
+        wxz[wxz < 1e-3] = 0.0
+        # full jet state on the first 3 wall rows (held), decaying smoothly above them
+        jidx = np.arange(cfg.ny).reshape(1, -1, 1)
+        yj = (Y3 - Y3[:, 2:3, :])[:1]          # height above the last held row
+        gy = np.where(jidx < 3, 1.0, np.exp(-(yj / 0.3) ** 2))
+        wj = wxz * gy
         jrow = np.zeros_like(T)
         jrow[:, :3, :] = 1.0
-        wj = wj * jrow
-        wj[wj < 1e-3] = 0.0
         Yj = np.array([1.0, 0, 0, 0, 0]).reshape(5, 1, 1, 1)
         Ys = (1.0 - wj)[None] * Ys + wj[None] * Yj
         T = (1.0 - wj) * T + wj * Tinf
@@ -260,7 +264,7 @@ def initial_field(cfg: FlowConfig):
         cinf = math.sqrt(g * (_RU / _molar_mass(np.asarray(cfg.Y_inf))) * Tinf)
         v = (1.0 - wj) * v + wj * (cj / cinf)
         u = (1.0 - wj) * u
-        hold = np.flatnonzero(wj.reshape(-1) > 0.0).astype(np.int64)
+        hold = np.flatnonzero((wxz * jrow).reshape(-1) > 0.0).astype(np.int64)
     # assemble nondimensional conserved variables
     if cfg.gas == GAS_CPG:
         rho = p / (T / Tinf) * rho_fac
@@ -287,10 +291,12 @@ def initial_field(cfg: FlowConfig):
         Yp = Yp / np.sum(Yp, axis=0)
         Q[:nsp] = rho[None] * Yp
     if cfg.inflow_noise > 0.0 and cfg.ndim == 3:
-        fac = (1.0 - np.exp(-(Y3 - cfg.y0) / delta))
+        # wall-normal envelope, and a ramp that keeps the inflow column and its closures
+        # free of perturbations
+        fac = (1.0 - np.exp(-(Y3 - cfg.y0) / delta)) * (1.0 - np.exp(-((X3 - cfg.x0) / 1.5) ** 2))
         for k in range(3):
             n = rng.standard_normal(T.shape)
-            for _ in range(2):
+            for _ in range(4):
                 n = _smooth121(n, 2, False)
                 n = _smooth121(n, 1, False)
                 n = _smooth121(n, 0, True)
@@ -302,10 +308,14 @@ def initial_field(cfg: FlowConfig):
             Q[nsp + k] = Q[nsp + k] + rho * du
     if cfg.noise > 0.0:
         Q = Q * (1.0 + cfg.noise * rng.standard_normal(Q.shape))
-    # no-slip wall: zero momentum at j = 0 (both fields)
+    # no-slip wall: zero momentum at j = 0 (both fields), except on the jet inlet
+    wall = np.ones(T.shape, dtype=bool)
+    wall[:, 1:, :] = False
+    if hold is not None:
+        wall.reshape(-1)[hold] = False
     for k in range(cfg.ndim):
-        Q[nsp + k][:, 0, :] = 0.0
-        Qref[nsp + k][:, 0, :] = 0.0
+        Q[nsp + k][wall] = 0.0
+        Qref[nsp + k][wall] = 0.0
     if hold is not None:
         Q.reshape(Q.shape[0], -1)[:, hold] = Qref.reshape(Q.shape[0], -1)[:, hold]
     # time step: acoustic CFL on the nominal field (c ~ sqrt(T/T_inf) in units of c_inf)
