@@ -21,15 +21,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE on this workload, scaled
+# by a 256 MiB copy kernel (fetch x2.0, write x1.0); None until taken for the current
+# kernels (profiles/stage_air5_flatplate_512x256.md)
+PRIM_TRAFFIC_BYTES = None
+TRAFFIC_BYTES = {}
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # Algorithmic HBM bytes per grid point of each kernel (FP64 planes read once + written
 # once; stencil neighbours counted once), for a 2-D 5-species-air stage without AD:
-#   prim : read Q (8 planes), write W (u, v, T, X_1..5, p, mu, kappa, D_1..5, wdot_1..5: 21)
-#   flux : read W (u, v, T, X_s, p, mu, kappa, D_s: 16) + Q (8), write F (2 x 8)
-#   div  : read F (16) + wdot (5) + Q (8) + dQ (8), write Q, dQ (16)  (+ Q_ref in sponges)
-BYTES_PER_POINT_AIR5_2D = {"prim": 8 * (8 + 21), "flux": 8 * (16 + 8 + 16),
-                           "div": 8 * (16 + 5 + 8 + 8 + 16)}
+#   prim : read Q (8 planes) + T of the previous stage; write Wd (u, v, T, X_1..5, p: 9) and
+#          Wp (mu, kappa, D_1..5, wdot_1..5, h_1..5: 17)
+#   flux : read Wd (9) + Wp (mu, kappa, D_s, h_s: 12) + Q (8); write F (2 x 8)
+#   div  : read F (16) + wdot (5) + Q (8) + dQ (8); write Q, dQ (16)  (+ Q_ref in sponges)
+BYTES_PER_POINT_AIR5_2D = {"prim": 8 * (9 + 26), "flux": 8 * (29 + 16),
+                           "div": 8 * (37 + 16)}
+# FP64 floating-point operations per grid point of the pointwise thermochemistry
+# (energy inversion from the previous stage's temperature, transport, kinetics,
+# enthalpies): SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / points, read with rocprofv3 on
+# this workload (profiles/stage_air5_flatplate_512x256.md).  MI355X has no FP64
+# transcendental unit, so this includes the instruction sequences of exp/log/sqrt/div.
+FLOPS_PER_POINT_PRIM_AIR5_2D = 4189.0
 
 
 def sponge_fraction(cfg):
@@ -65,6 +77,30 @@ def cpu_baseline(cfg, Q, Qr, info, budget_s):
                        f"single thread, {dt:.1f} s")
 
 
+def time_form(cfg, Q, Qr, info, steps, warmup, precision):
+    """Mpts/s of the same stage loop with another precision form (graph replay on)."""
+    import torch
+    from paper_2210_05547_amd import hrx
+    ctx = hrx.Context(cfg, info["x"], info["y"], info["z"], info["hold"], precision=precision)
+    Qd = torch.from_numpy(Q).to("cuda:0")
+    Qrd = torch.from_numpy(Qr).to("cuda:0")
+    dQd = torch.zeros_like(Qd)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for k in range(warmup):
+            hrx.rk_stage(ctx, k, info["dt"], Qd, dQd, Qrd)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k in range(warmup, warmup + steps):
+            hrx.rk_stage(ctx, k, info["dt"], Qd, dQd, Qrd)
+        b.record()
+        torch.cuda.synchronize()
+    ctx.close()
+    return cfg.npts * steps / (a.elapsed_time(b) * 1e-3) / 1e6
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +109,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip timing the mixed FP32/FP64 form on the same workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 10 times (counter scaling)")
     args = ap.parse_args()
@@ -136,19 +174,32 @@ def main():
     kernels = {}
     for name, (tms, nl) in kt.items():
         if nl:
-            kernels[name] = dict(avg_us=1e3 * tms / nl, launches=nl)
+            kernels[name] = dict(avg_us=round(1e3 * tms / nl, 3), launches=nl)
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
-    bpp = dict(BYTES_PER_POINT_AIR5_2D)
-    if cfg.gas == 1 and cfg.ndim == 2 and not cfg.ad:
+    model = cfg.gas == 1 and cfg.ndim == 2 and not cfg.ad
+    roofs = {}
+    if model:
+        bpp = dict(BYTES_PER_POINT_AIR5_2D)
         bpp["div"] = bpp["div"] + 8 * 8 * sponge_fraction(cfg)
-    for name, kd in kernels.items():
-        if name in bpp:
-            kd["GBps"] = bpp[name] * cfg.npts / (kd["avg_us"] * 1e-6) / 1e9
-    roof = None
-    if dom in bpp:
-        ach = bpp[dom] * cfg.npts / (kernels[dom]["avg_us"] * 1e-6) / 1e9
-        roof = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+        for name, kd in kernels.items():
+            if name not in bpp:
+                continue
+            sec = kd["avg_us"] * 1e-6
+            gbs = bpp[name] * cfg.npts / sec / 1e9
+            kd["GBps"] = round(gbs, 1)
+            if name == "prim":
+                tf = FLOPS_PER_POINT_PRIM_AIR5_2D * cfg.npts / sec / 1e12
+                kd["TFLOPs_fp64"] = round(tf, 2)
+                roofs[name] = dict(kernel=name, bound="alu", achieved=round(tf, 2),
+                                   peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                                   frac=round(tf / FP64_VECTOR_PEAK_TFLOPS, 4),
+                                   traffic=PRIM_TRAFFIC_BYTES)
+            else:
+                roofs[name] = dict(kernel=name, bound="hbm", achieved=round(gbs, 1),
+                                   peak=HBM_PEAK_GBS, unit="GB/s",
+                                   frac=round(gbs / HBM_PEAK_GBS, 4),
+                                   traffic=TRAFFIC_BYTES.get(name))
+    roof = roofs.get(dom)
     out = {
         "metric": "grid-point RHS+RK-stage evals/s (Mpts/s), FP64",
         "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
@@ -160,9 +211,14 @@ def main():
                    "fd_order": cfg.fd_order, "artificial_diffusivity": bool(cfg.ad)},
         "roofline": roof,
         "kernels": kernels,
+        "kernel_rooflines": roofs,
         "state_finite": finite,
         "newton_failures": cnt["newton_nonconverged"] + cnt["energy_below_min"],
     }
+    if not args.no_mixed:
+        out["forms"] = {"fp64": out["value"],
+                        "mixed": round(time_form(cfg, Q, Qr, info, args.steps, args.warmup,
+                                                 hrx.PREC_MIXED), 2)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, Q, Qr, info, args.cpu_seconds)
     ctx.close()

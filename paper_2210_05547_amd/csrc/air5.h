@@ -82,17 +82,19 @@ struct SpeciesThermo {
 };
 
 HRX_HD void species_e_cv(double T, SpeciesThermo& st) {
+  const double iT = 1.0 / T;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const double Rs = gas_const(s);
     const double hf = hf0_molar(s) / molar_mass(s);
     if (is_diatomic(s)) {
-      const double x = theta_vib(s) / T;
+      const double x = theta_vib(s) * iT;
       const double em1 = expm1(x);
+      const double iem = 1.0 / em1;
       const double ex = em1 + 1.0;
       st.em1[s] = em1;
-      st.e[s] = Rs * (2.5 * T + theta_vib(s) / em1) + hf;
-      st.cv[s] = Rs * (2.5 + x * x * ex / (em1 * em1));
+      st.e[s] = Rs * (2.5 * T + theta_vib(s) * iem) + hf;
+      st.cv[s] = Rs * (2.5 + x * x * ex * (iem * iem));
     } else {
       st.e[s] = Rs * (1.5 * T) + hf;
       st.cv[s] = Rs * 1.5;
@@ -101,12 +103,13 @@ HRX_HD void species_e_cv(double T, SpeciesThermo& st) {
 }
 
 HRX_HD void species_h(double T, double* h) {
+  const double iT = 1.0 / T;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const double Rs = gas_const(s);
     const double hf = hf0_molar(s) / molar_mass(s);
     if (is_diatomic(s)) {
-      const double em1 = expm1(theta_vib(s) / T);
+      const double em1 = expm1(theta_vib(s) * iT);
       h[s] = Rs * (2.5 * T + theta_vib(s) / em1) + hf + Rs * T;
     } else {
       h[s] = Rs * (1.5 * T) + hf + Rs * T;
@@ -213,13 +216,16 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
   const R Tr = R(T);
   const R sqT = sqrt(Tr);
   const R lnT = log(Tr);
+  // (T/eps)^a = T^a eps^-a: one power of T per fit, shared by all species or pairs
+  const R T22 = exp(R(-0.14874) * lnT);
+  const R T11 = exp(R(-0.15610) * lnT);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const double m = molar_mass(s) / NAV;
     const double sig = lj_sigma(s);
     const R A = R((5.0 / 16.0) * sqrt(PI * m * KB) / (PI * sig * sig));
     const R Ts = Tr * R(1.0 / lj_eps(s));
-    const R om = R(1.16145) * exp(R(-0.14874) * (lnT - R(log(lj_eps(s))))) +
+    const R om = R(1.16145 * pow(lj_eps(s), 0.14874)) * T22 +
                  R(0.52487) * exp(R(-0.77320) * Ts) + R(2.16178) * exp(R(-2.43787) * Ts);
     mu_s[s] = A * sqT / om;
     const R Rs = R(gas_const(s));
@@ -243,8 +249,9 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
       }
       den += R(X[r]) * phi;
     }
-    mu += R(X[s]) * mu_s[s] / den;
-    kap += R(X[s]) * k_s[s] / den;
+    const R xd = R(X[s]) / den;
+    mu += xd * mu_s[s];
+    kap += xd * k_s[s];
   }
   out.mu = mu;
   out.kappa = kap;
@@ -261,7 +268,7 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
       const double eps = sqrt(lj_eps(s) * lj_eps(r));
       const R iB = R((PI * sig * sig) / ((3.0 / 16.0) * sqrt(2.0 * PI * KB * KB * KB / msr)));
       const R Ts = Tr * R(1.0 / eps);
-      const R om = R(1.06036) * exp(R(-0.15610) * (lnT - R(log(eps)))) +
+      const R om = R(1.06036 * pow(eps, 0.15610)) * T11 +
                    R(0.19300) * exp(R(-0.47635) * Ts) + R(1.03587) * exp(R(-1.52996) * Ts) +
                    R(1.76474) * exp(R(-3.89411) * Ts);
       const R v = pr_iT15 * om * iB;
@@ -296,12 +303,12 @@ HRX_HD R sutherland(R T) {
 //   g_s/(R_u T) = h_f,s/(R_u T) - ln[(2 pi m_s k T/h^2)^(3/2) k T/p0] - ln g_el,s
 //                 - r_s ln(T/(sigma_s theta_r,s)) + r_s ln(1 - exp(-theta_s/T))
 // em1[s] = exp(theta_s/T) - 1 of the diatomics (1 - exp(-x) = em1/(em1 + 1)).
-HRX_HD void gibbs_over_RT(double T, double lnT, const double* em1, double* g) {
+HRX_HD void gibbs_over_RT(double iT, double lnT, const double* em1, double* g) {
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const double m = molar_mass(s) / NAV;
     const double ltr = 1.5 * log(2.0 * PI * m * KB / (HPL * HPL)) + 2.5 * lnT + log(KB / P0);
-    double gs = hf0_molar(s) / (RU * T) - ltr - log(g_elec(s));
+    double gs = (hf0_molar(s) / RU) * iT - ltr - log(g_elec(s));
     if (is_diatomic(s)) {
       gs -= lnT - log(sym_number(s) * theta_rot(s));
       gs += log(em1[s] / (em1[s] + 1.0));
@@ -355,10 +362,10 @@ HRX_HD void production_rates(const double* rho_s, double T, const double* em1, R
   const double lnT = log(T);
   const double iT = 1.0 / T;
   double g[NS];
-  gibbs_over_RT(T, lnT, em1, g);
+  gibbs_over_RT(iT, lnT, em1, g);
   R c[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) c[s] = R(rho_s[s] / molar_mass(s));
+  for (int s = 0; s < NS; ++s) c[s] = R(rho_s[s] * (1.0 / molar_mass(s)));
   const double ln_c0 = log(P0 / RU) - lnT;     // ln(p0/(R_u T))
   const double dG[5] = {2.0 * g[3] - g[0], 2.0 * g[4] - g[1], g[3] + g[4] - g[2],
                         g[2] + g[3] - g[0] - g[4], g[1] + g[3] - g[2] - g[4]};

@@ -34,6 +34,10 @@ struct Dev {
   int nx, ny, nz, ndim, nvar, ns, fd_order;
   long N;
   double gamma, Re, Pr, T_ref, mu_inf, kappa_inf, c_inf, rho_inf, L_ref, R_inf;
+  // reciprocals and products of the reference values, formed once on the host:
+  // 1/T_ref, 1/c_inf^2, (gamma - 1)/(gamma R_inf), 1/mu_inf, 1/kappa_inf,
+  // 1/(c_inf L_ref), L_ref/(rho_inf c_inf), 1/c_inf
+  double iT_ref, ic2, p_fac, imu_inf, ikappa_inf, iDscale, wscale, ic_inf;
   int wall;
   double T_wall;  // K
   double newton_rtol;
@@ -135,38 +139,30 @@ struct Sten {
 
 template <int ORDER>
 __device__ __forceinline__ Sten make_sten(long idx, long s, int i, int n) {
-  Sten t;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    t.p[m] = idx;
-    t.q[m] = idx;
-    t.a[m] = 0.0;
-  }
+  // row class: 0 = central 6th order, 1 = central 4th order, 2 = boundary point,
+  // 3 = first point off the boundary.  Offsets and weights are formed with selects
+  // (no per-class branches, so the stencil lives in registers, not private memory).
   const bool c6 = ORDER == 6 && i >= 3 && i <= n - 4;
   const bool c4 = (ORDER == 4 && i >= 2 && i <= n - 3) ||
                   (ORDER == 6 && (i == 2 || i == n - 3));
-  if (c6) {
-    t.p[0] = idx + s; t.q[0] = idx - s; t.a[0] = 0.75;
-    t.p[1] = idx + 2 * s; t.q[1] = idx - 2 * s; t.a[1] = -0.15;
-    t.p[2] = idx + 3 * s; t.q[2] = idx - 3 * s; t.a[2] = 1.0 / 60.0;
-  } else if (c4) {
-    t.p[0] = idx + s; t.q[0] = idx - s; t.a[0] = 2.0 / 3.0;
-    t.p[1] = idx + 2 * s; t.q[1] = idx - 2 * s; t.a[1] = -1.0 / 12.0;
-  } else if (i == 0 || i == n - 1) {
-    const long sg = i == 0 ? s : -s;
-    const double f = i == 0 ? 1.0 : -1.0;
-    t.p[0] = idx + sg; t.a[0] = f * 4.0;
-    t.p[1] = idx + 2 * sg; t.a[1] = f * -3.0;
-    t.p[2] = idx + 3 * sg; t.a[2] = f * (4.0 / 3.0);
-    t.p[3] = idx + 4 * sg; t.a[3] = f * -0.25;
-  } else {  // i == 1 or i == n - 2
-    const long sg = i == 1 ? s : -s;
-    const double f = i == 1 ? 1.0 : -1.0;
-    t.p[0] = idx - sg; t.a[0] = f * -0.25;
-    t.p[1] = idx + sg; t.a[1] = f * 1.5;
-    t.p[2] = idx + 2 * sg; t.a[2] = f * -0.5;
-    t.p[3] = idx + 3 * sg; t.a[3] = f * (1.0 / 12.0);
-  }
+  const int cls = c6 ? 0 : (c4 ? 1 : ((i == 0 || i == n - 1) ? 2 : 3));
+  const bool lo = 2 * i < n;                  // closure at the low end of the line
+  const long sg = (cls >= 2 && !lo) ? -s : s;
+  const double f = (cls >= 2 && !lo) ? -1.0 : 1.0;
+  const bool cen = cls < 2;
+  Sten t;
+  t.p[0] = cls == 3 ? idx - sg : idx + sg;
+  t.p[1] = cls == 3 ? idx + sg : idx + 2 * sg;
+  t.p[2] = cls == 3 ? idx + 2 * sg : (cls == 1 ? idx : idx + 3 * sg);
+  t.p[3] = cls == 3 ? idx + 3 * sg : (cls == 2 ? idx + 4 * sg : idx);
+  t.q[0] = cen ? idx - s : idx;
+  t.q[1] = cen ? idx - 2 * s : idx;
+  t.q[2] = cls == 0 ? idx - 3 * s : idx;
+  t.q[3] = idx;
+  t.a[0] = cls == 0 ? 0.75 : (cls == 1 ? 2.0 / 3.0 : (cls == 2 ? 4.0 * f : -0.25 * f));
+  t.a[1] = cls == 0 ? -0.15 : (cls == 1 ? -1.0 / 12.0 : (cls == 2 ? -3.0 * f : 1.5 * f));
+  t.a[2] = cls == 0 ? 1.0 / 60.0 : (cls == 1 ? 0.0 : (cls == 2 ? (4.0 / 3.0) * f : -0.5 * f));
+  t.a[3] = cen ? 0.0 : (cls == 2 ? -0.25 * f : (1.0 / 12.0) * f);
   return t;
 }
 
@@ -340,16 +336,17 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
     rs[s] = Q[s * N + idx];
     rho += rs[s];
   }
+  const double irho = 1.0 / rho;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) Y[s] = rs[s] / rho;
+  for (int s = 0; s < NS; ++s) Y[s] = rs[s] * irho;
   double u[3] = {0.0, 0.0, 0.0};
   double ke = 0.0;
 #pragma unroll
   for (int a = 0; a < ND; ++a) {
-    u[a] = Q[(NS + a) * N + idx] / rho;
+    u[a] = Q[(NS + a) * N + idx] * irho;
     ke += u[a] * u[a];
   }
-  const double E = Q[(NS + ND) * N + idx] / rho;
+  const double E = Q[(NS + ND) * N + idx] * irho;
   const double e = E - 0.5 * ke;
   const double c2 = d.c_inf * d.c_inf;
   int status, iters;
@@ -357,19 +354,19 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
                                             &iters, Tguess);
   if (status) count(d, status);
-  const double T = Tk / d.T_ref;
+  const double T = Tk * d.iT_ref;
   const double Rmix = mixture_R(Y);
-  const double g = d.gamma;
-  const double p = rho * T * (g - 1.0) / g * Rmix / d.R_inf;
+  const double p = rho * T * Rmix * d.p_fac;
   const double p_d = p * d.rho_inf * c2;
   double X[NS], n = 0.0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    X[s] = Y[s] / molar_mass(s);
+    X[s] = Y[s] * (1.0 / molar_mass(s));
     n += X[s];
   }
+  const double in = 1.0 / n;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) X[s] = X[s] / n;
+  for (int s = 0; s < NS; ++s) X[s] = X[s] * in;
   SpeciesThermo st;
   species_e_cv(Tk, st);
   // surrogate form: the network already wrote the transport planes, except where it
@@ -392,24 +389,23 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   for (int s = 0; s < NS; ++s) Wd[(ND + 1 + s) * N + idx] = X[s];
   Wd[d.w_p * N + idx] = p;
   if (plain_transport) {
-    Wp[d.w_mu * N + idx] = tr.mu / RT(d.mu_inf);
-    Wp[d.w_kap * N + idx] = tr.kappa / RT(d.kappa_inf);
-    const RT Dscale = RT(d.c_inf * d.L_ref);
+    Wp[d.w_mu * N + idx] = tr.mu * RT(d.imu_inf);
+    Wp[d.w_kap * N + idx] = tr.kappa * RT(d.ikappa_inf);
+    const RT iDscale = RT(d.iDscale);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * N + idx] = tr.D[s] / Dscale;
+    for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * N + idx] = tr.D[s] * iDscale;
   }
-  const double wscale = d.L_ref / (d.rho_inf * d.c_inf);
 #pragma unroll
-  for (int s = 0; s < NS; ++s) Wp[(d.w_wdot + s) * N + idx] = RT(double(wd[s]) * wscale);
+  for (int s = 0; s < NS; ++s) Wp[(d.w_wdot + s) * N + idx] = RT(double(wd[s]) * d.wscale);
   // species enthalpies h_s = e_s + R_s T (nondimensional) for the diffusive heat flux
 #pragma unroll
-  for (int s = 0; s < NS; ++s) Wp[(d.w_h + s) * N + idx] = RT((st.e[s] + gas_const(s) * Tk) / c2);
+  for (int s = 0; s < NS; ++s) Wp[(d.w_h + s) * N + idx] = RT((st.e[s] + gas_const(s) * Tk) * d.ic2);
   if (d.ad_on) {
     double cv = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) cv += Y[s] * st.cv[s];
     const double gf = (cv + Rmix) / cv;
-    Wp[d.w_c * N + idx] = RT(sqrt(gf * Rmix * Tk) / d.c_inf);
+    Wp[d.w_c * N + idx] = RT(sqrt(gf * Rmix * Tk) * d.ic_inf);
   }
 }
 
@@ -1552,6 +1548,14 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   d.gamma = ref.gamma; d.Re = ref.Re; d.Pr = ref.Pr; d.T_ref = ref.T_ref;
   d.mu_inf = ref.mu_inf; d.kappa_inf = ref.kappa_inf; d.c_inf = ref.c_inf;
   d.rho_inf = ref.rho_inf; d.L_ref = ref.L_ref; d.R_inf = ref.R_inf;
+  d.iT_ref = 1.0 / d.T_ref;
+  d.ic2 = 1.0 / (d.c_inf * d.c_inf);
+  d.p_fac = (d.gamma - 1.0) / (d.gamma * d.R_inf);
+  d.imu_inf = 1.0 / d.mu_inf;
+  d.ikappa_inf = 1.0 / d.kappa_inf;
+  d.iDscale = 1.0 / (d.c_inf * d.L_ref);
+  d.wscale = d.L_ref / (d.rho_inf * d.c_inf);
+  d.ic_inf = 1.0 / d.c_inf;
   // ---------------------------------------------------------- metrics, spacing, sponge
   std::vector<double> x(c.x, c.x + c.nx), y(c.y, c.y + c.ny), Dx, Dy, Dx6, Dy6;
   host_deriv(x, c.fd_order, Dx);
