@@ -160,12 +160,20 @@ int hrx_mlp_init(hrx_ctx *ctx, int64_t max_batch);
 int hrx_mlp_set_params(hrx_ctx *ctx, const float *theta, void *hip_stream);
 /* Copy the current FP32 parameters to theta_out [9352] (device). */
 int hrx_mlp_get_params(hrx_ctx *ctx, float *theta_out, void *hip_stream);
-/* Standardisation (host arrays: input mean/std [7], output mean/std [8]) and the
- * training hull: log10 rho in [log10rho_min, log10rho_max], Y_s >= 0 and
- * sum_s Y_s e_s(T_lo) <= e <= sum_s Y_s e_s(T_hi). */
+/* Surrogate composition around the network (host arrays).  Inputs: the raw features
+ * f = (log10 rho, ln T_c, Y_1..Y_5), with T_c = (e - sum_s Y_s h0_s/M_s) / sum_s Y_s c_s
+ * and c_s = (3/2 + 2 r_s) R_s (every mode fully excited), are standardised with
+ * in_mean/in_std [7]: x = (f - in_mean)/in_std.  Outputs: (ln T, ln mu, ln kappa,
+ * ln(rho D_1..5)) (SI) = out_mean + out_std * net(x) + L [1, x], with out_mean/out_std
+ * [8] and L = out_lin [8][8] row-major (NULL: zero).  Training hull: log10 rho in
+ * [log10rho_min, log10rho_max], Y_s >= 0, sum_s Y_s e_s(T_lo) <= e <=
+ * sum_s Y_s e_s(T_hi), and the mass fraction of the element N,
+ * Y_N2 + Y_NO M_N/M_NO + Y_N, in [xiN_min, xiN_max].  HRX_EINVAL for non-positive
+ * std entries or empty ranges. */
 int hrx_mlp_set_norm(hrx_ctx *ctx, const float *in_mean, const float *in_std,
-                     const float *out_mean, const float *out_std, double log10rho_min,
-                     double log10rho_max, double T_lo, double T_hi);
+                     const float *out_mean, const float *out_std, const float *out_lin,
+                     double log10rho_min, double log10rho_max, double T_lo, double T_hi,
+                     double xiN_min, double xiN_max);
 /* HRX_THERMO_SURROGATE makes hrx_thermo_eval, hrx_rhs_eval and hrx_rk_stage (air5) take
  * mu, kappa, D_s from the network and start the FP64 energy inversion from its T, for
  * points inside the hull; points outside fall back to the plain evaluation and are

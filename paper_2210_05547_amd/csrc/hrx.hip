@@ -851,13 +851,12 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
 // ------------------------------------------------------------------ k_bc (wall row)
 __constant__ double c_wall[4] = {48.0 / 25.0, -36.0 / 25.0, 16.0 / 25.0, -3.0 / 25.0};
 
+// One wall point (i, k): no-slip velocity; temperature held (isothermal) or taken
+// from the 4th-order extrapolation of the interior temperature (adiabatic, zero normal
+// gradient); species mass fractions extrapolated likewise; the density already
+// advanced by the stage is kept.  Held inflow points are left alone.
 template <int GAS, int ND>
-__global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long nw = (long)(d.nx - 1) * d.nz;
-  if (t >= nw) return;
-  const int i = 1 + (int)(t % (d.nx - 1));
-  const int k = (int)(t / (d.nx - 1));
+__device__ __forceinline__ void wall_point(const Dev& d, double* __restrict__ Q, int i, int k) {
   if (d.hold && d.hold[((long)k * 3 + 0) * d.nx + i]) return;
   const long N = d.N;
   const long idx0 = (long)k * d.ny * d.nx + i;
@@ -929,6 +928,14 @@ __global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
   Q[(ns + ND) * N + idx0] = rho_w * ew;
 }
 
+template <int GAS, int ND>
+__global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nw = (long)(d.nx - 1) * d.nz;
+  if (t >= nw) return;
+  wall_point<GAS, ND>(d, Q, 1 + (int)(t % (d.nx - 1)), (int)(t / (d.nx - 1)));
+}
+
 // ------------------------------------------------------------------ pointwise SI calls
 template <class RT, bool SUR = false>
 __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int max_iter,
@@ -968,11 +975,12 @@ __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int ma
     for (int s = 0; s < NS; ++s) hout[s * n + i] = h[s];
   }
   if (in_hull) {
-    if (muout) muout[i] = exp(muout[i]);
-    if (kout) kout[i] = exp(kout[i]);
+    // the network's logarithms carry ~1e-4 relative error: FP32 exponentials suffice
+    if (muout) muout[i] = (double)expf((float)muout[i]);
+    if (kout) kout[i] = (double)expf((float)kout[i]);
     if (Dout) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) Dout[s * n + i] = exp(Dout[s * n + i]);
+      for (int s = 0; s < NS; ++s) Dout[s * n + i] = (double)expf((float)Dout[s * n + i]);
     }
   } else if (muout || kout || Dout) {
     if (SUR) atomicAdd(&counters[2], 1ull);
@@ -1028,7 +1036,9 @@ __global__ __launch_bounds__(256) void k_mlp_pack(const float* __restrict__ thet
     const int r = i - MLP_SW_OFF[L];
     const int q = r & 7, lane = (r >> 3) & 63, mt = r >> 9;
     const int m = mt / MLP_KS[L], t = mt % MLP_KS[L];
-    const int o = 32 * m + (lane & 31), k = 16 * t + 8 * (lane >> 5) + q;
+    const int o = 32 * m + (lane & 31);
+    // hidden-layer inputs come in the accumulator order of the previous layer
+    const int k = L == 0 ? 16 * t + 8 * (lane >> 5) + q : mlp_hidden_unit(t, lane >> 5, q);
     // first layer: columns k and 7 + k both carry W1[o][k] (hi/lo input pairs)
     const int kk = (L == 0 && k >= MLP_NIN && k < 2 * MLP_NIN) ? k - MLP_NIN : k;
     float v = 0.0f;
@@ -1201,25 +1211,41 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, float* 
 }
 
 // Inputs of the network from an SI state; returns false outside the training hull
-// (log10 rho outside [min, max], a negative mass fraction, or e outside
-// [sum Y e_s(T_lo), sum Y e_s(T_hi)]).
+// (log10 rho outside [min, max], a negative mass fraction, e outside
+// [sum Y e_s(T_lo), sum Y e_s(T_hi)], or the element-N mass fraction outside its range).
 __device__ __forceinline__ bool surrogate_inputs(const MlpNorm& nm, double rho, double e,
                                                  const double* Y, float* x) {
   const double lr = log10(rho);
-  double elo = 0.0, ehi = 0.0;
+  double elo = 0.0, ehi = 0.0, ef = 0.0, cf = 0.0;
   bool ok = lr >= nm.log10rho_min && lr <= nm.log10rho_max;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     elo += Y[s] * nm.e_lo[s];
     ehi += Y[s] * nm.e_hi[s];
+    ef += Y[s] * (hf0_molar(s) / molar_mass(s));
+    cf += Y[s] * (gas_const(s) * (is_diatomic(s) ? 3.5 : 1.5));
     ok = ok && Y[s] >= 0.0;
   }
-  ok = ok && e >= elo && e <= ehi;
-  const double raw[MLP_NIN] = {lr, e, Y[0], Y[1], Y[2], Y[3], Y[4]};
+  const double xiN = Y[0] + Y[2] * (molar_mass(3) / molar_mass(2)) + Y[3];
+  ok = ok && e >= elo && e <= ehi && xiN >= nm.xiN_min && xiN <= nm.xiN_max;
+  const float lTc = ok ? logf((float)((e - ef) / cf)) : 0.0f;
+  const float raw[MLP_NIN] = {(float)lr, lTc, (float)Y[0], (float)Y[1], (float)Y[2],
+                              (float)Y[3], (float)Y[4]};
 #pragma unroll
-  for (int k = 0; k < MLP_NIN; ++k)
-    x[k] = ok ? (float)((raw[k] - nm.in_mean[k]) / nm.in_std[k]) : 0.0f;
+  for (int k = 0; k < MLP_NIN; ++k) x[k] = ok ? (raw[k] - nm.in_mean[k]) / nm.in_std[k] : 0.0f;
   return ok;
+}
+
+// network outputs -> (ln T, ln mu, ln kappa, ln(rho D_s)) (SI), FP32
+__device__ __forceinline__ void surrogate_outputs(const MlpNorm& nm, const float* x,
+                                                  const float* y, float* ys) {
+#pragma unroll
+  for (int o = 0; o < MLP_NOUT; ++o) {
+    float v = nm.out_mean[o] + nm.out_std[o] * y[o] + nm.out_lin[o][0];
+#pragma unroll
+    for (int k = 0; k < MLP_NIN; ++k) v += nm.out_lin[o][1 + k] * x[k];
+    ys[o] = v;
+  }
 }
 
 // Network evaluation on physical states (the surrogate's first pass).  MODE_STATE_SI:
@@ -1273,24 +1299,24 @@ __global__ __launch_bounds__(256) void k_mlp_state(
     const bool in_hull = surrogate_inputs(nm, r, ee, Y, x) && valid;
     mlp_wave64(sW, sB, sH[wave], x, y, nullptr, 0, 0, valid);
     if (!valid) continue;
-    double ys[MLP_NOUT];
-#pragma unroll
-    for (int o = 0; o < MLP_NOUT; ++o) ys[o] = (double)y[o] * nm.out_std[o] + nm.out_mean[o];
+    float ys[MLP_NOUT];
+    surrogate_outputs(nm, x, y, ys);
     if (MODE == MODE_STATE_SI) {
-      Tg[i] = in_hull ? ys[0] : __builtin_nan("");
+      Tg[i] = in_hull ? (double)expf(ys[0]) : __builtin_nan("");
       if (mu) mu[i] = ys[1];
       if (kap) kap[i] = ys[2];
       if (D) {
+        const float lr = logf((float)r);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) D[s * n + i] = ys[3 + s] - log(r);   // ln D_s
+        for (int s = 0; s < NS; ++s) D[s * n + i] = ys[3 + s] - lr;   // ln D_s
       }
     } else {
       if (in_hull) {
-        Wp[d.w_mu * n + i] = RT(exp(ys[1]) / d.mu_inf);
-        Wp[d.w_kap * n + i] = RT(exp(ys[2]) / d.kappa_inf);
-        const double Dscale = d.c_inf * d.L_ref;
+        Wp[d.w_mu * n + i] = RT(expf(ys[1]) * (float)d.imu_inf);
+        Wp[d.w_kap * n + i] = RT(expf(ys[2]) * (float)d.ikappa_inf);
+        const float iDr = (float)(d.iDscale / r);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * n + i] = RT(exp(ys[3 + s]) / (r * Dscale));
+        for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * n + i] = RT(expf(ys[3 + s]) * iDr);
       } else {
         Wp[d.w_mu * n + i] = RT(__builtin_nan(""));
       }
@@ -1999,10 +2025,12 @@ int hrx_mlp_get_params(hrx_ctx* ctx, float* theta_out, void* hip_stream) {
 }
 
 int hrx_mlp_set_norm(hrx_ctx* ctx, const float* in_mean, const float* in_std,
-                     const float* out_mean, const float* out_std, double log10rho_min,
-                     double log10rho_max, double T_lo, double T_hi) {
+                     const float* out_mean, const float* out_std, const float* out_lin,
+                     double log10rho_min, double log10rho_max, double T_lo, double T_hi,
+                     double xiN_min, double xiN_max) {
   if (!ctx || !in_mean || !in_std || !out_mean || !out_std) return HRX_EINVAL;
   if (!(log10rho_min < log10rho_max) || !(T_lo > T_MIN) || !(T_lo < T_hi)) return HRX_EINVAL;
+  if (!(xiN_min <= xiN_max)) return HRX_EINVAL;
   MlpNorm& nm = ctx->norm;
   for (int k = 0; k < MLP_NIN; ++k) {
     if (!(in_std[k] > 0.0f)) return HRX_EINVAL;
@@ -2014,7 +2042,11 @@ int hrx_mlp_set_norm(hrx_ctx* ctx, const float* in_mean, const float* in_std,
     nm.out_mean[k] = out_mean[k];
     nm.out_std[k] = out_std[k];
   }
+  for (int o = 0; o < MLP_NOUT; ++o)
+    for (int k = 0; k <= MLP_NIN; ++k) nm.out_lin[o][k] = out_lin ? out_lin[o * (MLP_NIN + 1) + k] : 0.0f;
   clear_graphs(ctx);   // the statistics are kernel arguments baked into captured graphs
+  nm.xiN_min = xiN_min;
+  nm.xiN_max = xiN_max;
   nm.log10rho_min = log10rho_min;
   nm.log10rho_max = log10rho_max;
   SpeciesThermo lo, hi;

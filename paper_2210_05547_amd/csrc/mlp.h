@@ -2,9 +2,11 @@
 // FP32 accumulation, FP32 backward pass and Adam.
 //
 // The paper closes (Sec. 5) by pointing at machine learning as a way to replace the
-// expensive calls of its thermochemical library.  The network maps
-//   x = standardised (log10 rho, e, Y_1..Y_5)  ->  y = standardised (T, ln mu, ln kappa,
-//                                                     ln D_1..ln D_5)
+// expensive calls of its thermochemical library.  The network maps standardised inputs
+//   x = (log10 rho, ln T_c, Y_1..Y_5),   T_c = (e - sum_s Y_s h0_s/M_s) / sum_s Y_s c_s,
+// (c_s = (3/2 + 2 r_s) R_s: every mode fully excited, so T_c is a closed-form lower bound
+// of T) to standardised residuals of y = (ln T, ln mu, ln kappa, ln(rho D_1..5)) about a
+// linear function of x (fitted on the training set): y = m + s net(x) + L [1, x],
 // with three tanh hidden layers of 64 units: 7 -> 64 -> 64 -> 64 -> 8, 9352 parameters,
 // flat order [W1 (64x7, row = output), b1, W2, b2, W3, b3, W4 (8x64), b4].
 //
@@ -12,10 +14,14 @@
 //   A (32x16, weights):     lane l holds A[l%32][8(l/32) + q], q = 0..7
 //   B (16x32, activations): lane l holds B[8(l/32) + q][l%32]
 //   D (32x32, FP32):        lane l, register r holds D[(r%4) + 8(r/4) + 4(l/32)][l%32]
-// A wavefront evaluates 64 points as two 32-point column tiles; hidden activations
-// pass between layers through a per-wave LDS buffer in BF16.  Weights are stored
-// once, pre-swizzled so that each lane's A operand is 16 contiguous bytes.
-// The network's inputs enter the first layer as hi + lo BF16 pairs (see mlp_wave64).
+// A wavefront evaluates 64 points as two 32-point column tiles.  The hidden layers'
+// K order is permuted so that the B operand of a layer is exactly what the lane holds
+// in its accumulators of the previous layer: K step t, lane half h, element q is
+// hidden unit 32(t/2) + 4h + (r%4) + 8(r/4) with r = 8(t%2) + q.  Hidden activations
+// therefore stay in registers; only the network's inputs (hi + lo BF16 pairs, see
+// mlp_wave64) and its 8 outputs pass through a small per-wave LDS buffer.  Biases
+// initialise the accumulators.  Weights are stored once, pre-swizzled so that each
+// lane's A operand is 16 contiguous bytes.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -38,10 +44,17 @@ constexpr int MLP_KS[4] = {1, 4, 4, 4};
 constexpr int MLP_SW_OFF[4] = {0, 1024, 1024 + 4096, 1024 + 2 * 4096};
 constexpr int MLP_SW_SIZE = 1024 + 2 * 4096 + 2048;  // 11264
 constexpr int MLP_NBIAS = 64 + 64 + 64 + 8;
-constexpr int MLP_HPITCH = 72;  // BF16 elements per point row of the activation buffer
+constexpr int MLP_HPITCH = 16;  // BF16 elements per point row of the input/output buffer
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+typedef __attribute__((__vector_size__(8 * sizeof(float)))) float f32x8_t;
+
+// hidden unit carried by K index (step t, lane half h, element q) of layers 2..4
+__host__ __device__ __forceinline__ int mlp_hidden_unit(int t, int h, int q) {
+  const int r = 8 * (t & 1) + q;
+  return 32 * (t >> 1) + 4 * h + (r & 3) + 8 * (r >> 2);
+}
 
 // float -> bfloat16 bits, round to nearest even (the gfx950 conversion instruction)
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -71,10 +84,10 @@ __host__ __device__ __forceinline__ int mlp_sw_index(int L, int m, int t, int la
 
 // Evaluate the network for the 64 points of one wavefront.  Lane l owns point l:
 // x[7] standardised inputs in, y[8] standardised outputs out.  sW: swizzled BF16
-// weights (LDS), sB: biases (LDS), sH: this wave's activation buffer (LDS,
-// 64 x MLP_HPITCH BF16).  If save != nullptr the FP32 post-activations of the three
-// hidden layers are written to save[(L*ldn + point)*64 + unit] for training, with
-// point = base + lane and only for lanes with valid != 0.
+// weights (LDS), sB: biases (LDS), sH: this wave's staging buffer (LDS, 64 x
+// MLP_HPITCH BF16).  If save != nullptr the FP32 post-activations of the three hidden
+// layers are written to save[(L*ldn + point)*64 + unit] for training, with
+// point = base + lane and only for points below ldn.
 __device__ __forceinline__ void mlp_wave64(const uint16_t* __restrict__ sW,
                                            const float* __restrict__ sB, uint16_t* sH,
                                            const float* x, float* y, float* save, long base,
@@ -100,77 +113,78 @@ __device__ __forceinline__ void mlp_wave64(const uint16_t* __restrict__ sW,
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  bf16x8_t b[2][4];   // B operands of the current layer: [point tile][K step]
+#pragma unroll
+  for (int pt = 0; pt < 2; ++pt)
+    b[pt][0] = *reinterpret_cast<const bf16x8_t*>(sH + (32 * pt + col) * MLP_HPITCH + 8 * hl);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
   for (int L = 0; L < 4; ++L) {
     const int MT = MLP_MT[L], KS = MLP_KS[L];
+    const float* bias = sB + (L == 0 ? 0 : (L == 1 ? 64 : (L == 2 ? 128 : 192)));
     f32x16_t acc[2][2];  // [point tile][M tile]
 #pragma unroll
-    for (int pt = 0; pt < 2; ++pt) {
-      bf16x8_t b[4];
+    for (int m = 0; m < MT; ++m) {
+      f32x16_t c;
 #pragma unroll
-      for (int t = 0; t < KS; ++t)
-        b[t] = *reinterpret_cast<const bf16x8_t*>(sH + (32 * pt + col) * MLP_HPITCH + 16 * t +
-                                                  8 * hl);
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        f32x16_t c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                      0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < KS; ++t) {
-          const bf16x8_t a =
-              *reinterpret_cast<const bf16x8_t*>(sW + mlp_sw_index(L, m, t, lane, 0));
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[t], c, 0, 0, 0);
-        }
-        acc[pt][m] = c;
+      for (int r = 0; r < 16; ++r) {
+        const int u = 32 * m + (r & 3) + 8 * (r >> 2) + 4 * hl;
+        c[r] = (L < 3 || u < MLP_NOUT) ? bias[u] : 0.0f;
       }
+#pragma unroll
+      for (int pt = 0; pt < 2; ++pt) acc[pt][m] = c;
     }
-    // all B reads of this layer are complete (their data fed the MFMAs); overwrite
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const float* bias = sB + (L == 0 ? 0 : (L == 1 ? 64 : (L == 2 ? 128 : 192)));
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < KS; ++t) {
+        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(sW + mlp_sw_index(L, m, t, lane, 0));
+#pragma unroll
+        for (int pt = 0; pt < 2; ++pt)
+          acc[pt][m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[pt][t], acc[pt][m], 0, 0, 0);
+      }
     if (L < 3) {
+      // activations in registers; the next layer's B operand for K step t is the
+      // BF16 image of registers 8(t%2) .. 8(t%2)+7 of M tile t/2
 #pragma unroll
       for (int pt = 0; pt < 2; ++pt)
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+        for (int t = 0; t < 4; ++t) {
+          f32x8_t v;
 #pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            // registers 4g..4g+3 hold four consecutive units i0..i0+3 of one point
-            const int i0 = 32 * m + 8 * g + 4 * hl;
-            const int pnt = 32 * pt + col;
-            float a[4];
+          for (int q = 0; q < 8; ++q) v[q] = fast_tanh(acc[pt][t >> 1][8 * (t & 1) + q]);
+          b[pt][t] = __builtin_convertvector(v, bf16x8_t);
+          if (save) {
+            const long gp = base + 32 * pt + col;
+            if (gp < ldn) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] = fast_tanh(acc[pt][m][4 * g + q] + bias[i0 + q]);
-            const uint32_t lo = (uint32_t)f2bf(a[0]) | ((uint32_t)f2bf(a[1]) << 16);
-            const uint32_t hi = (uint32_t)f2bf(a[2]) | ((uint32_t)f2bf(a[3]) << 16);
-            *reinterpret_cast<uint2*>(sH + pnt * MLP_HPITCH + i0) = make_uint2(lo, hi);
-            if (save) {
-              const long gp = base + pnt;
-              if (gp < ldn) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) save[((long)L * ldn + gp) * 64 + i0 + q] = a[q];
+              for (int g = 0; g < 2; ++g) {
+                const int i0 = 32 * (t >> 1) + 8 * (2 * (t & 1) + g) + 4 * hl;
+                *reinterpret_cast<float4*>(save + ((long)L * ldn + gp) * 64 + i0) =
+                    make_float4(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]);
               }
             }
           }
+        }
     } else {
       // outputs 0..7 live in registers r = 0..3 of both halves; stage through LDS as FP32
       float* sO = reinterpret_cast<float*>(sH);
 #pragma unroll
       for (int pt = 0; pt < 2; ++pt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = r + 4 * hl;
-          sO[(32 * pt + col) * 8 + i] = acc[pt][0][r] + bias[i];
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  const float* sO = reinterpret_cast<const float*>(sH);
+        for (int r = 0; r < 4; ++r) sO[(32 * pt + col) * 8 + r + 4 * hl] = acc[pt][0][r];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-  for (int o = 0; o < MLP_NOUT; ++o) y[o] = sO[lane * 8 + o];
+      for (int o = 0; o < MLP_NOUT; ++o) y[o] = sO[lane * 8 + o];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
   (void)valid;
 }
 
@@ -184,12 +198,15 @@ __device__ __forceinline__ void mlp_load_lds(const uint16_t* __restrict__ gW,
   for (int i = threadIdx.x; i < MLP_NBIAS; i += blockDim.x) sB[i] = gB[i];
 }
 
-// Standardisation statistics and training-domain bounds of the surrogate (device).
+// Standardisation statistics, linear output baseline and training-domain bounds of the
+// surrogate (device).
 struct MlpNorm {
   float in_mean[MLP_NIN], in_std[MLP_NIN];
   float out_mean[MLP_NOUT], out_std[MLP_NOUT];
+  float out_lin[MLP_NOUT][MLP_NIN + 1];  // y_o += L[o][0] + sum_k L[o][1 + k] x_k
   double log10rho_min, log10rho_max;   // kg/m^3
   double e_lo[5], e_hi[5];             // species energies at the T bounds (J/kg)
+  double xiN_min, xiN_max;             // mass fraction of the element N
 };
 
 }  // namespace hrx

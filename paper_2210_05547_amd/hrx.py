@@ -94,8 +94,8 @@ def load(path: str = LIB_PATH):
     lib.hrx_mlp_set_params.argtypes = [vp, dp, vp]
     lib.hrx_mlp_get_params.argtypes = [vp, dp, vp]
     lib.hrx_mlp_set_norm.argtypes = [vp, C.POINTER(f32), C.POINTER(f32), C.POINTER(f32),
-                                     C.POINTER(f32), C.c_double, C.c_double, C.c_double,
-                                     C.c_double]
+                                     C.POINTER(f32), C.POINTER(f32), C.c_double, C.c_double,
+                                     C.c_double, C.c_double, C.c_double, C.c_double]
     lib.hrx_set_thermo_mode.argtypes = [vp, C.c_int]
     lib.hrx_mlp_forward.argtypes = [vp, i64, dp, dp, vp]
     lib.hrx_mlp_backward.argtypes = [vp, i64, dp, dp, dp, vp]
@@ -245,15 +245,22 @@ def mlp_get_params(ctx, theta_out, stream=None):
     _check(_lib.hrx_mlp_get_params(ctx._h, _ptr(theta_out), _stream(stream)))
 
 
-def mlp_set_norm(ctx, in_mean, in_std, out_mean, out_std, log10rho_range, T_range):
-    def f(a, n):
+def mlp_set_norm(ctx, in_mean, in_std, out_mean, out_std, log10rho_range, T_range,
+                 out_lin=None, xiN_range=(0.0, 1.0)):
+    """Feature standardisation, output composition (out_lin: [8][8] or None) and the
+    training hull of the surrogate (hrx_mlp_set_norm)."""
+    def f(a, shape):
         a = np.ascontiguousarray(a, dtype=np.float32)
-        assert a.shape == (n,)
+        if a.shape != shape:
+            raise HrxError(f"expected shape {shape}, got {a.shape}")
         return a
-    arrs = [f(in_mean, 7), f(in_std, 7), f(out_mean, 8), f(out_std, 8)]
+    arrs = [f(in_mean, (7,)), f(in_std, (7,)), f(out_mean, (8,)), f(out_std, (8,))]
     ptrs = [a.ctypes.data_as(C.POINTER(C.c_float)) for a in arrs]
-    _check(_lib.hrx_mlp_set_norm(ctx._h, *ptrs, float(log10rho_range[0]), float(log10rho_range[1]),
-                                 float(T_range[0]), float(T_range[1])))
+    lin = None if out_lin is None else f(out_lin, (8, 8))
+    lptr = None if lin is None else lin.ctypes.data_as(C.POINTER(C.c_float))
+    _check(_lib.hrx_mlp_set_norm(ctx._h, *ptrs, lptr, float(log10rho_range[0]),
+                                 float(log10rho_range[1]), float(T_range[0]), float(T_range[1]),
+                                 float(xiN_range[0]), float(xiN_range[1])))
 
 
 def set_thermo_mode(ctx, mode):
