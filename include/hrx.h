@@ -144,9 +144,10 @@ int hrx_get_counters(hrx_ctx *ctx, hrx_counters *out /* (host) */, int reset);
 
 /* ---- Learned thermochemistry surrogate (motivated by Sec. 5: replacing the costly
  * thermochemical-library calls with a learned model).  Network 7 -> 64 -> 64 -> 64 -> 8,
- * tanh hidden layers, mapping standardised (log10 rho [kg/m^3], e [J/kg], Y_1..Y_5) to
- * standardised (T [K], ln mu, ln kappa, ln(rho D_1)..ln(rho D_5)) in SI units (the
- * diffusion coefficients are recovered as D_s = exp(y)/rho).  Parameters: 9352
+ * hidden activation max(z, 0)^2, mapping the standardised features of an SI
+ * state (rho, e, Y_s) to standardised residuals of (ln T, ln mu, ln kappa,
+ * ln(rho D_1)..ln(rho D_5)) (composition: hrx_mlp_set_norm; D_s = exp(y)/rho).
+ * Parameters: 9352
  * FP32 values in the order [W1 (64x7, row-major by output), b1, W2 (64x64), b2, W3, b3,
  * W4 (8x64), b4].  Inference and the training forward pass run on the matrix cores in
  * BF16 with FP32 accumulation (weights and layer inputs rounded to BF16, nearest even);
@@ -166,7 +167,7 @@ int hrx_mlp_get_params(hrx_ctx *ctx, float *theta_out, void *hip_stream);
  * in_mean/in_std [7]: x = (f - in_mean)/in_std.  Outputs: (ln T, ln mu, ln kappa,
  * ln(rho D_1..5)) (SI) = out_mean + out_std * net(x) + L [1, x], with out_mean/out_std
  * [8] and L = out_lin [8][8] row-major (NULL: zero).  Training hull: log10 rho in
- * [log10rho_min, log10rho_max], Y_s >= 0, sum_s Y_s e_s(T_lo) <= e <=
+ * [log10rho_min, log10rho_max], Y_s >= -1e-6, sum_s Y_s e_s(T_lo) <= e <=
  * sum_s Y_s e_s(T_hi), and the mass fraction of the element N,
  * Y_N2 + Y_NO M_N/M_NO + Y_N, in [xiN_min, xiN_max].  HRX_EINVAL for non-positive
  * std entries or empty ranges. */
@@ -196,12 +197,12 @@ int hrx_mlp_train_step(hrx_ctx *ctx, int64_t n, const int32_t *idx, const float 
 /* Per-kernel timing with HIP events recorded on the launching stream around every
  * kernel of the calls that follow hrx_timing_enable(ctx, 1).  Kernel ids (index into
  * the arrays of hrx_timing_read): 0 prim, 1 ad_src, 2 ad_d4, 3 ad_filter_x,
- * 4 ad_filter_y, 5 ad_filter_z, 6 flux, 7 div, 8 bc, 9 thermo_eval, 10 chem_source,
- * 11 surrogate network pass.
+ * 4 ad_filter_y, 5 ad_filter_z, 6 flux, 7 div, 8 bc, 9 thermo_eval, 10 chem_source
+ * (in the surrogate form the network runs inside prim and thermo_eval).
  * hrx_timing_read synchronises, returns the summed milliseconds and launch counts
  * per kernel since enabling (arrays of HRX_NKERNELS, host) and keeps timing on.
  * hrx_timing_enable(ctx, 0) stops and releases the events. */
-#define HRX_NKERNELS 12
+#define HRX_NKERNELS 11
 int hrx_timing_enable(hrx_ctx *ctx, int on);
 int hrx_timing_read(hrx_ctx *ctx, double *ms /* (host) */, int64_t *launches /* (host) */);
 

@@ -1,13 +1,14 @@
 """Surrogate network reference: forward, backward, Adam (oracle; test infrastructure only).
 
 The paper closes by pointing at machine learning as a way to replace the costly
-calls of its thermochemical library (Sec. 5).  The surrogate here maps
-x = standardised (log10 rho, e, Y_1..Y_5) to y = standardised (T, ln mu, ln kappa,
-ln D_1..ln D_5) with the network
+calls of its thermochemical library (Sec. 5).  The network
 
-    h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), h3 = tanh(W3 h2 + b3), y = W4 h3 + b4
+    h1 = f(W1 x + b1), h2 = f(W2 h1 + b2), h3 = f(W3 h2 + b3), y = W4 h3 + b4,
+    f(z) = max(z, 0)^2   (squared rectifier, f' = 2 max(z, 0))
 
-of widths 7 -> 64 -> 64 -> 64 -> 8.  Parameters are one flat vector in the order
+has widths 7 -> 64 -> 64 -> 64 -> 8; x and y are the surrogate's standardised
+features and targets (the composition around the network lives with the tests'
+training data).  Parameters are one flat vector in the order
 [W1 (64x7, row = output unit), b1, W2 (64x64), b2, W3 (64x64), b3, W4 (8x64), b4],
 9352 values.  With ``bf16=True`` every matrix-product operand (weights and layer
 inputs) is first rounded to bfloat16 (round to nearest even, from float32), as the
@@ -56,6 +57,17 @@ def to_split_bf16(a):
     return hi.astype(np.float64) + lo
 
 
+def activation(z):
+    """Squared rectifier max(z, 0)^2."""
+    r = np.maximum(z, 0.0)
+    return r * r
+
+
+def activation_slope(a):
+    """f'(z) written with the output a = f(z) >= 0: f'(z) = 2 max(z, 0) = 2 sqrt(a)."""
+    return 2.0 * np.sqrt(a)
+
+
 def init_params(seed=0):
     """Glorot-uniform weights, zero biases."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -76,7 +88,7 @@ def forward(theta, X, bf16=False):
     for li, (W, b) in enumerate(layers):
         qa = (to_split_bf16 if (bf16 and li == 0) else q)(a)
         z = qa @ q(W).T + b
-        a = np.tanh(z) if li < 3 else z
+        a = activation(z) if li < 3 else z
         acts.append(a)
     return a, acts
 
@@ -95,7 +107,7 @@ def backward(theta, acts, dY, bf16=False):
         grads[li] = (gW, gb)
         if li > 0:
             da = d @ q(W)
-            d = da * (1.0 - acts[li] ** 2)
+            d = da * activation_slope(acts[li])
     return pack(grads)
 
 

@@ -299,10 +299,104 @@ constexpr double T_HI_MIXED = 2000.0;
 
 // ------------------------------------------------------------------ k_prim
 // Wd planes (double): [u, v, (w), T, X_1..X_5 (air5), p]   -- differentiated or convective
-// Wp planes (RT):     [mu, kappa, D_1..D_5, wdot_1..wdot_5, (c)] (air5), [mu, (c)] (CPG)
+// Wp planes (RT):     [mu, kappa, D_1..D_5, wdot_1..wdot_5, h_1..h_5, (c)] (air5),
+//                     [mu, (c)] (CPG)
+
+// Pointwise thermochemistry of one 5-species point from its conserved values (partial
+// densities rs, momentum m, total energy rhoE; nondimensional): energy inversion
+// (warm start from the stored temperature, else from T_start > 0, else cold), pressure,
+// mole fractions, transport (plain, or, when net is set, from the surrogate's outputs
+// ys = (ln T, ln mu, ln kappa, ln(rho D_s)) in SI), production rates, species
+// enthalpies and, with artificial diffusivity, the sound speed.
+template <int ND, class RT>
+__device__ __forceinline__ void prim_air5(const Dev& d, double* __restrict__ Wd,
+                                          RT* __restrict__ Wp, long idx, const double* rs,
+                                          const double* mom, double rhoE, bool net,
+                                          const float (&ys)[MLP_NOUT]) {
+  const long N = d.N;
+  double Y[NS];
+  double rho = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rho += rs[s];
+  const double irho = 1.0 / rho;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Y[s] = rs[s] * irho;
+  double u[3] = {0.0, 0.0, 0.0};
+  double ke = 0.0;
+#pragma unroll
+  for (int a = 0; a < ND; ++a) {
+    u[a] = mom[a] * irho;
+    ke += u[a] * u[a];
+  }
+  const double e = rhoE * irho - 0.5 * ke;
+  const double c2 = d.c_inf * d.c_inf;
+  int status, iters;
+  const double Tguess = d.warm ? Wd[ND * N + idx] * d.T_ref : (net ? (double)__expf(ys[0]) : 0.0);
+  const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
+                                            &iters, Tguess);
+  if (status) count(d, status);
+  const double T = Tk * d.iT_ref;
+  const double Rmix = mixture_R(Y);
+  const double p = rho * T * Rmix * d.p_fac;
+  const double p_d = p * d.rho_inf * c2;
+  double X[NS], n = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    X[s] = Y[s] * (1.0 / molar_mass(s));
+    n += X[s];
+  }
+  const double in = 1.0 / n;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) X[s] = X[s] * in;
+  SpeciesThermo st;
+  species_e_cv(Tk, st);
+  if (net) {
+    // the network's logarithms carry ~1e-4 relative error: FP32 exponentials suffice
+    Wp[d.w_mu * N + idx] = RT(__expf(ys[1]) * (float)d.imu_inf);
+    Wp[d.w_kap * N + idx] = RT(__expf(ys[2]) * (float)d.ikappa_inf);
+    const float iDr = (float)(d.iDscale / (rho * d.rho_inf));
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * N + idx] = RT(__expf(ys[3 + s]) * iDr);
+  } else {
+    Transport<RT> tr;
+    mixture_transport<RT>(Tk, p_d, X, st.cv, tr);
+    Wp[d.w_mu * N + idx] = tr.mu * RT(d.imu_inf);
+    Wp[d.w_kap * N + idx] = tr.kappa * RT(d.ikappa_inf);
+    const RT iDscale = RT(d.iDscale);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * N + idx] = tr.D[s] * iDscale;
+  }
+  double rsd[NS];
+  RT wd[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rsd[s] = rs[s] * d.rho_inf;
+  production_rates<RT>(rsd, Tk, st.em1, wd, T_HI_MIXED);
+#pragma unroll
+  for (int a = 0; a < ND; ++a) Wd[a * N + idx] = u[a];
+  Wd[ND * N + idx] = T;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Wd[(ND + 1 + s) * N + idx] = X[s];
+  Wd[d.w_p * N + idx] = p;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Wp[(d.w_wdot + s) * N + idx] = RT(double(wd[s]) * d.wscale);
+  // species enthalpies h_s = e_s + R_s T (nondimensional) for the diffusive heat flux
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Wp[(d.w_h + s) * N + idx] = RT((st.e[s] + gas_const(s) * Tk) * d.ic2);
+  if (d.ad_on) {
+    double cv = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) cv += Y[s] * st.cv[s];
+    const double gf = (cv + Rmix) / cv;
+    Wp[d.w_c * N + idx] = RT(sqrt(gf * Rmix * Tk) * d.ic_inf);
+  }
+}
+
+// Plain form, or (SUR) the surrogate form reading the network's outputs ys[8][N]
+// (NaN in ys[0]: outside the hull, plain transport, counted).
 template <int GAS, int ND, class RT, bool SUR = false>
 __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ Q,
-                                              double* __restrict__ Wd, RT* __restrict__ Wp) {
+                                              double* __restrict__ Wd, RT* __restrict__ Wp,
+                                              const float* __restrict__ ysin) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d.N) return;
   const long N = d.N;
@@ -329,84 +423,20 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
     if (d.ad_on) Wp[d.w_c * N + idx] = RT(sqrt(g * p / rho));
     return;
   }
-  double rs[NS], Y[NS];
-  double rho = 0.0;
+  double rs[NS], mom[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    rs[s] = Q[s * N + idx];
-    rho += rs[s];
+  for (int s = 0; s < NS; ++s) rs[s] = Q[s * N + idx];
+#pragma unroll
+  for (int a = 0; a < ND; ++a) mom[a] = Q[(NS + a) * N + idx];
+  float ys[MLP_NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  bool net = false;
+  if (SUR) {
+#pragma unroll
+    for (int o = 0; o < MLP_NOUT; ++o) ys[o] = ysin[o * N + idx];
+    net = !isnan(ys[0]);
+    if (!net) atomicAdd(&d.counters[2], 1ull);
   }
-  const double irho = 1.0 / rho;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) Y[s] = rs[s] * irho;
-  double u[3] = {0.0, 0.0, 0.0};
-  double ke = 0.0;
-#pragma unroll
-  for (int a = 0; a < ND; ++a) {
-    u[a] = Q[(NS + a) * N + idx] * irho;
-    ke += u[a] * u[a];
-  }
-  const double E = Q[(NS + ND) * N + idx] * irho;
-  const double e = E - 0.5 * ke;
-  const double c2 = d.c_inf * d.c_inf;
-  int status, iters;
-  const double Tguess = d.warm ? Wd[ND * N + idx] * d.T_ref : 0.0;
-  const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
-                                            &iters, Tguess);
-  if (status) count(d, status);
-  const double T = Tk * d.iT_ref;
-  const double Rmix = mixture_R(Y);
-  const double p = rho * T * Rmix * d.p_fac;
-  const double p_d = p * d.rho_inf * c2;
-  double X[NS], n = 0.0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    X[s] = Y[s] * (1.0 / molar_mass(s));
-    n += X[s];
-  }
-  const double in = 1.0 / n;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) X[s] = X[s] * in;
-  SpeciesThermo st;
-  species_e_cv(Tk, st);
-  // surrogate form: the network already wrote the transport planes, except where it
-  // marked the point as outside its hull (NaN)
-  const bool plain_transport = !SUR || isnan(Wp[d.w_mu * N + idx]);
-  Transport<RT> tr;
-  if (plain_transport) {
-    if (SUR) atomicAdd(&d.counters[2], 1ull);
-    mixture_transport<RT>(Tk, p_d, X, st.cv, tr);
-  }
-  double rsd[NS];
-  RT wd[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) rsd[s] = rs[s] * d.rho_inf;
-  production_rates<RT>(rsd, Tk, st.em1, wd, T_HI_MIXED);
-#pragma unroll
-  for (int a = 0; a < ND; ++a) Wd[a * N + idx] = u[a];
-  Wd[ND * N + idx] = T;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) Wd[(ND + 1 + s) * N + idx] = X[s];
-  Wd[d.w_p * N + idx] = p;
-  if (plain_transport) {
-    Wp[d.w_mu * N + idx] = tr.mu * RT(d.imu_inf);
-    Wp[d.w_kap * N + idx] = tr.kappa * RT(d.ikappa_inf);
-    const RT iDscale = RT(d.iDscale);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * N + idx] = tr.D[s] * iDscale;
-  }
-#pragma unroll
-  for (int s = 0; s < NS; ++s) Wp[(d.w_wdot + s) * N + idx] = RT(double(wd[s]) * d.wscale);
-  // species enthalpies h_s = e_s + R_s T (nondimensional) for the diffusive heat flux
-#pragma unroll
-  for (int s = 0; s < NS; ++s) Wp[(d.w_h + s) * N + idx] = RT((st.e[s] + gas_const(s) * Tk) * d.ic2);
-  if (d.ad_on) {
-    double cv = 0.0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) cv += Y[s] * st.cv[s];
-    const double gf = (cv + Rmix) / cv;
-    Wp[d.w_c * N + idx] = RT(sqrt(gf * Rmix * Tk) * d.ic_inf);
-  }
+  prim_air5<ND, RT>(d, Wd, Wp, idx, rs, mom, Q[(NS + ND) * N + idx], net, ys);
 }
 
 // ------------------------------------------------------------------ artificial diffusivity
@@ -937,6 +967,66 @@ __global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
 }
 
 // ------------------------------------------------------------------ pointwise SI calls
+// One SI state (rho, e, Y): energy inversion (from T_start > 0, else cold), pressure,
+// enthalpies, and transport from the surrogate's outputs ys = (ln T, ln mu, ln kappa,
+// ln(rho D_s)) when net is set, else the plain evaluation.  Null outputs are skipped.
+template <class RT>
+__device__ __forceinline__ void thermo_point(long n, long i, double rtol, int max_iter,
+                                             double r, double ee, const double* Y,
+                                             double T_start, bool net,
+                                             const float (&ys)[MLP_NOUT], double* Tout,
+                                             double* pout, double* hout, double* muout,
+                                             double* kout, double* Dout, int32_t* stout,
+                                             unsigned long long* counters) {
+  int status, iters;
+  const double T = temperature_from_energy(ee, Y, rtol, max_iter, &status, &iters, T_start);
+  if (status == 1) atomicAdd(&counters[0], 1ull);
+  if (status == 2) atomicAdd(&counters[1], 1ull);
+  Tout[i] = T;
+  if (stout) stout[i] = status;
+  const double p = r * mixture_R(Y) * T;
+  if (pout) pout[i] = p;
+  if (hout) {
+    double h[NS];
+    species_h(T, h);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) hout[s * n + i] = h[s];
+  }
+  if (net) {
+    // the network's logarithms carry ~1e-4 relative error: FP32 exponentials suffice
+    if (muout) muout[i] = (double)__expf(ys[1]);
+    if (kout) kout[i] = (double)__expf(ys[2]);
+    if (Dout) {
+      const float ir = (float)(1.0 / r);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) Dout[s * n + i] = (double)(__expf(ys[3 + s]) * ir);
+    }
+  } else if (muout || kout || Dout) {
+    double X[NS], nsum = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      X[s] = Y[s] * (1.0 / molar_mass(s));
+      nsum += X[s];
+    }
+    const double inv = 1.0 / nsum;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) X[s] = X[s] * inv;
+    SpeciesThermo st;
+    species_e_cv(T, st);
+    Transport<RT> tr;
+    mixture_transport<RT>(T, p, X, st.cv, tr);
+    if (muout) muout[i] = double(tr.mu);
+    if (kout) kout[i] = double(tr.kappa);
+    if (Dout) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) Dout[s * n + i] = double(tr.D[s]);
+    }
+  }
+}
+
+// Plain form, or (SUR) the surrogate form's second pass reading the network's outputs
+// ys[8][n] (NaN in ys[0]: outside the hull, plain evaluation, counted when transport is
+// requested).
 template <class RT, bool SUR = false>
 __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int max_iter,
                                                      const double* __restrict__ rho,
@@ -949,60 +1039,23 @@ __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int ma
                                                      double* __restrict__ kout,
                                                      double* __restrict__ Dout,
                                                      int32_t* __restrict__ stout,
-                                                     unsigned long long* counters) {
+                                                     unsigned long long* counters,
+                                                     const float* __restrict__ ysin) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double Y[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + i];
-  int status, iters;
-  // surrogate form: Tout holds the network's temperature (NaN outside its hull) and
-  // mu, kappa, D hold ln mu, ln kappa, ln D_s
-  const double Tg = SUR ? Tout[i] : 0.0;
-  const bool in_hull = SUR && !isnan(Tg);
-  const double T = temperature_from_energy(e[i], Y, rtol, max_iter, &status, &iters,
-                                           in_hull ? Tg : 0.0);
-  if (status == 1) atomicAdd(&counters[0], 1ull);
-  if (status == 2) atomicAdd(&counters[1], 1ull);
-  Tout[i] = T;
-  if (stout) stout[i] = status;
-  const double p = rho[i] * mixture_R(Y) * T;
-  if (pout) pout[i] = p;
-  if (hout) {
-    double h[NS];
-    species_h(T, h);
+  float ys[MLP_NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  bool net = false;
+  if (SUR) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) hout[s * n + i] = h[s];
+    for (int o = 0; o < MLP_NOUT; ++o) ys[o] = ysin[o * n + i];
+    net = !isnan(ys[0]);
+    if (!net && (muout || kout || Dout)) atomicAdd(&counters[2], 1ull);
   }
-  if (in_hull) {
-    // the network's logarithms carry ~1e-4 relative error: FP32 exponentials suffice
-    if (muout) muout[i] = (double)expf((float)muout[i]);
-    if (kout) kout[i] = (double)expf((float)kout[i]);
-    if (Dout) {
-#pragma unroll
-      for (int s = 0; s < NS; ++s) Dout[s * n + i] = (double)expf((float)Dout[s * n + i]);
-    }
-  } else if (muout || kout || Dout) {
-    if (SUR) atomicAdd(&counters[2], 1ull);
-    double X[NS], nsum = 0.0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      X[s] = Y[s] / molar_mass(s);
-      nsum += X[s];
-    }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) X[s] = X[s] / nsum;
-    SpeciesThermo st;
-    species_e_cv(T, st);
-    Transport<RT> tr;
-    mixture_transport<RT>(T, p, X, st.cv, tr);
-    if (muout) muout[i] = double(tr.mu);
-    if (kout) kout[i] = double(tr.kappa);
-    if (Dout) {
-#pragma unroll
-      for (int s = 0; s < NS; ++s) Dout[s * n + i] = double(tr.D[s]);
-    }
-  }
+  thermo_point<RT>(n, i, rtol, max_iter, rho[i], e[i], Y, net ? (double)__expf(ys[0]) : 0.0, net,
+                   ys, Tout, pout, hout, muout, kout, Dout, stout, counters);
 }
 
 template <class RT>
@@ -1135,7 +1188,7 @@ __global__ __launch_bounds__(128) void k_mlp_bwd_delta(long n, const float* __re
 #pragma unroll
     for (int o = 0; o < MLP_NOUT; ++o) sacc += d4[o] * W4[o * 64 + k];
     const float a = save[(2 * n + b) * 64 + k];
-    d3[k] = sacc * (1.0f - a * a);
+    d3[k] = sacc * (2.0f * sqrtf(a));
     db[128 + k] = d3[k];
   }
   const float* W3 = wq + MLP_OFF_W[2];
@@ -1145,7 +1198,7 @@ __global__ __launch_bounds__(128) void k_mlp_bwd_delta(long n, const float* __re
 #pragma unroll
     for (int o = 0; o < 64; ++o) sacc += d3[o] * W3[o * 64 + k];
     const float a = save[(1 * n + b) * 64 + k];
-    d2[k] = sacc * (1.0f - a * a);
+    d2[k] = sacc * (2.0f * sqrtf(a));
     db[64 + k] = d2[k];
   }
   const float* W2 = wq + MLP_OFF_W[1];
@@ -1155,7 +1208,7 @@ __global__ __launch_bounds__(128) void k_mlp_bwd_delta(long n, const float* __re
 #pragma unroll
     for (int o = 0; o < 64; ++o) sacc += d2[o] * W2[o * 64 + k];
     const float a = save[(0 * n + b) * 64 + k];
-    db[k] = sacc * (1.0f - a * a);
+    db[k] = sacc * (2.0f * sqrtf(a));
   }
 }
 
@@ -1210,12 +1263,16 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, float* 
   theta[i] = theta[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
 }
 
+// Mass fractions this far below zero (round-off in the transport of a vanishing
+// species) still count as inside the hull.
+constexpr double Y_NEG_TOL = 1e-6;
+
 // Inputs of the network from an SI state; returns false outside the training hull
 // (log10 rho outside [min, max], a negative mass fraction, e outside
 // [sum Y e_s(T_lo), sum Y e_s(T_hi)], or the element-N mass fraction outside its range).
 __device__ __forceinline__ bool surrogate_inputs(const MlpNorm& nm, double rho, double e,
                                                  const double* Y, float* x) {
-  const double lr = log10(rho);
+  const float lr = __log10f((float)rho);
   double elo = 0.0, ehi = 0.0, ef = 0.0, cf = 0.0;
   bool ok = lr >= nm.log10rho_min && lr <= nm.log10rho_max;
 #pragma unroll
@@ -1224,15 +1281,15 @@ __device__ __forceinline__ bool surrogate_inputs(const MlpNorm& nm, double rho, 
     ehi += Y[s] * nm.e_hi[s];
     ef += Y[s] * (hf0_molar(s) / molar_mass(s));
     cf += Y[s] * (gas_const(s) * (is_diatomic(s) ? 3.5 : 1.5));
-    ok = ok && Y[s] >= 0.0;
+    ok = ok && Y[s] >= -Y_NEG_TOL;
   }
   const double xiN = Y[0] + Y[2] * (molar_mass(3) / molar_mass(2)) + Y[3];
   ok = ok && e >= elo && e <= ehi && xiN >= nm.xiN_min && xiN <= nm.xiN_max;
-  const float lTc = ok ? logf((float)((e - ef) / cf)) : 0.0f;
-  const float raw[MLP_NIN] = {(float)lr, lTc, (float)Y[0], (float)Y[1], (float)Y[2],
-                              (float)Y[3], (float)Y[4]};
+  const float lTc = ok ? __logf((float)(e - ef) / (float)cf) : 0.0f;
+  const float raw[MLP_NIN] = {lr, lTc, (float)Y[0], (float)Y[1], (float)Y[2], (float)Y[3],
+                              (float)Y[4]};
 #pragma unroll
-  for (int k = 0; k < MLP_NIN; ++k) x[k] = ok ? (raw[k] - nm.in_mean[k]) / nm.in_std[k] : 0.0f;
+  for (int k = 0; k < MLP_NIN; ++k) x[k] = ok ? (raw[k] - nm.in_mean[k]) * nm.in_istd[k] : 0.0f;
   return ok;
 }
 
@@ -1248,23 +1305,32 @@ __device__ __forceinline__ void surrogate_outputs(const MlpNorm& nm, const float
   }
 }
 
-// Network evaluation on physical states (the surrogate's first pass).  MODE_STATE_SI:
-// inputs rho [n], e [n], Y [5][n] (SI); outputs (de-standardised) written in place of
-// the caller's outputs: T guess into Tg [n] (NaN outside the hull), ln mu, ln kappa,
-// ln D_s into mu, kappa, D when given.  MODE_STATE_Q: inputs from the nondimensional
-// conserved state Q; outputs mu/mu_inf, kappa/kappa_inf, D_s/(c_inf L_ref) into the
-// transport planes of Wp, with NaN in the mu plane outside the hull.
-enum { MODE_STATE_SI = 0, MODE_STATE_Q = 1 };
-template <int MODE, int ND, class RT>
-__global__ __launch_bounds__(256) void k_mlp_state(
-    Dev d, MlpNorm nm, long n, const double* __restrict__ rho, const double* __restrict__ e,
-    const double* __restrict__ Yin, double* __restrict__ Tg, double* __restrict__ mu,
-    double* __restrict__ kap, double* __restrict__ D, const double* __restrict__ Q,
-    RT* __restrict__ Wp, const uint16_t* __restrict__ gW, const float* __restrict__ gB) {
+// Network pass of the surrogate form.  A block of 4 wavefronts holds the network in
+// LDS and walks the points in steps of 256; each wavefront computes the standardised
+// features of its 64 states and evaluates the network on the matrix cores.  Output:
+// ys[8][n] (FP32) = (ln T, ln mu, ln kappa, ln(rho D_1..5)) in SI, with ys[0] = NaN for
+// states outside the training hull.  States are SI (rho, e, Y) or, with FROM_Q, the
+// nondimensional conserved state Q.
+template <int ND, bool FROM_Q>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_eval(Dev d, const MlpNorm* __restrict__ gnm, long n,
+                                                  const double* __restrict__ rho,
+                                                  const double* __restrict__ e,
+                                                  const double* __restrict__ Yin,
+                                                  const double* __restrict__ Q,
+                                                  float* __restrict__ ysout,
+                                                  const uint16_t* __restrict__ gW,
+                                                  const float* __restrict__ gB) {
   __shared__ __attribute__((aligned(16))) uint16_t sW[MLP_SW_SIZE];
   __shared__ float sB[MLP_NBIAS];
   __shared__ __attribute__((aligned(16))) uint16_t sH[4][64 * MLP_HPITCH];
+  // the composition statistics (about 0.5 KB) live in LDS next to the weights
+  __shared__ __attribute__((aligned(16))) MlpNorm nm;
   mlp_load_lds(gW, gB, sW, sB);
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(gnm);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&nm);
+    for (int k = threadIdx.x; k < (int)(sizeof(MlpNorm) / 4); k += blockDim.x) dst[k] = src[k];
+  }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (long base = (long)blockIdx.x * 256 + wave * 64; base < n; base += (long)gridDim.x * 256) {
@@ -1272,55 +1338,38 @@ __global__ __launch_bounds__(256) void k_mlp_state(
     const bool valid = i < n;
     const long ix = valid ? i : 0;
     double Y[NS], r, ee;
-    if (MODE == MODE_STATE_SI) {
-#pragma unroll
-      for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + ix];
-      r = rho[ix];
-      ee = e[ix];
-    } else {
+    if (FROM_Q) {
       double rs = 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         Y[s] = Q[s * n + ix];
         rs += Y[s];
       }
+      const double irs = 1.0 / rs;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) Y[s] = Y[s] / rs;
+      for (int s = 0; s < NS; ++s) Y[s] = Y[s] * irs;
       double ke = 0.0;
 #pragma unroll
       for (int a = 0; a < ND; ++a) {
-        const double ua = Q[(NS + a) * n + ix] / rs;
+        const double ua = Q[(NS + a) * n + ix] * irs;
         ke += ua * ua;
       }
       r = rs * d.rho_inf;
-      ee = (Q[(NS + ND) * n + ix] / rs - 0.5 * ke) * (d.c_inf * d.c_inf);
+      ee = (Q[(NS + ND) * n + ix] * irs - 0.5 * ke) * (d.c_inf * d.c_inf);
+    } else {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + ix];
+      r = rho[ix];
+      ee = e[ix];
     }
-    float x[MLP_NIN], y[MLP_NOUT];
+    float x[MLP_NIN], y[MLP_NOUT], ys[MLP_NOUT];
     const bool in_hull = surrogate_inputs(nm, r, ee, Y, x) && valid;
     mlp_wave64(sW, sB, sH[wave], x, y, nullptr, 0, 0, valid);
     if (!valid) continue;
-    float ys[MLP_NOUT];
     surrogate_outputs(nm, x, y, ys);
-    if (MODE == MODE_STATE_SI) {
-      Tg[i] = in_hull ? (double)expf(ys[0]) : __builtin_nan("");
-      if (mu) mu[i] = ys[1];
-      if (kap) kap[i] = ys[2];
-      if (D) {
-        const float lr = logf((float)r);
+    ysout[i] = in_hull ? ys[0] : __builtin_nanf("");
 #pragma unroll
-        for (int s = 0; s < NS; ++s) D[s * n + i] = ys[3 + s] - lr;   // ln D_s
-      }
-    } else {
-      if (in_hull) {
-        Wp[d.w_mu * n + i] = RT(expf(ys[1]) * (float)d.imu_inf);
-        Wp[d.w_kap * n + i] = RT(expf(ys[2]) * (float)d.ikappa_inf);
-        const float iDr = (float)(d.iDscale / r);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * n + i] = RT(expf(ys[3 + s]) * iDr);
-      } else {
-        Wp[d.w_mu * n + i] = RT(__builtin_nan(""));
-      }
-    }
+    for (int o = 1; o < MLP_NOUT; ++o) ysout[o * n + i] = ys[o];
   }
 }
 
@@ -1357,7 +1406,9 @@ struct hrx_ctx {
   float *bias = nullptr, *wq = nullptr, *save = nullptr, *ybuf = nullptr, *dybuf = nullptr,
         *delta = nullptr;
   uint16_t* wsw = nullptr;
-  MlpNorm norm;
+  MlpNorm* norm_dev = nullptr;   // composition statistics and hull (device copy)
+  float* ys = nullptr;       // network outputs of the surrogate form, [8][ys_cap]
+  int64_t ys_cap = 0;
   // replayable graphs of one RK stage, keyed by the call's arguments (non-null streams)
   struct StageGraph {
     const double *Q, *dQ, *Qref;
@@ -1373,7 +1424,19 @@ struct hrx_ctx {
 namespace {
 
 enum { K_PRIM = 0, K_AD_SRC, K_AD_D4, K_AD_FX, K_AD_FY, K_AD_FZ, K_FLUX, K_DIV, K_BC, K_THERMO,
-       K_CHEM, K_MLP };
+       K_CHEM };
+
+// Workspace of the surrogate's network outputs, [8][n] floats (grown on demand; a
+// reallocation synchronises the device).
+int ensure_ys(hrx_ctx* c, int64_t n) {
+  if (n <= c->ys_cap) return HRX_OK;
+  if (c->ys) (void)hipFree(c->ys);
+  c->ys = nullptr;
+  c->ys_cap = 0;
+  if (hipMalloc(&c->ys, sizeof(float) * MLP_NOUT * (size_t)n) != hipSuccess) return HRX_ENOMEM;
+  c->ys_cap = n;
+  return HRX_OK;
+}
 
 int flush_timing(hrx_ctx* c) {
   for (auto& p : c->pending) {
@@ -1488,6 +1551,8 @@ void hrx_destroy(hrx_ctx* c) {
   (void)hipFree(c->metrics);
   (void)hipFree(c->hold);
   (void)hipFree(c->counters);
+  (void)hipFree(c->ys);
+  (void)hipFree(c->norm_dev);
   for (void* q : {(void*)c->theta, (void*)c->adam_m, (void*)c->adam_v, (void*)c->grad,
                   (void*)c->bias, (void*)c->wq, (void*)c->save, (void*)c->ybuf, (void*)c->dybuf,
                   (void*)c->delta, (void*)c->wsw})
@@ -1760,15 +1825,15 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
   RT* Wp = (RT*)ctx->Wp;
   double* F = ctx->F;
   if (GAS == AIR5 && ctx->thermo_mode == HRX_THERMO_SURROGATE) {
+    // network pass (its outputs in the context's ys workspace), then the pointwise pass
     const unsigned nbs = (unsigned)std::min<long>((N + 255) / 256, 2048);
-    timed(ctx, K_MLP, st, [&] {
-      k_mlp_state<MODE_STATE_Q, ND, RT><<<nbs, 256, 0, st>>>(
-          d, ctx->norm, N, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, Q, Wp,
-          ctx->wsw, ctx->bias);
+    timed(ctx, K_PRIM, st, [&] {
+      k_mlp_eval<ND, true><<<nbs, 256, 0, st>>>(d, ctx->norm_dev, N, nullptr, nullptr, nullptr, Q,
+                                                ctx->ys, ctx->wsw, ctx->bias);
+      k_prim<GAS, ND, RT, true><<<nb, bs, 0, st>>>(d, Q, Wd, Wp, ctx->ys);
     });
-    timed(ctx, K_PRIM, st, [&] { k_prim<GAS, ND, RT, true><<<nb, bs, 0, st>>>(d, Q, Wd, Wp); });
   } else {
-    timed(ctx, K_PRIM, st, [&] { k_prim<GAS, ND, RT><<<nb, bs, 0, st>>>(d, Q, Wd, Wp); });
+    timed(ctx, K_PRIM, st, [&] { k_prim<GAS, ND, RT><<<nb, bs, 0, st>>>(d, Q, Wd, Wp, nullptr); });
   }
   if (d.ad_on) {
     RT* A = (RT*)ctx->AD;
@@ -1896,23 +1961,27 @@ int hrx_thermo_eval(hrx_ctx* ctx, int64_t n, const double* rho, const double* e,
   hipStream_t st = (hipStream_t)hip_stream;
   ctx->last_stream = st;
   const bool mixed = ctx->cfg.precision == HRX_PREC_MIXED;
+  const bool sur = ctx->thermo_mode == HRX_THERMO_SURROGATE;
+  if (sur) {
+    const int rc = ensure_ys(ctx, n);
+    if (rc) return rc;
+  }
   timed(ctx, K_THERMO, st, [&] {
-    if (ctx->thermo_mode == HRX_THERMO_SURROGATE) {
+    if (sur) {
       const unsigned nbs = (unsigned)std::min<long>((n + 255) / 256, 2048);
-      k_mlp_state<MODE_STATE_SI, 2, double><<<nbs, 256, 0, st>>>(
-          ctx->dev, ctx->norm, n, rho, e, Y, T, mu, kappa, D, nullptr, nullptr, ctx->wsw,
-          ctx->bias);
+      k_mlp_eval<2, false><<<nbs, 256, 0, st>>>(ctx->dev, ctx->norm_dev, n, rho, e, Y, nullptr,
+                                               ctx->ys, ctx->wsw, ctx->bias);
       k_thermo_eval<double, true><<<blocks_for(n, 128), 128, 0, st>>>(
           n, ctx->dev.newton_rtol, ctx->dev.newton_max, rho, e, Y, T, p, h, mu, kappa, D, status,
-          ctx->counters);
+          ctx->counters, ctx->ys);
     } else if (mixed)
       k_thermo_eval<float><<<blocks_for(n, 128), 128, 0, st>>>(
           n, ctx->dev.newton_rtol, ctx->dev.newton_max, rho, e, Y, T, p, h, mu, kappa, D, status,
-          ctx->counters);
+          ctx->counters, nullptr);
     else
       k_thermo_eval<double><<<blocks_for(n, 128), 128, 0, st>>>(
           n, ctx->dev.newton_rtol, ctx->dev.newton_max, rho, e, Y, T, p, h, mu, kappa, D, status,
-          ctx->counters);
+          ctx->counters, nullptr);
   });
   return check(hipGetLastError());
 }
@@ -2031,11 +2100,11 @@ int hrx_mlp_set_norm(hrx_ctx* ctx, const float* in_mean, const float* in_std,
   if (!ctx || !in_mean || !in_std || !out_mean || !out_std) return HRX_EINVAL;
   if (!(log10rho_min < log10rho_max) || !(T_lo > T_MIN) || !(T_lo < T_hi)) return HRX_EINVAL;
   if (!(xiN_min <= xiN_max)) return HRX_EINVAL;
-  MlpNorm& nm = ctx->norm;
+  MlpNorm nm;
   for (int k = 0; k < MLP_NIN; ++k) {
     if (!(in_std[k] > 0.0f)) return HRX_EINVAL;
     nm.in_mean[k] = in_mean[k];
-    nm.in_std[k] = in_std[k];
+    nm.in_istd[k] = 1.0f / in_std[k];
   }
   for (int k = 0; k < MLP_NOUT; ++k) {
     if (!(out_std[k] > 0.0f)) return HRX_EINVAL;
@@ -2044,7 +2113,6 @@ int hrx_mlp_set_norm(hrx_ctx* ctx, const float* in_mean, const float* in_std,
   }
   for (int o = 0; o < MLP_NOUT; ++o)
     for (int k = 0; k <= MLP_NIN; ++k) nm.out_lin[o][k] = out_lin ? out_lin[o * (MLP_NIN + 1) + k] : 0.0f;
-  clear_graphs(ctx);   // the statistics are kernel arguments baked into captured graphs
   nm.xiN_min = xiN_min;
   nm.xiN_max = xiN_max;
   nm.log10rho_min = log10rho_min;
@@ -2056,6 +2124,12 @@ int hrx_mlp_set_norm(hrx_ctx* ctx, const float* in_mean, const float* in_std,
     nm.e_lo[s] = lo.e[s];
     nm.e_hi[s] = hi.e[s];
   }
+  if (!ctx->norm_dev && hipMalloc(&ctx->norm_dev, sizeof(MlpNorm)) != hipSuccess)
+    return HRX_ENOMEM;
+  // setup call: work still queued on any stream reads the previous statistics first
+  int rc = check(hipDeviceSynchronize());
+  if (!rc) rc = check(hipMemcpy(ctx->norm_dev, &nm, sizeof(MlpNorm), hipMemcpyHostToDevice));
+  if (rc) return rc;
   ctx->mlp_norm = true;
   return HRX_OK;
 }
@@ -2069,6 +2143,8 @@ int hrx_set_thermo_mode(hrx_ctx* ctx, int mode) {
   }
   if (mode != HRX_THERMO_SURROGATE || ctx->cfg.gas != HRX_GAS_AIR5) return HRX_EINVAL;
   if (!ctx->mlp_params || !ctx->mlp_norm) return HRX_EINVAL;
+  const int rc = ensure_ys(ctx, ctx->dev.N);
+  if (rc) return rc;
   ctx->thermo_mode = mode;
   return HRX_OK;
 }

@@ -196,7 +196,7 @@ class Context:
 
 
 KERNEL_NAMES = ("prim", "ad_src", "ad_d4", "ad_filter_x", "ad_filter_y", "ad_filter_z", "flux",
-                "div", "bc", "thermo_eval", "chem_source", "surrogate_net")
+                "div", "bc", "thermo_eval", "chem_source")
 
 
 def timing_enable(ctx, on=True):

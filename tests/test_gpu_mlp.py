@@ -2,8 +2,8 @@
 
 Forward: BF16 matrix-core inference vs the oracle forward with the same BF16-rounded
 weights and layer inputs.  Backward: FP32 gradient kernels vs the oracle backward on
-the same rounded operands.  Differences come from FP32 accumulation order and the
-fast tanh (~1e-7) and from the rare BF16 rounding decisions they flip (one BF16 ulp,
+the same rounded operands.  Differences come from FP32 accumulation order and
+from the rare BF16 rounding decisions it flips (one BF16 ulp,
 0.4 %, of a hidden activation); the bars below leave room for those and nothing
 else.  Adam: one step vs the oracle's closed form.
 """

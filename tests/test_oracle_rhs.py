@@ -288,3 +288,20 @@ def test_split_bf16_inputs():
     # two bfloat16 terms carry 16 significand bits
     assert np.all(np.abs(s - x.astype(np.float64)) <= 2.0 ** -16 * np.abs(x.astype(np.float64)))
     assert np.all(s == mlp.to_bf16(x) + mlp.to_bf16(x - mlp.to_bf16(x).astype(np.float32)))
+
+
+def test_mlp_activation_closed_forms():
+    """max(z, 0)^2: f(3) = 9, zero for z <= 0, f(z) = z^2 for z > 0; the slope written
+    with the output equals a central difference of f (also across the kink at 0,
+    where both one-sided slopes vanish)."""
+    f = mlp.activation
+    assert f(3.0) == 9.0 and f(-2.0) == 0.0 and f(0.0) == 0.0
+    z = np.linspace(-8, 8, 33)
+    assert np.all(f(z[z > 0]) == z[z > 0] ** 2) and np.all(f(z[z <= 0]) == 0.0)
+    h = 1e-5
+    z = z + 0.123
+    num = (f(z + h) - f(z - h)) / (2 * h)
+    assert np.allclose(mlp.activation_slope(f(z)), num, rtol=1e-8, atol=1e-9)
+    # at the kink the central difference is h/2 (only the right side is curved)
+    assert mlp.activation_slope(f(0.0)) == 0.0
+    assert abs((f(h) - f(-h)) / (2 * h) - h / 2) <= 1e-15
