@@ -167,7 +167,7 @@ int hrx_mlp_get_params(hrx_ctx *ctx, float *theta_out, void *hip_stream);
  * in_mean/in_std [7]: x = (f - in_mean)/in_std.  Outputs: (ln T, ln mu, ln kappa,
  * ln(rho D_1..5)) (SI) = out_mean + out_std * net(x) + L [1, x], with out_mean/out_std
  * [8] and L = out_lin [8][8] row-major (NULL: zero).  Training hull: log10 rho in
- * [log10rho_min, log10rho_max], Y_s >= -1e-6, sum_s Y_s e_s(T_lo) <= e <=
+ * [log10rho_min, log10rho_max], Y_s >= -1e-3, sum_s Y_s e_s(T_lo) <= e <=
  * sum_s Y_s e_s(T_hi), and the mass fraction of the element N,
  * Y_N2 + Y_NO M_N/M_NO + Y_N, in [xiN_min, xiN_max].  HRX_EINVAL for non-positive
  * std entries or empty ranges. */

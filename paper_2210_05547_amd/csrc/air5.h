@@ -143,9 +143,12 @@ constexpr double T_GUESS_MAX = 1.0e5;
 // fully excited vibration (a lower bound of the root).  Warm start: a previous
 // temperature T_guess in (T_MIN, T_GUESS_MAX), which the caller may pass to save
 // iterations; the root is the same.  Stops when |dT| <= rtol T.  status: 0 converged,
-// 1 no convergence in max_iter, 2 energy below e(T_MIN).
+// 1 no convergence in max_iter, 2 energy below e(T_MIN).  When st_last is given and the
+// iteration converged, it receives the species state at the last iterate, which lies
+// within rtol T of the returned root (callers reuse it instead of a fresh evaluation).
 HRX_HD double temperature_from_energy(double e, const double* Y, double rtol, int max_iter,
-                                      int* status, int* iters, double T_guess = 0.0) {
+                                      int* status, int* iters, double T_guess = 0.0,
+                                      SpeciesThermo* st_last = nullptr) {
   double ef = 0.0, cfull = 0.0, emin = 0.0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
@@ -179,6 +182,7 @@ HRX_HD double temperature_from_energy(double e, const double* Y, double rtol, in
     *iters = it + 1;
     if (fabs(dT) <= rtol * T) {
       *status = 0;
+      if (st_last) *st_last = st;
       return T;
     }
   }

@@ -332,9 +332,13 @@ __device__ __forceinline__ void prim_air5(const Dev& d, double* __restrict__ Wd,
   const double c2 = d.c_inf * d.c_inf;
   int status, iters;
   const double Tguess = d.warm ? Wd[ND * N + idx] * d.T_ref : (net ? (double)__expf(ys[0]) : 0.0);
+  SpeciesThermo st;   // species state at the last Newton iterate (within rtol of Tk)
   const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
-                                            &iters, Tguess);
-  if (status) count(d, status);
+                                            &iters, Tguess, &st);
+  if (status) {
+    count(d, status);
+    species_e_cv(Tk, st);
+  }
   const double T = Tk * d.iT_ref;
   const double Rmix = mixture_R(Y);
   const double p = rho * T * Rmix * d.p_fac;
@@ -348,8 +352,6 @@ __device__ __forceinline__ void prim_air5(const Dev& d, double* __restrict__ Wd,
   const double in = 1.0 / n;
 #pragma unroll
   for (int s = 0; s < NS; ++s) X[s] = X[s] * in;
-  SpeciesThermo st;
-  species_e_cv(Tk, st);
   if (net) {
     // the network's logarithms carry ~1e-4 relative error: FP32 exponentials suffice
     Wp[d.w_mu * N + idx] = RT(__expf(ys[1]) * (float)d.imu_inf);
@@ -979,18 +981,18 @@ __device__ __forceinline__ void thermo_point(long n, long i, double rtol, int ma
                                              double* kout, double* Dout, int32_t* stout,
                                              unsigned long long* counters) {
   int status, iters;
-  const double T = temperature_from_energy(ee, Y, rtol, max_iter, &status, &iters, T_start);
+  SpeciesThermo st;   // species state at the last Newton iterate (within rtol of T)
+  const double T = temperature_from_energy(ee, Y, rtol, max_iter, &status, &iters, T_start, &st);
   if (status == 1) atomicAdd(&counters[0], 1ull);
   if (status == 2) atomicAdd(&counters[1], 1ull);
+  if (status) species_e_cv(T, st);
   Tout[i] = T;
   if (stout) stout[i] = status;
   const double p = r * mixture_R(Y) * T;
   if (pout) pout[i] = p;
   if (hout) {
-    double h[NS];
-    species_h(T, h);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) hout[s * n + i] = h[s];
+    for (int s = 0; s < NS; ++s) hout[s * n + i] = st.e[s] + gas_const(s) * T;
   }
   if (net) {
     // the network's logarithms carry ~1e-4 relative error: FP32 exponentials suffice
@@ -1011,8 +1013,6 @@ __device__ __forceinline__ void thermo_point(long n, long i, double rtol, int ma
     const double inv = 1.0 / nsum;
 #pragma unroll
     for (int s = 0; s < NS; ++s) X[s] = X[s] * inv;
-    SpeciesThermo st;
-    species_e_cv(T, st);
     Transport<RT> tr;
     mixture_transport<RT>(T, p, X, st.cv, tr);
     if (muout) muout[i] = double(tr.mu);
@@ -1263,9 +1263,10 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, float* 
   theta[i] = theta[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
 }
 
-// Mass fractions this far below zero (round-off in the transport of a vanishing
-// species) still count as inside the hull.
-constexpr double Y_NEG_TOL = 1e-6;
+// Mass fractions this far below zero still count as inside the hull: central
+// differences leave undershoots of this size where a species vanishes (shocks, the
+// wall extrapolation), and the network sees them as the zero it was trained on.
+constexpr double Y_NEG_TOL = 1e-3;
 
 // Inputs of the network from an SI state; returns false outside the training hull
 // (log10 rho outside [min, max], a negative mass fraction, e outside

