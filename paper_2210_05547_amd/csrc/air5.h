@@ -259,8 +259,15 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
   }
   out.mu = mu;
   out.kappa = kap;
-  // reciprocal binary coefficients 1/D_sr = p Omega11 / (B_sr T^(3/2))
-  R iD[NS][NS];
+  // reciprocal binary coefficients 1/D_sr = p Omega11 / (B_sr T^(3/2)), each pair
+  // accumulated straight into the two sums of Eq. (19) that use it (the pairs are
+  // visited so that every sum still runs over r in increasing order)
+  R Xc[NS], den[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    Xc[s] = R(X[s] > X_CLIP ? X[s] : X_CLIP);
+    den[s] = R(0);
+  }
   const R pr_iT15 = R(p) / (Tr * sqT);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
@@ -276,23 +283,17 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
                    R(0.19300) * exp(R(-0.47635) * Ts) + R(1.03587) * exp(R(-1.52996) * Ts) +
                    R(1.76474) * exp(R(-3.89411) * Ts);
       const R v = pr_iT15 * om * iB;
-      iD[s][r] = v;
-      iD[r][s] = v;
+      den[s] += Xc[r] * v;
+      den[r] += Xc[s] * v;
     }
   }
-  R Xc[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) Xc[s] = R(X[s] > X_CLIP ? X[s] : X_CLIP);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    R num = R(0), den = R(0);
+    R num = R(0);
 #pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      if (r == s) continue;
-      num += Xc[r];
-      den += Xc[r] * iD[s][r];
-    }
-    out.D[s] = num / den;
+    for (int r = 0; r < NS; ++r)
+      if (r != s) num += Xc[r];
+    out.D[s] = num / den[s];
   }
 }
 

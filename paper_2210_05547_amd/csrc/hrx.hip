@@ -54,6 +54,7 @@ struct Dev {
   int nad;                        // artificial-diffusivity planes (3 + ns)
   int gx;                         // x segments of TX points per grid row
   int tgx, tgy;                   // 2-D LDS tiles per row / column
+  int tgz;                        // 3-D (x, z) tiles along z
   int warm;                       // W holds a previous temperature field (Newton warm start)
 };
 
@@ -232,6 +233,23 @@ __device__ __forceinline__ bool grid_point(const Dev& d, Pt& p) {
   return p.i < d.nx;
 }
 
+// Same grid with the plane index k varying fastest (then the x segment, then the row
+// j): the blocks an XCD runs back to back hold z-neighbours, which its L2 then serves.
+// For kernels whose only stencil runs along z.
+__device__ __forceinline__ bool grid_point_zfast(const Dev& d, Pt& p) {
+  const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
+  const unsigned per = nb >> 3;
+  const unsigned L = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
+  const unsigned nz = (unsigned)d.nz, gx = (unsigned)d.gx;
+  const unsigned r = L / nz;
+  p.k = (int)(L - r * nz);
+  const unsigned jr = r / gx;
+  p.i = (int)((r - jr * gx) * TX + threadIdx.x);
+  p.j = (int)jr;
+  p.idx = ((long)p.k * d.ny + p.j) * d.nx + p.i;
+  return p.i < d.nx;
+}
+
 // 2-D stencil tiles staged through LDS: a block of 256 threads owns TTX x TTY points
 // and loads its source planes with a halo of 4 on each side (TW x TH values per plane;
 // 4 = the reach of the one-sided closures from an end point) in one pass of
@@ -269,6 +287,36 @@ __device__ __forceinline__ void tile_origin(const Dev& d, int& i0, int& j0) {
   const unsigned by = L / tgx;
   i0 = (int)(L - by * tgx) * TTX;
   j0 = (int)by * TTY;
+}
+
+// 3-D tiles lie in the (x, z) plane, TTX x TTY points with a halo of 4 (z periodic),
+// one grid row j per block.  Consecutive blocks (one XCD's range) walk the z tiles of a
+// row, then the next row: the z halo a tile stages was staged by the block before it.
+__device__ __forceinline__ void tile_origin3(const Dev& d, int& i0, int& j, int& k0) {
+  const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
+  const unsigned per = nb >> 3;
+  const unsigned L = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
+  const unsigned ny = (unsigned)d.ny, tgz = (unsigned)d.tgz;
+  const unsigned t = L / tgz;
+  k0 = (int)(L - t * tgz) * TTY;
+  const unsigned xt = t / ny;
+  j = (int)(t - xt * ny);
+  i0 = (int)xt * TTX;
+}
+
+// central first-derivative stencil (periodic direction staged with its halo)
+template <int ORDER>
+__device__ __forceinline__ Sten make_sten_central(long idx, long s) {
+  Sten t;
+  t.p[0] = idx + s; t.q[0] = idx - s;
+  t.p[1] = idx + 2 * s; t.q[1] = idx - 2 * s;
+  t.p[2] = ORDER == 6 ? idx + 3 * s : idx; t.q[2] = ORDER == 6 ? idx - 3 * s : idx;
+  t.p[3] = idx; t.q[3] = idx;
+  t.a[0] = ORDER == 6 ? 0.75 : 2.0 / 3.0;
+  t.a[1] = ORDER == 6 ? -0.15 : -1.0 / 12.0;
+  t.a[2] = ORDER == 6 ? 1.0 / 60.0 : 0.0;
+  t.a[3] = 0.0;
+  return t;
 }
 
 __device__ __forceinline__ Pt point_of(const Dev& d, long idx) {
@@ -448,7 +496,7 @@ __global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict_
                                                 const double* __restrict__ Wd,
                                                 RT* __restrict__ A) {
   Pt p;
-  if (!grid_point(d, p)) return;
+  if (!(ND == 3 ? grid_point_zfast(d, p) : grid_point(d, p))) return;
   const long idx = p.idx;
   const long N = d.N;
   Sten sd[3];
@@ -528,7 +576,7 @@ template <int GAS, int ND, class RT>
 __global__ __launch_bounds__(128) void k_ad_d4(Dev d, const RT* __restrict__ A,
                                                RT* __restrict__ B) {
   Pt p;
-  if (!grid_point(d, p)) return;
+  if (!(ND == 3 ? grid_point_zfast(d, p) : grid_point(d, p))) return;
   const long idx = p.idx;
   const long N = d.N;
   const RT dl[3] = {RT(d.dlx[p.i]), RT(d.dly[p.j]), ND == 3 ? RT(d.dlz[p.k]) : RT(1)};
@@ -572,7 +620,7 @@ template <int DIR, class RT>
 __global__ __launch_bounds__(128) void k_ad_filter(Dev d, const RT* __restrict__ in,
                                                    RT* __restrict__ out) {
   Pt p;
-  if (!grid_point(d, p)) return;
+  if (!(DIR == 2 ? grid_point_zfast(d, p) : grid_point(d, p))) return;
   const long idx = p.idx;
   const long N = d.N;
   const int i = DIR == 0 ? p.i : (DIR == 1 ? p.j : p.k);
@@ -626,27 +674,39 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
   long splane;              // distance between source planes
   Sten sd[3];
   if (TILED) {
-    int i0, j0;
-    tile_origin(d, i0, j0);
+    // 2-D: tile in (x, y); 3-D: tile in (x, z) at row j0, y differences from memory
+    int i0, j0, k0 = 0;
+    if (ND == 2) tile_origin(d, i0, j0);
+    else tile_origin3(d, i0, j0, k0);
     stage_tile<NSRC * TILE_E, TTX * TTY>(smem, [&](int e) {
       const int v = e / TILE_E, r = e - v * TILE_E;
       const int ly = r / TW, lx = r - ly * TW;
       const int gi = min(max(i0 + lx - THALO, 0), d.nx - 1);
-      const int gj = min(max(j0 + ly - THALO, 0), d.ny - 1);
-      return Wd[(long)v * N + (long)gj * d.nx + gi];
+      if (ND == 2) {
+        const int gj = min(max(j0 + ly - THALO, 0), d.ny - 1);
+        return Wd[(long)v * N + (long)gj * d.nx + gi];
+      }
+      int gk = k0 + ly - THALO;
+      gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
+      return Wd[(long)v * N + ((long)gk * d.ny + j0) * d.nx + gi];
     });
     __syncthreads();
     const int tx = threadIdx.x & (TTX - 1), ty = threadIdx.x / TTX;
     p.i = i0 + tx;
-    p.j = j0 + ty;
-    p.k = 0;
-    if (p.i >= d.nx || p.j >= d.ny) return;
-    p.idx = (long)p.j * d.nx + p.i;
+    p.j = ND == 2 ? j0 + ty : j0;
+    p.k = ND == 2 ? 0 : k0 + ty;
+    if (p.i >= d.nx || p.j >= d.ny || p.k >= d.nz) return;
+    p.idx = ((long)p.k * d.ny + p.j) * d.nx + p.i;
     sidx = (long)(ty + THALO) * TW + tx + THALO;
     src = smem;
     splane = TILE_E;
     sd[0] = make_sten<ORDER>(sidx, 1, p.i, d.nx);
-    sd[1] = make_sten<ORDER>(sidx, TW, p.j, d.ny);
+    if (ND == 2) {
+      sd[1] = make_sten<ORDER>(sidx, TW, p.j, d.ny);
+    } else {
+      sd[1] = make_sten<ORDER>(p.idx, d.nx, p.j, d.ny);
+      sd[2] = make_sten_central<ORDER>(sidx, TW);
+    }
   } else {
     if (!grid_point(d, p)) return;
     sidx = p.idx;
@@ -664,6 +724,7 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
   constexpr int NPI = ORDER == 6 ? 3 : 2;
   // derivative of source plane a along direction b (z is periodic: central pairs only)
   auto deriv = [&](int a, int b) -> RT {
+    if (TILED && ND == 3 && b == 1) return sten_apply<RT>(sd[1], Wd + (long)a * N) * md[1];
     const double* f = src + a * splane;
     if (b == 2) return sten_apply<RT, NPI>(sd[b], f) * md[b];
     return sten_apply<RT>(sd[b], f) * md[b];
@@ -1595,6 +1656,7 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   d.gx = (c.nx + TX - 1) / TX;
   d.tgx = (c.nx + TTX - 1) / TTX;
   d.tgy = (c.ny + TTY - 1) / TTY;
+  d.tgz = (c.nz + TTY - 1) / TTY;
   d.newton_rtol = c.newton_rtol > 0.0 ? c.newton_rtol : 1e-13;
   d.newton_max = c.newton_max_iter > 0 ? c.newton_max_iter : 50;
   d.wall = c.wall; d.T_wall = c.T_wall;
@@ -1779,19 +1841,12 @@ template <int GAS, int ND, int ORDER, bool AD, class RT>
 void launch_flux(hrx_ctx* ctx, hipStream_t st, const double* Q, const double* Wd, const RT* Wp,
                  const RT* Gad, double* F) {
   const Dev& d = ctx->dev;
-  if (ND == 2) {
-    constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);
-    const unsigned nt = (unsigned)d.tgx * d.tgy;
-    timed(ctx, K_FLUX, st, [&] {
-      k_flux<GAS, ND, ORDER, AD, RT, true>
-          <<<nt, TTX * TTY, NSRC * TILE_E * sizeof(double), st>>>(d, Q, Wd, Wp, Gad, F);
-    });
-  } else {
-    const unsigned ng = (unsigned)d.gx * d.ny * d.nz;
-    timed(ctx, K_FLUX, st, [&] {
-      k_flux<GAS, ND, ORDER, AD, RT, false><<<ng, TX, 0, st>>>(d, Q, Wd, Wp, Gad, F);
-    });
-  }
+  constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);
+  const unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
+  timed(ctx, K_FLUX, st, [&] {
+    k_flux<GAS, ND, ORDER, AD, RT, true>
+        <<<nt, TTX * TTY, NSRC * TILE_E * sizeof(double), st>>>(d, Q, Wd, Wp, Gad, F);
+  });
 }
 
 template <int GAS, int ND, int ORDER, int MODE, class RT>
