@@ -77,11 +77,15 @@ def cpu_baseline(cfg, Q, Qr, info, budget_s):
                        f"single thread, {dt:.1f} s")
 
 
-def time_form(cfg, Q, Qr, info, steps, warmup, precision):
-    """Mpts/s of the same stage loop with another precision form (graph replay on)."""
+def time_form(cfg, Q, Qr, info, steps, warmup, precision, setup=None):
+    """Mpts/s of the same stage loop in another form (graph replay on); setup(ctx) may
+    prepare the context first (the surrogate form trains its network there)."""
     import torch
     from paper_2210_05547_amd import hrx
     ctx = hrx.Context(cfg, info["x"], info["y"], info["z"], info["hold"], precision=precision)
+    if setup is not None:
+        setup(ctx)
+    ctx.counters(reset=True)
     Qd = torch.from_numpy(Q).to("cuda:0")
     Qrd = torch.from_numpy(Qr).to("cuda:0")
     dQd = torch.zeros_like(Qd)
@@ -97,6 +101,7 @@ def time_form(cfg, Q, Qr, info, steps, warmup, precision):
             hrx.rk_stage(ctx, k, info["dt"], Qd, dQd, Qrd)
         b.record()
         torch.cuda.synchronize()
+    time_form.fallbacks = ctx.counters()["surrogate_fallbacks"]
     ctx.close()
     return cfg.npts * steps / (a.elapsed_time(b) * 1e-3) / 1e6
 
@@ -111,6 +116,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip timing the mixed FP32/FP64 form on the same workload")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip training the surrogate and timing its form")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 10 times (counter scaling)")
     args = ap.parse_args()
@@ -219,6 +226,21 @@ def main():
         out["forms"] = {"fp64": out["value"],
                         "mixed": round(time_form(cfg, Q, Qr, info, args.steps, args.warmup,
                                                  hrx.PREC_MIXED), 2)}
+    if not args.no_surrogate and cfg.gas == 1:
+        from paper_2210_05547_amd import surrogate
+        summary = {}
+
+        def setup(ctx):
+            t0 = time.perf_counter()
+            summary.update(surrogate.train(ctx))
+            torch.cuda.synchronize()
+            summary["train_seconds"] = round(time.perf_counter() - t0, 1)
+            hrx.set_thermo_mode(ctx, hrx.THERMO_SURROGATE)
+        rate = time_form(cfg, Q, Qr, info, args.steps, args.warmup, hrx.PREC_FP64, setup)
+        out.setdefault("forms", {"fp64": out["value"]})["surrogate"] = round(rate, 2)
+        summary["fallback_fraction"] = round(
+            time_form.fallbacks / (cfg.npts * (args.steps + args.warmup)), 5)
+        out["surrogate"] = summary
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, Q, Qr, info, args.cpu_seconds)
     ctx.close()

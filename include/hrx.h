@@ -171,6 +171,11 @@ int hrx_mlp_get_params(hrx_ctx *ctx, float *theta_out, void *hip_stream);
  * sum_s Y_s e_s(T_hi), and the mass fraction of the element N,
  * Y_N2 + Y_NO M_N/M_NO + Y_N, in [xiN_min, xiN_max].  HRX_EINVAL for non-positive
  * std entries or empty ranges. */
+/* Raw surrogate features f [n][7] (device, FP32, row per state) of SI states rho [n],
+ * e [n], Y [5][n] (device): (log10 rho, ln T_c, Y_1..Y_5) as defined for
+ * hrx_mlp_set_norm below -- the inputs a training set needs.  No hull check. */
+int hrx_mlp_features(hrx_ctx *ctx, int64_t n, const double *rho, const double *e,
+                     const double *Y, float *f, void *hip_stream);
 int hrx_mlp_set_norm(hrx_ctx *ctx, const float *in_mean, const float *in_std,
                      const float *out_mean, const float *out_std, const float *out_lin,
                      double log10rho_min, double log10rho_max, double T_lo, double T_hi,

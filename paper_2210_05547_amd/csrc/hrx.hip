@@ -1332,27 +1332,56 @@ constexpr double Y_NEG_TOL = 1e-3;
 // Inputs of the network from an SI state; returns false outside the training hull
 // (log10 rho outside [min, max], a negative mass fraction, e outside
 // [sum Y e_s(T_lo), sum Y e_s(T_hi)], or the element-N mass fraction outside its range).
+// Raw features of an SI state: (log10 rho, ln T_c, Y_1..Y_5) with T_c the energy over
+// the heat capacity of fully excited modes, (e - sum Y_s h0_s/M_s) / sum Y_s c_s.
+__device__ __forceinline__ void surrogate_features(double rho, double e, const double* Y,
+                                                   float* f) {
+  double ef = 0.0, cf = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    ef += Y[s] * (hf0_molar(s) / molar_mass(s));
+    cf += Y[s] * (gas_const(s) * (is_diatomic(s) ? 3.5 : 1.5));
+  }
+  const double ex = e - ef;
+  f[0] = __log10f((float)rho);
+  f[1] = ex > 0.0 && cf > 0.0 ? __logf((float)ex / (float)cf) : 0.0f;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) f[2 + s] = (float)Y[s];
+}
+
 __device__ __forceinline__ bool surrogate_inputs(const MlpNorm& nm, double rho, double e,
                                                  const double* Y, float* x) {
-  const float lr = __log10f((float)rho);
-  double elo = 0.0, ehi = 0.0, ef = 0.0, cf = 0.0;
-  bool ok = lr >= nm.log10rho_min && lr <= nm.log10rho_max;
+  float f[MLP_NIN];
+  surrogate_features(rho, e, Y, f);
+  double elo = 0.0, ehi = 0.0;
+  bool ok = f[0] >= nm.log10rho_min && f[0] <= nm.log10rho_max;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     elo += Y[s] * nm.e_lo[s];
     ehi += Y[s] * nm.e_hi[s];
-    ef += Y[s] * (hf0_molar(s) / molar_mass(s));
-    cf += Y[s] * (gas_const(s) * (is_diatomic(s) ? 3.5 : 1.5));
     ok = ok && Y[s] >= -Y_NEG_TOL;
   }
   const double xiN = Y[0] + Y[2] * (molar_mass(3) / molar_mass(2)) + Y[3];
   ok = ok && e >= elo && e <= ehi && xiN >= nm.xiN_min && xiN <= nm.xiN_max;
-  const float lTc = ok ? __logf((float)(e - ef) / (float)cf) : 0.0f;
-  const float raw[MLP_NIN] = {lr, lTc, (float)Y[0], (float)Y[1], (float)Y[2], (float)Y[3],
-                              (float)Y[4]};
 #pragma unroll
-  for (int k = 0; k < MLP_NIN; ++k) x[k] = ok ? (raw[k] - nm.in_mean[k]) * nm.in_istd[k] : 0.0f;
+  for (int k = 0; k < MLP_NIN; ++k) x[k] = ok ? (f[k] - nm.in_mean[k]) * nm.in_istd[k] : 0.0f;
   return ok;
+}
+
+// Raw features of n SI states, f [n][7] (FP32), for building training sets.
+__global__ __launch_bounds__(256) void k_mlp_features(long n, const double* __restrict__ rho,
+                                                      const double* __restrict__ e,
+                                                      const double* __restrict__ Yin,
+                                                      float* __restrict__ f) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double Y[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + i];
+  float v[MLP_NIN];
+  surrogate_features(rho[i], e[i], Y, v);
+#pragma unroll
+  for (int k = 0; k < MLP_NIN; ++k) f[i * MLP_NIN + k] = v[k];
 }
 
 // network outputs -> (ln T, ln mu, ln kappa, ln(rho D_s)) (SI), FP32
@@ -2188,6 +2217,16 @@ int hrx_mlp_set_norm(hrx_ctx* ctx, const float* in_mean, const float* in_std,
   if (rc) return rc;
   ctx->mlp_norm = true;
   return HRX_OK;
+}
+
+int hrx_mlp_features(hrx_ctx* ctx, int64_t n, const double* rho, const double* e,
+                     const double* Y, float* f, void* hip_stream) {
+  if (!ctx || n < 0 || (n > 0 && (!rho || !e || !Y || !f))) return HRX_EINVAL;
+  if (n == 0) return HRX_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  k_mlp_features<<<blocks_for(n, 256), 256, 0, st>>>(n, rho, e, Y, f);
+  return check(hipGetLastError());
 }
 
 int hrx_set_thermo_mode(hrx_ctx* ctx, int mode) {

@@ -368,3 +368,33 @@ def thermo_states(n, seed=7, T_range=(200.0, 8000.0), logrho_range=(-4.0, 0.0)):
     rho = 10.0 ** rng.uniform(logrho_range[0], logrho_range[1], n)
     Y = np.ascontiguousarray(rng.dirichlet(np.ones(5), n).T)
     return rho, T, Y, _crude_energy(T, Y)
+
+
+def air_compositions(n, rng, xi_range=(0.70, 0.83)):
+    """Air mass fractions [5][n] at every dissociation degree (surrogate training set).
+
+    The mass fraction of the element N is xi_N ~ U(xi_range) (air: 0.767); a share of
+    the elements is bound in NO (up to half of what the scarcer element allows, density
+    rising towards zero); the rest of each element splits between its molecule and its
+    atom with an atomic share ~ U(0, 1).
+    """
+    xiN = rng.uniform(xi_range[0], xi_range[1], n)
+    xiO = 1.0 - xiN
+    fN, fO = _M[3] / _M[2], _M[4] / _M[2]     # element mass shares of NO
+    no_max = np.minimum(xiN / fN, xiO / fO)
+    yNO = rng.uniform(0.0, 1.0, n) ** 2 * 0.5 * no_max
+    remN, remO = xiN - fN * yNO, xiO - fO * yNO
+    aN, aO = rng.uniform(0.0, 1.0, n), rng.uniform(0.0, 1.0, n)
+    Y = np.stack([remN * (1.0 - aN), remO * (1.0 - aO), yNO, remN * aN, remO * aO])
+    return np.ascontiguousarray(Y / Y.sum(0))
+
+
+def air_states(n, seed, T_range=(200.0, 8000.0), logrho_range=(-4.0, 0.0)):
+    """Random SI air states (rho [kg/m3], T [K], Y [5][n], e [J/kg]): T ~ U(T_range),
+    rho ~ 10^U(logrho_range), Y from air_compositions; e is the generator's crude energy
+    at (T, Y) (a thermodynamic model recovers a temperature near, not at, T)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = rng.uniform(T_range[0], T_range[1], n)
+    rho = 10.0 ** rng.uniform(logrho_range[0], logrho_range[1], n)
+    Y = air_compositions(n, rng)
+    return rho, T, Y, _crude_energy(T, Y)

@@ -97,11 +97,13 @@ def load(path: str = LIB_PATH):
                                      C.POINTER(f32), C.POINTER(f32), C.c_double, C.c_double,
                                      C.c_double, C.c_double, C.c_double, C.c_double]
     lib.hrx_set_thermo_mode.argtypes = [vp, C.c_int]
+    lib.hrx_mlp_features.argtypes = [vp, i64, dp, dp, dp, dp, vp]
     lib.hrx_mlp_forward.argtypes = [vp, i64, dp, dp, vp]
     lib.hrx_mlp_backward.argtypes = [vp, i64, dp, dp, dp, vp]
     lib.hrx_adam_step.argtypes = [vp, dp, f32, C.c_int, vp]
     lib.hrx_mlp_train_step.argtypes = [vp, i64, dp, dp, dp, f32, C.c_int, dp, vp]
     for fn in ("hrx_mlp_init", "hrx_mlp_set_params", "hrx_mlp_get_params", "hrx_mlp_set_norm",
+               "hrx_mlp_features",
                "hrx_set_thermo_mode", "hrx_mlp_forward", "hrx_mlp_backward", "hrx_adam_step",
                "hrx_mlp_train_step"):
         getattr(lib, fn).restype = C.c_int
@@ -261,6 +263,12 @@ def mlp_set_norm(ctx, in_mean, in_std, out_mean, out_std, log10rho_range, T_rang
     _check(_lib.hrx_mlp_set_norm(ctx._h, *ptrs, lptr, float(log10rho_range[0]),
                                  float(log10rho_range[1]), float(T_range[0]), float(T_range[1]),
                                  float(xiN_range[0]), float(xiN_range[1])))
+
+
+def mlp_features(ctx, n, rho, e, Y, f, stream=None):
+    """Raw surrogate features f [n][7] (FP32) of SI states (hrx_mlp_features)."""
+    _check(_lib.hrx_mlp_features(ctx._h, int(n), _ptr(rho), _ptr(e), _ptr(Y), _ptr(f),
+                                 _stream(stream)))
 
 
 def set_thermo_mode(ctx, mode):

@@ -1,0 +1,87 @@
+"""Training the thermochemistry surrogate with the library alone (no CPU reference).
+
+States are drawn by ``fields.air_states``; the labels (T, mu, kappa, D_s) come from the
+library's plain FP64 evaluation (``thermo_eval``), the features from
+``hrx_mlp_features``, and the training from ``hrx_mlp_train_step`` -- every step on the
+GPU.  The composition around the network follows ``hrx_mlp_set_norm``: standardised
+features, and targets (ln T, ln mu, ln kappa, ln(rho D_s)) standardised about their
+least-squares linear fit in the standardised features.
+"""
+import math
+
+import numpy as np
+import torch
+
+from . import fields, hrx
+
+T_RANGE = (200.0, 8000.0)
+LOGRHO_RANGE = (-4.0, 0.0)
+XI_N_RANGE = (0.70, 0.83)
+
+
+def training_set(ctx, n, seed, device="cuda:0"):
+    """(features [n][7] float64 host, targets [n][8] float64 host) of n air states."""
+    rho, _, Y, e = fields.air_states(n, seed, T_RANGE, LOGRHO_RANGE)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
+    rd, ed, Yd = d(rho), d(e), d(Y)
+    T = torch.empty(n, dtype=torch.float64, device=device)
+    mu, ka = torch.empty_like(T), torch.empty_like(T)
+    D = torch.empty((5, n), dtype=torch.float64, device=device)
+    f = torch.empty((n, 7), dtype=torch.float32, device=device)
+    mode = hrx.THERMO_PLAIN
+    hrx.set_thermo_mode(ctx, mode)
+    hrx.thermo_eval(ctx, n, rd, ed, Yd, T, mu=mu, kappa=ka, D=D)
+    hrx.mlp_features(ctx, n, rd, ed, Yd, f)
+    targets = torch.cat([T.log()[None], mu.log()[None], ka.log()[None], (D * rd[None]).log()])
+    return f.double().cpu().numpy(), np.ascontiguousarray(targets.T.cpu().numpy())
+
+
+def fit_norm(X, Yt):
+    xm, xs = X.mean(0), X.std(0)
+    A = np.concatenate([np.ones((len(X), 1)), (X - xm) / xs], 1)
+    L = np.linalg.lstsq(A, Yt, rcond=None)[0].T
+    res = Yt - A @ L.T
+    return dict(xm=xm, xs=xs, L=L, ym=res.mean(0), ys=res.std(0))
+
+
+def train(ctx, n=400_000, epochs=60, seed=20221016, batch=4096, lr0=2e-3, init_seed=11,
+          device="cuda:0"):
+    """Train the context's network and install its composition; returns a summary."""
+    X, Yt = training_set(ctx, n, seed, device)
+    nm = fit_norm(X, Yt)
+    A = np.concatenate([np.ones((n, 1)), (X - nm["xm"]) / nm["xs"]], 1)
+    Ys = (Yt - A @ nm["L"].T - nm["ym"]) / nm["ys"]
+    Xd = torch.from_numpy(((X - nm["xm"]) / nm["xs"]).astype(np.float32)).to(device)
+    Yd = torch.from_numpy(np.ascontiguousarray(Ys.astype(np.float32))).to(device)
+    hrx.mlp_init(ctx, batch)
+    theta0 = _glorot(init_seed)
+    hrx.mlp_set_params(ctx, torch.from_numpy(theta0).to(device))
+    loss = torch.zeros(1, dtype=torch.float32, device=device)
+    rng = np.random.default_rng(seed)
+    spe = n // batch
+    total, t = epochs * spe, 0
+    first = None
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n).astype(np.int32)).to(device)
+        loss.zero_()
+        for b in range(spe):
+            t += 1
+            lr = lr0 * 0.5 * (1.0 + math.cos(math.pi * t / total)) + 1e-6
+            hrx.mlp_train_step(ctx, batch, perm[b * batch:(b + 1) * batch], Xd, Yd, lr, t, loss)
+        if first is None:
+            first = float(loss.item()) / spe
+    last = float(loss.item()) / spe
+    hrx.mlp_set_norm(ctx, nm["xm"], nm["xs"], nm["ym"], nm["ys"], LOGRHO_RANGE, T_RANGE,
+                     out_lin=nm["L"], xiN_range=XI_N_RANGE)
+    return dict(states=n, epochs=epochs, loss_first=first, loss_last=last)
+
+
+def _glorot(seed):
+    """Glorot-uniform weights and zero biases in the flat parameter order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for n_in, n_out in ((7, 64), (64, 64), (64, 64), (64, 8)):
+        lim = math.sqrt(6.0 / (n_in + n_out))
+        parts.append(rng.uniform(-lim, lim, n_out * n_in))
+        parts.append(np.zeros(n_out))
+    return np.concatenate(parts).astype(np.float32)

@@ -28,7 +28,7 @@ from oracle import thermo as oth  # noqa: E402
 from oracle import transport as otr  # noqa: E402
 from gpu_util import field_errors, normwise  # noqa: E402
 from surrogate_util import (LOGRHO_RANGE, T_RANGE, XI_N_RANGE, element_N_fraction,  # noqa: E402
-                            fit_norm, network_targets, raw_dataset, set_norm, states)
+                            features, fit_norm, network_targets, raw_dataset, set_norm, states)
 
 DEV = "cuda:0"
 NTOT = 1_000_000
@@ -100,6 +100,20 @@ def with_surrogate(ctx, tr):
     set_norm(hrx, ctx, tr["norm"])
     hrx.set_thermo_mode(ctx, hrx.THERMO_SURROGATE)
     return ctx
+
+
+def test_features_match_oracle_side():
+    """The library's raw features (log10 rho, ln T_c, Y) equal the ones the training set
+    is built with here, to FP32 precision."""
+    n = 5000
+    rho, T, Y = states(n, seed=77)
+    e = oth.mixture_e(T, Y)
+    ctx = air_ctx()
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)  # noqa: E731
+    f = torch.empty((n, 7), dtype=torch.float32, device=DEV)
+    hrx.mlp_features(ctx, n, d(rho), d(e), d(Y), f)
+    ref = features(rho, e, Y)
+    assert np.max(np.abs(f.cpu().numpy() - ref)) <= 2e-5
 
 
 def test_training_reduces_loss(trained):
