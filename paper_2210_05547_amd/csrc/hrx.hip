@@ -263,10 +263,10 @@ constexpr int KCH = 4;                          // flux components staged per LD
 // Stage TOTAL values into LDS: element e comes from src_of(e).  Every thread first issues
 // all of its global loads (held in registers), then writes them, so the loads of a
 // thread are in flight together instead of one round trip per element.
-template <int TOTAL, int NTHREADS, class SrcOf>
-__device__ __forceinline__ void stage_tile(double* __restrict__ dst, SrcOf src_of) {
+template <int TOTAL, int NTHREADS, class T, class SrcOf>
+__device__ __forceinline__ void stage_tile(T* __restrict__ dst, SrcOf src_of) {
   constexpr int PER = (TOTAL + NTHREADS - 1) / NTHREADS;
-  double v[PER];
+  T v[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * NTHREADS;
@@ -652,6 +652,115 @@ __global__ __launch_bounds__(128) void k_ad_filter(Dev d, const RT* __restrict__
       r = acc / wsum;
     }
     out[(long)v * N + idx] = r;
+  }
+}
+
+// The 2-D chain fourth difference -> x filter -> y filter in one pass: a block owns a
+// TTX x STY tile, stages the source plane with a halo of 6 in LDS, forms the fourth
+// differences on the tile plus a halo of 4, filters them along x on the tile's columns,
+// then along y on the tile -- the same formulas, weights and evaluation order as
+// k_ad_d4 and k_ad_filter, read from LDS instead of two intermediate planes in memory.
+// Halo values outside the domain are clamped copies that carry zero filter weight.
+constexpr int STY = 16;                                        // tile rows
+constexpr int AH = 6, AW = TTX + 2 * AH, AHT = STY + 2 * AH;    // staged source
+constexpr int DW = TTX + 8, DHT = STY + 8;                      // fourth differences
+template <int GAS, class RT>
+__global__ __launch_bounds__(256) void k_ad_smooth2(Dev d, const RT* __restrict__ A,
+                                                    RT* __restrict__ B) {
+  __shared__ RT sA[AW * AHT];
+  __shared__ RT sD[DW * DHT];
+  __shared__ RT sX[TTX * DHT];
+  const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
+  const unsigned per = nb >> 3;
+  const unsigned L = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
+  const unsigned by = L / (unsigned)d.tgx;
+  const int i0 = (int)(L - by * (unsigned)d.tgx) * TTX, j0 = (int)by * STY;
+  const int nx = d.nx, ny = d.ny;
+  const long N = d.N;
+  const int t = threadIdx.x;
+  // per fourth-difference slot of this thread (the same for every plane): LDS offsets of
+  // the x taps, the y taps and the centre, and the spacing factors
+  constexpr int NDS = (DW * DHT + 255) / 256;
+  int ox[NDS], oy[NDS], oc[NDS];
+  RT fdx[NDS], fdy[NDS], fdb[NDS];
+#pragma unroll
+  for (int q = 0; q < NDS; ++q) {
+    const int e = t + 256 * q;
+    const int ly = e / DW, lx = e - ly * DW;
+    const int gx = min(max(i0 - 4 + lx, 0), nx - 1);
+    const int gy = min(max(j0 - 4 + ly, 0), ny - 1);
+    const int ic = gx < 2 ? 2 : (gx > nx - 3 ? nx - 3 : gx);
+    const int jc = gy < 2 ? 2 : (gy > ny - 3 ? ny - 3 : gy);
+    ox[q] = (gy - (j0 - AH)) * AW + (ic - 2 - (i0 - AH));
+    oy[q] = (jc - 2 - (j0 - AH)) * AW + (gx - (i0 - AH));
+    oc[q] = (gy - (j0 - AH)) * AW + (gx - (i0 - AH));
+    fdx[q] = RT(d.dlx[gx]);
+    fdy[q] = RT(d.dly[gy]);
+    fdb[q] = RT(sqrt(d.dlx[gx] * d.dly[gy]));
+  }
+  for (int v = 0; v < d.nad; ++v) {
+    const RT* f = A + (long)v * N;
+    if (v > 0) __syncthreads();   // the previous plane's buffers are consumed
+    stage_tile<AW * AHT, 256>(sA, [&](int e) {
+      const int ly = e / AW, lx = e - ly * AW;
+      const int gx = min(max(i0 - AH + lx, 0), nx - 1);
+      const int gy = min(max(j0 - AH + ly, 0), ny - 1);
+      return f[(long)gy * nx + gx];
+    });
+    __syncthreads();
+    const bool sq = v < 2;
+#pragma unroll
+    for (int q = 0; q < NDS; ++q) {
+      const int e = t + 256 * q;
+      if (e >= DW * DHT) break;
+      const RT* ax = sA + ox[q];
+      const RT* ay = sA + oy[q];
+      const RT qx = ax[0] - RT(4) * ax[1] + RT(6) * ax[2] - RT(4) * ax[3] + ax[4];
+      const RT qy = ay[0] - RT(4) * ay[AW] + RT(6) * ay[2 * AW] - RT(4) * ay[3 * AW] + ay[4 * AW];
+      const RT dlx = fdx[q], dly = fdy[q];
+      RT acc = RT(0);
+      acc += qx * (sq ? dlx * dlx : dlx);
+      acc += qy * (sq ? dly * dly : dly);
+      RT out = fabs(acc);
+      if (GAS == AIR5 && v >= 3) {
+        const RT Ys = sA[oc[q]];
+        const RT over = RT(0.5) * (fabs(Ys) - RT(1) + fabs(RT(1) - Ys));
+        out = RT(d.CD) * out + RT(d.CY) * over * fdb[q];
+      }
+      sD[e] = out;
+    }
+    __syncthreads();
+    for (int e = t; e < TTX * DHT; e += 256) {
+      const int ly = e / TTX, lx = e - ly * TTX;
+      const int gx = i0 + lx;
+      if (gx >= nx) continue;
+      RT acc = RT(0), wsum = RT(0);
+#pragma unroll
+      for (int k = -4; k <= 4; ++k) {
+        const int q = gx + k;
+        const RT w = (q >= 0 && q < nx) ? RT(c_gauss9[k < 0 ? -k : k]) : RT(0);
+        const int qc = q < 0 ? 0 : (q >= nx ? nx - 1 : q);
+        acc += w * sD[ly * DW + (qc - (i0 - 4))];
+        wsum += w;
+      }
+      sX[e] = acc / wsum;
+    }
+    __syncthreads();
+    for (int e = t; e < TTX * STY; e += 256) {
+      const int ty = e / TTX, tx = e - ty * TTX;
+      const int gx = i0 + tx, gy = j0 + ty;
+      if (gx >= nx || gy >= ny) continue;
+      RT acc = RT(0), wsum = RT(0);
+#pragma unroll
+      for (int k = -4; k <= 4; ++k) {
+        const int q = gy + k;
+        const RT w = (q >= 0 && q < ny) ? RT(c_gauss9[k < 0 ? -k : k]) : RT(0);
+        const int qc = q < 0 ? 0 : (q >= ny ? ny - 1 : q);
+        acc += w * sX[(qc - (j0 - 4)) * TTX + tx];
+        wsum += w;
+      }
+      B[(long)v * N + (long)gy * nx + gx] = acc / wsum;
+    }
   }
 }
 
@@ -1925,9 +2034,17 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
     RT* B = A + (long)d.nad * N;
     const RT* Gad;
     timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER, RT><<<ng, TX, 0, st>>>(d, Q, Wd, A); });
-    timed(ctx, K_AD_D4, st, [&] { k_ad_d4<GAS, ND, RT><<<ng, TX, 0, st>>>(d, A, B); });
-    timed(ctx, K_AD_FX, st, [&] { k_ad_filter<0, RT><<<ng, TX, 0, st>>>(d, B, A); });
-    timed(ctx, K_AD_FY, st, [&] { k_ad_filter<1, RT><<<ng, TX, 0, st>>>(d, A, B); });
+    if (ND == 2) {
+      // fourth differences and both filters in one LDS pass (timed as ad_d4)
+      timed(ctx, K_AD_D4, st, [&] {
+        k_ad_smooth2<GAS, RT>
+            <<<(unsigned)(d.tgx * ((d.ny + STY - 1) / STY)), 256, 0, st>>>(d, A, B);
+      });
+    } else {
+      timed(ctx, K_AD_D4, st, [&] { k_ad_d4<GAS, ND, RT><<<ng, TX, 0, st>>>(d, A, B); });
+      timed(ctx, K_AD_FX, st, [&] { k_ad_filter<0, RT><<<ng, TX, 0, st>>>(d, B, A); });
+      timed(ctx, K_AD_FY, st, [&] { k_ad_filter<1, RT><<<ng, TX, 0, st>>>(d, A, B); });
+    }
     if (ND == 3) {
       timed(ctx, K_AD_FZ, st, [&] { k_ad_filter<2, RT><<<ng, TX, 0, st>>>(d, B, A); });
       Gad = A;
