@@ -552,105 +552,32 @@ __global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict_
   }
 }
 
-// fourth difference along a line, copying the nearest interior value at the two
-// first and last points of a non-periodic line
-template <class RT>
-__device__ __forceinline__ RT d4line(const RT* __restrict__ f, long idx, long s, int i, int n) {
-  int ic = i < 2 ? 2 : (i > n - 3 ? n - 3 : i);
-  const long c = idx + (long)(ic - i) * s;
-  return f[c - 2 * s] - RT(4) * f[c - s] + RT(6) * f[c] - RT(4) * f[c + s] + f[c + 2 * s];
-}
-template <class RT>
-__device__ __forceinline__ RT d4per(const RT* __restrict__ f, long idx, long s, int i, int n) {
-  const long base = idx - (long)i * s;
-  auto at = [&](int m) {
-    int q = i + m;
-    q = q < 0 ? q + n : (q >= n ? q - n : q);
-    return f[base + (long)q * s];
-  };
-  return at(-2) - RT(4) * at(-1) + RT(6) * f[idx] - RT(4) * at(1) + at(2);
-}
 
-// B planes: [a_mu, a_beta, a_kappa, a_D,1..ns] before filtering
-template <int GAS, int ND, class RT>
-__global__ __launch_bounds__(128) void k_ad_d4(Dev d, const RT* __restrict__ A,
-                                               RT* __restrict__ B) {
-  Pt p;
-  if (!(ND == 3 ? grid_point_zfast(d, p) : grid_point(d, p))) return;
-  const long idx = p.idx;
-  const long N = d.N;
-  const RT dl[3] = {RT(d.dlx[p.i]), RT(d.dly[p.j]), ND == 3 ? RT(d.dlz[p.k]) : RT(1)};
-  RT dbar;
-  if (ND == 2)
-    dbar = RT(pow(d.dlx[p.i] * d.dly[p.j], 0.5));
-  else
-    dbar = RT(pow(d.dlx[p.i] * d.dly[p.j] * d.dlz[p.k], 1.0 / 3.0));
-  const int nplanes = 3 + ((GAS == AIR5) ? NS : 0);
-  for (int v = 0; v < nplanes; ++v) {
-    const RT* f = A + (long)v * N;
-    const bool sq = v < 2;
-    RT acc = RT(0);
-#pragma unroll
-    for (int l = 0; l < ND; ++l) {
-      RT q;
-      if (l == 0)
-        q = d4line<RT>(f, idx, 1, p.i, d.nx);
-      else if (l == 1)
-        q = d4line<RT>(f, idx, d.nx, p.j, d.ny);
-      else
-        q = d4per<RT>(f, idx, (long)d.nx * d.ny, p.k, d.nz);
-      acc += q * (sq ? dl[l] * dl[l] : dl[l]);
-    }
-    RT out = fabs(acc);
-    if (v >= 3) {
-      const RT Ys = f[idx];
-      const RT over = RT(0.5) * (fabs(Ys) - RT(1) + fabs(RT(1) - Ys));
-      out = RT(d.CD) * out + RT(d.CY) * over * dbar;
-    }
-    B[(long)v * N + idx] = out;
-  }
-}
-
-// 9-point truncated Gaussian filter along one direction (renormalised at
-// non-periodic ends; periodic in z)
+// 9-point truncated Gaussian filter (Gaussian weights renormalised at non-periodic
+// ends; x and y are filtered inside k_ad_smooth), here along the periodic z direction
 __constant__ double c_gauss9[5] = {3565.0 / 10368.0, 3091.0 / 12960.0, 1997.0 / 25920.0,
                                    149.0 / 12960.0, 107.0 / 103680.0};
 
-template <int DIR, class RT>
-__global__ __launch_bounds__(128) void k_ad_filter(Dev d, const RT* __restrict__ in,
-                                                   RT* __restrict__ out) {
+template <class RT>
+__global__ __launch_bounds__(128) void k_ad_filter_z(Dev d, const RT* __restrict__ in,
+                                                     RT* __restrict__ out) {
   Pt p;
-  if (!(DIR == 2 ? grid_point_zfast(d, p) : grid_point(d, p))) return;
+  if (!grid_point_zfast(d, p)) return;
   const long idx = p.idx;
   const long N = d.N;
-  const int i = DIR == 0 ? p.i : (DIR == 1 ? p.j : p.k);
-  const int n = DIR == 0 ? d.nx : (DIR == 1 ? d.ny : d.nz);
-  const long s = DIR == 0 ? 1 : (DIR == 1 ? (long)d.nx : (long)d.nx * d.ny);
+  const int i = p.k, n = d.nz;
+  const long s = (long)d.nx * d.ny;
+  const long base = idx - (long)i * s;
   for (int v = 0; v < d.nad; ++v) {
     const RT* f = in + (long)v * N;
-    RT r;
-    if (DIR == 2) {
-      const long base = idx - (long)i * s;
-      auto at = [&](int m) {
-        int q = i + m;
-        q = q < 0 ? q + n : (q >= n ? q - n : q);
-        return f[base + (long)q * s];
-      };
-      r = RT(c_gauss9[0]) * f[idx];
+    auto at = [&](int m) {
+      int q = i + m;
+      q = q < 0 ? q + n : (q >= n ? q - n : q);
+      return f[base + (long)q * s];
+    };
+    RT r = RT(c_gauss9[0]) * f[idx];
 #pragma unroll
-      for (int k = 1; k <= 4; ++k) r += RT(c_gauss9[k]) * (at(-k) + at(k));
-    } else {
-      RT acc = RT(0), wsum = RT(0);
-#pragma unroll
-      for (int k = -4; k <= 4; ++k) {
-        const int q = i + k;
-        const RT w = (q >= 0 && q < n) ? RT(c_gauss9[k < 0 ? -k : k]) : RT(0);
-        const int qc = q < 0 ? 0 : (q >= n ? n - 1 : q);
-        acc += w * f[idx + (long)(qc - i) * s];
-        wsum += w;
-      }
-      r = acc / wsum;
-    }
+    for (int k = 1; k <= 4; ++k) r += RT(c_gauss9[k]) * (at(-k) + at(k));
     out[(long)v * N + idx] = r;
   }
 }
@@ -659,29 +586,40 @@ __global__ __launch_bounds__(128) void k_ad_filter(Dev d, const RT* __restrict__
 // TTX x STY tile, stages the source plane with a halo of 6 in LDS, forms the fourth
 // differences on the tile plus a halo of 4, filters them along x on the tile's columns,
 // then along y on the tile -- the same formulas, weights and evaluation order as
-// k_ad_d4 and k_ad_filter, read from LDS instead of two intermediate planes in memory.
+// the separate passes they replace, read from LDS instead of two intermediate planes.
 // Halo values outside the domain are clamped copies that carry zero filter weight.
+// Within two points of a non-periodic end the fourth difference is the one centred two
+// points in (the stencil never leaves the line).
 constexpr int STY = 16;                                        // tile rows
 constexpr int AH = 6, AW = TTX + 2 * AH, AHT = STY + 2 * AH;    // staged source
 constexpr int DW = TTX + 8, DHT = STY + 8;                      // fourth differences
-template <int GAS, class RT>
-__global__ __launch_bounds__(256) void k_ad_smooth2(Dev d, const RT* __restrict__ A,
-                                                    RT* __restrict__ B) {
+// In 3-D the block works on one plane k of the tile (consecutive blocks hold
+// consecutive planes) and the z term of the fourth difference reads the planes k +- 1,
+// k +- 2 from memory, which the neighbouring blocks have just staged; the z filter
+// follows as its own pass.
+template <int GAS, int ND, class RT>
+__global__ __launch_bounds__(256) void k_ad_smooth(Dev d, const RT* __restrict__ A,
+                                                   RT* __restrict__ B) {
   __shared__ RT sA[AW * AHT];
   __shared__ RT sD[DW * DHT];
   __shared__ RT sX[TTX * DHT];
   const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
   const unsigned per = nb >> 3;
   const unsigned L = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
-  const unsigned by = L / (unsigned)d.tgx;
-  const int i0 = (int)(L - by * (unsigned)d.tgx) * TTX, j0 = (int)by * STY;
-  const int nx = d.nx, ny = d.ny;
+  const unsigned tt = ND == 3 ? L / (unsigned)d.nz : L;
+  const int k = ND == 3 ? (int)(L - tt * (unsigned)d.nz) : 0;
+  const unsigned by = tt / (unsigned)d.tgx;
+  const int i0 = (int)(tt - by * (unsigned)d.tgx) * TTX, j0 = (int)by * STY;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
   const long N = d.N;
+  const long P = (long)nx * ny;        // plane stride
+  const long kb = (long)k * P;         // this plane
   const int t = threadIdx.x;
   // per fourth-difference slot of this thread (the same for every plane): LDS offsets of
   // the x taps, the y taps and the centre, and the spacing factors
   constexpr int NDS = (DW * DHT + 255) / 256;
   int ox[NDS], oy[NDS], oc[NDS];
+  long og[NDS];                        // global in-plane index (z term, 3-D)
   RT fdx[NDS], fdy[NDS], fdb[NDS];
 #pragma unroll
   for (int q = 0; q < NDS; ++q) {
@@ -694,9 +632,20 @@ __global__ __launch_bounds__(256) void k_ad_smooth2(Dev d, const RT* __restrict_
     ox[q] = (gy - (j0 - AH)) * AW + (ic - 2 - (i0 - AH));
     oy[q] = (jc - 2 - (j0 - AH)) * AW + (gx - (i0 - AH));
     oc[q] = (gy - (j0 - AH)) * AW + (gx - (i0 - AH));
+    og[q] = (long)gy * nx + gx;
     fdx[q] = RT(d.dlx[gx]);
     fdy[q] = RT(d.dly[gy]);
-    fdb[q] = RT(sqrt(d.dlx[gx] * d.dly[gy]));
+    fdb[q] = ND == 2 ? RT(sqrt(d.dlx[gx] * d.dly[gy]))
+                     : RT(pow(d.dlx[gx] * d.dly[gy] * d.dlz[k], 1.0 / 3.0));
+  }
+  const RT fdz = ND == 3 ? RT(d.dlz[k]) : RT(0);
+  // the planes k - 2 .. k + 2 (periodic)
+  long kz[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    int q = k + m - 2;
+    q = q < 0 ? q + nz : (q >= nz ? q - nz : q);
+    kz[m] = (long)q * P;
   }
   for (int v = 0; v < d.nad; ++v) {
     const RT* f = A + (long)v * N;
@@ -705,7 +654,7 @@ __global__ __launch_bounds__(256) void k_ad_smooth2(Dev d, const RT* __restrict_
       const int ly = e / AW, lx = e - ly * AW;
       const int gx = min(max(i0 - AH + lx, 0), nx - 1);
       const int gy = min(max(j0 - AH + ly, 0), ny - 1);
-      return f[(long)gy * nx + gx];
+      return f[kb + (long)gy * nx + gx];
     });
     __syncthreads();
     const bool sq = v < 2;
@@ -721,6 +670,12 @@ __global__ __launch_bounds__(256) void k_ad_smooth2(Dev d, const RT* __restrict_
       RT acc = RT(0);
       acc += qx * (sq ? dlx * dlx : dlx);
       acc += qy * (sq ? dly * dly : dly);
+      if (ND == 3) {
+        const RT* fz = f + og[q];
+        const RT qz = fz[kz[0]] - RT(4) * fz[kz[1]] + RT(6) * sA[oc[q]] - RT(4) * fz[kz[3]] +
+                      fz[kz[4]];
+        acc += qz * (sq ? fdz * fdz : fdz);
+      }
       RT out = fabs(acc);
       if (GAS == AIR5 && v >= 3) {
         const RT Ys = sA[oc[q]];
@@ -759,7 +714,7 @@ __global__ __launch_bounds__(256) void k_ad_smooth2(Dev d, const RT* __restrict_
         acc += w * sX[(qc - (j0 - 4)) * TTX + tx];
         wsum += w;
       }
-      B[(long)v * N + (long)gy * nx + gx] = acc / wsum;
+      B[(long)v * N + kb + (long)gy * nx + gx] = acc / wsum;
     }
   }
 }
@@ -2034,19 +1989,13 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
     RT* B = A + (long)d.nad * N;
     const RT* Gad;
     timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER, RT><<<ng, TX, 0, st>>>(d, Q, Wd, A); });
-    if (ND == 2) {
-      // fourth differences and both filters in one LDS pass (timed as ad_d4)
-      timed(ctx, K_AD_D4, st, [&] {
-        k_ad_smooth2<GAS, RT>
-            <<<(unsigned)(d.tgx * ((d.ny + STY - 1) / STY)), 256, 0, st>>>(d, A, B);
-      });
-    } else {
-      timed(ctx, K_AD_D4, st, [&] { k_ad_d4<GAS, ND, RT><<<ng, TX, 0, st>>>(d, A, B); });
-      timed(ctx, K_AD_FX, st, [&] { k_ad_filter<0, RT><<<ng, TX, 0, st>>>(d, B, A); });
-      timed(ctx, K_AD_FY, st, [&] { k_ad_filter<1, RT><<<ng, TX, 0, st>>>(d, A, B); });
-    }
+    // fourth differences and the x and y filters in one LDS pass (timed as ad_d4)
+    timed(ctx, K_AD_D4, st, [&] {
+      k_ad_smooth<GAS, ND, RT>
+          <<<(unsigned)(d.tgx * ((d.ny + STY - 1) / STY) * d.nz), 256, 0, st>>>(d, A, B);
+    });
     if (ND == 3) {
-      timed(ctx, K_AD_FZ, st, [&] { k_ad_filter<2, RT><<<ng, TX, 0, st>>>(d, B, A); });
+      timed(ctx, K_AD_FZ, st, [&] { k_ad_filter_z<RT><<<ng, TX, 0, st>>>(d, B, A); });
       Gad = A;
     } else {
       Gad = B;
