@@ -279,8 +279,8 @@ __device__ __forceinline__ void stage_tile(T* __restrict__ dst, SrcOf src_of) {
   }
 }
 
-__device__ __forceinline__ void tile_origin(const Dev& d, int& i0, int& j0) {
-  const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
+__device__ __forceinline__ void tile_origin(const Dev& d, int& i0, int& j0,
+                                            unsigned b = blockIdx.x, unsigned nb = gridDim.x) {
   const unsigned per = nb >> 3;
   const unsigned L = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
   const unsigned tgx = (unsigned)d.tgx;
@@ -911,6 +911,10 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
 // R = -sum_j dF_j/dx_j (FP64 differences, RT weighted sums) + wdot (species)
 //     - sigma (Q - Q_ref) (FP64); boundary rows; then R out, or the low-storage update
 // of Q and dQ in FP64.
+// Tiled (2-D): a block takes the chunks of KCH components of its tile one after the
+// other, or, when the grid holds one block per tile and chunk (small grids), the chunk
+// its block index names (chunk major: blocks [c nt, (c + 1) nt) take chunk c), so the
+// chunks of a tile run side by side and twice the wavefronts are in flight.
 template <int GAS, int ND, int ORDER, int MODE, class RT, bool TILED>
 __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F,
                                              const RT* __restrict__ Wp, const double* Qin,
@@ -925,8 +929,17 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
   Sten sx, sy, sz;
   int i0 = 0, j0 = 0, tx = 0, ty = 0;
   bool active = true;
+  int kbeg = 0, kend = nvar;
   if (TILED) {
-    tile_origin(d, i0, j0);
+    const unsigned nt = (unsigned)d.tgx * d.tgy;
+    if (gridDim.x > nt) {
+      const unsigned c = blockIdx.x / nt;
+      tile_origin(d, i0, j0, blockIdx.x - c * nt, nt);
+      kbeg = (int)c * KCH;
+      kend = min(kbeg + KCH, nvar);
+    } else {
+      tile_origin(d, i0, j0);
+    }
     tx = threadIdx.x & (TTX - 1);
     ty = threadIdx.x / TTX;
     p.i = i0 + tx;
@@ -951,12 +964,12 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
   if (active && d.hold && p.j < 3) held = held || d.hold[((long)p.k * 3 + p.j) * d.nx + p.i];
   constexpr int NPI = ORDER == 6 ? 3 : 2;
   // components in chunks of KCH; the tiled form stages each chunk's flux tiles in LDS
-  for (int k0 = 0; k0 < nvar; k0 += KCH) {
-    const int kn = min(KCH, nvar - k0);
+  for (int k0 = kbeg; k0 < kend; k0 += KCH) {
+    const int kn = min(KCH, kend - k0);
     if (TILED) {
       double* tx_ = smem;
       double* ty_ = smem + KCH * FXE;
-      if (k0 > 0) __syncthreads();   // previous chunk fully consumed
+      if (k0 > kbeg) __syncthreads();   // previous chunk fully consumed
       // x-flux tiles of the chunk, then y-flux tiles (components past nvar read any
       // valid plane and are never used)
       stage_tile<KCH * FXE, TTX * TTY>(tx_, [&](int e) {
@@ -1337,40 +1350,77 @@ __global__ __launch_bounds__(128) void k_mlp_bwd_delta(long n, const float* __re
   }
 }
 
-// Weight and bias gradients: one block per (layer, output unit); the batch sum runs
-// in four interleaved partial sums combined in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_mlp_wgrad(long n, const float* __restrict__ X,
+// Weight and bias gradients, sum over the batch of delta_L[b][o] a_{L-1}[b][k] (a = the
+// layer's BF16-rounded input as the forward pass used it; a_k = 1 for the bias).  Block
+// (c, L) sums the batch chunk [c cb, (c + 1) cb) for layer L, staging 32 points at a
+// time in LDS; thread t holds the products of output o = t mod O and inputs
+// k = t / O + (256 / O) j.  Partial sums go to part[c][param], summed in chunk order by
+// k_mlp_wgrad_sum (a fixed order: the result does not depend on scheduling).
+constexpr int WG_MAXCH = 64, WG_SB = 32;
+__global__ __launch_bounds__(256) void k_mlp_wgrad(long n, long cb, const float* __restrict__ X,
                                                    const int32_t* __restrict__ idx,
                                                    const float* __restrict__ save,
                                                    const float* __restrict__ delta,
-                                                   float* __restrict__ grad) {
-  __shared__ float redw[4][64];
-  __shared__ float redb[4];
-  int bid = blockIdx.x, L = 0;
-  while (L < 3 && bid >= MLP_NOUT_L[L]) {
-    bid -= MLP_NOUT_L[L];
-    ++L;
-  }
-  const int o = bid;
-  const int nin = MLP_NIN_L[L];
-  const int k = threadIdx.x & 63, part = threadIdx.x >> 6;
-  const int doff = L == 0 ? 0 : (L == 1 ? 64 : (L == 2 ? 128 : 192));
-  float acc = 0.0f, bsum = 0.0f;
-  for (long b = part; b < n; b += 4) {
-    const float dl = delta[b * 200 + doff + o];
-    if (k < nin) {
-      const float ain = (L == 0) ? split_bf(X[(idx ? (long)idx[b] : b) * MLP_NIN + k])
-                                 : bf2f(f2bf(save[((long)(L - 1) * n + b) * 64 + k]));
-      acc += dl * ain;
+                                                   float* __restrict__ part) {
+  __shared__ float sD[WG_SB][64];
+  __shared__ float sA[WG_SB][65];
+  const int L = blockIdx.y;
+  const int O = L == 3 ? MLP_NOUT : MLP_NH, K = L == 0 ? MLP_NIN : MLP_NH;
+  const int doff = 64 * L;
+  const int t = threadIdx.x;
+  const int ks = 256 / O;
+  const int o = t % O, kq = t / O;
+  constexpr int NJ = 17;   // ceil(65 / 4)
+  float acc[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) acc[j] = 0.0f;
+  const long b0 = (long)blockIdx.x * cb, b1 = min(n, b0 + cb);
+  for (long s0 = b0; s0 < b1; s0 += WG_SB) {
+    const int sb = (int)min((long)WG_SB, b1 - s0);
+    for (int e = t; e < WG_SB * O; e += 256) {
+      const int r = e / O, c = e - r * O;
+      sD[r][c] = r < sb ? delta[(s0 + r) * 200 + doff + c] : 0.0f;
     }
-    if (k == 0) bsum += dl;
+    for (int e = t; e < WG_SB * (K + 1); e += 256) {
+      const int r = e / (K + 1), c = e - r * (K + 1);
+      float a = 0.0f;
+      if (r < sb) {
+        const long bb = s0 + r;
+        if (c == K) a = 1.0f;
+        else if (L == 0) a = split_bf(X[(idx ? (long)idx[bb] : bb) * MLP_NIN + c]);
+        else a = bf2f(f2bf(save[((long)(L - 1) * n + bb) * 64 + c]));
+      }
+      sA[r][c] = a;
+    }
+    __syncthreads();
+    for (int r = 0; r < sb; ++r) {
+      const float dl = sD[r][o];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int k = kq + ks * j;
+        if (k <= K) acc[j] += dl * sA[r][k];
+      }
+    }
+    __syncthreads();
   }
-  redw[part][k] = acc;
-  if (k == 0) redb[part] = bsum;
-  __syncthreads();
-  if (part == 0 && k < nin)
-    grad[MLP_OFF_W[L] + o * nin + k] = ((redw[0][k] + redw[1][k]) + redw[2][k]) + redw[3][k];
-  if (threadIdx.x == 0) grad[MLP_OFF_B[L] + o] = ((redb[0] + redb[1]) + redb[2]) + redb[3];
+  float* pc = part + (long)blockIdx.x * MLP_NPARAM;
+  const int offw = L == 0 ? MLP_OFF_W[0] : (L == 1 ? MLP_OFF_W[1] : (L == 2 ? MLP_OFF_W[2] : MLP_OFF_W[3]));
+  const int offb = L == 0 ? MLP_OFF_B[0] : (L == 1 ? MLP_OFF_B[1] : (L == 2 ? MLP_OFF_B[2] : MLP_OFF_B[3]));
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int k = kq + ks * j;
+    if (k < K) pc[offw + o * K + k] = acc[j];
+    else if (k == K) pc[offb + o] = acc[j];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad_sum(int nch, const float* __restrict__ part,
+                                                       float* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= MLP_NPARAM) return;
+  float acc = 0.0f;
+  for (int c = 0; c < nch; ++c) acc += part[(long)c * MLP_NPARAM + p];
+  grad[p] = acc;
 }
 
 // Adam (beta1 = 0.9, beta2 = 0.999, eps = 1e-8) on the FP32 master parameters.
@@ -1559,7 +1609,7 @@ struct hrx_ctx {
   int64_t mlp_maxb = 0;
   float *theta = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
   float *bias = nullptr, *wq = nullptr, *save = nullptr, *ybuf = nullptr, *dybuf = nullptr,
-        *delta = nullptr;
+        *delta = nullptr, *wpart = nullptr;
   uint16_t* wsw = nullptr;
   MlpNorm* norm_dev = nullptr;   // composition statistics and hull (device copy)
   float* ys = nullptr;       // network outputs of the surrogate form, [8][ys_cap]
@@ -1710,7 +1760,7 @@ void hrx_destroy(hrx_ctx* c) {
   (void)hipFree(c->norm_dev);
   for (void* q : {(void*)c->theta, (void*)c->adam_m, (void*)c->adam_v, (void*)c->grad,
                   (void*)c->bias, (void*)c->wq, (void*)c->save, (void*)c->ybuf, (void*)c->dybuf,
-                  (void*)c->delta, (void*)c->wsw})
+                  (void*)c->delta, (void*)c->wpart, (void*)c->wsw})
     (void)hipFree(q);
   delete c;
 }
@@ -1942,13 +1992,19 @@ void launch_flux(hrx_ctx* ctx, hipStream_t st, const double* Q, const double* Wd
   });
 }
 
+// 2-D grids up to this many points run k_div with one block per tile and component
+// chunk (below about two wavefronts per SIMD the chunks of a tile are latency bound).
+constexpr long DIV_SPLIT_MAX_POINTS = 1L << 18;
+
 template <int GAS, int ND, int ORDER, int MODE, class RT>
 void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, const double* Q,
                 const double* Qref, double* R, double* Qio, double* dQ, double A, double B,
                 double dt) {
   const Dev& d = ctx->dev;
   if (ND == 2) {
-    const unsigned nt = (unsigned)d.tgx * d.tgy;
+    constexpr int nvar = (GAS == CPG ? 1 : NS) + ND + 1;
+    unsigned nt = (unsigned)d.tgx * d.tgy;
+    if (d.N <= DIV_SPLIT_MAX_POINTS) nt *= (nvar + KCH - 1) / KCH;
     const size_t sh = (size_t)KCH * (FXE + FYE) * sizeof(double);
     timed(ctx, K_DIV, st, [&] {
       k_div<GAS, ND, ORDER, MODE, RT, true>
@@ -2214,7 +2270,8 @@ int hrx_mlp_init(hrx_ctx* ctx, int64_t max_batch) {
       hipMalloc(&ctx->save, 3 * B * 64 * sizeof(float)) != hipSuccess ||
       hipMalloc(&ctx->ybuf, B * MLP_NOUT * sizeof(float)) != hipSuccess ||
       hipMalloc(&ctx->dybuf, B * MLP_NOUT * sizeof(float)) != hipSuccess ||
-      hipMalloc(&ctx->delta, B * 200 * sizeof(float)) != hipSuccess)
+      hipMalloc(&ctx->delta, B * 200 * sizeof(float)) != hipSuccess ||
+      hipMalloc(&ctx->wpart, (size_t)WG_MAXCH * P) != hipSuccess)
     return HRX_ENOMEM;
   if (hipMemset(ctx->adam_m, 0, P) != hipSuccess || hipMemset(ctx->adam_v, 0, P) != hipSuccess)
     return HRX_EHIP;
@@ -2320,12 +2377,21 @@ int hrx_mlp_forward(hrx_ctx* ctx, int64_t n, const float* X, float* Y, void* hip
   return check(hipGetLastError());
 }
 
+static void launch_wgrad(hrx_ctx* ctx, int64_t n, const float* X, const int32_t* idx,
+                         float* grad, hipStream_t st) {
+  const int64_t nch = std::min<int64_t>(WG_MAXCH, (n + 255) / 256);
+  const int64_t cb = (n + nch - 1) / nch;
+  k_mlp_wgrad<<<dim3((unsigned)nch, 4), 256, 0, st>>>(n, cb, X, idx, ctx->save, ctx->delta,
+                                                       ctx->wpart);
+  k_mlp_wgrad_sum<<<blocks_for(MLP_NPARAM, 256), 256, 0, st>>>((int)nch, ctx->wpart, grad);
+}
+
 static int mlp_backward_impl(hrx_ctx* ctx, int64_t n, const int32_t* idx, const float* X,
                              const float* dY, float* grad, hipStream_t st) {
   const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
   k_mlp_fwd<<<nb, 256, 0, st>>>(n, X, idx, ctx->ybuf, ctx->save, ctx->wsw, ctx->bias);
   k_mlp_bwd_delta<<<blocks_for(n, 128), 128, 0, st>>>(n, dY, ctx->save, ctx->wq, ctx->delta);
-  k_mlp_wgrad<<<200, 256, 0, st>>>(n, X, idx, ctx->save, ctx->delta, grad);
+  launch_wgrad(ctx, n, X, idx, grad, st);
   return check(hipGetLastError());
 }
 
@@ -2361,7 +2427,7 @@ int hrx_mlp_train_step(hrx_ctx* ctx, int64_t n, const int32_t* idx, const float*
       n, ctx->ybuf, Yt, idx, ctx->dybuf, loss);
   k_mlp_bwd_delta<<<blocks_for(n, 128), 128, 0, st>>>(n, ctx->dybuf, ctx->save, ctx->wq,
                                                       ctx->delta);
-  k_mlp_wgrad<<<200, 256, 0, st>>>(n, X, idx, ctx->save, ctx->delta, ctx->grad);
+  launch_wgrad(ctx, n, X, idx, ctx->grad, st);
   int rc = check(hipGetLastError());
   if (rc) return rc;
   return hrx_adam_step(ctx, ctx->grad, lr, t, hip_stream);
