@@ -259,6 +259,8 @@ constexpr int TTX = 64, TTY = 4, THALO = 4;
 constexpr int TW = TTX + 2 * THALO, TH = TTY + 2 * THALO, TILE_E = TW * TH;
 constexpr int FXE = TTY * TW, FYE = TH * TTX;   // flux tiles: x halo only, y halo only
 constexpr int KCH = 4;                          // flux components staged per LDS pass
+// components per pass of the divergence kernel (3-D: 9 = 3 x 3, no idle pass)
+constexpr int div_chunk(int nd) { return nd == 3 ? 3 : KCH; }
 
 // Stage TOTAL values into LDS: element e comes from src_of(e).  Every thread first issues
 // all of its global loads (held in registers), then writes them, so the loads of a
@@ -292,8 +294,8 @@ __device__ __forceinline__ void tile_origin(const Dev& d, int& i0, int& j0,
 // 3-D tiles lie in the (x, z) plane, TTX x TTY points with a halo of 4 (z periodic),
 // one grid row j per block.  Consecutive blocks (one XCD's range) walk the z tiles of a
 // row, then the next row: the z halo a tile stages was staged by the block before it.
-__device__ __forceinline__ void tile_origin3(const Dev& d, int& i0, int& j, int& k0) {
-  const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
+__device__ __forceinline__ void tile_origin3(const Dev& d, int& i0, int& j, int& k0,
+                                             unsigned b = blockIdx.x, unsigned nb = gridDim.x) {
   const unsigned per = nb >> 3;
   const unsigned L = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
   const unsigned ny = (unsigned)d.ny, tgz = (unsigned)d.tgz;
@@ -911,10 +913,13 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
 // R = -sum_j dF_j/dx_j (FP64 differences, RT weighted sums) + wdot (species)
 //     - sigma (Q - Q_ref) (FP64); boundary rows; then R out, or the low-storage update
 // of Q and dQ in FP64.
-// Tiled (2-D): a block takes the chunks of KCH components of its tile one after the
-// other, or, when the grid holds one block per tile and chunk (small grids), the chunk
-// its block index names (chunk major: blocks [c nt, (c + 1) nt) take chunk c), so the
-// chunks of a tile run side by side and twice the wavefronts are in flight.
+// Tiled: a block takes the chunks of KC components of its tile one after the other,
+// or, when the grid holds one block per tile and chunk (small grids), the chunk its
+// block index names (chunk major: blocks [c nt, (c + 1) nt) take chunk c), so the
+// chunks of a tile run side by side and more wavefronts are in flight.  2-D tiles stage
+// the x fluxes with their x halo and the y fluxes with their y halo; 3-D tiles lie in
+// the (x, z) plane of one row (the order of the flux kernel) and stage the x and z
+// fluxes, the y differences reading the neighbouring rows from memory.
 template <int GAS, int ND, int ORDER, int MODE, class RT, bool TILED>
 __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F,
                                              const RT* __restrict__ Wp, const double* Qin,
@@ -923,32 +928,41 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
                                              double dt) {
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
+  constexpr int KC = div_chunk(ND);
   extern __shared__ double smem[];
   const long N = d.N;
   Pt p;
   Sten sx, sy, sz;
-  int i0 = 0, j0 = 0, tx = 0, ty = 0;
+  int i0 = 0, j0 = 0, k0t = 0, tx = 0, ty = 0;
   bool active = true;
   int kbeg = 0, kend = nvar;
   if (TILED) {
-    const unsigned nt = (unsigned)d.tgx * d.tgy;
+    const unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
+    unsigned b = blockIdx.x, nb = gridDim.x;
     if (gridDim.x > nt) {
       const unsigned c = blockIdx.x / nt;
-      tile_origin(d, i0, j0, blockIdx.x - c * nt, nt);
-      kbeg = (int)c * KCH;
-      kend = min(kbeg + KCH, nvar);
-    } else {
-      tile_origin(d, i0, j0);
+      b -= c * nt;
+      nb = nt;
+      kbeg = (int)c * KC;
+      kend = min(kbeg + KC, nvar);
     }
+    if (ND == 2) tile_origin(d, i0, j0, b, nb);
+    else tile_origin3(d, i0, j0, k0t, b, nb);
     tx = threadIdx.x & (TTX - 1);
-    ty = threadIdx.x / TTX;
+    ty = threadIdx.x / TTX;   // tile row: y in 2-D, z in 3-D
     p.i = i0 + tx;
-    p.j = j0 + ty;
-    p.k = 0;
-    active = p.i < d.nx && p.j < d.ny;   // inactive threads still help stage the tiles
-    p.idx = (long)p.j * d.nx + p.i;
+    p.j = ND == 2 ? j0 + ty : j0;
+    p.k = ND == 2 ? 0 : k0t + ty;
+    // inactive threads still help stage the tiles
+    active = p.i < d.nx && p.j < d.ny && p.k < d.nz;
+    p.idx = ((long)p.k * d.ny + p.j) * d.nx + p.i;
     sx = make_sten<ORDER>((long)ty * TW + tx + THALO, 1, p.i, d.nx);
-    sy = make_sten<ORDER>((long)(ty + THALO) * TTX + tx, TTX, p.j, d.ny);
+    if (ND == 2) {
+      sy = make_sten<ORDER>((long)(ty + THALO) * TTX + tx, TTX, p.j, d.ny);
+    } else {
+      sy = make_sten<ORDER>(p.idx, d.nx, p.j, d.ny);
+      sz = make_sten_central<ORDER>((long)(ty + THALO) * TTX + tx, TTX);
+    }
   } else {
     if (!grid_point(d, p)) return;
     sx = make_sten<ORDER>(p.idx, 1, p.i, d.nx);
@@ -958,35 +972,44 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
   const long idx = p.idx;
   const RT mx = active ? RT(d.mx[p.i]) : RT(0);
   const RT my = active ? RT(d.my[p.j]) : RT(0);
-  const RT mz = (ND == 3) ? RT(d.mz[p.k]) : RT(0);
+  const RT mz = (ND == 3 && active) ? RT(d.mz[p.k]) : RT(0);
   const double sig = active ? fmax(d.sx[p.i], d.sy[p.j]) : 0.0;
   bool held = (p.i == 0);
   if (active && d.hold && p.j < 3) held = held || d.hold[((long)p.k * 3 + p.j) * d.nx + p.i];
   constexpr int NPI = ORDER == 6 ? 3 : 2;
-  // components in chunks of KCH; the tiled form stages each chunk's flux tiles in LDS
-  for (int k0 = kbeg; k0 < kend; k0 += KCH) {
-    const int kn = min(KCH, kend - k0);
+  // components in chunks of KC; the tiled form stages each chunk's flux tiles in LDS
+  for (int k0 = kbeg; k0 < kend; k0 += KC) {
+    const int kn = min(KC, kend - k0);
     if (TILED) {
       double* tx_ = smem;
-      double* ty_ = smem + KCH * FXE;
+      double* ty_ = smem + KC * FXE;
       if (k0 > kbeg) __syncthreads();   // previous chunk fully consumed
-      // x-flux tiles of the chunk, then y-flux tiles (components past nvar read any
-      // valid plane and are never used)
-      stage_tile<KCH * FXE, TTX * TTY>(tx_, [&](int e) {
+      // x-flux tiles of the chunk, then y-flux (2-D) or z-flux (3-D, periodic) tiles
+      // (components past nvar read any valid plane and are never used)
+      stage_tile<KC * FXE, TTX * TTY>(tx_, [&](int e) {
         const int kk = e / FXE, r = e - kk * FXE;
         const int ly = r / TW, lx = r - ly * TW;
         const int gi = min(max(i0 + lx - THALO, 0), d.nx - 1);
-        const int gj = min(j0 + ly, d.ny - 1);
         const int k = min(k0 + kk, nvar - 1);
-        return F[(long)k * N + (long)gj * d.nx + gi];
+        if (ND == 2) {
+          const int gj = min(j0 + ly, d.ny - 1);
+          return F[(long)k * N + (long)gj * d.nx + gi];
+        }
+        const int gk = min(k0t + ly, d.nz - 1);
+        return F[(long)k * N + ((long)gk * d.ny + j0) * d.nx + gi];
       });
-      stage_tile<KCH * FYE, TTX * TTY>(ty_, [&](int e) {
+      stage_tile<KC * FYE, TTX * TTY>(ty_, [&](int e) {
         const int kk = e / FYE, r = e - kk * FYE;
         const int ly = r / TTX, lx = r - ly * TTX;
         const int gi = min(i0 + lx, d.nx - 1);
-        const int gj = min(max(j0 + ly - THALO, 0), d.ny - 1);
         const int k = min(k0 + kk, nvar - 1);
-        return F[((long)nvar + k) * N + (long)gj * d.nx + gi];
+        if (ND == 2) {
+          const int gj = min(max(j0 + ly - THALO, 0), d.ny - 1);
+          return F[((long)nvar + k) * N + (long)gj * d.nx + gi];
+        }
+        int gk = k0t + ly - THALO;
+        gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
+        return F[((long)2 * nvar + k) * N + ((long)gk * d.ny + j0) * d.nx + gi];
       });
       __syncthreads();
     }
@@ -994,9 +1017,13 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
     for (int kk = 0; kk < kn; ++kk) {
       const int k = k0 + kk;
       RT acc;
-      if (TILED) {
+      if (TILED && ND == 2) {
         acc = sten_apply<RT>(sx, smem + kk * FXE) * mx;
-        acc += sten_apply<RT>(sy, smem + KCH * FXE + kk * FYE) * my;
+        acc += sten_apply<RT>(sy, smem + KC * FXE + kk * FYE) * my;
+      } else if (TILED) {
+        acc = sten_apply<RT>(sx, smem + kk * FXE) * mx;
+        acc += sten_apply<RT>(sy, F + ((long)nvar + k) * N) * my;
+        acc += sten_apply<RT, NPI>(sz, smem + KC * FXE + kk * FYE) * mz;
       } else {
         acc = sten_apply<RT>(sx, F + (long)k * N) * mx;
         acc += sten_apply<RT>(sy, F + ((long)nvar + k) * N) * my;
@@ -2001,22 +2028,15 @@ void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, con
                 const double* Qref, double* R, double* Qio, double* dQ, double A, double B,
                 double dt) {
   const Dev& d = ctx->dev;
-  if (ND == 2) {
-    constexpr int nvar = (GAS == CPG ? 1 : NS) + ND + 1;
-    unsigned nt = (unsigned)d.tgx * d.tgy;
-    if (d.N <= DIV_SPLIT_MAX_POINTS) nt *= (nvar + KCH - 1) / KCH;
-    const size_t sh = (size_t)KCH * (FXE + FYE) * sizeof(double);
-    timed(ctx, K_DIV, st, [&] {
-      k_div<GAS, ND, ORDER, MODE, RT, true>
-          <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
-    });
-  } else {
-    const unsigned ng = (unsigned)d.gx * d.ny * d.nz;
-    timed(ctx, K_DIV, st, [&] {
-      k_div<GAS, ND, ORDER, MODE, RT, false><<<ng, TX, 0, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A,
-                                                               B, dt);
-    });
-  }
+  constexpr int nvar = (GAS == CPG ? 1 : NS) + ND + 1;
+  unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
+  constexpr int KC = div_chunk(ND);
+  if (d.N <= DIV_SPLIT_MAX_POINTS) nt *= (nvar + KC - 1) / KC;
+  const size_t sh = (size_t)KC * (FXE + FYE) * sizeof(double);
+  timed(ctx, K_DIV, st, [&] {
+    k_div<GAS, ND, ORDER, MODE, RT, true>
+        <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
+  });
 }
 
 template <int GAS, int ND, int ORDER, class RT>
