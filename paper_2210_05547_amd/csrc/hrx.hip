@@ -556,7 +556,7 @@ __global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict_
 
 
 // 9-point truncated Gaussian filter (Gaussian weights renormalised at non-periodic
-// ends; x and y are filtered inside k_ad_smooth), here along the periodic z direction
+// ends; x and y are filtered inside k_ad_march), here along the periodic z direction
 __constant__ double c_gauss9[5] = {3565.0 / 10368.0, 3091.0 / 12960.0, 1997.0 / 25920.0,
                                    149.0 / 12960.0, 107.0 / 103680.0};
 
@@ -584,139 +584,175 @@ __global__ __launch_bounds__(128) void k_ad_filter_z(Dev d, const RT* __restrict
   }
 }
 
-// The 2-D chain fourth difference -> x filter -> y filter in one pass: a block owns a
-// TTX x STY tile, stages the source plane with a halo of 6 in LDS, forms the fourth
-// differences on the tile plus a halo of 4, filters them along x on the tile's columns,
-// then along y on the tile -- the same formulas, weights and evaluation order as
-// the separate passes they replace, read from LDS instead of two intermediate planes.
-// Halo values outside the domain are clamped copies that carry zero filter weight.
-// Within two points of a non-periodic end the fourth difference is the one centred two
-// points in (the stencil never leaves the line).
-constexpr int STY = 16;                                        // tile rows
-constexpr int AH = 6, AW = TTX + 2 * AH, AHT = STY + 2 * AH;    // staged source
-constexpr int DW = TTX + 8, DHT = STY + 8;                      // fourth differences
-// In 3-D the block works on one plane k of the tile (consecutive blocks hold
-// consecutive planes) and the z term of the fourth difference reads the planes k +- 1,
-// k +- 2 from memory, which the neighbouring blocks have just staged; the z filter
-// follows as its own pass.
+// Fourth difference -> x filter -> y filter in one pass, as a march down y: a
+// wavefront owns a strip of MW fourth-difference columns (MO = MW - 8 output columns,
+// the x filter's halo of 4 on each side) and a segment of MSEG output rows of one AD
+// plane (and one z plane in 3-D), and walks down the rows.  Lane l keeps its column's
+// five source rows (the fourth difference's y taps) and nine x-filtered rows (the y
+// filter's taps) in registers and exchanges only the current row through LDS for the x
+// taps: one global read per source value, about 17 LDS accesses per output and no
+// block barriers (one wavefront per block).  A segment starts 4 rows early (the y
+// filter's reach).  Within two points of a non-periodic end the fourth difference is the
+// one centred two points in (the stencil never leaves the line); filter taps outside
+// the domain carry zero weight and the weights are renormalised.  In 3-D the z term of
+// the fourth difference reads the planes k +- 1, k +- 2 from memory (consecutive blocks
+// hold consecutive planes, so they come from L2); the z filter follows as its own pass.
+constexpr int MW = 64, MO = MW - 8, MSEG = 32;
 template <int GAS, int ND, class RT>
-__global__ __launch_bounds__(256) void k_ad_smooth(Dev d, const RT* __restrict__ A,
-                                                   RT* __restrict__ B) {
-  __shared__ RT sA[AW * AHT];
-  __shared__ RT sD[DW * DHT];
-  __shared__ RT sX[TTX * DHT];
+__global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A,
+                                                RT* __restrict__ B, int nstrip, int nseg) {
+  __shared__ RT sa[MW + 4];   // source row q, columns i0 - 6 .. i0 + MW - 3
+  __shared__ RT sd[MW];       // fourth differences of row q, columns i0 - 4 .. i0 + MW - 5
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const long N = d.N, P = (long)nx * ny;
   const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
   const unsigned per = nb >> 3;
-  const unsigned L = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
-  const unsigned tt = ND == 3 ? L / (unsigned)d.nz : L;
-  const int k = ND == 3 ? (int)(L - tt * (unsigned)d.nz) : 0;
-  const unsigned by = tt / (unsigned)d.tgx;
-  const int i0 = (int)(tt - by * (unsigned)d.tgx) * TTX, j0 = (int)by * STY;
-  const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const long N = d.N;
-  const long P = (long)nx * ny;        // plane stride
-  const long kb = (long)k * P;         // this plane
-  const int t = threadIdx.x;
-  // per fourth-difference slot of this thread (the same for every plane): LDS offsets of
-  // the x taps, the y taps and the centre, and the spacing factors
-  constexpr int NDS = (DW * DHT + 255) / 256;
-  int ox[NDS], oy[NDS], oc[NDS];
-  long og[NDS];                        // global in-plane index (z term, 3-D)
-  RT fdx[NDS], fdy[NDS], fdb[NDS];
-#pragma unroll
-  for (int q = 0; q < NDS; ++q) {
-    const int e = t + 256 * q;
-    const int ly = e / DW, lx = e - ly * DW;
-    const int gx = min(max(i0 - 4 + lx, 0), nx - 1);
-    const int gy = min(max(j0 - 4 + ly, 0), ny - 1);
-    const int ic = gx < 2 ? 2 : (gx > nx - 3 ? nx - 3 : gx);
-    const int jc = gy < 2 ? 2 : (gy > ny - 3 ? ny - 3 : gy);
-    ox[q] = (gy - (j0 - AH)) * AW + (ic - 2 - (i0 - AH));
-    oy[q] = (jc - 2 - (j0 - AH)) * AW + (gx - (i0 - AH));
-    oc[q] = (gy - (j0 - AH)) * AW + (gx - (i0 - AH));
-    og[q] = (long)gy * nx + gx;
-    fdx[q] = RT(d.dlx[gx]);
-    fdy[q] = RT(d.dly[gy]);
-    fdb[q] = ND == 2 ? RT(sqrt(d.dlx[gx] * d.dly[gy]))
-                     : RT(pow(d.dlx[gx] * d.dly[gy] * d.dlz[k], 1.0 / 3.0));
+  unsigned t = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
+  // block -> (z plane fastest in 3-D, strip, segment, AD plane)
+  int k = 0;
+  if (ND == 3) {
+    const unsigned tk = t / (unsigned)nz;
+    k = (int)(t - tk * (unsigned)nz);
+    t = tk;
   }
-  const RT fdz = ND == 3 ? RT(d.dlz[k]) : RT(0);
-  // the planes k - 2 .. k + 2 (periodic)
+  const unsigned ts = t / (unsigned)nstrip;
+  const int strip = (int)(t - ts * (unsigned)nstrip);
+  const unsigned tg = ts / (unsigned)nseg;
+  const int seg = (int)(ts - tg * (unsigned)nseg);
+  const int v = (int)tg;
+  const int l = threadIdx.x;
+  const int i0 = strip * MO, y0 = seg * MSEG, y1 = min(y0 + MSEG, ny);
+  const long kb = (long)k * P;
+  const RT* f = A + (long)v * N + kb;       // this plane
+  const bool sq = v < 2;
+  // the lane's fourth-difference column, the centre of its x taps, its spacing
+  const int gx = min(max(i0 - 4 + l, 0), nx - 1);
+  const int ic = gx < 2 ? 2 : (gx > nx - 3 ? nx - 3 : gx);
+  const int jx = ic - 2 - (i0 - 6);           // first x tap in sa
+  const RT dlx = RT(d.dlx[gx]);
+  const RT wxf = sq ? dlx * dlx : dlx;
+  // extra source columns for the x taps of the strip's end columns (lanes 0..3)
+  const int ex = l < 2 ? i0 - 6 + l : i0 + MW - 6 + l;   // l = 2, 3 -> i0 + MW - 4, - 3
+  const int gex = min(max(ex, 0), nx - 1);
+  const int sex = l < 2 ? l : MW + l;                     // its slot in sa
+  // x filter of output lane l (column i0 - 4 + l, lanes 4 .. MW - 5)
+  RT wx[9];
+  RT wxs = RT(0);
+  const int ocol = i0 - 4 + l;
+#pragma unroll
+  for (int m = -4; m <= 4; ++m) {
+    const int q = ocol + m;
+    wx[m + 4] = (q >= 0 && q < nx) ? RT(c_gauss9[m < 0 ? -m : m]) : RT(0);
+    wxs += wx[m + 4];
+  }
+  const bool olane = l >= 4 && l < MW - 4 && ocol < nx;
+  const RT iwx = olane ? RT(1) / wxs : RT(0);
+  const int xl = min(max(l, 4), MW - 5) - 4;   // first x-filter tap in sd (in range)
+  // 3-D: the planes k - 2 .. k + 2 (periodic)
   long kz[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     int q = k + m - 2;
-    q = q < 0 ? q + nz : (q >= nz ? q - nz : q);
-    kz[m] = (long)q * P;
+    q = ND == 3 ? (q < 0 ? q + nz : (q >= nz ? q - nz : q)) : 0;
+    kz[m] = (long)q * P - kb;
   }
-  for (int v = 0; v < d.nad; ++v) {
-    const RT* f = A + (long)v * N;
-    if (v > 0) __syncthreads();   // the previous plane's buffers are consumed
-    stage_tile<AW * AHT, 256>(sA, [&](int e) {
-      const int ly = e / AW, lx = e - ly * AW;
-      const int gx = min(max(i0 - AH + lx, 0), nx - 1);
-      const int gy = min(max(j0 - AH + ly, 0), ny - 1);
-      return f[kb + (long)gy * nx + gx];
-    });
-    __syncthreads();
-    const bool sq = v < 2;
+  const RT fdz = ND == 3 ? RT(d.dlz[k]) : RT(0);
+  const RT wzf = sq ? fdz * fdz : fdz;
+  // source rows qc - 2 .. qc + 2 of the lane's column (qc = the y centre of row q)
+  const int qs = y0 - 4, qe = y1 + 3;
+  int cur = min(max(max(qs, 0), 2), ny - 3);
+  RT a0 = f[(long)(cur - 2) * nx + gx], a1 = f[(long)(cur - 1) * nx + gx],
+     a2 = f[(long)cur * nx + gx], a3 = f[(long)(cur + 1) * nx + gx],
+     a4 = f[(long)(cur + 2) * nx + gx];
+  RT pf = f[(long)min(cur + 3, ny - 1) * nx + gx];   // the next row, one step ahead
+  // interior y-filter weight sum (every tap inside the domain), in the filter's order
+  RT wint = RT(0);
 #pragma unroll
-    for (int q = 0; q < NDS; ++q) {
-      const int e = t + 256 * q;
-      if (e >= DW * DHT) break;
-      const RT* ax = sA + ox[q];
-      const RT* ay = sA + oy[q];
+  for (int m = -4; m <= 4; ++m) wint += RT(c_gauss9[m < 0 ? -m : m]);
+  const RT iwint = RT(1) / wint;
+  RT xr[9];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) xr[m] = RT(0);
+  for (int q = qs; q <= qe; ++q) {
+    RT xf = RT(0);
+    if (q >= 0 && q < ny) {
+      const int want = q < 2 ? 2 : (q > ny - 3 ? ny - 3 : q);
+      if (want > cur) {
+        a0 = a1; a1 = a2; a2 = a3; a3 = a4; a4 = pf;
+        cur = want;
+        pf = f[(long)min(cur + 3, ny - 1) * nx + gx];
+      }
+      RT aq = a2;   // row q in the ring (its centre away from the ends)
+      if (q != cur) {
+        const int dq = q - cur;
+        aq = dq < 0 ? (dq == -1 ? a1 : a0) : (dq == 1 ? a3 : a4);
+      }
+      RT zt[4];
+      if (ND == 3) {
+        const RT* fz = f + (long)q * nx + gx;
+        zt[0] = fz[kz[0]]; zt[1] = fz[kz[1]]; zt[2] = fz[kz[3]]; zt[3] = fz[kz[4]];
+      }
+      sa[l + 2] = aq;
+      if (l < 4) sa[sex] = f[(long)q * nx + gex];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const RT* ax = sa + jx;
       const RT qx = ax[0] - RT(4) * ax[1] + RT(6) * ax[2] - RT(4) * ax[3] + ax[4];
-      const RT qy = ay[0] - RT(4) * ay[AW] + RT(6) * ay[2 * AW] - RT(4) * ay[3 * AW] + ay[4 * AW];
-      const RT dlx = fdx[q], dly = fdy[q];
+      const RT qy = a0 - RT(4) * a1 + RT(6) * a2 - RT(4) * a3 + a4;
+      const RT dly = RT(d.dly[q]);
       RT acc = RT(0);
-      acc += qx * (sq ? dlx * dlx : dlx);
+      acc += qx * wxf;
       acc += qy * (sq ? dly * dly : dly);
       if (ND == 3) {
-        const RT* fz = f + og[q];
-        const RT qz = fz[kz[0]] - RT(4) * fz[kz[1]] + RT(6) * sA[oc[q]] - RT(4) * fz[kz[3]] +
-                      fz[kz[4]];
-        acc += qz * (sq ? fdz * fdz : fdz);
+        const RT qz = zt[0] - RT(4) * zt[1] + RT(6) * aq - RT(4) * zt[2] + zt[3];
+        acc += qz * wzf;
       }
       RT out = fabs(acc);
       if (GAS == AIR5 && v >= 3) {
-        const RT Ys = sA[oc[q]];
-        const RT over = RT(0.5) * (fabs(Ys) - RT(1) + fabs(RT(1) - Ys));
-        out = RT(d.CD) * out + RT(d.CY) * over * fdb[q];
+        const RT over = RT(0.5) * (fabs(aq) - RT(1) + fabs(RT(1) - aq));
+        out = RT(d.CD) * out;
+        if (over != RT(0)) {
+          const RT fdb = ND == 2 ? RT(sqrt(d.dlx[gx] * d.dly[q]))
+                                 : RT(cbrt(d.dlx[gx] * d.dly[q] * d.dlz[k]));
+          out = out + RT(d.CY) * over * fdb;
+        }
       }
-      sD[e] = out;
-    }
-    __syncthreads();
-    for (int e = t; e < TTX * DHT; e += 256) {
-      const int ly = e / TTX, lx = e - ly * TTX;
-      const int gx = i0 + lx;
-      if (gx >= nx) continue;
-      RT acc = RT(0), wsum = RT(0);
+      sd[l] = out;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      RT xa = RT(0);
 #pragma unroll
-      for (int k = -4; k <= 4; ++k) {
-        const int q = gx + k;
-        const RT w = (q >= 0 && q < nx) ? RT(c_gauss9[k < 0 ? -k : k]) : RT(0);
-        const int qc = q < 0 ? 0 : (q >= nx ? nx - 1 : q);
-        acc += w * sD[ly * DW + (qc - (i0 - 4))];
-        wsum += w;
-      }
-      sX[e] = acc / wsum;
+      for (int m = 0; m < 9; ++m) xa += wx[m] * sd[xl + m];
+      xf = xa * iwx;
+      // sa and sd are rewritten next row only after every lane's reads above
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __syncthreads();
-    for (int e = t; e < TTX * STY; e += 256) {
-      const int ty = e / TTX, tx = e - ty * TTX;
-      const int gx = i0 + tx, gy = j0 + ty;
-      if (gx >= nx || gy >= ny) continue;
-      RT acc = RT(0), wsum = RT(0);
 #pragma unroll
-      for (int k = -4; k <= 4; ++k) {
-        const int q = gy + k;
-        const RT w = (q >= 0 && q < ny) ? RT(c_gauss9[k < 0 ? -k : k]) : RT(0);
-        const int qc = q < 0 ? 0 : (q >= ny ? ny - 1 : q);
-        acc += w * sX[(qc - (j0 - 4)) * TTX + tx];
-        wsum += w;
+    for (int m = 0; m < 8; ++m) xr[m] = xr[m + 1];
+    xr[8] = xf;
+    const int r = q - 4;   // output row: x-filtered rows r - 4 .. r + 4 are in xr
+    if (r >= y0 && r < y1) {
+      RT yacc = RT(0), res;
+      if (r >= 4 && r < ny - 4) {
+#pragma unroll
+        for (int m = -4; m <= 4; ++m) yacc += RT(c_gauss9[m < 0 ? -m : m]) * xr[m + 4];
+        res = yacc * iwint;
+      } else {
+        RT wsum = RT(0);
+#pragma unroll
+        for (int m = -4; m <= 4; ++m) {
+          const int qq = r + m;
+          const RT w = (qq >= 0 && qq < ny) ? RT(c_gauss9[m < 0 ? -m : m]) : RT(0);
+          yacc += w * xr[m + 4];
+          wsum += w;
+        }
+        res = yacc / wsum;
       }
-      B[(long)v * N + kb + (long)gy * nx + gx] = acc / wsum;
+      if (olane) B[(long)v * N + kb + (long)r * nx + ocol] = res;
     }
   }
 }
@@ -2065,10 +2101,11 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
     RT* B = A + (long)d.nad * N;
     const RT* Gad;
     timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER, RT><<<ng, TX, 0, st>>>(d, Q, Wd, A); });
-    // fourth differences and the x and y filters in one LDS pass (timed as ad_d4)
+    // fourth differences and the x and y filters in one pass (timed as ad_d4)
     timed(ctx, K_AD_D4, st, [&] {
-      k_ad_smooth<GAS, ND, RT>
-          <<<(unsigned)(d.tgx * ((d.ny + STY - 1) / STY) * d.nz), 256, 0, st>>>(d, A, B);
+      const int nstrip = (d.nx + MO - 1) / MO, nseg = (d.ny + MSEG - 1) / MSEG;
+      k_ad_march<GAS, ND, RT><<<(unsigned)((long)d.nz * nstrip * nseg * d.nad), MW, 0, st>>>(
+          d, A, B, nstrip, nseg);
     });
     if (ND == 3) {
       timed(ctx, K_AD_FZ, st, [&] { k_ad_filter_z<RT><<<ng, TX, 0, st>>>(d, B, A); });
