@@ -560,27 +560,48 @@ __global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict_
 __constant__ double c_gauss9[5] = {3565.0 / 10368.0, 3091.0 / 12960.0, 1997.0 / 25920.0,
                                    149.0 / 12960.0, 107.0 / 103680.0};
 
+// The z filter as a march along z: a wavefront owns 64 consecutive x points of one row
+// j, a segment of ZSEG planes and one AD plane, keeps the nine taps of its column in
+// registers and reads each input value once (plus the 8 planes a segment starts with).
+constexpr int ZSEG = 64;
 template <class RT>
-__global__ __launch_bounds__(128) void k_ad_filter_z(Dev d, const RT* __restrict__ in,
-                                                     RT* __restrict__ out) {
-  Pt p;
-  if (!grid_point_zfast(d, p)) return;
-  const long idx = p.idx;
-  const long N = d.N;
-  const int i = p.k, n = d.nz;
-  const long s = (long)d.nx * d.ny;
-  const long base = idx - (long)i * s;
-  for (int v = 0; v < d.nad; ++v) {
-    const RT* f = in + (long)v * N;
-    auto at = [&](int m) {
-      int q = i + m;
-      q = q < 0 ? q + n : (q >= n ? q - n : q);
-      return f[base + (long)q * s];
-    };
-    RT r = RT(c_gauss9[0]) * f[idx];
+__global__ __launch_bounds__(64) void k_ad_filter_z(Dev d, const RT* __restrict__ in,
+                                                    RT* __restrict__ out, int nxs, int nzs) {
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const long N = d.N, P = (long)nx * ny;
+  const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
+  const unsigned per = nb >> 3;
+  unsigned t = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
+  // block -> (x strip fastest, row, z segment, AD plane)
+  const unsigned tx = t / (unsigned)nxs;
+  const int xs = (int)(t - tx * (unsigned)nxs);
+  const unsigned tj = tx / (unsigned)ny;
+  const int j = (int)(tx - tj * (unsigned)ny);
+  const unsigned tz = tj / (unsigned)nzs;
+  const int zs = (int)(tj - tz * (unsigned)nzs);
+  const int v = (int)tz;
+  const int i = xs * 64 + (int)threadIdx.x;
+  if (i >= nx) return;
+  const RT* f = in + (long)v * N + (long)j * nx + i;
+  RT* o = out + (long)v * N + (long)j * nx + i;
+  const int z0 = zs * ZSEG, z1 = min(z0 + ZSEG, nz);
+  auto at = [&](int q) {
+    q = q < 0 ? q + nz : (q >= nz ? q - nz : q);
+    return f[(long)q * P];
+  };
+  RT w[9];   // planes k - 4 .. k + 4
 #pragma unroll
-    for (int k = 1; k <= 4; ++k) r += RT(c_gauss9[k]) * (at(-k) + at(k));
-    out[(long)v * N + idx] = r;
+  for (int m = 0; m < 8; ++m) w[m] = at(z0 - 4 + m);
+  RT pf = at(z0 + 4);
+  for (int k = z0; k < z1; ++k) {
+    w[8] = pf;
+    if (k + 1 < z1) pf = at(k + 5);
+    RT r = RT(c_gauss9[0]) * w[4];
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) r += RT(c_gauss9[m]) * (w[4 - m] + w[4 + m]);
+    o[(long)k * P] = r;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) w[m] = w[m + 1];
   }
 }
 
@@ -2108,7 +2129,11 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
           d, A, B, nstrip, nseg);
     });
     if (ND == 3) {
-      timed(ctx, K_AD_FZ, st, [&] { k_ad_filter_z<RT><<<ng, TX, 0, st>>>(d, B, A); });
+      const int nxs = (d.nx + 63) / 64, nzs = (d.nz + ZSEG - 1) / ZSEG;
+      timed(ctx, K_AD_FZ, st, [&] {
+        k_ad_filter_z<RT><<<(unsigned)((long)nxs * d.ny * nzs * d.nad), 64, 0, st>>>(d, B, A, nxs,
+                                                                                  nzs);
+      });
       Gad = A;
     } else {
       Gad = B;
