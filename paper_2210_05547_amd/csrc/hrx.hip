@@ -56,6 +56,7 @@ struct Dev {
   int tgx, tgy;                   // 2-D LDS tiles per row / column
   int tgz;                        // 3-D (x, z) tiles along z
   int warm;                       // W holds a previous temperature field (Newton warm start)
+  void* ad;                       // artificial-diffusivity source planes (RT), or null
 };
 
 // ------------------------------------------------------------------ stencils
@@ -442,6 +443,11 @@ __device__ __forceinline__ void prim_air5(const Dev& d, double* __restrict__ Wd,
     for (int s = 0; s < NS; ++s) cv += Y[s] * st.cv[s];
     const double gf = (cv + Rmix) / cv;
     Wp[d.w_c * N + idx] = RT(sqrt(gf * Rmix * Tk) * d.ic_inf);
+    // the pointwise sources of the artificial diffusivity: e and Y_s
+    RT* Aad = static_cast<RT*>(d.ad);
+    Aad[2 * N + idx] = RT(e);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Aad[(3 + s) * N + idx] = RT(Y[s]);
   }
 }
 
@@ -474,7 +480,10 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
     Wd[ND * N + idx] = T;
     Wd[d.w_p * N + idx] = p;
     Wp[d.w_mu * N + idx] = mu;
-    if (d.ad_on) Wp[d.w_c * N + idx] = RT(sqrt(g * p / rho));
+    if (d.ad_on) {
+      Wp[d.w_c * N + idx] = RT(sqrt(g * p / rho));
+      static_cast<RT*>(d.ad)[2 * N + idx] = RT(e);
+    }
     return;
   }
   double rs[NS], mom[3] = {0.0, 0.0, 0.0};
@@ -494,10 +503,10 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
 }
 
 // ------------------------------------------------------------------ artificial diffusivity
-// A planes (RT): [|S|, theta, e, Y_1..Y_ns]
+// A planes (RT): [|S|, theta, e, Y_1..Y_ns].  The pointwise pass writes e and Y_s (it
+// holds them already); k_ad_src forms |S| and theta from the velocity gradient.
 template <int GAS, int ND, int ORDER, class RT>
-__global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict__ Q,
-                                                const double* __restrict__ Wd,
+__global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict__ Wd,
                                                 RT* __restrict__ A) {
   Pt p;
   if (!(ND == 3 ? grid_point_zfast(d, p) : grid_point(d, p))) return;
@@ -532,28 +541,8 @@ __global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict_
   RT theta = RT(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a) theta += G[a][a];
-  const int ns = (GAS == CPG) ? 1 : NS;
-  double rho = 0.0;
-  if (GAS == CPG) {
-    rho = Q[idx];
-  } else {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) rho += Q[s * N + idx];
-  }
-  double ke = 0.0;
-#pragma unroll
-  for (int a = 0; a < ND; ++a) {
-    const double ua = Q[(ns + a) * N + idx] / rho;
-    ke += ua * ua;
-  }
-  const double e = Q[(ns + ND) * N + idx] / rho - 0.5 * ke;
   A[0 * N + idx] = sqrt(s2);
   A[1 * N + idx] = theta;
-  A[2 * N + idx] = RT(e);
-  if (GAS == AIR5) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) A[(3 + s) * N + idx] = RT(Q[s * N + idx] / rho);
-  }
 }
 
 
@@ -2045,6 +2034,7 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   if (hipMalloc(&ctx->F, sizeof(double) * N * ctx->nF) != hipSuccess) return fail(HRX_ENOMEM);
   if (hipMalloc(&ctx->R, sizeof(double) * N * d.nvar) != hipSuccess) return fail(HRX_ENOMEM);
   if (d.ad_on && hipMalloc(&ctx->AD, rts * N * d.nad * 2) != hipSuccess) return fail(HRX_ENOMEM);
+  d.ad = ctx->AD;
   if (hipMalloc(&ctx->counters, 4 * sizeof(unsigned long long)) != hipSuccess)
     return fail(HRX_ENOMEM);
   if ((rc = check(hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long))))) return fail(rc);
@@ -2123,7 +2113,7 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
     RT* A = (RT*)ctx->AD;
     RT* B = A + (long)d.nad * N;
     const RT* Gad;
-    timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER, RT><<<ng, TX, 0, st>>>(d, Q, Wd, A); });
+    timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER, RT><<<ng, TX, 0, st>>>(d, Wd, A); });
     // fourth differences and the x and y filters in one pass (timed as ad_d4)
     timed(ctx, K_AD_D4, st, [&] {
       const int nstrip = (d.nx + MO - 1) / MO, nseg = (d.ny + MSEG - 1) / MSEG;
