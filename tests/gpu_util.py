@@ -1,5 +1,14 @@
-"""Helpers shared by the GPU parity tests (device transfers and error norms)."""
+"""Helpers shared by the GPU parity tests (error norms, oracle windows of a full grid)."""
+import dataclasses
+
 import numpy as np
+
+# x-y window of the full 3-D jet grid checked against the oracle (every z plane; wall
+# row and jet inlet inside), and the margin kept from its cut edges: the RHS at a point
+# depends on points up to 12 away through the artificial-diffusivity chain (source
+# derivative 3, fourth difference 2, filter 4, flux derivative 3) plus the metric's
+# reach; at 12 or more the window oracle equals the whole-domain oracle exactly.
+JET_WINDOW = dict(ia=196, ib=260, jb=48, margin=16)
 
 
 def normwise(a, b):
@@ -15,3 +24,23 @@ def normwise(a, b):
 
 def field_errors(A, B):
     return [normwise(A[k], B[k]) for k in range(A.shape[0])]
+
+
+def oracle_window(cfg, info, Q, Qr, ia, ib, jb):
+    """Oracle case and fields of the window x in [ia, ib), y in [0, jb), all z, of a
+    full grid: the window's own coordinates (metrics), no sponge (the window lies outside
+    the sponges) and the held inlet points inside it."""
+    from oracle import rhs as orhs
+    nw = ib - ia
+    hw = None
+    if info["hold"] is not None:
+        hold = np.asarray(info["hold"], dtype=np.int64)
+        k, rem = np.divmod(hold, cfg.nx * cfg.ny)
+        j, i = np.divmod(rem, cfg.nx)
+        inw = (i >= ia) & (i < ib) & (j < jb)
+        hw = (k[inw] * jb + j[inw]) * nw + (i[inw] - ia)
+    cw = dataclasses.replace(cfg, nx=nw, ny=jb, sponge_in=0, sponge_out=0, sponge_top=0)
+    case = orhs.Case(cw, info["x"][ia:ib], info["y"][:jb], info["z"], hw)
+    Qw = np.ascontiguousarray(Q[..., :jb, ia:ib])
+    Qrw = np.ascontiguousarray(Qr[..., :jb, ia:ib])
+    return case, Qw, Qrw

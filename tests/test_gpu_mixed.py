@@ -23,7 +23,7 @@ from oracle import chemistry as och  # noqa: E402
 from oracle import rhs as orhs  # noqa: E402
 from oracle import thermo as oth  # noqa: E402
 from oracle import transport as otr  # noqa: E402
-from gpu_util import field_errors, normwise  # noqa: E402
+from gpu_util import JET_WINDOW, field_errors, normwise, oracle_window  # noqa: E402
 
 TOL = 1e-5
 DEV = "cuda:0"
@@ -88,6 +88,44 @@ def test_mixed_c3_sbli_ad():
 
 def test_mixed_c4_jisc():
     _mixed_case(fields.get_config("c4").scaled(48, 32, 16), 2, "c4_48x32x16")
+
+
+def test_mixed_c3_full_rhs():
+    _mixed_case(fields.get_config("c3"), 0, "c3_full")
+
+
+def test_mixed_c4_full_size_window():
+    """The full 3-D jet grid in the mixed form: R and the change of Q over one stage on
+    an x-y window, against the oracle on that window (see the FP64 window test)."""
+    cfg = fields.get_config("c4")
+    Q, Qr, info = fields.initial_field(cfg)
+    ia, ib, jb, M = (JET_WINDOW[k] for k in ("ia", "ib", "jb", "margin"))
+    say("mixed case c4 full size; window x", ia, ib, "y 0", jb)
+    ctx = hrx.Context(cfg, info["x"], info["y"], info["z"], info["hold"], precision=hrx.PREC_MIXED)
+    Qd, Qrd = dev(Q), dev(Qr)
+    Rd = torch.empty_like(Qd)
+    hrx.rhs_eval(ctx, Qd, Qrd, Rd)
+    dQd = torch.zeros_like(Qd)
+    hrx.rk_stage(ctx, 0, info["dt"], Qd, dQd, Qrd)
+    torch.cuda.synchronize()
+    Rg = Rd[..., :jb, ia:ib].cpu().numpy()
+    Qg = Qd[..., :jb, ia:ib].cpu().numpy()
+    ctx.close()
+    del Rd, Qd, dQd, Qrd
+    case, Qw, Qrw = oracle_window(cfg, info, Q, Qr, ia, ib, jb)
+    del Q, Qr
+    sl = (slice(None), slice(None), slice(0, jb - M), slice(M, ib - ia - M))
+    R = orhs.rhs(Qw, Qrw, case)
+    errs = field_errors(Rg[sl], R[sl])
+    say("  R errors", ["%.2e" % e for e in errs])
+    _record("c4_full_window:R", errs)
+    assert max(errs) <= TOL
+    Qo, dQo = Qw.copy(), np.zeros_like(Qw)
+    orhs.rk_stage(Qo, dQo, Qrw, case, 0, info["dt"])
+    errs = field_errors(Qg[sl] - Qw[sl], Qo[sl] - Qw[sl])
+    say("  dQ-over-stages errors", ["%.2e" % e for e in errs])
+    _record("c4_full_window:Q_change", errs)
+    assert max(errs) <= TOL
 
 
 def test_mixed_pointwise():
