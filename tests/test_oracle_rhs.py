@@ -305,3 +305,37 @@ def test_mlp_activation_closed_forms():
     # at the kink the central difference is h/2 (only the right side is curved)
     assert mlp.activation_slope(f(0.0)) == 0.0
     assert abs((f(h) - f(-h)) / (2 * h) - h / 2) <= 1e-15
+
+
+def test_window_of_a_grid_sees_the_whole_domain_inside_its_margin():
+    """Locality of the RHS, which the full-size 3-D GPU test relies on: the oracle run on
+    an x-y window of a 3-D jet grid (every z plane, wall row and jet inlet inside, the
+    window's own metrics, no sponge) reproduces the whole-domain RHS and RK stage
+    exactly at the points at least 12 from the window's cut edges (reach of the
+    artificial-diffusivity chain plus the fluxes' derivatives), and not at 8."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from gpu_util import field_errors, oracle_window
+    cfg = f.get_config("c4").scaled(120, 56, 8)
+    Q, Qr, info = f.initial_field(cfg)
+    case = R.Case(cfg, info["x"], info["y"], info["z"], info["hold"])
+    Rf = R.rhs(Q, Qr, case)
+    Qf, dQf = Q.copy(), np.zeros_like(Q)
+    R.rk_stage(Qf, dQf, Qr, case, 0, info["dt"])
+    i_jet = int(np.argmin(np.abs(info["x"] - cfg.jet_x)))
+    ia, ib, jb = i_jet - 28, i_jet + 28, 40
+    cw, Qw, Qrw = oracle_window(cfg, info, Q, Qr, ia, ib, jb)
+    assert cw.hold is not None and len(cw.hold) > 0
+    assert float(case.sigma[..., :jb, ia:ib].max()) == 0.0
+    Rw = R.rhs(Qw, Qrw, cw)
+    Qo, dQo = Qw.copy(), np.zeros_like(Qw)
+    R.rk_stage(Qo, dQo, Qrw, cw, 0, info["dt"])
+    nw = ib - ia
+
+    def err(M):
+        sl = (slice(None), slice(None), slice(0, jb - M), slice(M, nw - M))
+        return (max(field_errors(Rf[..., :jb, ia:ib][sl], Rw[sl])),
+                max(field_errors(Qf[..., :jb, ia:ib][sl], Qo[sl])))
+
+    assert err(12) == (0.0, 0.0)
+    assert err(8)[0] > 0.0
