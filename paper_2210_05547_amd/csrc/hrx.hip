@@ -957,6 +957,95 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
   }
 }
 
+// ------------------------------------------------------------------ k_bc (wall row)
+__constant__ double c_wall[4] = {48.0 / 25.0, -36.0 / 25.0, 16.0 / 25.0, -3.0 / 25.0};
+
+// One wall point (i, k): no-slip velocity; temperature held (isothermal) or taken
+// from the 4th-order extrapolation of the interior temperature (adiabatic, zero normal
+// gradient); species mass fractions extrapolated likewise; the density already
+// advanced by the stage is kept.  Held inflow points are left alone.
+// get(v, m): component v of Q at row m = 1 .. 4 of the column (after the stage's update).
+template <int GAS, int ND, class Get>
+__device__ __forceinline__ void wall_point(const Dev& d, double* __restrict__ Q, int i, int k,
+                                           Get get) {
+  if (d.hold && d.hold[((long)k * 3 + 0) * d.nx + i]) return;
+  const long N = d.N;
+  const long idx0 = (long)k * d.ny * d.nx + i;
+  constexpr int ns = (GAS == CPG) ? 1 : NS;
+  if (GAS == CPG) {
+    const double rho_w = Q[idx0];
+    double Tw;
+    if (d.wall == HRX_WALL_ISOTHERMAL) {
+      Tw = d.T_wall / d.T_ref;
+    } else {
+      Tw = 0.0;
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) {
+        const double rho = get(0, m);
+        double ke = 0.0;
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+          const double ua = get(1 + a, m) / rho;
+          ke += ua * ua;
+        }
+        const double e = get(1 + ND, m) / rho - 0.5 * ke;
+        Tw += c_wall[m - 1] * (d.gamma * e);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < ND; ++a) Q[(1 + a) * N + idx0] = 0.0;
+    Q[(1 + ND) * N + idx0] = rho_w * Tw / d.gamma;
+    return;
+  }
+  double rho_w = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rho_w += Q[s * N + idx0];
+  double Yw[NS] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double Tw = 0.0;
+  const double c2 = d.c_inf * d.c_inf;
+#pragma unroll
+  for (int m = 1; m <= 4; ++m) {
+    double rho = 0.0, Y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) rho += get(s, m);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      Y[s] = get(s, m) / rho;
+      Yw[s] += c_wall[m - 1] * Y[s];
+    }
+    if (d.wall != HRX_WALL_ISOTHERMAL) {
+      double ke = 0.0;
+#pragma unroll
+      for (int a = 0; a < ND; ++a) {
+        const double ua = get(NS + a, m) / rho;
+        ke += ua * ua;
+      }
+      const double e = get(NS + ND, m) / rho - 0.5 * ke;
+      int status, iters;
+      const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
+                                                &iters);
+      Tw += c_wall[m - 1] * (Tk / d.T_ref);
+    }
+  }
+  if (d.wall == HRX_WALL_ISOTHERMAL) Tw = d.T_wall / d.T_ref;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Q[s * N + idx0] = rho_w * Yw[s];
+#pragma unroll
+  for (int a = 0; a < ND; ++a) Q[(ns + a) * N + idx0] = 0.0;
+  const double ew = mixture_e(Tw * d.T_ref, Yw) / c2;
+  Q[(ns + ND) * N + idx0] = rho_w * ew;
+}
+
+template <int GAS, int ND>
+__global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nw = (long)(d.nx - 1) * d.nz;
+  if (t >= nw) return;
+  const int i = 1 + (int)(t % (d.nx - 1)), k = (int)(t / (d.nx - 1));
+  const long idx0 = (long)k * d.ny * d.nx + i;
+  wall_point<GAS, ND>(d, Q, i, k, [&](int v, int m) { return Q[v * d.N + idx0 + (long)m * d.nx]; });
+}
+
 // ------------------------------------------------------------------ k_div (+ RK)
 // R = -sum_j dF_j/dx_j (FP64 differences, RT weighted sums) + wdot (species)
 //     - sigma (Q - Q_ref) (FP64); boundary rows; then R out, or the low-storage update
@@ -968,6 +1057,10 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
 // the x fluxes with their x halo and the y fluxes with their y halo; 3-D tiles lie in
 // the (x, z) plane of one row (the order of the flux kernel) and stage the x and z
 // fluxes, the y differences reading the neighbouring rows from memory.
+// 2-D RK stages without the chunk split: the tiles of the bottom tile row (rows 0 ..
+// TTY - 1) hold the four interior rows the wall condition extrapolates from, so their
+// blocks apply it after the update (block barriers only) and no wall pass follows.
+// (With the split, a tile's chunks sit in different blocks; the wall pass stays.)
 template <int GAS, int ND, int ORDER, int MODE, class RT, bool TILED>
 __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F,
                                              const RT* __restrict__ Wp, const double* Qin,
@@ -977,6 +1070,8 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
   constexpr int KC = div_chunk(ND);
+  // 2-D RK stage without the chunk split: the wall condition runs here (see above)
+  bool wall_in_div = TILED && ND == 2 && MODE == MODE_RK;
   extern __shared__ double smem[];
   const long N = d.N;
   Pt p;
@@ -993,6 +1088,7 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
       nb = nt;
       kbeg = (int)c * KC;
       kend = min(kbeg + KC, nvar);
+      wall_in_div = false;
     }
     if (ND == 2) tile_origin(d, i0, j0, b, nb);
     else tile_origin3(d, i0, j0, k0t, b, nb);
@@ -1091,94 +1187,17 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
       }
     }
   }
-}
-
-// ------------------------------------------------------------------ k_bc (wall row)
-__constant__ double c_wall[4] = {48.0 / 25.0, -36.0 / 25.0, 16.0 / 25.0, -3.0 / 25.0};
-
-// One wall point (i, k): no-slip velocity; temperature held (isothermal) or taken
-// from the 4th-order extrapolation of the interior temperature (adiabatic, zero normal
-// gradient); species mass fractions extrapolated likewise; the density already
-// advanced by the stage is kept.  Held inflow points are left alone.
-template <int GAS, int ND>
-__device__ __forceinline__ void wall_point(const Dev& d, double* __restrict__ Q, int i, int k) {
-  if (d.hold && d.hold[((long)k * 3 + 0) * d.nx + i]) return;
-  const long N = d.N;
-  const long idx0 = (long)k * d.ny * d.nx + i;
-  const long sy = d.nx;
-  constexpr int ns = (GAS == CPG) ? 1 : NS;
-  if (GAS == CPG) {
-    const double rho_w = Q[idx0];
-    double Tw;
-    if (d.wall == HRX_WALL_ISOTHERMAL) {
-      Tw = d.T_wall / d.T_ref;
-    } else {
-      Tw = 0.0;
-#pragma unroll
-      for (int m = 1; m <= 4; ++m) {
-        const long im = idx0 + m * sy;
-        const double rho = Q[im];
-        double ke = 0.0;
-#pragma unroll
-        for (int a = 0; a < ND; ++a) {
-          const double ua = Q[(1 + a) * N + im] / rho;
-          ke += ua * ua;
-        }
-        const double e = Q[(1 + ND) * N + im] / rho - 0.5 * ke;
-        Tw += c_wall[m - 1] * (d.gamma * e);
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < ND; ++a) Q[(1 + a) * N + idx0] = 0.0;
-    Q[(1 + ND) * N + idx0] = rho_w * Tw / d.gamma;
-    return;
+  if (wall_in_div && j0 == 0) {
+    // rows 1 .. 4 of the updated state (each thread re-reads its own stores) through LDS
+    // to the wall row's threads
+    __syncthreads();   // the flux tiles in LDS are consumed
+    if (active && ty >= 1 && ty <= 4)
+      for (int k = 0; k < nvar; ++k) smem[(k * 4 + ty - 1) * TTX + tx] = Qio[k * N + idx];
+    __syncthreads();
+    if (ty == 0 && p.i >= 1 && p.i < d.nx)
+      wall_point<GAS, ND>(d, Qio, p.i, 0,
+                          [&](int v, int m) { return smem[(v * 4 + m - 1) * TTX + tx]; });
   }
-  double rho_w = 0.0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) rho_w += Q[s * N + idx0];
-  double Yw[NS] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  double Tw = 0.0;
-  const double c2 = d.c_inf * d.c_inf;
-#pragma unroll
-  for (int m = 1; m <= 4; ++m) {
-    const long im = idx0 + m * sy;
-    double rho = 0.0, Y[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) rho += Q[s * N + im];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      Y[s] = Q[s * N + im] / rho;
-      Yw[s] += c_wall[m - 1] * Y[s];
-    }
-    if (d.wall != HRX_WALL_ISOTHERMAL) {
-      double ke = 0.0;
-#pragma unroll
-      for (int a = 0; a < ND; ++a) {
-        const double ua = Q[(NS + a) * N + im] / rho;
-        ke += ua * ua;
-      }
-      const double e = Q[(NS + ND) * N + im] / rho - 0.5 * ke;
-      int status, iters;
-      const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
-                                                &iters);
-      Tw += c_wall[m - 1] * (Tk / d.T_ref);
-    }
-  }
-  if (d.wall == HRX_WALL_ISOTHERMAL) Tw = d.T_wall / d.T_ref;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) Q[s * N + idx0] = rho_w * Yw[s];
-#pragma unroll
-  for (int a = 0; a < ND; ++a) Q[(ns + a) * N + idx0] = 0.0;
-  const double ew = mixture_e(Tw * d.T_ref, Yw) / c2;
-  Q[(ns + ND) * N + idx0] = rho_w * ew;
-}
-
-template <int GAS, int ND>
-__global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long nw = (long)(d.nx - 1) * d.nz;
-  if (t >= nw) return;
-  wall_point<GAS, ND>(d, Q, 1 + (int)(t % (d.nx - 1)), (int)(t / (d.nx - 1)));
 }
 
 // ------------------------------------------------------------------ pointwise SI calls
@@ -2153,8 +2172,13 @@ int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, 
   } else {
     launch_div<GAS, ND, ORDER, MODE_RK, RT>(ctx, st, F, Wp, nullptr, Qref, nullptr, Qio, dQ, A,
                                             B, dt);
-    const long nw = (long)(d.nx - 1) * d.nz;
-    timed(ctx, K_BC, st, [&] { k_bc<GAS, ND><<<blocks_for(nw, 128), 128, 0, st>>>(d, Qio); });
+    constexpr int nvar = (GAS == CPG ? 1 : NS) + ND + 1;
+    constexpr int nch = (nvar + div_chunk(ND) - 1) / div_chunk(ND);
+    const bool split = d.N <= DIV_SPLIT_MAX_POINTS && nch > 1;
+    if (ND == 3 || split) {   // else it ran inside k_div
+      const long nw = (long)(d.nx - 1) * d.nz;
+      timed(ctx, K_BC, st, [&] { k_bc<GAS, ND><<<blocks_for(nw, 128), 128, 0, st>>>(d, Qio); });
+    }
   }
   return check(hipGetLastError());
 }
