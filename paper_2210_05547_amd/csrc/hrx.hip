@@ -506,20 +506,47 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
 // A planes (RT): [|S|, theta, e, Y_1..Y_ns].  The pointwise pass writes e and Y_s (it
 // holds them already); k_ad_src forms |S| and theta from the velocity gradient.
 template <int GAS, int ND, int ORDER, class RT>
-__global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict__ Wd,
+__global__ __launch_bounds__(256) void k_ad_src(Dev d, const double* __restrict__ Wd,
                                                 RT* __restrict__ A) {
-  Pt p;
-  if (!(ND == 3 ? grid_point_zfast(d, p) : grid_point(d, p))) return;
-  const long idx = p.idx;
+  // velocity planes staged like the flux's tiles: 2-D (x, y) tiles, 3-D (x, z) tiles of
+  // one row with the y differences from memory
+  extern __shared__ double smem[];
   const long N = d.N;
+  int i0, j0, k0 = 0;
+  if (ND == 2) tile_origin(d, i0, j0);
+  else tile_origin3(d, i0, j0, k0);
+  stage_tile<ND * TILE_E, TTX * TTY>(smem, [&](int e) {
+    const int v = e / TILE_E, r = e - v * TILE_E;
+    const int ly = r / TW, lx = r - ly * TW;
+    const int gi = min(max(i0 + lx - THALO, 0), d.nx - 1);
+    if (ND == 2) {
+      const int gj = min(max(j0 + ly - THALO, 0), d.ny - 1);
+      return Wd[(long)v * N + (long)gj * d.nx + gi];
+    }
+    int gk = k0 + ly - THALO;
+    gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
+    return Wd[(long)v * N + ((long)gk * d.ny + j0) * d.nx + gi];
+  });
+  __syncthreads();
+  const int tx = threadIdx.x & (TTX - 1), ty = threadIdx.x / TTX;
+  Pt p;
+  p.i = i0 + tx;
+  p.j = ND == 2 ? j0 + ty : j0;
+  p.k = ND == 2 ? 0 : k0 + ty;
+  if (p.i >= d.nx || p.j >= d.ny || p.k >= d.nz) return;
+  p.idx = ((long)p.k * d.ny + p.j) * d.nx + p.i;
+  const long idx = p.idx;
+  const long sidx = (long)(ty + THALO) * TW + tx + THALO;
   Sten sd[3];
   RT md[3];
-  sd[0] = make_sten<ORDER>(idx, 1, p.i, d.nx);
+  sd[0] = make_sten<ORDER>(sidx, 1, p.i, d.nx);
   md[0] = RT(d.mx[p.i]);
-  sd[1] = make_sten<ORDER>(idx, d.nx, p.j, d.ny);
   md[1] = RT(d.my[p.j]);
-  if (ND == 3) {
-    sd[2] = make_sten_per<ORDER>(idx, (long)d.nx * d.ny, p.k, d.nz);
+  if (ND == 2) {
+    sd[1] = make_sten<ORDER>(sidx, TW, p.j, d.ny);
+  } else {
+    sd[1] = make_sten<ORDER>(idx, d.nx, p.j, d.ny);
+    sd[2] = make_sten_central<ORDER>(sidx, TW);
     md[2] = RT(d.mz[p.k]);
   }
   constexpr int NPI = ORDER == 6 ? 3 : 2;
@@ -527,9 +554,14 @@ __global__ __launch_bounds__(128) void k_ad_src(Dev d, const double* __restrict_
 #pragma unroll
   for (int a = 0; a < ND; ++a)
 #pragma unroll
-    for (int b = 0; b < ND; ++b)
-      G[a][b] = (b == 2 ? sten_apply<RT, NPI>(sd[b], Wd + a * N)
-                        : sten_apply<RT>(sd[b], Wd + a * N)) * md[b];
+    for (int b = 0; b < ND; ++b) {
+      const double* f = smem + a * TILE_E;
+      RT g;
+      if (b == 2) g = sten_apply<RT, NPI>(sd[2], f);
+      else if (ND == 3 && b == 1) g = sten_apply<RT>(sd[1], Wd + (long)a * N);
+      else g = sten_apply<RT>(sd[b], f);
+      G[a][b] = g * md[b];
+    }
   RT s2 = RT(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a)
@@ -2132,7 +2164,10 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
     RT* A = (RT*)ctx->AD;
     RT* B = A + (long)d.nad * N;
     const RT* Gad;
-    timed(ctx, K_AD_SRC, st, [&] { k_ad_src<GAS, ND, ORDER, RT><<<ng, TX, 0, st>>>(d, Wd, A); });
+    const unsigned nts = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
+    timed(ctx, K_AD_SRC, st, [&] {
+      k_ad_src<GAS, ND, ORDER, RT><<<nts, TTX * TTY, ND * TILE_E * sizeof(double), st>>>(d, Wd, A);
+    });
     // fourth differences and the x and y filters in one pass (timed as ad_d4)
     timed(ctx, K_AD_D4, st, [&] {
       const int nstrip = (d.nx + MO - 1) / MO, nseg = (d.ny + MSEG - 1) / MSEG;
