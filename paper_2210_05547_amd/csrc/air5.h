@@ -193,6 +193,23 @@ HRX_HD double temperature_from_energy(double e, const double* Y, double rtol, in
 // ----------------------------------------------------------------- transport
 constexpr double X_CLIP = 1e-12;
 
+// Reciprocals of NS nonzero values with one division (prefix products, then the
+// inverse of the full product walked back): r_s = 1/x_s to a few ulp.
+template <class R>
+HRX_HD void reciprocals(const R* x, R* r) {
+  R pre[NS];
+  pre[0] = x[0];
+#pragma unroll
+  for (int s = 1; s < NS; ++s) pre[s] = pre[s - 1] * x[s];
+  R inv = R(1) / pre[NS - 1];
+#pragma unroll
+  for (int s = NS - 1; s > 0; --s) {
+    r[s] = inv * pre[s - 1];
+    inv = inv * x[s];
+  }
+  r[0] = inv;
+}
+
 template <class R>
 struct Transport {
   R mu, kappa;     // Pa s, W/(m K)
@@ -216,7 +233,7 @@ struct Transport {
 template <class R>
 HRX_HD void mixture_transport(double T, double p, const double* X, const double* cv,
                               Transport<R>& out) {
-  R mu_s[NS], k_s[NS], smu[NS], ismu[NS];
+  R mu_s[NS], k_s[NS], smu[NS], ismu[NS], om[NS], iom[NS];
   const R Tr = R(T);
   const R sqT = sqrt(Tr);
   const R lnT = log(Tr);
@@ -225,20 +242,25 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
   const R T11 = exp(R(-0.15610) * lnT);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
+    const R Ts = Tr * R(1.0 / lj_eps(s));
+    om[s] = R(1.16145 * pow(lj_eps(s), 0.14874)) * T22 +
+            R(0.52487) * exp(R(-0.77320) * Ts) + R(2.16178) * exp(R(-2.43787) * Ts);
+  }
+  reciprocals(om, iom);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
     const double m = molar_mass(s) / NAV;
     const double sig = lj_sigma(s);
     const R A = R((5.0 / 16.0) * sqrt(PI * m * KB) / (PI * sig * sig));
-    const R Ts = Tr * R(1.0 / lj_eps(s));
-    const R om = R(1.16145 * pow(lj_eps(s), 0.14874)) * T22 +
-                 R(0.52487) * exp(R(-0.77320) * Ts) + R(2.16178) * exp(R(-2.43787) * Ts);
-    mu_s[s] = A * sqT / om;
+    mu_s[s] = A * sqT * iom[s];
     const R Rs = R(gas_const(s));
     const R cv_int = R(cv[s]) - R(1.5) * Rs;
     k_s[s] = mu_s[s] * (R(3.75) * Rs + cv_int);
     smu[s] = sqrt(mu_s[s]);
-    ismu[s] = R(1) / smu[s];
   }
+  reciprocals(smu, ismu);
   R mu = R(0), kap = R(0);
+  R wden[NS], iwden[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     R den = R(0);
@@ -253,7 +275,12 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
       }
       den += R(X[r]) * phi;
     }
-    const R xd = R(X[s]) / den;
+    wden[s] = den;
+  }
+  reciprocals(wden, iwden);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const R xd = R(X[s]) * iwden[s];
     mu += xd * mu_s[s];
     kap += xd * k_s[s];
   }
@@ -287,13 +314,15 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
       den[r] += Xc[s] * v;
     }
   }
+  R iden[NS];
+  reciprocals(den, iden);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     R num = R(0);
 #pragma unroll
     for (int r = 0; r < NS; ++r)
       if (r != s) num += Xc[r];
-    out.D[s] = num / den[s];
+    out.D[s] = num * iden[s];
   }
 }
 
