@@ -81,6 +81,27 @@ __device__ __forceinline__ float mlp_act(float z) {
   return r * r;
 }
 
+// The same activation for eight values at once, straight to the next layer's BF16
+// operand: z |z| (one multiply: the square with z's sign), rounded to BF16 pairs, then
+// the rectifier as a packed 16-bit integer max with 0 (negative BF16 values, -0
+// included, are negative integers).  Bit-identical to rounding mlp_act(z) to BF16, at
+// two operations per value instead of two and a half.
+__device__ __forceinline__ bf16x8_t mlp_act_bf16x8(const float* z) {
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  typedef short s16x2_t __attribute__((ext_vector_type(2)));
+  bf16x8_t out;
+#pragma unroll
+  for (int q = 0; q < 8; q += 2) {
+    const f32x2_t v = {z[q] * __builtin_fabsf(z[q]), z[q + 1] * __builtin_fabsf(z[q + 1])};
+    const s16x2_t h = __builtin_bit_cast(s16x2_t, __builtin_convertvector(v, bf16x2_t));
+    const bf16x2_t r = __builtin_bit_cast(bf16x2_t, __builtin_elementwise_max(h, (s16x2_t)0));
+    out[q] = r[0];
+    out[q + 1] = r[1];
+  }
+  return out;
+}
+
 // Swizzled weight index of element (row o, column k) of layer L (padded with zeros).
 __host__ __device__ __forceinline__ int mlp_sw_index(int L, int m, int t, int lane, int q) {
   return MLP_SW_OFF[L] + ((m * MLP_KS[L] + t) * 64 + lane) * 8 + q;
@@ -156,11 +177,18 @@ __device__ __forceinline__ void mlp_wave64(const uint16_t* __restrict__ sW,
       for (int pt = 0; pt < 2; ++pt)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
+          if (!save) {
+            float z[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) z[q] = acc[pt][t >> 1][8 * (t & 1) + q];
+            b[pt][t] = mlp_act_bf16x8(z);
+            continue;
+          }
           f32x8_t v;
 #pragma unroll
           for (int q = 0; q < 8; ++q) v[q] = mlp_act(acc[pt][t >> 1][8 * (t & 1) + q]);
           b[pt][t] = __builtin_convertvector(v, bf16x8_t);
-          if (save) {
+          {
             const long gp = base + 32 * pt + col;
             if (gp < ldn) {
 #pragma unroll
