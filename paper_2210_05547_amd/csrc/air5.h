@@ -83,18 +83,30 @@ struct SpeciesThermo {
 
 HRX_HD void species_e_cv(double T, SpeciesThermo& st) {
   const double iT = 1.0 / T;
+  // the three molecules (species 0..2): e^x - 1 and its reciprocal, one division for
+  // the three (prefix products)
+  double x[3], em1[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    x[s] = theta_vib(s) * iT;
+    em1[s] = expm1(x[s]);
+  }
+  const double p01 = em1[0] * em1[1];
+  const double inv = 1.0 / (p01 * em1[2]);
+  double iem[3];
+  iem[2] = inv * p01;
+  const double inv01 = inv * em1[2];
+  iem[1] = inv01 * em1[0];
+  iem[0] = inv01 * em1[1];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const double Rs = gas_const(s);
     const double hf = hf0_molar(s) / molar_mass(s);
     if (is_diatomic(s)) {
-      const double x = theta_vib(s) * iT;
-      const double em1 = expm1(x);
-      const double iem = 1.0 / em1;
-      const double ex = em1 + 1.0;
-      st.em1[s] = em1;
-      st.e[s] = Rs * (2.5 * T + theta_vib(s) * iem) + hf;
-      st.cv[s] = Rs * (2.5 + x * x * ex * (iem * iem));
+      const double ex = em1[s] + 1.0;
+      st.em1[s] = em1[s];
+      st.e[s] = Rs * (2.5 * T + theta_vib(s) * iem[s]) + hf;
+      st.cv[s] = Rs * (2.5 + x[s] * x[s] * ex * (iem[s] * iem[s]));
     } else {
       st.e[s] = Rs * (1.5 * T) + hf;
       st.cv[s] = Rs * 1.5;
