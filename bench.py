@@ -24,8 +24,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the flat-plate stage kernels, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE scaled by a 256 MiB copy kernel (fetch x2.0, write x1.0), for the kernels
 # as they stand (profiles/stage_air5_flatplate_512x256.md)
-PRIM_TRAFFIC_BYTES = (9462 + 26624) * 1024
-TRAFFIC_BYTES = {"flux": (31858 + 16384) * 1024, "div": (43136 + 16384) * 1024}
+PRIM_TRAFFIC_BYTES = (9448 + 26624) * 1024
+TRAFFIC_BYTES = {"flux": (32618 + 16384) * 1024, "div": (43136 + 16384) * 1024}
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # Algorithmic HBM bytes per grid point of each kernel (FP64 planes read once + written
@@ -41,7 +41,7 @@ BYTES_PER_POINT_AIR5_2D = {"prim": 8 * (9 + 26), "flux": 8 * (29 + 16),
 # enthalpies): SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / points, read with rocprofv3 on
 # this workload (profiles/stage_air5_flatplate_512x256.md).  MI355X has no FP64
 # transcendental unit, so this includes the instruction sequences of exp/log/sqrt/div.
-FLOPS_PER_POINT_PRIM_AIR5_2D = 2996.0
+FLOPS_PER_POINT_PRIM_AIR5_2D = 2766.0
 
 
 def sponge_fraction(cfg):
