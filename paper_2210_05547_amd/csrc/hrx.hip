@@ -812,6 +812,9 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
   constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);   // u, v, (w), T, (X_s)
+  // mole-fraction derivatives formed per flux direction (fewer live registers) where the
+  // kernel is register bound: with artificial diffusivity and in 3-D (measured)
+  constexpr bool DX_PER_DIR = AD || ND == 3;
   extern __shared__ double smem[];
   const long N = d.N;
   Pt p;
@@ -939,10 +942,12 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
       if (AD) Ds = Ds + cs * Gad[(3 + s) * N + idx];
       a_s[s] = rho_r * (RT(molar_mass(s)) / Mbar) * Ds;
     }
+    if (!DX_PER_DIR) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+      for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int b = 0; b < ND; ++b) dX[s][b] = deriv(ND + 1 + s, b);
+        for (int b = 0; b < ND; ++b) dX[s][b] = deriv(ND + 1 + s, b);
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) h[s] = Wp[(d.w_h + s) * N + idx];
   }
@@ -951,6 +956,10 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
     double* Fj = F + (long)j * nvar * N;
     RT J[NS];
     if (GAS == AIR5) {
+      if (DX_PER_DIR) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) dX[s][j] = deriv(ND + 1 + s, j);
+      }
       RT corr = RT(0);
 #pragma unroll
       for (int s = 0; s < NS; ++s) corr += a_s[s] * dX[s][j];
