@@ -1049,19 +1049,20 @@ __device__ __forceinline__ void wall_point(const Dev& d, double* __restrict__ Q,
     double rho = 0.0, Y[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) rho += get(s, m);
+    const double irho = 1.0 / rho;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      Y[s] = get(s, m) / rho;
+      Y[s] = get(s, m) * irho;
       Yw[s] += c_wall[m - 1] * Y[s];
     }
     if (d.wall != HRX_WALL_ISOTHERMAL) {
       double ke = 0.0;
 #pragma unroll
       for (int a = 0; a < ND; ++a) {
-        const double ua = get(NS + a, m) / rho;
+        const double ua = get(NS + a, m) * irho;
         ke += ua * ua;
       }
-      const double e = get(NS + ND, m) / rho - 0.5 * ke;
+      const double e = get(NS + ND, m) * irho - 0.5 * ke;
       int status, iters;
       const double Tk = temperature_from_energy(e * c2, Y, d.newton_rtol, d.newton_max, &status,
                                                 &iters);
