@@ -457,7 +457,12 @@ template <int GAS, int ND, class RT, bool SUR = false>
 __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ Q,
                                               double* __restrict__ Wd, RT* __restrict__ Wp,
                                               const float* __restrict__ ysin) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  // Without artificial diffusivity each XCD takes one contiguous band of points, the band
+  // its stencil blocks of the previous and next passes cover (their planes may still sit
+  // in its L2; flat plate -3 %).  With it the AD passes that follow walk other orders and
+  // the plain order measured better.
+  const long blk = d.ad_on ? (long)blockIdx.x : xcd_block();
+  const long idx = blk * blockDim.x + threadIdx.x;
   if (idx >= d.N) return;
   const long N = d.N;
   if (GAS == CPG) {
