@@ -2,16 +2,22 @@
 //
 // One right-hand-side evaluation (Eqs. 5-6 with the sponge of Eq. 26) runs as
 //   k_prim     pointwise: Q -> velocities, T (Newton, Sec. 3.4), p, X_s, mu, kappa,
-//              D_s (Eq. 19), wdot_s (Eqs. 13-15)            [FP64-ALU bound]
-//   k_ad_*     artificial diffusivity (Sec. 3.3 reading): sources, fourth
-//              differences, separable 9-point Gaussian filter  [HBM bound]
-//   k_flux     stencil gradients of u, T, X_s at each point, then the total flux
-//              F_j = F_C,j - F_D,j for every direction j (Eqs. 9, 10, 18)  [HBM bound]
+//              D_s (Eq. 19), wdot_s (Eqs. 13-15), h_s, and the AD sources e, Y_s
+//              [FP64-ALU bound]
+//   k_ad_src, k_ad_march, k_ad_filter_z
+//              artificial diffusivity (Sec. 3.3 reading): |S| and theta, fourth
+//              differences and the separable 9-point Gaussian filter (x and y in a
+//              march down y, z in a march along z)  [HBM / latency bound]
+//   k_flux     stencil gradients of u, T, X_s at each point (LDS tiles), then the
+//              total flux F_j = F_C,j - F_D,j for every direction j (Eqs. 9, 10, 18)
+//              [HBM bound]
 //   k_div      -sum_j dF_j/dx_j + S - sigma (Q - Q_ref), boundary rows, and either
-//              the R output or the fused low-storage RK update (Sec. 3.1)  [HBM bound]
-//   k_bc       wall row after a stage (no slip, non-catalytic, T_w or adiabatic)
-// Fields are SoA planes with x fastest; a thread owns one grid point, so x-neighbour
-// loads of a wavefront are contiguous and y/z neighbours are reused through L2.
+//              the R output or the fused low-storage RK update (Sec. 3.1), with the wall
+//              condition on 2-D grids past the small-grid split  [HBM bound]
+//   k_bc       wall row after a stage otherwise (no slip, non-catalytic, T_w or
+//              adiabatic)
+// Fields are SoA planes with x fastest; stencil kernels stage LDS tiles (32 x 8 points
+// plus halos) or march along a direction keeping the taps in registers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
