@@ -357,6 +357,38 @@ __device__ __forceinline__ void count(const Dev& d, int status) {
 constexpr double T_HI_MIXED = 2000.0;
 
 // ------------------------------------------------------------------ k_prim
+// Mole fractions and pressure of 5-species air from the partial densities, in the one
+// order of operations the pointwise pass and the flux share.  In 2-D the flux forms its
+// tile's X_s and its point's p itself, bit-identical to the pointwise pass, which then
+// stores neither (the 3-D flux reads the y neighbours' X_s from the stored planes).
+// rho = sum rho_s, Y_s = rho_s / rho, X_s = (Y_s/M_s) / sum(Y_r/M_r), p = rho T R_mix
+// p_fac (T nondimensional).
+__device__ __forceinline__ void air5_mole_fractions(const double* rs, double* X) {
+  double rho = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rho += rs[s];
+  const double irho = 1.0 / rho;
+  double n = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    X[s] = (rs[s] * irho) * (1.0 / molar_mass(s));
+    n += X[s];
+  }
+  const double in = 1.0 / n;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) X[s] = X[s] * in;
+}
+__device__ __forceinline__ double air5_pressure(const Dev& d, const double* rs, double T) {
+  double rho = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rho += rs[s];
+  const double irho = 1.0 / rho;
+  double Y[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Y[s] = rs[s] * irho;
+  return rho * T * mixture_R(Y) * d.p_fac;
+}
+
 // Wd planes (double): [u, v, (w), T, X_1..X_5 (air5), p]   -- differentiated or convective
 // Wp planes (RT):     [mu, kappa, D_1..D_5, wdot_1..wdot_5, h_1..h_5, (c)] (air5),
 //                     [mu, (c)] (CPG)
@@ -400,17 +432,10 @@ __device__ __forceinline__ void prim_air5(const Dev& d, double* __restrict__ Wd,
   }
   const double T = Tk * d.iT_ref;
   const double Rmix = mixture_R(Y);
-  const double p = rho * T * Rmix * d.p_fac;
+  const double p = air5_pressure(d, rs, T);
   const double p_d = p * d.rho_inf * c2;
-  double X[NS], n = 0.0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    X[s] = Y[s] * (1.0 / molar_mass(s));
-    n += X[s];
-  }
-  const double in = 1.0 / n;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) X[s] = X[s] * in;
+  double X[NS];
+  air5_mole_fractions(rs, X);
   if (net) {
     // the network's logarithms carry ~1e-4 relative error: FP32 exponentials suffice
     Wp[d.w_mu * N + idx] = RT(__expf(ys[1]) * (float)d.imu_inf);
@@ -435,9 +460,11 @@ __device__ __forceinline__ void prim_air5(const Dev& d, double* __restrict__ Wd,
 #pragma unroll
   for (int a = 0; a < ND; ++a) Wd[a * N + idx] = u[a];
   Wd[ND * N + idx] = T;
+  if (ND == 3) {
 #pragma unroll
-  for (int s = 0; s < NS; ++s) Wd[(ND + 1 + s) * N + idx] = X[s];
-  Wd[d.w_p * N + idx] = p;
+    for (int s = 0; s < NS; ++s) Wd[(ND + 1 + s) * N + idx] = X[s];
+    Wd[d.w_p * N + idx] = p;
+  }
 #pragma unroll
   for (int s = 0; s < NS; ++s) Wp[(d.w_wdot + s) * N + idx] = RT(double(wd[s]) * d.wscale);
   // species enthalpies h_s = e_s + R_s T (nondimensional) for the diffusive heat flux
@@ -822,6 +849,8 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
                                               const RT* __restrict__ Gad, double* __restrict__ F) {
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
+  static_assert(TILED, "the flux stages its tile (the mole fractions are formed there)");
+  constexpr bool XQ = GAS == AIR5 && ND == 2;   // X_s and p formed here from Q
   constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);   // u, v, (w), T, (X_s)
   // mole-fraction derivatives formed per flux direction (fewer live registers) where the
   // kernel is register bound: with artificial diffusivity and in 3-D (measured)
@@ -838,18 +867,44 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
     int i0, j0, k0 = 0;
     if (ND == 2) tile_origin(d, i0, j0);
     else tile_origin3(d, i0, j0, k0);
-    stage_tile<NSRC * TILE_E, TTX * TTY>(smem, [&](int e) {
-      const int v = e / TILE_E, r = e - v * TILE_E;
+    // flat index of tile element r (clamped halo in x and y, periodic in z)
+    auto tile_point = [&](int r) -> long {
       const int ly = r / TW, lx = r - ly * TW;
       const int gi = min(max(i0 + lx - THALO, 0), d.nx - 1);
       if (ND == 2) {
         const int gj = min(max(j0 + ly - THALO, 0), d.ny - 1);
-        return Wd[(long)v * N + (long)gj * d.nx + gi];
+        return (long)gj * d.nx + gi;
       }
       int gk = k0 + ly - THALO;
       gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
-      return Wd[(long)v * N + ((long)gk * d.ny + j0) * d.nx + gi];
+      return ((long)gk * d.ny + j0) * d.nx + gi;
+    };
+    // u, v, (w), T (and in 3-D X_s) from the pointwise pass's planes
+    stage_tile<(XQ ? ND + 1 : NSRC) * TILE_E, TTX * TTY>(smem, [&](int e) {
+      const int v = e / TILE_E;
+      return Wd[(long)v * N + tile_point(e - v * TILE_E)];
     });
+    if (XQ) {
+      // X_s formed here from the partial densities (all loads first, then the planes)
+      constexpr int PER = (TILE_E + TTX * TTY - 1) / (TTX * TTY);
+      double rsv[PER][NS];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * TTX * TTY;
+        const long g = tile_point(e < TILE_E ? e : 0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) rsv[q][s] = Q[(long)s * N + g];
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * TTX * TTY;
+        if (e >= TILE_E) continue;
+        double X[NS];
+        air5_mole_fractions(rsv[q], X);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) smem[(ND + 1 + s) * TILE_E + e] = X[s];
+      }
+    }
     __syncthreads();
     const int tx = threadIdx.x & (TTX - 1), ty = threadIdx.x / TTX;
     p.i = i0 + tx;
@@ -867,14 +922,6 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
       sd[1] = make_sten<ORDER>(p.idx, d.nx, p.j, d.ny);
       sd[2] = make_sten_central<ORDER>(sidx, TW);
     }
-  } else {
-    if (!grid_point(d, p)) return;
-    sidx = p.idx;
-    src = Wd;
-    splane = N;
-    sd[0] = make_sten<ORDER>(sidx, 1, p.i, d.nx);
-    sd[1] = make_sten<ORDER>(sidx, d.nx, p.j, d.ny);
-    if (ND == 3) sd[2] = make_sten_per<ORDER>(sidx, (long)d.nx * d.ny, p.k, d.nz);
   }
   const long idx = p.idx;
   RT md[3];
@@ -899,12 +946,12 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
   double u[3];
 #pragma unroll
   for (int a = 0; a < ND; ++a) u[a] = Wd[a * N + idx];
-  const double pr = Wd[d.w_p * N + idx];
   const RT mu = Wp[d.w_mu * N + idx];
-  double rho, rs[NS];
+  double rho, rs[NS], pr;
   RT Y[NS];
   if (GAS == CPG) {
     rho = Q[idx];
+    pr = Wd[d.w_p * N + idx];
   } else {
     rho = 0.0;
 #pragma unroll
@@ -914,6 +961,7 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) Y[s] = RT(rs[s] / rho);
+    pr = XQ ? air5_pressure(d, rs, Wd[ND * N + idx]) : Wd[d.w_p * N + idx];
   }
   RT theta = RT(0);
 #pragma unroll
@@ -1123,8 +1171,9 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
   constexpr int KC = div_chunk(ND);
+  static_assert(TILED, "the divergence stages its flux tiles");
   // 2-D RK stage without the chunk split: the wall condition runs here (see above)
-  bool wall_in_div = TILED && ND == 2 && MODE == MODE_RK;
+  bool wall_in_div = ND == 2 && MODE == MODE_RK;
   extern __shared__ double smem[];
   const long N = d.N;
   Pt p;
@@ -1160,11 +1209,6 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
       sy = make_sten<ORDER>(p.idx, d.nx, p.j, d.ny);
       sz = make_sten_central<ORDER>((long)(ty + THALO) * TTX + tx, TTX);
     }
-  } else {
-    if (!grid_point(d, p)) return;
-    sx = make_sten<ORDER>(p.idx, 1, p.i, d.nx);
-    sy = make_sten<ORDER>(p.idx, d.nx, p.j, d.ny);
-    if (ND == 3) sz = make_sten_per<ORDER>(p.idx, (long)d.nx * d.ny, p.k, d.nz);
   }
   const long idx = p.idx;
   const RT mx = active ? RT(d.mx[p.i]) : RT(0);
@@ -1217,14 +1261,10 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
       if (TILED && ND == 2) {
         acc = sten_apply<RT>(sx, smem + kk * FXE) * mx;
         acc += sten_apply<RT>(sy, smem + KC * FXE + kk * FYE) * my;
-      } else if (TILED) {
+      } else {
         acc = sten_apply<RT>(sx, smem + kk * FXE) * mx;
         acc += sten_apply<RT>(sy, F + ((long)nvar + k) * N) * my;
         acc += sten_apply<RT, NPI>(sz, smem + KC * FXE + kk * FYE) * mz;
-      } else {
-        acc = sten_apply<RT>(sx, F + (long)k * N) * mx;
-        acc += sten_apply<RT>(sy, F + ((long)nvar + k) * N) * my;
-        if (ND == 3) acc += sten_apply<RT, NPI>(sz, F + ((long)2 * nvar + k) * N) * mz;
       }
       double R = -double(acc);
       if (GAS == AIR5 && k < NS) R = R + double(Wp[(d.w_wdot + k) * N + idx]);
