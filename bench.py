@@ -30,11 +30,12 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # Algorithmic HBM bytes per grid point of each kernel (FP64 planes read once + written
 # once; stencil neighbours counted once), for a 2-D 5-species-air stage without AD:
-#   prim : read Q (8 planes) + T of the previous stage; write Wd (u, v, T, X_1..5, p: 9) and
+#   prim : read Q (8 planes) + T of the previous stage; write Wd (u, v, T: 3) and
 #          Wp (mu, kappa, D_1..5, wdot_1..5, h_1..5: 17)
-#   flux : read Wd (9) + Wp (mu, kappa, D_s, h_s: 12) + Q (8); write F (2 x 8)
+#   flux : read Wd (3) + Wp (mu, kappa, D_s, h_s: 12) + Q (8: the partial densities give
+#          the tile's mole fractions and the pressure); write F (2 x 8)
 #   div  : read F (16) + wdot (5) + Q (8) + dQ (8); write Q, dQ (16)  (+ Q_ref in sponges)
-BYTES_PER_POINT_AIR5_2D = {"prim": 8 * (9 + 26), "flux": 8 * (29 + 16),
+BYTES_PER_POINT_AIR5_2D = {"prim": 8 * (9 + 20), "flux": 8 * (23 + 16),
                            "div": 8 * (37 + 16)}
 # FP64 floating-point operations per grid point of the pointwise thermochemistry
 # (energy inversion from the previous stage's temperature, transport, kinetics,
