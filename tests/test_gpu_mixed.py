@@ -90,8 +90,8 @@ def test_mixed_c4_jisc():
     _mixed_case(fields.get_config("c4").scaled(48, 32, 16), 2, "c4_48x32x16")
 
 
-def test_mixed_c3_full_rhs():
-    _mixed_case(fields.get_config("c3"), 0, "c3_full")
+def test_mixed_c3_full():
+    _mixed_case(fields.get_config("c3"), 1, "c3_full")
 
 
 def test_mixed_c4_full_size_window():

@@ -172,6 +172,12 @@ def test_c3_full_size_rhs():
     _run_case(fields.get_config("c3"), 0)
 
 
+def test_c3_full_size_stages():
+    """Two RK stages on the full 2048 x 512 grid: above 2^18 points the 2-D divergence
+    applies the wall condition itself (no separate wall pass)."""
+    _run_case(fields.get_config("c3"), 2, rhs=False)
+
+
 def test_c4_full_size_window():
     """The full 512 x 256 x 128 jet in the launch shapes the bench times: right-hand side
     and one RK stage of the whole grid on the GPU, checked against the oracle run on an
