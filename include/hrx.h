@@ -171,15 +171,15 @@ int hrx_mlp_get_params(hrx_ctx *ctx, float *theta_out, void *hip_stream);
  * sum_s Y_s e_s(T_hi), and the mass fraction of the element N,
  * Y_N2 + Y_NO M_N/M_NO + Y_N, in [xiN_min, xiN_max].  HRX_EINVAL for non-positive
  * std entries or empty ranges. */
-/* Raw surrogate features f [n][7] (device, FP32, row per state) of SI states rho [n],
- * e [n], Y [5][n] (device): (log10 rho, ln T_c, Y_1..Y_5) as defined for
- * hrx_mlp_set_norm below -- the inputs a training set needs.  No hull check. */
-int hrx_mlp_features(hrx_ctx *ctx, int64_t n, const double *rho, const double *e,
-                     const double *Y, float *f, void *hip_stream);
 int hrx_mlp_set_norm(hrx_ctx *ctx, const float *in_mean, const float *in_std,
                      const float *out_mean, const float *out_std, const float *out_lin,
                      double log10rho_min, double log10rho_max, double T_lo, double T_hi,
                      double xiN_min, double xiN_max);
+/* Raw surrogate features f [n][7] (device, FP32, row per state) of SI states rho [n],
+ * e [n], Y [5][n] (device): (log10 rho, ln T_c, Y_1..Y_5) as defined for
+ * hrx_mlp_set_norm above -- the inputs a training set needs.  No hull check. */
+int hrx_mlp_features(hrx_ctx *ctx, int64_t n, const double *rho, const double *e,
+                     const double *Y, float *f, void *hip_stream);
 /* HRX_THERMO_SURROGATE makes hrx_thermo_eval, hrx_rhs_eval and hrx_rk_stage (air5) take
  * mu, kappa, D_s from the network and start the FP64 energy inversion from its T, for
  * points inside the hull; points outside fall back to the plain evaluation and are
@@ -203,8 +203,9 @@ int hrx_mlp_train_step(hrx_ctx *ctx, int64_t n, const int32_t *idx, const float 
  * kernel of the calls that follow hrx_timing_enable(ctx, 1).  Kernel ids (index into
  * the arrays of hrx_timing_read): 0 prim, 1 ad_src, 2 ad_d4 (the fourth difference
  * fused with the x and y filters), 3 and 4 (no launches: the x and y filters run inside
- * 2), 5 ad_filter_z, 6 flux, 7 div, 8 bc (3-D, and 2-D grids of at most 2^18 points;
- * on larger 2-D grids the wall condition runs inside div), 9 thermo_eval,
+ * 2), 5 ad_filter_z, 6 flux, 7 div, 8 bc (3-D, and 2-D grids of at most 2^18
+ * points with more than four conserved variables, whose divergence runs split into
+ * component chunks; on other 2-D grids the wall condition runs inside div), 9 thermo_eval,
  * 10 chem_source (in the surrogate form the network pass is counted with prim and
  * thermo_eval).
  * hrx_timing_read synchronises, returns the summed milliseconds and launch counts
