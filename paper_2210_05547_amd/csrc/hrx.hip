@@ -679,6 +679,10 @@ __global__ __launch_bounds__(64) void k_ad_filter_z(Dev d, const RT* __restrict_
 // the domain carry zero weight and the weights are renormalised.  In 3-D the z term of
 // the fourth difference reads the planes k +- 1, k +- 2 from memory (consecutive blocks
 // hold consecutive planes, so they come from L2); the z filter follows as its own pass.
+// The row's source values (the lane's column, and the four extra x-tap columns of lanes
+// 0..3) are loaded one row ahead, so their latency overlaps the previous row's work; the
+// z taps are loaded in their own row (a prefetch of them too costs a wavefront per SIMD
+// and was slower).
 constexpr int MW = 64, MO = MW - 8, MSEG = 32;
 template <int GAS, int ND, class RT>
 __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A,
@@ -718,15 +722,16 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
   const int gex = min(max(ex, 0), nx - 1);
   const int sex = l < 2 ? l : MW + l;                     // its slot in sa
   // x filter of output lane l (column i0 - 4 + l, lanes 4 .. MW - 5)
-  RT wx[9];
   RT wxs = RT(0);
   const int ocol = i0 - 4 + l;
 #pragma unroll
   for (int m = -4; m <= 4; ++m) {
     const int q = ocol + m;
-    wx[m + 4] = (q >= 0 && q < nx) ? RT(c_gauss9[m < 0 ? -m : m]) : RT(0);
-    wxs += wx[m + 4];
+    wxs += (q >= 0 && q < nx) ? RT(c_gauss9[m < 0 ? -m : m]) : RT(0);
   }
+  // sd holds zero for columns outside the domain: their taps then add nothing, as a
+  // zero weight would, with the filter's coefficients as constants
+  const bool incol = ocol >= 0 && ocol < nx;
   const bool olane = l >= 4 && l < MW - 4 && ocol < nx;
   const RT iwx = olane ? RT(1) / wxs : RT(0);
   const int xl = min(max(l, 4), MW - 5) - 4;   // first x-filter tap in sd (in range)
@@ -755,6 +760,9 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
   RT xr[9];
 #pragma unroll
   for (int m = 0; m < 9; ++m) xr[m] = RT(0);
+  // the extra x-tap column's value of the next row to stage (lanes 0..3), one row ahead
+  RT exn = RT(0);
+  if (l < 4) exn = f[(long)max(qs, 0) * nx + gex];
   for (int q = qs; q <= qe; ++q) {
     RT xf = RT(0);
     if (q >= 0 && q < ny) {
@@ -775,7 +783,10 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
         zt[0] = fz[kz[0]]; zt[1] = fz[kz[1]]; zt[2] = fz[kz[3]]; zt[3] = fz[kz[4]];
       }
       sa[l + 2] = aq;
-      if (l < 4) sa[sex] = f[(long)q * nx + gex];
+      if (l < 4) {
+        sa[sex] = exn;
+        if (q + 1 < ny && q + 1 <= qe) exn = f[(long)(q + 1) * nx + gex];
+      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -800,13 +811,13 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
           out = out + RT(d.CY) * over * fdb;
         }
       }
-      sd[l] = out;
+      sd[l] = incol ? out : RT(0);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       RT xa = RT(0);
 #pragma unroll
-      for (int m = 0; m < 9; ++m) xa += wx[m] * sd[xl + m];
+      for (int m = 0; m < 9; ++m) xa += RT(c_gauss9[m < 4 ? 4 - m : m - 4]) * sd[xl + m];
       xf = xa * iwx;
       // sa and sd are rewritten next row only after every lane's reads above
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
