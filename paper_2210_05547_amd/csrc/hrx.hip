@@ -1173,7 +1173,7 @@ __global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
 // TTY - 1) hold the four interior rows the wall condition extrapolates from, so their
 // blocks apply it after the update (block barriers only) and no wall pass follows.
 // (With the split, a tile's chunks sit in different blocks; the wall pass stays.)
-template <int GAS, int ND, int ORDER, int MODE, class RT, bool TILED>
+template <int GAS, int ND, int ORDER, int MODE, class RT, bool TILED, bool PRE>
 __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F,
                                              const RT* __restrict__ Wp, const double* Qin,
                                              const double* __restrict__ Qref, double* Rout,
@@ -1230,8 +1230,23 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
   if (active && d.hold && p.j < 3) held = held || d.hold[((long)p.k * 3 + p.j) * d.nx + p.i];
   constexpr int NPI = ORDER == 6 ? 3 : 2;
   // components in chunks of KC; the tiled form stages each chunk's flux tiles in LDS
+  // PRE (2-D blocks that run several chunks): each chunk's pointwise inputs are loaded
+  // before its tiles are staged, so that their latency overlaps the staging (each thread
+  // reads only what it later writes); the production rates too in the mixed form.
+  constexpr bool PRE_W = sizeof(RT) == sizeof(float);
   for (int k0 = kbeg; k0 < kend; k0 += KC) {
     const int kn = min(KC, kend - k0);
+    double qv_[KC], dq_[KC];
+    RT wd_[KC];
+    if (PRE && active) {
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        const int k = min(k0 + kk, nvar - 1);
+        qv_[kk] = (MODE == MODE_RK) ? Qio[k * N + idx] : Qin[k * N + idx];
+        dq_[kk] = (MODE == MODE_RK) ? dQio[k * N + idx] : 0.0;
+        if (PRE_W) wd_[kk] = (GAS == AIR5 && k < NS) ? Wp[(d.w_wdot + k) * N + idx] : RT(0);
+      }
+    }
     if (TILED) {
       double* tx_ = smem;
       double* ty_ = smem + KC * FXE;
@@ -1266,7 +1281,8 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
       __syncthreads();
     }
     if (!active) continue;
-    for (int kk = 0; kk < kn; ++kk) {
+    // the component's update; qv_p, dq_p, wd_p are the preloaded inputs (PRE)
+    auto update = [&](int kk, double qv_p, double dq_p, double wd_p) {
       const int k = k0 + kk;
       RT acc;
       if (TILED && ND == 2) {
@@ -1278,17 +1294,25 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
         acc += sten_apply<RT, NPI>(sz, smem + KC * FXE + kk * FYE) * mz;
       }
       double R = -double(acc);
-      if (GAS == AIR5 && k < NS) R = R + double(Wp[(d.w_wdot + k) * N + idx]);
-      const double qv = (MODE == MODE_RK) ? Qio[k * N + idx] : Qin[k * N + idx];
+      if (GAS == AIR5 && k < NS)
+        R = R + (PRE && PRE_W ? wd_p : double(Wp[(d.w_wdot + k) * N + idx]));
+      const double qv = PRE ? qv_p : (MODE == MODE_RK) ? Qio[k * N + idx] : Qin[k * N + idx];
       if (Qref != nullptr && sig != 0.0) R = R - sig * (qv - Qref[k * N + idx]);
       if (held || (p.j == 0 && k >= ns && k < ns + ND)) R = 0.0;
       if (MODE == MODE_RHS) {
         Rout[k * N + idx] = R;
       } else {
-        const double dq = A * dQio[k * N + idx] + dt * R;
+        const double dq = A * (PRE ? dq_p : dQio[k * N + idx]) + dt * R;
         dQio[k * N + idx] = dq;
         Qio[k * N + idx] = qv + B * dq;
       }
+    };
+    if (PRE) {
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk)
+        if (kk < kn) update(kk, qv_[kk], dq_[kk], PRE_W ? double(wd_[kk]) : 0.0);
+    } else {
+      for (int kk = 0; kk < kn; ++kk) update(kk, 0.0, 0.0, 0.0);
     }
   }
   if (wall_in_div && j0 == 0) {
@@ -2203,10 +2227,19 @@ void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, con
   constexpr int nvar = (GAS == CPG ? 1 : NS) + ND + 1;
   unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
   constexpr int KC = div_chunk(ND);
-  if (d.N <= DIV_SPLIT_MAX_POINTS) nt *= (nvar + KC - 1) / KC;
+  constexpr int nch = (nvar + KC - 1) / KC;
+  const bool split = d.N <= DIV_SPLIT_MAX_POINTS;
+  if (split) nt *= nch;
   const size_t sh = (size_t)KC * (FXE + FYE) * sizeof(double);
   timed(ctx, K_DIV, st, [&] {
-    k_div<GAS, ND, ORDER, MODE, RT, true>
+    if constexpr (ND == 2 && nch > 1) {
+      if (!split) {
+        k_div<GAS, ND, ORDER, MODE, RT, true, true>
+            <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
+        return;
+      }
+    }
+    k_div<GAS, ND, ORDER, MODE, RT, true, false>
         <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
   });
 }
