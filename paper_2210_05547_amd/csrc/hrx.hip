@@ -583,7 +583,7 @@ __global__ __launch_bounds__(256) void k_ad_src(Dev d, const double* __restrict_
   if (ND == 2) {
     sd[1] = make_sten<ORDER>(sidx, TW, p.j, d.ny);
   } else {
-    sd[1] = make_sten<ORDER>(idx, d.nx, p.j, d.ny);
+    sd[1] = make_sten<ORDER>(0, d.nx, p.j, d.ny);   // offsets from the point (row-uniform)
     sd[2] = make_sten_central<ORDER>(sidx, TW);
     md[2] = RT(d.mz[p.k]);
   }
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(256) void k_ad_src(Dev d, const double* __restrict_
       const double* f = smem + a * TILE_E;
       RT g;
       if (b == 2) g = sten_apply<RT, NPI>(sd[2], f);
-      else if (ND == 3 && b == 1) g = sten_apply<RT>(sd[1], Wd + (long)a * N);
+      else if (ND == 3 && b == 1) g = sten_apply<RT>(sd[1], Wd + (long)a * N + idx);
       else g = sten_apply<RT>(sd[b], f);
       G[a][b] = g * md[b];
     }
@@ -853,14 +853,13 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
 // ------------------------------------------------------------------ k_flux
 // F planes (double): F[j][k] for direction j and conserved component k.  Convective
 // fluxes are formed in FP64; stresses, heat and diffusion fluxes in RT.
-template <int GAS, int ND, int ORDER, bool AD, class RT, bool TILED>
+template <int GAS, int ND, int ORDER, bool AD, class RT>
 __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ Q,
                                               const double* __restrict__ Wd,
                                               const RT* __restrict__ Wp,
                                               const RT* __restrict__ Gad, double* __restrict__ F) {
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
-  static_assert(TILED, "the flux stages its tile (the mole fractions are formed there)");
   constexpr bool XQ = GAS == AIR5 && ND == 2;   // X_s and p formed here from Q
   constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);   // u, v, (w), T, (X_s)
   // mole-fraction derivatives formed per flux direction (fewer live registers) where the
@@ -869,11 +868,9 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
   extern __shared__ double smem[];
   const long N = d.N;
   Pt p;
-  long sidx;                // index of the point in the source planes (global or tile)
-  const double* src;        // source planes: Wd, or the LDS tile
-  long splane;              // distance between source planes
+  long sidx;                // index of the point in the LDS tile
   Sten sd[3];
-  if (TILED) {
+  {
     // 2-D: tile in (x, y); 3-D: tile in (x, z) at row j0, y differences from memory
     int i0, j0, k0 = 0;
     if (ND == 2) tile_origin(d, i0, j0);
@@ -924,13 +921,11 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
     if (p.i >= d.nx || p.j >= d.ny || p.k >= d.nz) return;
     p.idx = ((long)p.k * d.ny + p.j) * d.nx + p.i;
     sidx = (long)(ty + THALO) * TW + tx + THALO;
-    src = smem;
-    splane = TILE_E;
     sd[0] = make_sten<ORDER>(sidx, 1, p.i, d.nx);
     if (ND == 2) {
       sd[1] = make_sten<ORDER>(sidx, TW, p.j, d.ny);
     } else {
-      sd[1] = make_sten<ORDER>(p.idx, d.nx, p.j, d.ny);
+      sd[1] = make_sten<ORDER>(0, d.nx, p.j, d.ny);   // offsets from the point (row-uniform)
       sd[2] = make_sten_central<ORDER>(sidx, TW);
     }
   }
@@ -942,8 +937,8 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
   constexpr int NPI = ORDER == 6 ? 3 : 2;
   // derivative of source plane a along direction b (z is periodic: central pairs only)
   auto deriv = [&](int a, int b) -> RT {
-    if (TILED && ND == 3 && b == 1) return sten_apply<RT>(sd[1], Wd + (long)a * N) * md[1];
-    const double* f = src + a * splane;
+    if (ND == 3 && b == 1) return sten_apply<RT>(sd[1], Wd + (long)a * N + idx) * md[1];
+    const double* f = smem + a * TILE_E;
     if (b == 2) return sten_apply<RT, NPI>(sd[b], f) * md[b];
     return sten_apply<RT>(sd[b], f) * md[b];
   };
@@ -1173,7 +1168,7 @@ __global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
 // TTY - 1) hold the four interior rows the wall condition extrapolates from, so their
 // blocks apply it after the update (block barriers only) and no wall pass follows.
 // (With the split, a tile's chunks sit in different blocks; the wall pass stays.)
-template <int GAS, int ND, int ORDER, int MODE, class RT, bool TILED, bool PRE>
+template <int GAS, int ND, int ORDER, int MODE, class RT, bool PRE>
 __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F,
                                              const RT* __restrict__ Wp, const double* Qin,
                                              const double* __restrict__ Qref, double* Rout,
@@ -1182,7 +1177,6 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
   constexpr int KC = div_chunk(ND);
-  static_assert(TILED, "the divergence stages its flux tiles");
   // 2-D RK stage without the chunk split: the wall condition runs here (see above)
   bool wall_in_div = ND == 2 && MODE == MODE_RK;
   extern __shared__ double smem[];
@@ -1192,7 +1186,7 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
   int i0 = 0, j0 = 0, k0t = 0, tx = 0, ty = 0;
   bool active = true;
   int kbeg = 0, kend = nvar;
-  if (TILED) {
+  {
     const unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
     unsigned b = blockIdx.x, nb = gridDim.x;
     if (gridDim.x > nt) {
@@ -1217,7 +1211,7 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
     if (ND == 2) {
       sy = make_sten<ORDER>((long)(ty + THALO) * TTX + tx, TTX, p.j, d.ny);
     } else {
-      sy = make_sten<ORDER>(p.idx, d.nx, p.j, d.ny);
+      sy = make_sten<ORDER>(0, d.nx, p.j, d.ny);   // offsets from the point (row-uniform)
       sz = make_sten_central<ORDER>((long)(ty + THALO) * TTX + tx, TTX);
     }
   }
@@ -1229,7 +1223,7 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
   bool held = (p.i == 0);
   if (active && d.hold && p.j < 3) held = held || d.hold[((long)p.k * 3 + p.j) * d.nx + p.i];
   constexpr int NPI = ORDER == 6 ? 3 : 2;
-  // components in chunks of KC; the tiled form stages each chunk's flux tiles in LDS
+  // components in chunks of KC; each chunk's flux tiles are staged in LDS
   // PRE (2-D blocks that run several chunks): each chunk's pointwise inputs are loaded
   // before its tiles are staged, so that their latency overlaps the staging (each thread
   // reads only what it later writes); the production rates too in the mixed form.
@@ -1247,7 +1241,7 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
         if (PRE_W) wd_[kk] = (GAS == AIR5 && k < NS) ? Wp[(d.w_wdot + k) * N + idx] : RT(0);
       }
     }
-    if (TILED) {
+    {
       double* tx_ = smem;
       double* ty_ = smem + KC * FXE;
       if (k0 > kbeg) __syncthreads();   // previous chunk fully consumed
@@ -1285,12 +1279,12 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
     auto update = [&](int kk, double qv_p, double dq_p, double wd_p) {
       const int k = k0 + kk;
       RT acc;
-      if (TILED && ND == 2) {
+      if (ND == 2) {
         acc = sten_apply<RT>(sx, smem + kk * FXE) * mx;
         acc += sten_apply<RT>(sy, smem + KC * FXE + kk * FYE) * my;
       } else {
         acc = sten_apply<RT>(sx, smem + kk * FXE) * mx;
-        acc += sten_apply<RT>(sy, F + ((long)nvar + k) * N) * my;
+        acc += sten_apply<RT>(sy, F + ((long)nvar + k) * N + idx) * my;
         acc += sten_apply<RT, NPI>(sz, smem + KC * FXE + kk * FYE) * mz;
       }
       double R = -double(acc);
@@ -2210,7 +2204,7 @@ void launch_flux(hrx_ctx* ctx, hipStream_t st, const double* Q, const double* Wd
   constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);
   const unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
   timed(ctx, K_FLUX, st, [&] {
-    k_flux<GAS, ND, ORDER, AD, RT, true>
+    k_flux<GAS, ND, ORDER, AD, RT>
         <<<nt, TTX * TTY, NSRC * TILE_E * sizeof(double), st>>>(d, Q, Wd, Wp, Gad, F);
   });
 }
@@ -2234,12 +2228,12 @@ void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, con
   timed(ctx, K_DIV, st, [&] {
     if constexpr (ND == 2 && nch > 1) {
       if (!split) {
-        k_div<GAS, ND, ORDER, MODE, RT, true, true>
+        k_div<GAS, ND, ORDER, MODE, RT, true>
             <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
         return;
       }
     }
-    k_div<GAS, ND, ORDER, MODE, RT, true, false>
+    k_div<GAS, ND, ORDER, MODE, RT, false>
         <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
   });
 }
