@@ -854,10 +854,10 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
 // F planes (double): F[j][k] for direction j and conserved component k.  Convective
 // fluxes are formed in FP64; stresses, heat and diffusion fluxes in RT.
 template <int GAS, int ND, int ORDER, bool AD, class RT>
-__global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ Q,
-                                              const double* __restrict__ Wd,
-                                              const RT* __restrict__ Wp,
-                                              const RT* __restrict__ Gad, double* __restrict__ F) {
+__device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict__ Q,
+                                          const double* __restrict__ Wd,
+                                          const RT* __restrict__ Wp,
+                                          const RT* __restrict__ Gad, double* __restrict__ F) {
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
   constexpr bool XQ = GAS == AIR5 && ND == 2;   // X_s and p formed here from Q
@@ -1061,6 +1061,22 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
     for (int a = 0; a < ND; ++a) work += tau[a] * RT(u[a]);
     Fj[(ns + ND) * N + idx] = (rhoE + pr) * u[j] - double(work - q);
   }
+}
+template <int GAS, int ND, int ORDER, bool AD, class RT>
+__global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ Q,
+                                              const double* __restrict__ Wd,
+                                              const RT* __restrict__ Wp,
+                                              const RT* __restrict__ Gad, double* __restrict__ F) {
+  flux_tile<GAS, ND, ORDER, AD, RT>(d, Q, Wd, Wp, Gad, F);
+}
+// The same for FP64 on 2-D grids of at most two wavefronts per SIMD: occupancy is then
+// bounded by the grid, not by registers, so the compiler may spend up to 256 VGPRs on
+// instruction-level parallelism (measured: flat-plate flux -3 %; no gain in the mixed form).
+template <int GAS, int ND, int ORDER, bool AD, class RT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_flux_small(
+    Dev d, const double* __restrict__ Q, const double* __restrict__ Wd,
+    const RT* __restrict__ Wp, const RT* __restrict__ Gad, double* __restrict__ F) {
+  flux_tile<GAS, ND, ORDER, AD, RT>(d, Q, Wd, Wp, Gad, F);
 }
 
 // ------------------------------------------------------------------ k_bc (wall row)
@@ -1811,6 +1827,7 @@ struct hrx_ctx {
   double *metrics = nullptr;   // mx, my, mz, sx, sy, dlx, dly, dlz
   unsigned char *hold = nullptr;
   unsigned long long *counters = nullptr;
+  bool small_grid = false;   // at most two wavefronts per SIMD at one thread per point
   hipStream_t last_stream = nullptr;
   // kernel timing
   bool timing = false;
@@ -2180,6 +2197,13 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     return fail(HRX_ENOMEM);
   if ((rc = check(hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long))))) return fail(rc);
   d.counters = ctx->counters;
+  {
+    int dev = 0, ncu = 0;
+    if ((rc = check(hipGetDevice(&dev)))) return fail(rc);
+    if ((rc = check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev))))
+      return fail(rc);
+    ctx->small_grid = (long)N <= 2L * 64 * 4 * ncu;   // 4 SIMDs per compute unit
+  }
   // zeroed temperature plane: the first energy inversion starts cold
   if ((rc = check(hipMemset(ctx->Wd, 0, sizeof(double) * N * ctx->nWd)))) return fail(rc);
   *out = ctx;
@@ -2196,16 +2220,21 @@ int hrx_get_reference(const hrx_ctx* ctx, hrx_reference* out) {
 
 namespace {
 
-// 2-D grids use the LDS-tiled stencil kernels; 3-D grids read neighbours from memory.
 template <int GAS, int ND, int ORDER, bool AD, class RT>
 void launch_flux(hrx_ctx* ctx, hipStream_t st, const double* Q, const double* Wd, const RT* Wp,
                  const RT* Gad, double* F) {
   const Dev& d = ctx->dev;
   constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);
   const unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
+  const size_t sh = NSRC * TILE_E * sizeof(double);
   timed(ctx, K_FLUX, st, [&] {
-    k_flux<GAS, ND, ORDER, AD, RT>
-        <<<nt, TTX * TTY, NSRC * TILE_E * sizeof(double), st>>>(d, Q, Wd, Wp, Gad, F);
+    if constexpr (ND == 2 && sizeof(RT) == sizeof(double)) {
+      if (ctx->small_grid) {
+        k_flux_small<GAS, ND, ORDER, AD, RT><<<nt, TTX * TTY, sh, st>>>(d, Q, Wd, Wp, Gad, F);
+        return;
+      }
+    }
+    k_flux<GAS, ND, ORDER, AD, RT><<<nt, TTX * TTY, sh, st>>>(d, Q, Wd, Wp, Gad, F);
   });
 }
 
