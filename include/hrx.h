@@ -203,9 +203,8 @@ int hrx_mlp_train_step(hrx_ctx *ctx, int64_t n, const int32_t *idx, const float 
  * kernel of the calls that follow hrx_timing_enable(ctx, 1).  Kernel ids (index into
  * the arrays of hrx_timing_read): 0 prim, 1 ad_src, 2 ad_d4 (the fourth difference
  * fused with the x and y filters), 3 and 4 (no launches: the x and y filters run inside
- * 2), 5 ad_filter_z, 6 flux, 7 div, 8 bc (3-D, and 2-D grids of at most 2^18
- * points with more than four conserved variables, whose divergence runs split into
- * component chunks; on other 2-D grids the wall condition runs inside div), 9 thermo_eval,
+ * 2), 5 ad_filter_z, 6 flux, 7 div, 8 bc (3-D; in 2-D the wall condition runs
+ * inside div), 9 thermo_eval,
  * 10 chem_source (in the surrogate form the network pass is counted with prim and
  * thermo_eval).
  * hrx_timing_read synchronises, returns the summed milliseconds and launch counts

@@ -275,17 +275,18 @@ constexpr int div_chunk(int nd) { return nd == 3 ? 3 : KCH; }
 // all of its global loads (held in registers), then writes them, so the loads of a
 // thread are in flight together instead of one round trip per element.
 template <int TOTAL, int NTHREADS, class T, class SrcOf>
-__device__ __forceinline__ void stage_tile(T* __restrict__ dst, SrcOf src_of) {
+__device__ __forceinline__ void stage_tile(T* __restrict__ dst, SrcOf src_of,
+                                           int tid = threadIdx.x) {
   constexpr int PER = (TOTAL + NTHREADS - 1) / NTHREADS;
   T v[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * NTHREADS;
+    const int e = tid + q * NTHREADS;
     v[q] = (e < TOTAL) ? src_of(e) : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * NTHREADS;
+    const int e = tid + q * NTHREADS;
     if (e < TOTAL) dst[e] = v[q];
   }
 }
@@ -1184,8 +1185,8 @@ __global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
 // TTY - 1) hold the four interior rows the wall condition extrapolates from, so their
 // blocks apply it after the update (block barriers only) and no wall pass follows.
 // (With the split, a tile's chunks sit in different blocks; the wall pass stays.)
-template <int GAS, int ND, int ORDER, int MODE, class RT, bool PRE>
-__global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F,
+template <int GAS, int ND, int ORDER, int MODE, class RT, bool PRE, int NH>
+__global__ __launch_bounds__(256 * NH) void k_div(Dev d, const double* __restrict__ F,
                                              const RT* __restrict__ Wp, const double* Qin,
                                              const double* __restrict__ Qref, double* Rout,
                                              double* Qio, double* dQio, double A, double B,
@@ -1193,19 +1194,29 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
   constexpr int ns = (GAS == CPG) ? 1 : NS;
   constexpr int nvar = ns + ND + 1;
   constexpr int KC = div_chunk(ND);
-  // 2-D RK stage without the chunk split: the wall condition runs here (see above)
+  // 2-D RK stage: the wall condition runs here (see above), unless the tile's chunks run
+  // in different blocks
   bool wall_in_div = ND == 2 && MODE == MODE_RK;
-  extern __shared__ double smem[];
+  // NH = 2: two halves of 256 threads update the two chunks of one tile side by side
+  static_assert(NH == 1 || (ND == 2 && (nvar + KC - 1) / KC == 2), "two halves, two chunks");
+  const int lt = NH == 1 ? (int)threadIdx.x : (int)(threadIdx.x & 255);
+  const int half = NH == 1 ? 0 : (int)(threadIdx.x >> 8);
+  extern __shared__ double smem_all[];
+  double* smem = smem_all + half * KC * (FXE + FYE);
   const long N = d.N;
   Pt p;
   Sten sx, sy, sz;
   int i0 = 0, j0 = 0, k0t = 0, tx = 0, ty = 0;
   bool active = true;
   int kbeg = 0, kend = nvar;
+  if (NH == 2) {
+    kbeg = half * KC;
+    kend = min(kbeg + KC, nvar);
+  }
   {
     const unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
     unsigned b = blockIdx.x, nb = gridDim.x;
-    if (gridDim.x > nt) {
+    if (NH == 1 && gridDim.x > nt) {
       const unsigned c = blockIdx.x / nt;
       b -= c * nt;
       nb = nt;
@@ -1215,8 +1226,8 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
     }
     if (ND == 2) tile_origin(d, i0, j0, b, nb);
     else tile_origin3(d, i0, j0, k0t, b, nb);
-    tx = threadIdx.x & (TTX - 1);
-    ty = threadIdx.x / TTX;   // tile row: y in 2-D, z in 3-D
+    tx = lt & (TTX - 1);
+    ty = lt / TTX;   // tile row: y in 2-D, z in 3-D
     p.i = i0 + tx;
     p.j = ND == 2 ? j0 + ty : j0;
     p.k = ND == 2 ? 0 : k0t + ty;
@@ -1274,7 +1285,7 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
         }
         const int gk = min(k0t + ly, d.nz - 1);
         return F[(long)k * N + ((long)gk * d.ny + j0) * d.nx + gi];
-      });
+      }, lt);
       stage_tile<KC * FYE, TTX * TTY>(ty_, [&](int e) {
         const int kk = e / FYE, r = e - kk * FYE;
         const int ly = r / TTX, lx = r - ly * TTX;
@@ -1287,7 +1298,7 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
         int gk = k0t + ly - THALO;
         gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
         return F[((long)2 * nvar + k) * N + ((long)gk * d.ny + j0) * d.nx + gi];
-      });
+      }, lt);
       __syncthreads();
     }
     if (!active) continue;
@@ -1326,15 +1337,15 @@ __global__ __launch_bounds__(256) void k_div(Dev d, const double* __restrict__ F
     }
   }
   if (wall_in_div && j0 == 0) {
-    // rows 1 .. 4 of the updated state (each thread re-reads its own stores) through LDS
-    // to the wall row's threads
+    // rows 1 .. 4 of the updated state (each thread re-reads its own stores, each half
+    // its own chunk) through LDS to the wall row's threads
     __syncthreads();   // the flux tiles in LDS are consumed
     if (active && ty >= 1 && ty <= 4)
-      for (int k = 0; k < nvar; ++k) smem[(k * 4 + ty - 1) * TTX + tx] = Qio[k * N + idx];
+      for (int k = kbeg; k < kend; ++k) smem_all[(k * 4 + ty - 1) * TTX + tx] = Qio[k * N + idx];
     __syncthreads();
-    if (ty == 0 && p.i >= 1 && p.i < d.nx)
+    if (half == 0 && ty == 0 && p.i >= 1 && p.i < d.nx)
       wall_point<GAS, ND>(d, Qio, p.i, 0,
-                          [&](int v, int m) { return smem[(v * 4 + m - 1) * TTX + tx]; });
+                          [&](int v, int m) { return smem_all[(v * 4 + m - 1) * TTX + tx]; });
   }
 }
 
@@ -2252,18 +2263,21 @@ void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, con
   constexpr int KC = div_chunk(ND);
   constexpr int nch = (nvar + KC - 1) / KC;
   const bool split = d.N <= DIV_SPLIT_MAX_POINTS;
-  if (split) nt *= nch;
   const size_t sh = (size_t)KC * (FXE + FYE) * sizeof(double);
   timed(ctx, K_DIV, st, [&] {
-    if constexpr (ND == 2 && nch > 1) {
-      if (!split) {
-        k_div<GAS, ND, ORDER, MODE, RT, true>
+    if constexpr (ND == 2 && nch == 2) {
+      // small grids: the two chunks of a tile in two halves of one 512-thread block;
+      // larger grids: one block runs both chunks, the first one's inputs preloaded
+      if (split)
+        k_div<GAS, ND, ORDER, MODE, RT, false, 2>
+            <<<nt, 2 * TTX * TTY, 2 * sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
+      else
+        k_div<GAS, ND, ORDER, MODE, RT, true, 1>
             <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
-        return;
-      }
+      return;
     }
-    k_div<GAS, ND, ORDER, MODE, RT, false>
-        <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
+    k_div<GAS, ND, ORDER, MODE, RT, false, 1>
+        <<<split ? nt * nch : nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
   });
 }
 
@@ -2337,7 +2351,8 @@ int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, 
                                             B, dt);
     constexpr int nvar = (GAS == CPG ? 1 : NS) + ND + 1;
     constexpr int nch = (nvar + div_chunk(ND) - 1) / div_chunk(ND);
-    const bool split = d.N <= DIV_SPLIT_MAX_POINTS && nch > 1;
+    // chunks of one tile in separate blocks (two chunks share a block in 2-D)
+    const bool split = d.N <= DIV_SPLIT_MAX_POINTS && nch > 2;
     if (ND == 3 || split) {   // else it ran inside k_div
       const long nw = (long)(d.nx - 1) * d.nz;
       timed(ctx, K_BC, st, [&] { k_bc<GAS, ND><<<blocks_for(nw, 128), 128, 0, st>>>(d, Qio); });

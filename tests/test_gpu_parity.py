@@ -165,6 +165,9 @@ def test_c4_jisc_3d_reduced():
 
 
 def test_c2_full_size():
+    """The bench's flat plate: at 2^17 points the divergence updates the two component
+    chunks of a tile in the two halves of one block, and the bottom blocks apply the wall
+    condition."""
     _run_case(fields.get_config("c2"), 3)
 
 
@@ -173,8 +176,9 @@ def test_c3_full_size_rhs():
 
 
 def test_c3_full_size_stages():
-    """Two RK stages on the full 2048 x 512 grid: above 2^18 points the 2-D divergence
-    applies the wall condition itself (no separate wall pass)."""
+    """Two RK stages on the full 2048 x 512 grid: above 2^18 points each 2-D divergence
+    block runs both component chunks of its tile and the bottom blocks apply the wall
+    condition."""
     _run_case(fields.get_config("c3"), 2, rhs=False)
 
 
