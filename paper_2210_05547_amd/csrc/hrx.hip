@@ -669,7 +669,7 @@ __global__ __launch_bounds__(64) void k_ad_filter_z(Dev d, const RT* __restrict_
 
 // Fourth difference -> x filter -> y filter in one pass, as a march down y: a
 // wavefront owns a strip of MW fourth-difference columns (MO = MW - 8 output columns,
-// the x filter's halo of 4 on each side) and a segment of MSEG output rows of one AD
+// the x filter's halo of 4 on each side) and a segment of mseg output rows of one AD
 // plane (and one z plane in 3-D), and walks down the rows.  Lane l keeps its column's
 // five source rows (the fourth difference's y taps) and nine x-filtered rows (the y
 // filter's taps) in registers and exchanges only the current row through LDS for the x
@@ -684,10 +684,14 @@ __global__ __launch_bounds__(64) void k_ad_filter_z(Dev d, const RT* __restrict_
 // 0..3) are loaded one row ahead, so their latency overlaps the previous row's work; the
 // z taps are loaded in their own row (a prefetch of them too costs a wavefront per SIMD
 // and was slower).
-constexpr int MW = 64, MO = MW - 8, MSEG = 32;
+// Segments of 24 rows in 2-D (SBLI: about six wavefronts per SIMD, all resident; 6-9 %
+// faster than 32) and 32 in 3-D (enough wavefronts already; shorter segments add halo
+// rows) -- measured.
+constexpr int MW = 64, MO = MW - 8, MSEG2 = 24, MSEG3 = 32;
 template <int GAS, int ND, class RT>
 __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A,
-                                                RT* __restrict__ B, int nstrip, int nseg) {
+                                                RT* __restrict__ B, int nstrip, int nseg,
+                                                int mseg) {
   __shared__ RT sa[MW + 4];   // source row q, columns i0 - 6 .. i0 + MW - 3
   __shared__ RT sd[MW];       // fourth differences of row q, columns i0 - 4 .. i0 + MW - 5
   const int nx = d.nx, ny = d.ny, nz = d.nz;
@@ -708,7 +712,7 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
   const int seg = (int)(ts - tg * (unsigned)nseg);
   const int v = (int)tg;
   const int l = threadIdx.x;
-  const int i0 = strip * MO, y0 = seg * MSEG, y1 = min(y0 + MSEG, ny);
+  const int i0 = strip * MO, y0 = seg * mseg, y1 = min(y0 + mseg, ny);
   const long kb = (long)k * P;
   const RT* f = A + (long)v * N + kb;       // this plane
   const bool sq = v < 2;
@@ -2312,9 +2316,10 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
     });
     // fourth differences and the x and y filters in one pass (timed as ad_d4)
     timed(ctx, K_AD_D4, st, [&] {
-      const int nstrip = (d.nx + MO - 1) / MO, nseg = (d.ny + MSEG - 1) / MSEG;
+      const int mseg = ND == 2 ? MSEG2 : MSEG3;
+      const int nstrip = (d.nx + MO - 1) / MO, nseg = (d.ny + mseg - 1) / mseg;
       k_ad_march<GAS, ND, RT><<<(unsigned)((long)d.nz * nstrip * nseg * d.nad), MW, 0, st>>>(
-          d, A, B, nstrip, nseg);
+          d, A, B, nstrip, nseg, mseg);
     });
     if (ND == 3) {
       const int nxs = (d.nx + 63) / 64, nzs = (d.nz + ZSEG - 1) / ZSEG;
