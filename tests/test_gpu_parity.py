@@ -160,6 +160,12 @@ def test_c3_sbli_ad_reduced():
     _run_case(fields.get_config("c3").scaled(96, 48), 3)
 
 
+def test_c3_above_split_ragged():
+    """SBLI with artificial diffusivity on 1100 x 250 points: ragged tiles, march strips
+    (56 columns) and march segments (24 rows) at the grid edges, above 2^18 points."""
+    _run_case(fields.get_config("c3").scaled(1100, 250), 1)
+
+
 def test_c4_jisc_3d_reduced():
     _run_case(fields.get_config("c4").scaled(40, 32, 16), 2)
 
@@ -169,6 +175,13 @@ def test_c2_full_size():
     chunks of a tile in the two halves of one block, and the bottom blocks apply the wall
     condition."""
     _run_case(fields.get_config("c2"), 3)
+
+
+def test_c2_above_split_ragged():
+    """A flat plate of 1030 x 270 points: above 2^18 points one block runs both
+    component chunks of its tile (the first chunk's inputs preloaded) and applies the wall
+    condition, on tiles cut by both grid edges."""
+    _run_case(fields.get_config("c2").scaled(1030, 270), 2)
 
 
 def test_c3_full_size_rhs():
