@@ -13,9 +13,8 @@
 //              [HBM bound]
 //   k_div      -sum_j dF_j/dx_j + S - sigma (Q - Q_ref), boundary rows, and either
 //              the R output or the fused low-storage RK update (Sec. 3.1), with the wall
-//              condition on 2-D grids past the small-grid split  [HBM bound]
-//   k_bc       wall row after a stage otherwise (no slip, non-catalytic, T_w or
-//              adiabatic)
+//              condition (no slip, non-catalytic, T_w or adiabatic) in 2-D  [HBM bound]
+//   k_bc       the wall row after a 3-D stage
 // Fields are SoA planes with x fastest; stencil kernels stage LDS tiles (32 x 8 points
 // plus halos) or march along a direction keeping the taps in registers.
 #include <hip/hip_runtime.h>
@@ -1178,17 +1177,17 @@ __global__ __launch_bounds__(128) void k_bc(Dev d, double* __restrict__ Q) {
 // R = -sum_j dF_j/dx_j (FP64 differences, RT weighted sums) + wdot (species)
 //     - sigma (Q - Q_ref) (FP64); boundary rows; then R out, or the low-storage update
 // of Q and dQ in FP64.
-// Tiled: a block takes the chunks of KC components of its tile one after the other,
-// or, when the grid holds one block per tile and chunk (small grids), the chunk its
-// block index names (chunk major: blocks [c nt, (c + 1) nt) take chunk c), so the
-// chunks of a tile run side by side and more wavefronts are in flight.  2-D tiles stage
-// the x fluxes with their x halo and the y fluxes with their y halo; 3-D tiles lie in
-// the (x, z) plane of one row (the order of the flux kernel) and stage the x and z
-// fluxes, the y differences reading the neighbouring rows from memory.
-// 2-D RK stages without the chunk split: the tiles of the bottom tile row (rows 0 ..
-// TTY - 1) hold the four interior rows the wall condition extrapolates from, so their
-// blocks apply it after the update (block barriers only) and no wall pass follows.
-// (With the split, a tile's chunks sit in different blocks; the wall pass stays.)
+// A block takes the chunks of KC components of its tile one after the other (PRE: each
+// chunk's pointwise inputs loaded before its tiles are staged).  On small grids the
+// chunks of a tile run side by side, so that more wavefronts are in flight: in 2-D in
+// the two 256-thread halves of one block (NH = 2), in 3-D in one block per tile and
+// chunk (chunk major: blocks [c nt, (c + 1) nt) take chunk c).  2-D tiles stage the x
+// fluxes with their x halo and the y fluxes with their y halo; 3-D tiles lie in the
+// (x, z) plane of one row (the order of the flux kernel) and stage the x and z fluxes,
+// the y differences reading the neighbouring rows from memory.
+// 2-D RK stages: the tiles of the bottom tile row (rows 0 .. TTY - 1) hold the four
+// interior rows the wall condition extrapolates from, so their blocks apply it after the
+// update (block barriers only) and no wall pass follows.
 template <int GAS, int ND, int ORDER, int MODE, class RT, bool PRE, int NH>
 __global__ __launch_bounds__(256 * NH) void k_div(Dev d, const double* __restrict__ F,
                                              const RT* __restrict__ Wp, const double* Qin,
@@ -2253,8 +2252,8 @@ void launch_flux(hrx_ctx* ctx, hipStream_t st, const double* Q, const double* Wd
   });
 }
 
-// 2-D grids up to this many points run k_div with one block per tile and component
-// chunk (below about two wavefronts per SIMD the chunks of a tile are latency bound).
+// Grids up to this many points run the component chunks of a tile side by side in k_div
+// (near two wavefronts per SIMD the chunks of a tile are latency bound).
 constexpr long DIV_SPLIT_MAX_POINTS = 1L << 18;
 
 template <int GAS, int ND, int ORDER, int MODE, class RT>
