@@ -29,6 +29,21 @@ def reference_cpg(gamma, Pr, mach, T_inf, Re):
                 mu_inf=float(transport.sutherland(T_inf)))
 
 
+def reference_tpg(gamma, mach, T_inf, Re):
+    """Thermally perfect gas (Sec. 2.2.2, module tpg): nondimensional constants, with
+    Pr = mu_inf c_p,inf / kappa_inf from Sutherland's and Keyes' laws at T_inf."""
+    from . import tpg
+    T_ref = (gamma - 1.0) * T_inf
+    mu = float(transport.sutherland(T_inf))
+    kap = float(tpg.keyes(T_inf))
+    cp = gamma * tpg.R_AIR / (gamma - 1.0)
+    out = dict(gas="tpg", gamma=gamma, Pr=mu * cp / kap, Re=Re, Ec=1.0, mach=mach,
+               T_inf=T_inf, T_ref=T_ref, T_inf_nd=1.0 / (gamma - 1.0), mu_inf=mu,
+               kappa_inf=kap, cp_inf=cp)
+    out.update(tpg.constants(gamma, T_inf))
+    return out
+
+
 def reference_air5(p_inf, T_inf, Y_inf, mach, Re=None, L_ref=None):
     """5-species air free stream and scales; exactly one of Re, L_ref (> 0) is used."""
     Y = np.asarray(Y_inf, dtype=np.float64).reshape(5, 1)
@@ -58,6 +73,8 @@ def reference_from_config(cfg):
     """Reference state for a workload configuration (fields.FlowConfig)."""
     if cfg.gas == 0:
         return reference_cpg(cfg.gamma, cfg.Pr, cfg.mach, cfg.T_inf, cfg.Re)
+    if cfg.gas == 2:
+        return reference_tpg(cfg.gamma, cfg.mach, cfg.T_inf, cfg.Re)
     if cfg.L_ref > 0.0:
         return reference_air5(cfg.p_inf, cfg.T_inf, cfg.Y_inf, cfg.mach, L_ref=cfg.L_ref)
     return reference_air5(cfg.p_inf, cfg.T_inf, cfg.Y_inf, cfg.mach, Re=cfg.Re)

@@ -18,6 +18,8 @@ Readings (where the paper is silent or garbled):
 * Eq. (18) prints grad Y_s with the molar prefactor c M_s; it is read as grad X_s,
   consistent with the driving force of Eq. (16).  Both readings give sum J_s = 0.
 * CPG conductivity: kappa = mu nondimensionally (Sec. 2.2.2).
+* Thermally perfect gas (Sec. 2.2.2): the state of module tpg, with the calorically
+  perfect gas's state vector and equation of state.
 * Boundaries (Sec. 3.2): inflow column held (R = 0); no-slip wall with zero momentum
   RHS; after each stage the wall row gets extrapolated mass fractions (zero normal
   gradient, non-catalytic), the evolved density, zero momentum and the energy of the
@@ -34,6 +36,7 @@ from . import thermo
 from . import transport
 from . import chemistry
 from . import refstate as rs
+from . import tpg
 
 # Low-storage (2N) Runge-Kutta coefficients: Williamson's third-order scheme and the
 # Carpenter-Kennedy five-stage fourth-order scheme.
@@ -57,6 +60,7 @@ class Case:
         self.cfg = cfg
         self.ref = rs.reference_from_config(cfg)
         self.air5 = cfg.gas == 1
+        self.gas = cfg.gas
         self.ns = 5 if self.air5 else 1
         self.ndim = cfg.ndim
         self.nvar = self.ns + self.ndim + 1
@@ -117,6 +121,19 @@ def primitives(Q, case):
     E = Q[ns + nd] / rho
     e = E - 0.5 * sum(u * u for u in vel)
     P.update(rho=rho, Y=Y, vel=vel, e=e)
+    if case.gas == 2:
+        # thermally perfect gas (module tpg): Newton for T, Eq. (22) for p, Eqs. (24-25)
+        g = ref["gamma"]
+        T, _, ok = tpg.temperature(e, ref["k0"], ref["th"], g)
+        p = thermo.cpg_pressure(rho, T, g)
+        Tk = T * ref["T_ref"]
+        mu = transport.sutherland(Tk) / ref["mu_inf"]
+        kap = tpg.keyes(Tk) / ref["kappa_inf"]
+        # equilibrium sound speed: gamma(T) = c_p / c_v = 1 + ((g - 1)/g) / c_v(T)
+        gT = 1.0 + ((g - 1.0) / g) / tpg.cv(T, ref["k0"], ref["th"], g)
+        P.update(T=T, p=p, mu=mu, kappa=kap, c=np.sqrt(gT * p / rho),
+                 status=np.where(ok, 0, 1))
+        return P
     if not case.air5:
         g = ref["gamma"]
         T = thermo.cpg_temperature(e, g)
@@ -244,6 +261,8 @@ def apply_rhs_boundaries(R, case):
 def wall_energy(rho, T, Y, case):
     """rho E at the wall from T (nondim) and Y with zero velocity."""
     ref = case.ref
+    if case.gas == 2:
+        return rho * tpg.energy(T, ref["k0"], ref["th"], ref["gamma"])
     if not case.air5:
         return rho * T / ref["gamma"]
     Tk = T * ref["T_ref"]

@@ -33,6 +33,7 @@ SPECIES = ("N2", "O2", "NO", "N", "O")
 
 GAS_CPG = 0
 GAS_AIR5 = 1
+GAS_TPG = 2      # thermally perfect single-species air
 WALL_ADIABATIC = 0
 WALL_ISOTHERMAL = 1
 
@@ -57,7 +58,7 @@ class FlowConfig:
     mach: float = 6.0
     T_inf: float = 220.0          # K
     p_inf: float = 3596.0         # Pa (air5)
-    gamma: float = 1.4            # CPG only
+    gamma: float = 1.4            # CPG and TPG
     Pr: float = 0.72              # CPG only
     Re: float = 1.0e5
     L_ref: float = 0.0            # m; > 0 overrides Re for air5
@@ -88,7 +89,7 @@ class FlowConfig:
 
     @property
     def ns(self):
-        return 1 if self.gas == GAS_CPG else 5
+        return 5 if self.gas == GAS_AIR5 else 1
 
     @property
     def ndim(self):
@@ -96,7 +97,7 @@ class FlowConfig:
 
     @property
     def nvar(self):
-        base = 1 if self.gas == GAS_CPG else 5
+        base = 5 if self.gas == GAS_AIR5 else 1
         return base + self.ndim + 1
 
     @property
@@ -151,7 +152,14 @@ def _cfg_c4():
                       seed=20221011 + 4)
 
 
-CONFIGS = {"c1": _cfg_c1, "c2": _cfg_c2, "c3": _cfg_c3, "c4": _cfg_c4}
+def _cfg_c1t():
+    """The c1 flat plate as a thermally perfect gas (Sec. 2.2.2): its adiabatic wall
+    reaches about 1600 K, where the vibrational specific heat matters."""
+    return dataclasses.replace(_cfg_c1(), name="flatplate_tpg_m6_128x64", gas=GAS_TPG,
+                               seed=20221011 + 5)
+
+
+CONFIGS = {"c1": _cfg_c1, "c2": _cfg_c2, "c3": _cfg_c3, "c4": _cfg_c4, "c1t": _cfg_c1t}
 
 
 def get_config(key: str) -> FlowConfig:
@@ -202,8 +210,8 @@ def initial_field(cfg: FlowConfig):
     rng = np.random.Generator(np.random.PCG64(cfg.seed))
     x, y, z = grid(cfg)
     Z3, Y3, X3 = np.meshgrid(z, y, x, indexing="ij")          # [nz][ny][nx]
-    g = cfg.gamma if cfg.gas == GAS_CPG else 1.4
-    Pr = cfg.Pr if cfg.gas == GAS_CPG else 0.72
+    g = cfg.gamma if cfg.gas != GAS_AIR5 else 1.4
+    Pr = cfg.Pr if cfg.gas != GAS_AIR5 else 0.72
     M = cfg.mach
     Tinf = cfg.T_inf
     # boundary-layer velocity and Crocco-Busemann temperature (nominal, K)
@@ -265,8 +273,9 @@ def initial_field(cfg: FlowConfig):
         v = (1.0 - wj) * v + wj * (cj / cinf)
         u = (1.0 - wj) * u
         hold = np.flatnonzero((wxz * jrow).reshape(-1) > 0.0).astype(np.int64)
-    # assemble nondimensional conserved variables
-    if cfg.gas == GAS_CPG:
+    # assemble nondimensional conserved variables (one species: the generator's energy
+    # model is the calorically perfect one for the thermally perfect gas too)
+    if cfg.gas != GAS_AIR5:
         rho = p / (T / Tinf) * rho_fac
         e = (T / Tinf) / (g * (g - 1.0))            # nominal e / c_inf^2
         rhos = rho[None]
