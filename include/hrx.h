@@ -44,7 +44,7 @@ typedef enum {
   HRX_EUNSUP = -4    /* valid request that this build does not support */
 } hrx_status;
 
-enum { HRX_GAS_CPG = 0, HRX_GAS_AIR5 = 1 };
+enum { HRX_GAS_CPG = 0, HRX_GAS_AIR5 = 1, HRX_GAS_TPG = 2 };
 enum { HRX_WALL_ADIABATIC = 0, HRX_WALL_ISOTHERMAL = 1 };
 enum { HRX_RK3_2N = 0, HRX_RK45_2N = 1 };
 enum { HRX_PREC_FP64 = 0, HRX_PREC_MIXED = 1 };
@@ -53,7 +53,9 @@ enum { HRX_THERMO_PLAIN = 0, HRX_THERMO_SURROGATE = 1 };
 /* Workload description (host).  Sec. 2.1 (reference scales, Eq. 7 and 11), Sec. 3.2
  * (sponges, wall), Sec. 3.3 (artificial diffusivity), Sec. 4 (case parameters). */
 typedef struct hrx_config {
-  int gas;                  /* HRX_GAS_* */
+  int gas;                  /* HRX_GAS_*: calorically perfect, 5-species air, or thermally
+                               perfect air (Sec. 2.2.2; no artificial diffusivity:
+                               HRX_EUNSUP) */
   int nx, ny, nz;           /* grid points; nz = 1 for a 2-D problem; nx, ny >= 8 */
   const double *x, *y, *z;  /* (host) separable coordinates, nondimensional; x, y
                                non-periodic, z uniform and periodic (may be NULL if nz = 1) */
@@ -66,7 +68,9 @@ typedef struct hrx_config {
                                stencil weighted sums and artificial-diffusivity planes */
   int ad_on;                /* artificial diffusivity on/off */
   double ad_coef[5];        /* C_mu, C_beta, C_kappa, C_D, C_Y */
-  double gamma, Pr;         /* calorically perfect gas only */
+  double gamma, Pr;         /* gamma_inf: perfect gases (CPG, TPG); Pr: CPG only (the
+                               thermally perfect gas derives it from Sutherland's and
+                               Keyes' laws at T_inf, Sec. 2.2.2) */
   double mach;              /* free-stream Mach number (informational) */
   double T_inf;             /* K */
   double p_inf;             /* Pa (air5) */

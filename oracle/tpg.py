@@ -23,7 +23,10 @@ Readings (where the paper is silent or garbled):
   c_v(T) = k0 [1 + (g - 1)/g f(th/T)] - (g - 1)/g,  f(x) = x^2 e^x / (e^x - 1)^2.
 * Energy inversion: Newton from the frozen-vibration bound T0 = e / (k0 - (g - 1)/g),
   which lies above the root (e(T) is convex and increasing), stopped at
-  |dT| <= 1e-13 T or after 50 iterations, as for 5-species air.
+  |dT| <= 1e-13 T or after 50 iterations, as for 5-species air; then one Newton step
+  whose residual is evaluated in extended precision, so that the returned T is the root
+  rounded to double (the right-hand side amplifies differences of a few units in the
+  last place of T near the wall).
 """
 import numpy as np
 
@@ -93,4 +96,10 @@ def temperature(e, k0, th, gamma, rtol=1e-13, max_iter=50):
         done = done | (np.abs(dT) <= rtol * np.abs(T))
         if done.all():
             break
+    # refinement: residual e(T) - e in extended precision (80-bit long double)
+    L = np.longdouble
+    TL = T.astype(L)
+    aL = L((gamma - 1.0) / gamma)
+    res = L(k0) * TL + L(k0) * aL * L(th) / np.expm1(L(th) / TL) - aL * TL - e.astype(L)
+    T = (TL - res / cv(T, k0, th, gamma).astype(L)).astype(np.float64)
     return T, it, done

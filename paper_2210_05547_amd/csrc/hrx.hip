@@ -27,12 +27,13 @@
 #include <vector>
 
 #include "air5.h"
+#include "tpg.h"
 #include "hrx.h"
 #include "mlp.h"
 
 namespace hrx {
 
-enum { CPG = 0, AIR5 = 1 };
+enum { CPG = 0, AIR5 = 1, TPG = 2 };
 enum { MODE_RHS = 0, MODE_RK = 1 };
 
 struct Dev {
@@ -49,6 +50,7 @@ struct Dev {
   int newton_max;
   int ad_on;
   double Cmu, Cbeta, Ckap, CD, CY;
+  double tpg_k0, tpg_th;          // thermally perfect gas: c_p0 / c_p,inf, Theta / T_ref
   const double *mx, *my, *mz;     // metrics d(xi)/dx
   const double *sx, *sy;          // sponge profiles
   const double *dlx, *dly, *dlz;  // local spacings dx/d(xi)
@@ -498,7 +500,7 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   const long idx = blk * blockDim.x + threadIdx.x;
   if (idx >= d.N) return;
   const long N = d.N;
-  if (GAS == CPG) {
+  if (GAS != AIR5) {
     const double rho = Q[idx];
     double u[3] = {0.0, 0.0, 0.0};
     double ke = 0.0;
@@ -510,7 +512,13 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
     const double E = Q[(1 + ND) * N + idx] / rho;
     const double e = E - 0.5 * ke;
     const double g = d.gamma;
-    const double T = g * e;
+    double T = g * e;
+    if (GAS == TPG) {
+      int status;
+      T = tpg_temperature(e, d.tpg_k0, d.tpg_th, (g - 1.0) / g, d.newton_rtol, d.newton_max,
+                          &status);
+      if (status) atomicAdd(&d.counters[0], 1ull);
+    }
     const double p = rho * (g - 1.0) * T / g;
     const RT mu = sutherland<RT>(RT(T * d.T_ref)) / RT(d.mu_inf);
 #pragma unroll
@@ -518,6 +526,7 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
     Wd[ND * N + idx] = T;
     Wd[d.w_p * N + idx] = p;
     Wp[d.w_mu * N + idx] = mu;
+    if (GAS == TPG) Wp[d.w_kap * N + idx] = RT(keyes(T * d.T_ref) * d.ikappa_inf);
     if (d.ad_on) {
       Wp[d.w_c * N + idx] = RT(sqrt(g * p / rho));
       static_cast<RT*>(d.ad)[2 * N + idx] = RT(e);
@@ -862,7 +871,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
                                           const double* __restrict__ Wd,
                                           const RT* __restrict__ Wp,
                                           const RT* __restrict__ Gad, double* __restrict__ F) {
-  constexpr int ns = (GAS == CPG) ? 1 : NS;
+  constexpr int ns = (GAS == AIR5) ? NS : 1;
   constexpr int nvar = ns + ND + 1;
   constexpr bool XQ = GAS == AIR5 && ND == 2;   // X_s and p formed here from Q
   constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);   // u, v, (w), T, (X_s)
@@ -959,7 +968,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
   const RT mu = Wp[d.w_mu * N + idx];
   double rho, rs[NS], pr;
   RT Y[NS];
-  if (GAS == CPG) {
+  if (GAS != AIR5) {
     rho = Q[idx];
     pr = Wd[d.w_p * N + idx];
   } else {
@@ -1097,9 +1106,10 @@ __device__ __forceinline__ void wall_point(const Dev& d, double* __restrict__ Q,
   if (d.hold && d.hold[((long)k * 3 + 0) * d.nx + i]) return;
   const long N = d.N;
   const long idx0 = (long)k * d.ny * d.nx + i;
-  constexpr int ns = (GAS == CPG) ? 1 : NS;
-  if (GAS == CPG) {
+  constexpr int ns = (GAS == AIR5) ? NS : 1;
+  if (GAS != AIR5) {
     const double rho_w = Q[idx0];
+    const double ag = (d.gamma - 1.0) / d.gamma;
     double Tw;
     if (d.wall == HRX_WALL_ISOTHERMAL) {
       Tw = d.T_wall / d.T_ref;
@@ -1115,12 +1125,19 @@ __device__ __forceinline__ void wall_point(const Dev& d, double* __restrict__ Q,
           ke += ua * ua;
         }
         const double e = get(1 + ND, m) / rho - 0.5 * ke;
-        Tw += c_wall[m - 1] * (d.gamma * e);
+        double Tm = d.gamma * e;
+        if (GAS == TPG) {
+          int status;
+          Tm = tpg_temperature(e, d.tpg_k0, d.tpg_th, ag, d.newton_rtol, d.newton_max,
+                               &status);
+        }
+        Tw += c_wall[m - 1] * Tm;
       }
     }
 #pragma unroll
     for (int a = 0; a < ND; ++a) Q[(1 + a) * N + idx0] = 0.0;
-    Q[(1 + ND) * N + idx0] = rho_w * Tw / d.gamma;
+    Q[(1 + ND) * N + idx0] =
+        GAS == TPG ? rho_w * tpg_energy(Tw, d.tpg_k0, d.tpg_th, ag) : rho_w * Tw / d.gamma;
     return;
   }
   double rho_w = 0.0;
@@ -1194,7 +1211,7 @@ __global__ __launch_bounds__(256 * NH) void k_div(Dev d, const double* __restric
                                              const double* __restrict__ Qref, double* Rout,
                                              double* Qio, double* dQio, double A, double B,
                                              double dt) {
-  constexpr int ns = (GAS == CPG) ? 1 : NS;
+  constexpr int ns = (GAS == AIR5) ? NS : 1;
   constexpr int nvar = ns + ND + 1;
   constexpr int KC = div_chunk(ND);
   // 2-D RK stage: the wall condition runs here (see above), unless the tile's chunks run
@@ -2016,7 +2033,8 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   if (!cfg || !out) return HRX_EINVAL;
   *out = nullptr;
   const hrx_config& c = *cfg;
-  if (c.gas != HRX_GAS_CPG && c.gas != HRX_GAS_AIR5) return HRX_EINVAL;
+  if (c.gas != HRX_GAS_CPG && c.gas != HRX_GAS_AIR5 && c.gas != HRX_GAS_TPG) return HRX_EINVAL;
+  if (c.gas == HRX_GAS_TPG && c.ad_on) return HRX_EUNSUP;
   if (c.nx < 8 || c.ny < 8 || c.nz < 1 || (c.nz > 1 && c.nz < 8)) return HRX_EINVAL;
   if (c.fd_order != 4 && c.fd_order != 6) return HRX_EINVAL;
   if (c.rk_scheme != HRX_RK3_2N && c.rk_scheme != HRX_RK45_2N) return HRX_EINVAL;
@@ -2061,6 +2079,18 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     ref.gamma = c.gamma; ref.Re = c.Re; ref.Pr = c.Pr; ref.Ec = 1.0;
     ref.T_ref = (c.gamma - 1.0) * c.T_inf;
     ref.mu_inf = sutherland<double>(c.T_inf);
+  } else if (c.gas == HRX_GAS_TPG) {
+    // Sec. 2.2.2: c_p0 from c_p(T_inf) = c_p,inf; Pr from Sutherland's and Keyes' laws
+    if (!(c.gamma > 1.0) || !(c.Re > 0.0)) { delete ctx; return HRX_EINVAL; }
+    const double a = (c.gamma - 1.0) / c.gamma, cp = TPG_R / a;
+    ref.gamma = c.gamma; ref.Re = c.Re; ref.Ec = 1.0;
+    ref.T_ref = (c.gamma - 1.0) * c.T_inf;
+    ref.mu_inf = sutherland<double>(c.T_inf);
+    ref.kappa_inf = keyes(c.T_inf);
+    ref.Pr = ref.mu_inf * cp / ref.kappa_inf;
+    ref.R_inf = TPG_R;
+    d.tpg_k0 = 1.0 / (1.0 + a * tpg_vib(TPG_THETA / c.T_inf));
+    d.tpg_th = TPG_THETA / ref.T_ref;
   } else {
     double Y[NS], ysum = 0.0;
     for (int s = 0; s < NS; ++s) { Y[s] = c.Y_inf[s]; ysum += Y[s]; }
@@ -2194,6 +2224,8 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     d.w_D = w; w += NS;
     d.w_wdot = w; w += NS;
     d.w_h = w; w += NS;
+  } else if (c.gas == HRX_GAS_TPG) {
+    d.w_kap = w++;
   }
   if (d.ad_on) d.w_c = w++;
   ctx->nWp = w;
@@ -2261,7 +2293,7 @@ void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, con
                 const double* Qref, double* R, double* Qio, double* dQ, double A, double B,
                 double dt) {
   const Dev& d = ctx->dev;
-  constexpr int nvar = (GAS == CPG ? 1 : NS) + ND + 1;
+  constexpr int nvar = (GAS == AIR5 ? NS : 1) + ND + 1;
   unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
   constexpr int KC = div_chunk(ND);
   constexpr int nch = (nvar + KC - 1) / KC;
@@ -2353,7 +2385,7 @@ int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, 
   } else {
     launch_div<GAS, ND, ORDER, MODE_RK, RT>(ctx, st, F, Wp, nullptr, Qref, nullptr, Qio, dQ, A,
                                             B, dt);
-    constexpr int nvar = (GAS == CPG ? 1 : NS) + ND + 1;
+    constexpr int nvar = (GAS == AIR5 ? NS : 1) + ND + 1;
     constexpr int nch = (nvar + div_chunk(ND) - 1) / div_chunk(ND);
     // chunks of one tile in separate blocks (two chunks share a block in 2-D)
     const bool split = d.N <= DIV_SPLIT_MAX_POINTS && nch > 2;
@@ -2368,7 +2400,7 @@ int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, 
 int dispatch(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, double* Qio,
              double* dQ, double A, double B, double dt, hipStream_t st) {
   const Dev& d = ctx->dev;
-  const bool air = ctx->cfg.gas == HRX_GAS_AIR5;
+  const bool air = ctx->cfg.gas == HRX_GAS_AIR5, tpg = ctx->cfg.gas == HRX_GAS_TPG;
   const bool o6 = d.fd_order == 6;
   const bool mixed = ctx->cfg.precision == HRX_PREC_MIXED;
 #define HRX_RUN(G, NDV, O)                                                         \
@@ -2376,9 +2408,11 @@ int dispatch(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double
                : run<G, NDV, O, double>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, st)
   if (d.ndim == 2) {
     if (air) { if (o6) HRX_RUN(AIR5, 2, 6); else HRX_RUN(AIR5, 2, 4); }
+    else if (tpg) { if (o6) HRX_RUN(TPG, 2, 6); else HRX_RUN(TPG, 2, 4); }
     else { if (o6) HRX_RUN(CPG, 2, 6); else HRX_RUN(CPG, 2, 4); }
   } else {
     if (air) { if (o6) HRX_RUN(AIR5, 3, 6); else HRX_RUN(AIR5, 3, 4); }
+    else if (tpg) { if (o6) HRX_RUN(TPG, 3, 6); else HRX_RUN(TPG, 3, 4); }
     else { if (o6) HRX_RUN(CPG, 3, 6); else HRX_RUN(CPG, 3, 4); }
   }
 #undef HRX_RUN

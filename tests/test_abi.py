@@ -55,3 +55,15 @@ def test_binding_refuses_non_contiguous_arrays():
     with pytest.raises(hrx.HrxError):
         hrx._ptr(t)
     assert hrx._ptr(None) is None
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhrx.so not built")
+def test_thermally_perfect_gas_with_artificial_diffusivity_refused():
+    """The thermally perfect gas runs without artificial diffusivity; the request is
+    refused before anything touches the device."""
+    import dataclasses
+    from paper_2210_05547_amd import fields, hrx
+    cfg = dataclasses.replace(fields.get_config("c1t"), ad=True)
+    x, y, z = fields.grid(cfg)
+    with pytest.raises(hrx.HrxError):
+        hrx.Context(cfg, x, y, z)

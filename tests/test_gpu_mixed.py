@@ -78,6 +78,10 @@ def test_mixed_c1_cpg():
     _mixed_case(fields.get_config("c1"), 10, "c1")
 
 
+def test_mixed_c1t_tpg():
+    _mixed_case(fields.get_config("c1t"), 10, "c1t")
+
+
 def test_mixed_c2_full():
     _mixed_case(fields.get_config("c2"), 3, "c2")
 

@@ -146,6 +146,18 @@ def test_c1_cpg_fourth_order_rk4():
     _run_case(cfg, 10)
 
 
+def test_c1t_tpg_rhs_and_stages():
+    """Thermally perfect gas (Sec. 2.2.2): Newton energy inversion in the pointwise pass
+    and at the adiabatic wall's extrapolation rows, Keyes' conductivity."""
+    _run_case(fields.get_config("c1t"), 20)
+
+
+def test_c1t_tpg_isothermal_fourth_order_rk4():
+    cfg = dataclasses.replace(fields.get_config("c1t").scaled(67, 41), fd_order=4, rk=1,
+                              wall=1, T_wall=900.0)
+    _run_case(cfg, 10)
+
+
 @pytest.mark.parametrize("shape", [(40, 24), (67, 41)])
 def test_c2_air5_reduced(shape):
     _run_case(fields.get_config("c2").scaled(*shape), 6)
