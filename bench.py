@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="c2")
+    ap.add_argument("--grid", type=int, nargs="+", default=None, metavar="N",
+                    help="run the configuration's workload on another grid (nx ny [nz])")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
@@ -143,6 +145,8 @@ def main():
     from paper_2210_05547_amd import fields, hrx
 
     cfg = fields.get_config(args.config)
+    if args.grid:
+        cfg = cfg.scaled(*args.grid)
     Q, Qr, info = fields.initial_field(cfg)
     dev = torch.device("cuda:0")
     ctx = hrx.Context(cfg, info["x"], info["y"], info["z"], info["hold"])
@@ -215,7 +219,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded flat-plate boundary-layer field)",
         "config": {"workload": cfg.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "points": cfg.npts,
-                   "gas": "air5" if cfg.gas == 1 else "cpg", "rk": "2N-RK3",
+                   "gas": {0: "cpg", 1: "air5", 2: "tpg"}[cfg.gas], "rk": "2N-RK3",
                    "fd_order": cfg.fd_order, "artificial_diffusivity": bool(cfg.ad)},
         "roofline": roof,
         "kernels": kernels,

@@ -1100,7 +1100,9 @@ __constant__ double c_wall[4] = {48.0 / 25.0, -36.0 / 25.0, 16.0 / 25.0, -3.0 / 
 // gradient); species mass fractions extrapolated likewise; the density already
 // advanced by the stage is kept.  Held inflow points are left alone.
 // get(v, m): component v of Q at row m = 1 .. 4 of the column (after the stage's update).
-template <int GAS, int ND, class Get>
+// TGET: get(nvar, m) returns the temperature of row m (thermally perfect gas: the rows'
+// own threads inverted their energies side by side)
+template <int GAS, int ND, class Get, bool TGET = false>
 __device__ __forceinline__ void wall_point(const Dev& d, double* __restrict__ Q, int i, int k,
                                            Get get) {
   if (d.hold && d.hold[((long)k * 3 + 0) * d.nx + i]) return;
@@ -1128,8 +1130,9 @@ __device__ __forceinline__ void wall_point(const Dev& d, double* __restrict__ Q,
         double Tm = d.gamma * e;
         if (GAS == TPG) {
           int status;
-          Tm = tpg_temperature(e, d.tpg_k0, d.tpg_th, ag, d.newton_rtol, d.newton_max,
-                               &status);
+          Tm = TGET ? get(2 + ND, m)
+                    : tpg_temperature(e, d.tpg_k0, d.tpg_th, ag, d.newton_rtol, d.newton_max,
+                                      &status);
         }
         Tw += c_wall[m - 1] * Tm;
       }
@@ -1360,12 +1363,28 @@ __global__ __launch_bounds__(256 * NH) void k_div(Dev d, const double* __restric
     // rows 1 .. 4 of the updated state (each thread re-reads its own stores, each half
     // its own chunk) through LDS to the wall row's threads
     __syncthreads();   // the flux tiles in LDS are consumed
-    if (active && ty >= 1 && ty <= 4)
+    if (active && ty >= 1 && ty <= 4) {
       for (int k = kbeg; k < kend; ++k) smem_all[(k * 4 + ty - 1) * TTX + tx] = Qio[k * N + idx];
+      if (GAS == TPG && d.wall != HRX_WALL_ISOTHERMAL) {
+        // the adiabatic wall extrapolates T: each row inverts its own energy
+        const double rho = Qio[idx];
+        double ke = 0.0;
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+          const double ua = Qio[(1 + a) * N + idx] / rho;
+          ke += ua * ua;
+        }
+        const double e = Qio[(1 + ND) * N + idx] / rho - 0.5 * ke;
+        int status;
+        smem_all[(nvar * 4 + ty - 1) * TTX + tx] =
+            tpg_temperature(e, d.tpg_k0, d.tpg_th, (d.gamma - 1.0) / d.gamma, d.newton_rtol,
+                            d.newton_max, &status);
+      }
+    }
     __syncthreads();
+    auto get = [&](int v, int m) { return smem_all[(v * 4 + m - 1) * TTX + tx]; };
     if (half == 0 && ty == 0 && p.i >= 1 && p.i < d.nx)
-      wall_point<GAS, ND>(d, Qio, p.i, 0,
-                          [&](int v, int m) { return smem_all[(v * 4 + m - 1) * TTX + tx]; });
+      wall_point<GAS, ND, decltype(get), GAS == TPG>(d, Qio, p.i, 0, get);
   }
 }
 
