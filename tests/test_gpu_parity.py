@@ -152,6 +152,14 @@ def test_c1t_tpg_rhs_and_stages():
     _run_case(fields.get_config("c1t"), 20)
 
 
+def test_tpg_3d_reduced():
+    """The 3-D box as thermally perfect air (no jet, no artificial diffusivity), adiabatic
+    wall: the separate 3-D wall pass inverts the energies of the extrapolation rows."""
+    cfg = dataclasses.replace(fields.get_config("c4").scaled(40, 32, 16), gas=2, ad=False,
+                              jet=False, species_noise=0.0, wall=0, T_wall=0.0)
+    _run_case(cfg, 2)
+
+
 def test_c1t_tpg_isothermal_fourth_order_rk4():
     cfg = dataclasses.replace(fields.get_config("c1t").scaled(67, 41), fd_order=4, rk=1,
                               wall=1, T_wall=900.0)
