@@ -516,7 +516,7 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
     if (GAS == TPG) {
       int status;
       T = tpg_temperature(e, d.tpg_k0, d.tpg_th, (g - 1.0) / g, d.newton_rtol, d.newton_max,
-                          &status);
+                          &status, d.warm ? Wd[ND * N + idx] : 0.0);
       if (status) atomicAdd(&d.counters[0], 1ull);
     }
     const double p = rho * (g - 1.0) * T / g;

@@ -43,15 +43,16 @@ HRX_HD void two_sum(double a, double b, double& s, double& err) {
   err = (a - (s - bb)) + (b - bb);
 }
 
-// Newton on e(T) = e from the frozen-vibration bound e / (k0 - a), which lies above the
-// root (e(T) is increasing and convex, so the iterates fall monotonically onto it);
+// Newton on e(T) = e from T0 > 0 (the previous stage's T), else from the frozen-vibration
+// bound e / (k0 - a), which lies above the root (e(T) is increasing and convex, so the
+// iterates fall monotonically onto it; from below, the first step lands above it);
 // status 1 when |dT| <= rtol T is not reached in max_iter steps.  A last step takes the
 // residual with its products split by fma and its sums by two_sum, so that T ends within
 // about one unit in the last place of the root (only the vibrational term keeps its own
 // rounding): the right-hand side amplifies differences of a few units in T near a wall.
 HRX_HD double tpg_temperature(double e, double k0, double th, double a, double rtol,
-                              int max_iter, int* status) {
-  double T = e / (k0 - a);
+                              int max_iter, int* status, double T0 = 0.0) {
+  double T = T0 > 0.0 ? T0 : e / (k0 - a);
   *status = 1;
   for (int it = 0; it < max_iter; ++it) {
     const double x = th / T;
