@@ -1044,7 +1044,9 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         J[s] = -a_s[s] * dX[s][j] + Y[s] * corr;
-        Fj[s * N + idx] = rs[s] * u[j] + double(J[s]);
+        // FP64: rho Y_s stands in for rho_s (equal to rounding; fewer live registers)
+        const double rsj = sizeof(RT) == sizeof(double) ? rho * double(Y[s]) : rs[s];
+        Fj[s * N + idx] = rsj * u[j] + double(J[s]);
       }
     } else {
       Fj[idx] = rho * u[j];
