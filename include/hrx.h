@@ -16,7 +16,8 @@
  *  - Fields are structure-of-arrays planes of doubles, x fastest:
  *    f[v][k][j][i] at offset ((v*nz + k)*ny + j)*nx + i, N = nx*ny*nz points.
  *  - Conserved state Q (nondimensional, Eq. 7):
- *      calorically perfect gas:  [rho, rho u, rho v, (rho w), rho E]
+ *      perfect gases (calorically or thermally perfect, Sec. 2.2.2):
+ *                                [rho, rho u, rho v, (rho w), rho E]
  *      5-species air:            [rho_N2, rho_O2, rho_NO, rho_N, rho_O, rho u, rho v,
  *                                 (rho w), rho E]  (all species equations, no global
  *                                 continuity: the alternative named in Sec. 2.1)
