@@ -135,3 +135,44 @@ def air5_properties(rho, T, Y):
     mu, kap = mixture_viscosity_conductivity(T, Y)
     D = averaged_diffusion(T, p, Y)
     return p, mu, kap, D
+
+
+def stefan_maxwell_fluxes(rho, Y, gradX, Dsr):
+    """Stefan-Maxwell diffusion mass fluxes J_s (Eq. 17 with the driving forces of Eq. 16),
+    SI: rho [kg/m^3], Y [5][...], gradX [5][nd][...] (1/m), Dsr [5][5][...] (m^2/s, e.g.
+    binary_diffusion(T, p)) -> J [5][nd][...] (kg/(m^2 s)).  No GPU counterpart yet
+    (the Stefan-Maxwell form is a later step); pinned against its limits.
+
+    The relations grad X_s = sum_{i != s} (X_s X_i / D_si) (V_i - V_s), written for the
+    molar fluxes j_s = J_s / M_s (V_i = J_i/(rho Y_i), X_i/Y_i = Mbar/M_i):
+        sum_{i != s} (X_s j_i - X_i j_s) / D_si = (rho / Mbar) grad X_s,
+    a system whose columns sum to zero, closed by the mass constraint sum_s M_s j_s = 0
+    (Eq. 20): (C + alpha 1 m^T) j = (rho/Mbar) grad X with m_s = M_s / Mbar; the added
+    term vanishes on the solution and 1 is outside C's range, so the matrix is regular for
+    any alpha != 0 (here the mean |C_ss|).  No entry carries 1/X_s, so vanishing species
+    keep the system well conditioned.
+    """
+    Y = np.asarray(Y, dtype=np.float64)
+    X = mole_fractions(Y)
+    sh = (5,) + (1,) * (Y.ndim - 1)
+    Mbar = 1.0 / np.sum(Y / sp.M.reshape(sh), axis=0)
+    rest = Y.shape[1:]
+    n = int(np.prod(rest)) if rest else 1
+    Xf = X.reshape(5, n)
+    Df = np.asarray(Dsr, dtype=np.float64).reshape(5, 5, n)
+    nd = gradX.shape[1]
+    C = np.zeros((n, 5, 5))
+    for s in range(5):
+        for i in range(5):
+            if i == s:
+                continue
+            C[:, s, i] = Xf[s] / Df[s, i]
+            C[:, s, s] -= Xf[i] / Df[s, i]
+    m = (sp.M.reshape(5, 1) / Mbar.reshape(1, n)).T          # [n][5]
+    alpha = np.mean(np.abs(np.diagonal(C, axis1=1, axis2=2)), axis=1)
+    A = C + alpha[:, None, None] * m[:, None, :]              # + alpha 1 m^T
+    b = (np.asarray(rho, dtype=np.float64).reshape(n) / Mbar.reshape(n))[:, None, None] * \
+        np.moveaxis(np.asarray(gradX, dtype=np.float64).reshape(5, nd, n), 2, 0)
+    j = np.linalg.solve(A, b)                                 # [n][5][nd]
+    J = sp.M.reshape(1, 5, 1) * j
+    return np.moveaxis(J, 0, 2).reshape((5, nd) + rest)
