@@ -12,6 +12,7 @@ Prints one JSON line with the metric, the dominant kernel's roofline position
 on a bounded sample of the same workload.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -115,6 +116,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--grid", type=int, nargs="+", default=None, metavar="N",
                     help="run the configuration's workload on another grid (nx ny [nz])")
+    ap.add_argument("--stefan-maxwell", action="store_true",
+                    help="Stefan-Maxwell diffusion (Eq. 17) instead of Eq. (18)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
@@ -147,6 +150,8 @@ def main():
     cfg = fields.get_config(args.config)
     if args.grid:
         cfg = cfg.scaled(*args.grid)
+    if args.stefan_maxwell:
+        cfg = dataclasses.replace(cfg, diffusion=1)
     Q, Qr, info = fields.initial_field(cfg)
     dev = torch.device("cuda:0")
     ctx = hrx.Context(cfg, info["x"], info["y"], info["z"], info["hold"])
@@ -222,7 +227,8 @@ def main():
         "data": "synthetic (seeded flat-plate boundary-layer field)",
         "config": {"workload": cfg.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "points": cfg.npts,
                    "gas": {0: "cpg", 1: "air5", 2: "tpg"}[cfg.gas], "rk": "2N-RK3",
-                   "fd_order": cfg.fd_order, "artificial_diffusivity": bool(cfg.ad)},
+                   "fd_order": cfg.fd_order, "artificial_diffusivity": bool(cfg.ad),
+                   "diffusion": "stefan-maxwell" if cfg.diffusion else "ramshaw"},
         "roofline": roof,
         "kernels": kernels,
         "kernel_rooflines": roofs,
@@ -233,7 +239,7 @@ def main():
         out["forms"] = {"fp64": out["value"],
                         "mixed": round(time_form(cfg, Q, Qr, info, args.steps, args.warmup,
                                                  hrx.PREC_MIXED), 2)}
-    if not args.no_surrogate and cfg.gas == 1:
+    if not args.no_surrogate and cfg.gas == 1 and not cfg.diffusion:
         from paper_2210_05547_amd import surrogate
         summary = {}
 

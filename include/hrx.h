@@ -50,6 +50,7 @@ enum { HRX_WALL_ADIABATIC = 0, HRX_WALL_ISOTHERMAL = 1 };
 enum { HRX_RK3_2N = 0, HRX_RK45_2N = 1 };
 enum { HRX_PREC_FP64 = 0, HRX_PREC_MIXED = 1 };
 enum { HRX_THERMO_PLAIN = 0, HRX_THERMO_SURROGATE = 1 };
+enum { HRX_DIFF_RAMSHAW = 0, HRX_DIFF_STEFAN_MAXWELL = 1 };
 
 /* Workload description (host).  Sec. 2.1 (reference scales, Eq. 7 and 11), Sec. 3.2
  * (sponges, wall), Sec. 3.3 (artificial diffusivity), Sec. 4 (case parameters). */
@@ -87,6 +88,10 @@ typedef struct hrx_config {
   int64_t n_hold;
   int newton_max_iter;      /* <= 0: 50 */
   double newton_rtol;       /* <= 0: 1e-13 */
+  int diffusion;            /* HRX_DIFF_RAMSHAW: Eq. (18) with the averaged coefficients of
+                               Eq. (19); HRX_DIFF_STEFAN_MAXWELL: the Stefan-Maxwell
+                               system of Eq. (17) solved per point (5-species air, 2-D,
+                               no artificial diffusivity; else HRX_EUNSUP) */
 } hrx_config;
 
 typedef struct hrx_ctx hrx_ctx;

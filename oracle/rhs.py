@@ -162,6 +162,8 @@ def primitives(Q, case):
     P.update(T=T, Tk=Tk, p=p, mu=mu / ref["mu_inf"], kappa=kap / ref["kappa_inf"],
              D=D / (ref["c_inf"] * ref["L_ref"]), h=h, X=X, Mbar=Mbar, wdot=wdot, c=c,
              status=status, rho_d=rho_d)
+    if getattr(case.cfg, "diffusion", 0) == 1:
+        P["Dsr"] = transport.binary_diffusion(Tk, p_d) / (ref["c_inf"] * ref["L_ref"])
     return P
 
 
@@ -197,8 +199,14 @@ def fluxes(Q, P, case, G, ad=None):
         F = [None] * case.nvar
         # species (or density) rows
         if case.air5:
-            corr = sum(a[i] * dX[i][j] for i in range(ns))
-            J = [-a[s] * dX[s][j] + P["Y"][s] * corr for s in range(ns)]
+            if "Dsr" in P:
+                # Stefan-Maxwell system, Eq. (17) (transport.stefan_maxwell_fluxes)
+                gX = np.stack([dX[s][j] for s in range(ns)])[:, None]
+                Jsm = transport.stefan_maxwell_fluxes(rho, P["Y"], gX, P["Dsr"])
+                J = [Jsm[s, 0] for s in range(ns)]
+            else:
+                corr = sum(a[i] * dX[i][j] for i in range(ns))
+                J = [-a[s] * dX[s][j] + P["Y"][s] * corr for s in range(ns)]
             for s in range(ns):
                 F[s] = Q[s] * vel[j] + J[s]
         else:

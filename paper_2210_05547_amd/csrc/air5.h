@@ -226,6 +226,8 @@ template <class R>
 struct Transport {
   R mu, kappa;     // Pa s, W/(m K)
   R D[NS];         // m^2/s, averaged coefficients of Eq. (19)
+  R iD[10];        // s/m^2, reciprocal binary coefficients 1/D_sr of the pairs s < r in
+                   // the order (0,1), (0,2), .., (3,4) (the Stefan-Maxwell system)
 };
 
 // Mixture viscosity, frozen conductivity (Wilke/Eucken) and averaged diffusion
@@ -308,10 +310,11 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
     den[s] = R(0);
   }
   const R pr_iT15 = R(p) / (Tr * sqT);
+  int q = 0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
 #pragma unroll
-    for (int r = s + 1; r < NS; ++r) {
+    for (int r = s + 1; r < NS; ++r, ++q) {
       const double ms = molar_mass(s) / NAV, mr = molar_mass(r) / NAV;
       const double msr = ms * mr / (ms + mr);
       const double sig = 0.5 * (lj_sigma(s) + lj_sigma(r));
@@ -322,6 +325,7 @@ HRX_HD void mixture_transport(double T, double p, const double* X, const double*
                    R(0.19300) * exp(R(-0.47635) * Ts) + R(1.03587) * exp(R(-1.52996) * Ts) +
                    R(1.76474) * exp(R(-3.89411) * Ts);
       const R v = pr_iT15 * om * iB;
+      out.iD[q] = v;
       den[s] += Xc[r] * v;
       den[r] += Xc[s] * v;
     }

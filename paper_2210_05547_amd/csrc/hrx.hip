@@ -51,6 +51,8 @@ struct Dev {
   int ad_on;
   double Cmu, Cbeta, Ckap, CD, CY;
   double tpg_k0, tpg_th;          // thermally perfect gas: c_p0 / c_p,inf, Theta / T_ref
+  int sm;                         // Stefan-Maxwell diffusion (Eq. 17) instead of Eq. (18)
+  int w_iD;                       // Stefan-Maxwell: 10 planes of nondimensional 1/D_sr
   const double *mx, *my, *mz;     // metrics d(xi)/dx
   const double *sx, *sy;          // sponge profiles
   const double *dlx, *dly, *dlz;  // local spacings dx/d(xi)
@@ -453,6 +455,12 @@ __device__ __forceinline__ void prim_air5(const Dev& d, double* __restrict__ Wd,
     const RT iDscale = RT(d.iDscale);
 #pragma unroll
     for (int s = 0; s < NS; ++s) Wp[(d.w_D + s) * N + idx] = tr.D[s] * iDscale;
+    if (d.sm) {
+      // nondimensional 1/D_sr = (1/D_sr,SI) c_inf L_ref
+      const RT Dscale = RT(d.c_inf * d.L_ref);
+#pragma unroll
+      for (int q = 0; q < 10; ++q) Wp[(d.w_iD + q) * N + idx] = tr.iD[q] * Dscale;
+    }
   }
   double rsd[NS];
   RT wd[NS];
@@ -866,7 +874,7 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
 // ------------------------------------------------------------------ k_flux
 // F planes (double): F[j][k] for direction j and conserved component k.  Convective
 // fluxes are formed in FP64; stresses, heat and diffusion fluxes in RT.
-template <int GAS, int ND, int ORDER, bool AD, class RT>
+template <int GAS, int ND, int ORDER, bool AD, class RT, bool SM>
 __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict__ Q,
                                           const double* __restrict__ Wd,
                                           const RT* __restrict__ Wp,
@@ -1029,6 +1037,69 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
 #pragma unroll
     for (int s = 0; s < NS; ++s) h[s] = Wp[(d.w_h + s) * N + idx];
   }
+  // Stefan-Maxwell diffusion (Eq. 17; 2-D, no artificial diffusivity).  With sx = sqrt(X)
+  // (X clipped below at 1e-12) and V = u / sx the system Q V = -grad X becomes
+  // K u = -grad X / sx with K_ss = sum_{i != s} X_i / D_si, K_si = -sx_s sx_i / D_si:
+  // symmetric, an O(1/D) diagonal even for vanishing species, null vector sx.  The mass
+  // constraint sum_s Y_s V_s = g . u = 0, g_s = (M_s / Mbar) sx_s, closes it:
+  // A = K + alpha g g^T (the added term vanishes on the solution; A is positive definite)
+  // is factored once per point as L D L^T and solved for each direction; then
+  // J_s = rho Y_s V_s = rho (M_s / Mbar) sx_s u_s.
+  constexpr bool sm = SM && GAS == AIR5 && ND == 2 && !AD;
+  RT Lm[NS][NS], Dd[NS], Dinv[NS], sxv[NS], isx[NS], gv[NS];
+  if constexpr (sm) {
+    RT iDm[NS][NS], Xc[NS], nsum = RT(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) nsum += Y[s] / RT(molar_mass(s));
+#pragma unroll
+    for (int s = 0, q = 0; s < NS; ++s)
+#pragma unroll
+      for (int r = s + 1; r < NS; ++r, ++q) {
+        const RT v = Wp[(d.w_iD + q) * N + idx];
+        iDm[s][r] = v;
+        iDm[r][s] = v;
+      }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const RT x = RT(smem[(ND + 1 + s) * TILE_E + sidx]);
+      Xc[s] = x > RT(1e-12) ? x : RT(1e-12);
+      sxv[s] = sqrt(Xc[s]);
+      isx[s] = RT(1) / sxv[s];
+      gv[s] = RT(molar_mass(s)) * nsum * sxv[s];
+    }
+    RT A[NS][NS], tr = RT(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      RT k = RT(0);
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+        if (i != s) k += Xc[i] * iDm[s][i];
+      A[s][s] = k;
+      tr += k;
+#pragma unroll
+      for (int i = 0; i < s; ++i) A[s][i] = -sxv[s] * sxv[i] * iDm[s][i];
+    }
+    const RT alpha = tr * RT(0.2);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int i = 0; i <= s; ++i) A[s][i] += alpha * gv[s] * gv[i];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      RT dk = A[k][k];
+#pragma unroll
+      for (int m = 0; m < k; ++m) dk -= Lm[k][m] * Lm[k][m] * Dd[m];
+      Dd[k] = dk;
+      Dinv[k] = RT(1) / dk;
+#pragma unroll
+      for (int i = k + 1; i < NS; ++i) {
+        RT v = A[i][k];
+#pragma unroll
+        for (int m = 0; m < k; ++m) v -= Lm[i][m] * Lm[k][m] * Dd[m];
+        Lm[i][k] = v * Dinv[k];
+      }
+    }
+  }
 #pragma unroll
   for (int j = 0; j < ND; ++j) {
     double* Fj = F + (long)j * nvar * N;
@@ -1039,11 +1110,32 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
         for (int s = 0; s < NS; ++s) dX[s][j] = deriv(ND + 1 + s, j);
       }
       RT corr = RT(0);
+      if constexpr (sm) {
+        RT z[NS];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) corr += a_s[s] * dX[s][j];
+        for (int i = 0; i < NS; ++i) {   // forward: L y = -grad X / sx
+          RT v = -dX[i][j] * isx[i];
+#pragma unroll
+          for (int m = 0; m < i; ++m) v -= Lm[i][m] * z[m];
+          z[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) z[i] *= Dinv[i];
+#pragma unroll
+        for (int i = NS - 1; i >= 0; --i) {   // backward: L^T u = D^-1 y
+#pragma unroll
+          for (int m = i + 1; m < NS; ++m) z[i] -= Lm[m][i] * z[m];
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) J[s] = rho_r * gv[s] * z[s];
+      } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) corr += a_s[s] * dX[s][j];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) J[s] = -a_s[s] * dX[s][j] + Y[s] * corr;
+      }
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        J[s] = -a_s[s] * dX[s][j] + Y[s] * corr;
         // FP64: rho Y_s stands in for rho_s (equal to rounding; fewer live registers)
         const double rsj = sizeof(RT) == sizeof(double) ? rho * double(Y[s]) : rs[s];
         Fj[s * N + idx] = rsj * u[j] + double(J[s]);
@@ -1077,21 +1169,21 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
     Fj[(ns + ND) * N + idx] = (rhoE + pr) * u[j] - double(work - q);
   }
 }
-template <int GAS, int ND, int ORDER, bool AD, class RT>
+template <int GAS, int ND, int ORDER, bool AD, class RT, bool SM = false>
 __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ Q,
                                               const double* __restrict__ Wd,
                                               const RT* __restrict__ Wp,
                                               const RT* __restrict__ Gad, double* __restrict__ F) {
-  flux_tile<GAS, ND, ORDER, AD, RT>(d, Q, Wd, Wp, Gad, F);
+  flux_tile<GAS, ND, ORDER, AD, RT, SM>(d, Q, Wd, Wp, Gad, F);
 }
 // The same for FP64 on 2-D grids of at most two wavefronts per SIMD: occupancy is then
 // bounded by the grid, not by registers, so the compiler may spend up to 256 VGPRs on
 // instruction-level parallelism (measured: flat-plate flux -3 %; no gain in the mixed form).
-template <int GAS, int ND, int ORDER, bool AD, class RT>
+template <int GAS, int ND, int ORDER, bool AD, class RT, bool SM = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_flux_small(
     Dev d, const double* __restrict__ Q, const double* __restrict__ Wd,
     const RT* __restrict__ Wp, const RT* __restrict__ Gad, double* __restrict__ F) {
-  flux_tile<GAS, ND, ORDER, AD, RT>(d, Q, Wd, Wp, Gad, F);
+  flux_tile<GAS, ND, ORDER, AD, RT, SM>(d, Q, Wd, Wp, Gad, F);
 }
 
 // ------------------------------------------------------------------ k_bc (wall row)
@@ -2056,6 +2148,9 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   const hrx_config& c = *cfg;
   if (c.gas != HRX_GAS_CPG && c.gas != HRX_GAS_AIR5 && c.gas != HRX_GAS_TPG) return HRX_EINVAL;
   if (c.gas == HRX_GAS_TPG && c.ad_on) return HRX_EUNSUP;
+  if (c.diffusion != HRX_DIFF_RAMSHAW && c.diffusion != HRX_DIFF_STEFAN_MAXWELL) return HRX_EINVAL;
+  if (c.diffusion == HRX_DIFF_STEFAN_MAXWELL && (c.gas != HRX_GAS_AIR5 || c.nz > 1 || c.ad_on))
+    return HRX_EUNSUP;
   if (c.nx < 8 || c.ny < 8 || c.nz < 1 || (c.nz > 1 && c.nz < 8)) return HRX_EINVAL;
   if (c.fd_order != 4 && c.fd_order != 6) return HRX_EINVAL;
   if (c.rk_scheme != HRX_RK3_2N && c.rk_scheme != HRX_RK45_2N) return HRX_EINVAL;
@@ -2245,6 +2340,10 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     d.w_D = w; w += NS;
     d.w_wdot = w; w += NS;
     d.w_h = w; w += NS;
+    if (c.diffusion == HRX_DIFF_STEFAN_MAXWELL) {
+      d.sm = 1;
+      d.w_iD = w; w += 10;
+    }
   } else if (c.gas == HRX_GAS_TPG) {
     d.w_kap = w++;
   }
@@ -2295,6 +2394,16 @@ void launch_flux(hrx_ctx* ctx, hipStream_t st, const double* Q, const double* Wd
   const unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
   const size_t sh = NSRC * TILE_E * sizeof(double);
   timed(ctx, K_FLUX, st, [&] {
+    if constexpr (GAS == AIR5 && ND == 2 && !AD) {
+      if (d.sm) {   // Stefan-Maxwell diffusion
+        if (ctx->small_grid && sizeof(RT) == sizeof(double))
+          k_flux_small<GAS, ND, ORDER, AD, RT, true><<<nt, TTX * TTY, sh, st>>>(d, Q, Wd, Wp,
+                                                                                Gad, F);
+        else
+          k_flux<GAS, ND, ORDER, AD, RT, true><<<nt, TTX * TTY, sh, st>>>(d, Q, Wd, Wp, Gad, F);
+        return;
+      }
+    }
     if constexpr (ND == 2 && sizeof(RT) == sizeof(double)) {
       if (ctx->small_grid) {
         k_flux_small<GAS, ND, ORDER, AD, RT><<<nt, TTX * TTY, sh, st>>>(d, Q, Wd, Wp, Gad, F);
@@ -2695,6 +2804,8 @@ int hrx_set_thermo_mode(hrx_ctx* ctx, int mode) {
     return HRX_OK;
   }
   if (mode != HRX_THERMO_SURROGATE || ctx->cfg.gas != HRX_GAS_AIR5) return HRX_EINVAL;
+  // the network yields the averaged coefficients of Eq. (19), not the binary ones
+  if (ctx->dev.sm) return HRX_EUNSUP;
   if (!ctx->mlp_params || !ctx->mlp_norm) return HRX_EINVAL;
   const int rc = ensure_ys(ctx, ctx->dev.N);
   if (rc) return rc;

@@ -70,6 +70,7 @@ class FlowConfig:
     sponge_top: int = 0
     sigma_max: float = 2.0
     ad: bool = False
+    diffusion: int = 0            # 0: Ramshaw (Eq. 18), 1: Stefan-Maxwell (Eq. 17)
     ad_coef: tuple = (0.002, 1.75, 0.01, 0.01, 100.0)   # C_mu, C_beta, C_kappa, C_D, C_Y
     fd_order: int = 6
     rk: int = 0                   # 0: 2N-RK3, 1: 2N-RK4(3)5

@@ -43,6 +43,7 @@ class _Config(C.Structure):
         ("sigma_max", C.c_double),
         ("hold", C.POINTER(C.c_int64)), ("n_hold", C.c_int64),
         ("newton_max_iter", C.c_int), ("newton_rtol", C.c_double),
+        ("diffusion", C.c_int),
     ]
 
 
@@ -168,6 +169,7 @@ class Context:
         else:
             c.hold, c.n_hold = None, 0
         c.newton_max_iter, c.newton_rtol = 0, 0.0
+        c.diffusion = getattr(cfg, "diffusion", 0)
         h = C.c_void_p()
         _check(lib.hrx_create(C.byref(c), C.byref(h)))
         self._h = h

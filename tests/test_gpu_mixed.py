@@ -82,6 +82,11 @@ def test_mixed_c1t_tpg():
     _mixed_case(fields.get_config("c1t"), 10, "c1t")
 
 
+def test_mixed_c2_stefan_maxwell():
+    cfg = dataclasses.replace(fields.get_config("c2").scaled(67, 41), diffusion=1)
+    _mixed_case(cfg, 3, "c2_sm_67x41")
+
+
 def test_mixed_c2_full():
     _mixed_case(fields.get_config("c2"), 3, "c2")
 

@@ -146,6 +146,14 @@ def test_c1_cpg_fourth_order_rk4():
     _run_case(cfg, 10)
 
 
+@pytest.mark.parametrize("shape", [(40, 24), (1030, 270)])
+def test_c2_stefan_maxwell(shape):
+    """Stefan-Maxwell diffusion (Eq. 17) instead of Eq. (18): the per-point system solved
+    in the flux, on a small grid and on a ragged one above the small-grid split."""
+    cfg = dataclasses.replace(fields.get_config("c2").scaled(*shape), diffusion=1)
+    _run_case(cfg, 3 if shape[0] < 100 else 1)
+
+
 def test_c1t_tpg_rhs_and_stages():
     """Thermally perfect gas (Sec. 2.2.2): Newton energy inversion in the pointwise pass
     and at the adiabatic wall's extrapolation rows, Keyes' conductivity."""

@@ -47,8 +47,10 @@ def test_binary_mixture_is_fick():
     Mbar = X[0] * sp.M[0] + X[1] * sp.M[1]
     gY0 = (sp.M[0] * sp.M[1] / Mbar ** 2) * gX[0]           # Y_0 = X_0 M_0 / Mbar
     fick = -rho * D[0, 1] * gY0
-    assert np.max(np.abs(J[0] - fick)) <= 1e-12 * np.max(np.abs(fick))
-    assert np.max(np.abs(J[2:])) <= 1e-14 * np.max(np.abs(fick))   # absent species: rounding only
+    # the three absent species enter at the clipped mole fraction 1e-12: a perturbation of
+    # that order, not an error of the formula
+    assert np.max(np.abs(J[0] - fick)) <= 1e-10 * np.max(np.abs(fick))
+    assert np.max(np.abs(J[2:])) <= 1e-11 * np.max(np.abs(fick))   # absent species: the clip only
 
 
 def test_mass_constraint_and_stefan_maxwell_relations():
