@@ -56,8 +56,7 @@ enum { HRX_DIFF_RAMSHAW = 0, HRX_DIFF_STEFAN_MAXWELL = 1 };
  * (sponges, wall), Sec. 3.3 (artificial diffusivity), Sec. 4 (case parameters). */
 typedef struct hrx_config {
   int gas;                  /* HRX_GAS_*: calorically perfect, 5-species air, or thermally
-                               perfect air (Sec. 2.2.2; no artificial diffusivity:
-                               HRX_EUNSUP) */
+                               perfect air (Sec. 2.2.2) */
   int nx, ny, nz;           /* grid points; nz = 1 for a 2-D problem; nx, ny >= 8 */
   const double *x, *y, *z;  /* (host) separable coordinates, nondimensional; x, y
                                non-periodic, z uniform and periodic (may be NULL if nz = 1) */

@@ -536,7 +536,13 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
     Wp[d.w_mu * N + idx] = mu;
     if (GAS == TPG) Wp[d.w_kap * N + idx] = RT(keyes(T * d.T_ref) * d.ikappa_inf);
     if (d.ad_on) {
-      Wp[d.w_c * N + idx] = RT(sqrt(g * p / rho));
+      // sound speed with gamma(T) = c_p / c_v = 1 + R / c_v(T) for the thermally perfect gas
+      double gT = g;
+      if (GAS == TPG) {
+        const double a = (g - 1.0) / g;
+        gT = 1.0 + a / (d.tpg_k0 * (1.0 + a * tpg_vib(d.tpg_th / T)) - a);
+      }
+      Wp[d.w_c * N + idx] = RT(sqrt(gT * p / rho));
       static_cast<RT*>(d.ad)[2 * N + idx] = RT(e);
     }
     return;
@@ -2147,7 +2153,6 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   *out = nullptr;
   const hrx_config& c = *cfg;
   if (c.gas != HRX_GAS_CPG && c.gas != HRX_GAS_AIR5 && c.gas != HRX_GAS_TPG) return HRX_EINVAL;
-  if (c.gas == HRX_GAS_TPG && c.ad_on) return HRX_EUNSUP;
   if (c.diffusion != HRX_DIFF_RAMSHAW && c.diffusion != HRX_DIFF_STEFAN_MAXWELL) return HRX_EINVAL;
   if (c.diffusion == HRX_DIFF_STEFAN_MAXWELL && (c.gas != HRX_GAS_AIR5 || c.nz > 1 || c.ad_on))
     return HRX_EUNSUP;

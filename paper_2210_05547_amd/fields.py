@@ -140,7 +140,7 @@ def _cfg_c3():
                       mach=5.92, T_inf=1110.5, p_inf=60967.0, Re=1631.8,
                       wall=WALL_ADIABATIC, sponge_in=40, sponge_out=80, sponge_top=48,
                       ad=True, delta0=1.0, shock_deflection_deg=12.0, shock_x_imp=119.05,
-                      species_noise=1e-3, seed=20221011 + 3)
+                      species_noise=1e-3, cfl=0.25, seed=20221011 + 3)
 
 
 def _cfg_c4():
@@ -160,7 +160,14 @@ def _cfg_c1t():
                                seed=20221011 + 5)
 
 
-CONFIGS = {"c1": _cfg_c1, "c2": _cfg_c2, "c3": _cfg_c3, "c4": _cfg_c4, "c1t": _cfg_c1t}
+def _cfg_c3t():
+    """The SBLI as a thermally perfect gas (Sec. 4.2 runs both gas models on it)."""
+    return dataclasses.replace(_cfg_c3(), name="sbli_tpg_m5.92_2048x512", gas=GAS_TPG,
+                               species_noise=0.0, cfl=0.1, seed=20221011 + 6)
+
+
+CONFIGS = {"c1": _cfg_c1, "c2": _cfg_c2, "c3": _cfg_c3, "c4": _cfg_c4, "c1t": _cfg_c1t,
+           "c3t": _cfg_c3t}
 
 
 def get_config(key: str) -> FlowConfig:

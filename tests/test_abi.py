@@ -58,18 +58,6 @@ def test_binding_refuses_non_contiguous_arrays():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libhrx.so not built")
-def test_thermally_perfect_gas_with_artificial_diffusivity_refused():
-    """The thermally perfect gas runs without artificial diffusivity; the request is
-    refused before anything touches the device."""
-    import dataclasses
-    from paper_2210_05547_amd import fields, hrx
-    cfg = dataclasses.replace(fields.get_config("c1t"), ad=True)
-    x, y, z = fields.grid(cfg)
-    with pytest.raises(hrx.HrxError):
-        hrx.Context(cfg, x, y, z)
-
-
-@pytest.mark.skipif(not os.path.exists(LIB), reason="libhrx.so not built")
 def test_stefan_maxwell_outside_its_scope_refused():
     """Stefan-Maxwell diffusion runs for 5-species air in 2-D without artificial
     diffusivity; other requests are refused before anything touches the device."""

@@ -168,6 +168,12 @@ def test_tpg_3d_reduced():
     _run_case(cfg, 2)
 
 
+def test_tpg_sbli_ad_reduced():
+    """The SBLI with the thermally perfect gas (the paper's Sec. 4.2 compares it with
+    5-species air): artificial diffusivity with the sound speed of gamma(T)."""
+    _run_case(fields.get_config("c3t").scaled(96, 48), 3)
+
+
 def test_c1t_tpg_isothermal_fourth_order_rk4():
     cfg = dataclasses.replace(fields.get_config("c1t").scaled(67, 41), fd_order=4, rk=1,
                               wall=1, T_wall=900.0)
