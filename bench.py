@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE scaled by a 256 MiB copy kernel (fetch x2.0, write x1.0), for the kernels
 # as they stand (profiles/stage_air5_flatplate_512x256.md)
 PRIM_TRAFFIC_BYTES = (9460 + 20480) * 1024
-TRAFFIC_BYTES = {"flux": (25566 + 16384) * 1024, "div": (43213 + 16392) * 1024}
+TRAFFIC_BYTES = {"flux": (25566 + 16384) * 1024, "div": (43205 + 16392) * 1024}
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # Algorithmic HBM bytes per grid point of each kernel (FP64 planes read once + written
