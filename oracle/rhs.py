@@ -200,10 +200,15 @@ def fluxes(Q, P, case, G, ad=None):
         # species (or density) rows
         if case.air5:
             if "Dsr" in P:
-                # Stefan-Maxwell system, Eq. (17) (transport.stefan_maxwell_fluxes)
+                # Stefan-Maxwell system, Eq. (17) (transport.stefan_maxwell_fluxes); the
+                # artificial diffusivities, if any, add a flux of the form of Eq. (18)
                 gX = np.stack([dX[s][j] for s in range(ns)])[:, None]
                 Jsm = transport.stefan_maxwell_fluxes(rho, P["Y"], gX, P["Dsr"])
                 J = [Jsm[s, 0] for s in range(ns)]
+                if ad is not None:
+                    aa = [rho * (sp.M[s] / P["Mbar"]) * ad["D"][s] for s in range(ns)]
+                    ca = sum(aa[i] * dX[i][j] for i in range(ns))
+                    J = [J[s] - aa[s] * dX[s][j] + P["Y"][s] * ca for s in range(ns)]
             else:
                 corr = sum(a[i] * dX[i][j] for i in range(ns))
                 J = [-a[s] * dX[s][j] + P["Y"][s] * corr for s in range(ns)]

@@ -154,6 +154,13 @@ def test_c2_stefan_maxwell(shape):
     _run_case(cfg, 3 if shape[0] < 100 else 1)
 
 
+def test_c3_stefan_maxwell_with_ad():
+    """Stefan-Maxwell diffusion with artificial diffusivity on the SBLI: the artificial
+    species diffusivities add a flux of the form of Eq. (18)."""
+    cfg = dataclasses.replace(fields.get_config("c3").scaled(96, 48), diffusion=1)
+    _run_case(cfg, 3)
+
+
 def test_c1t_tpg_rhs_and_stages():
     """Thermally perfect gas (Sec. 2.2.2): Newton energy inversion in the pointwise pass
     and at the adiabatic wall's extrapolation rows, Keyes' conductivity."""
