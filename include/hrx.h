@@ -89,8 +89,8 @@ typedef struct hrx_config {
   double newton_rtol;       /* <= 0: 1e-13 */
   int diffusion;            /* HRX_DIFF_RAMSHAW: Eq. (18) with the averaged coefficients of
                                Eq. (19); HRX_DIFF_STEFAN_MAXWELL: the Stefan-Maxwell
-                               system of Eq. (17) solved per point (5-species air, 2-D;
-                               else HRX_EUNSUP; artificial diffusivities add a flux of the
+                               system of Eq. (17) solved per point (5-species air, else
+                               HRX_EUNSUP; artificial diffusivities add a flux of the
                                form of Eq. 18) */
 } hrx_config;
 

@@ -1043,7 +1043,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
 #pragma unroll
     for (int s = 0; s < NS; ++s) h[s] = Wp[(d.w_h + s) * N + idx];
   }
-  // Stefan-Maxwell diffusion (Eq. 17; 2-D).  With sx = sqrt(X)
+  // Stefan-Maxwell diffusion (Eq. 17).  With sx = sqrt(X)
   // (X clipped below at 1e-12) and V = u / sx the system Q V = -grad X becomes
   // K u = -grad X / sx with K_ss = sum_{i != s} X_i / D_si, K_si = -sx_s sx_i / D_si:
   // symmetric, an O(1/D) diagonal even for vanishing species, null vector sx.  The mass
@@ -1052,7 +1052,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
   // is factored once per point as L D L^T and solved for each direction; then
   // J_s = rho Y_s V_s = rho (M_s / Mbar) sx_s u_s.  Artificial diffusivities, if any,
   // add a flux of the form of Eq. (18) with their coefficients alone (a_s below).
-  constexpr bool sm = SM && GAS == AIR5 && ND == 2;
+  constexpr bool sm = SM && GAS == AIR5;
   RT Lm[NS][NS], Dd[NS], Dinv[NS], sxv[NS], isx[NS], gv[NS];
   if constexpr (sm) {
     RT iDm[NS][NS], Xc[NS], nsum = RT(0);
@@ -2161,8 +2161,7 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   const hrx_config& c = *cfg;
   if (c.gas != HRX_GAS_CPG && c.gas != HRX_GAS_AIR5 && c.gas != HRX_GAS_TPG) return HRX_EINVAL;
   if (c.diffusion != HRX_DIFF_RAMSHAW && c.diffusion != HRX_DIFF_STEFAN_MAXWELL) return HRX_EINVAL;
-  if (c.diffusion == HRX_DIFF_STEFAN_MAXWELL && (c.gas != HRX_GAS_AIR5 || c.nz > 1))
-    return HRX_EUNSUP;
+  if (c.diffusion == HRX_DIFF_STEFAN_MAXWELL && c.gas != HRX_GAS_AIR5) return HRX_EUNSUP;
   if (c.nx < 8 || c.ny < 8 || c.nz < 1 || (c.nz > 1 && c.nz < 8)) return HRX_EINVAL;
   if (c.fd_order != 4 && c.fd_order != 6) return HRX_EINVAL;
   if (c.rk_scheme != HRX_RK3_2N && c.rk_scheme != HRX_RK45_2N) return HRX_EINVAL;
@@ -2406,9 +2405,9 @@ void launch_flux(hrx_ctx* ctx, hipStream_t st, const double* Q, const double* Wd
   const unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
   const size_t sh = NSRC * TILE_E * sizeof(double);
   timed(ctx, K_FLUX, st, [&] {
-    if constexpr (GAS == AIR5 && ND == 2) {
+    if constexpr (GAS == AIR5) {
       if (d.sm) {   // Stefan-Maxwell diffusion
-        if (ctx->small_grid && sizeof(RT) == sizeof(double))
+        if (ND == 2 && ctx->small_grid && sizeof(RT) == sizeof(double))
           k_flux_small<GAS, ND, ORDER, AD, RT, true><<<nt, TTX * TTY, sh, st>>>(d, Q, Wd, Wp,
                                                                                 Gad, F);
         else

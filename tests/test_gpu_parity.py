@@ -161,6 +161,12 @@ def test_c3_stefan_maxwell_with_ad():
     _run_case(cfg, 3)
 
 
+def test_c4_stefan_maxwell_3d():
+    """Stefan-Maxwell diffusion on the reduced 3-D jet (artificial diffusivity on)."""
+    cfg = dataclasses.replace(fields.get_config("c4").scaled(40, 32, 16), diffusion=1)
+    _run_case(cfg, 2)
+
+
 def test_c1t_tpg_rhs_and_stages():
     """Thermally perfect gas (Sec. 2.2.2): Newton energy inversion in the pointwise pass
     and at the adiabatic wall's extrapolation rows, Keyes' conductivity."""
