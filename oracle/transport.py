@@ -138,43 +138,45 @@ def air5_properties(rho, T, Y):
 
 
 def stefan_maxwell_fluxes(rho, Y, gradX, Dsr):
-    """Stefan-Maxwell diffusion mass fluxes J_s (Eq. 17 with the driving forces of Eq. 16),
-    in any consistent units: rho, Y [5][...], gradX [5][nd][...], Dsr [5][5][...] (e.g.
-    binary_diffusion(T, p)) -> J [5][nd][...].  Pinned against its limits.
+    """Stefan-Maxwell diffusion mass fluxes J_s (Eq. 17 with the driving forces of Eq. 16,
+    closed by the mass constraint of Eq. 20), in any consistent units: rho, Y [5][...],
+    gradX [5][nd][...], Dsr [5][5][...] (e.g. binary_diffusion(T, p)) -> J [5][nd][...].
 
-    The relations grad X_s = sum_{i != s} (X_s X_i / D_si) (V_i - V_s) are Q V = -grad X
-    with Q_ss = sum_{i != s} X_s X_i / D_si, Q_si = -X_s X_i / D_si.  They are solved in the
-    symmetric scaling V = u / sqrt(X): K u = -grad X / sqrt(X) with K_ss = sum_{i != s}
-    X_i / D_si and K_si = -sqrt(X_s X_i) / D_si, whose entries stay O(1/D) for a vanishing
-    species (so each flux keeps its own relative accuracy; unscaled, the error of a trace
-    species' flux follows the largest flux instead).  K is singular (null vector sqrt(X));
-    the mass constraint sum_s Y_s V_s = g . u = 0 with g_s = (M_s / Mbar) sqrt(X_s) (Eq. 20)
-    closes it: (K + alpha g g^T) u = -grad X / sqrt(X), the added term vanishing on the
-    solution and the matrix positive definite for alpha > 0 (here the mean K_ss).  Then
-    J_s = rho Y_s V_s = rho (M_s / Mbar) sqrt(X_s) u_s.  Reading: as in Eq. (19), mole
-    fractions are clipped below at 1e-12 in the system (a species absent at a point).
+    The relations grad X_s = sum_{i != s} (X_s X_i / D_si) (V_i - V_s) are written for the
+    molar fluxes j_s = J_s / M_s = rho Y_s V_s / M_s (so that X_i V_i = (Mbar / rho) j_i):
+        sum_{i != s} (X_s j_i - X_i j_s) / D_si = (rho / Mbar) grad X_s,
+    i.e. C j = (rho / Mbar) grad X with C_si = X_s / D_si (i != s) and
+    C_ss = -sum_{i != s} X_i / D_si.  Every column of C sums to zero, so the five
+    relations hold four independent conditions; the mass constraint sum_s M_s j_s = 0
+    (Eq. 20) is the fifth.  It is added to every row, (C + alpha 1 m^T) j = (rho/Mbar)
+    grad X with m_s = M_s / Mbar and alpha the mean |C_ss|: the added term vanishes on
+    the solution, and the matrix is regular whenever C has rank four (summing its rows
+    gives 5 alpha m.j = sum_s (rho/Mbar) grad X_s, which is zero when sum_s X_s = 1).
+    The mole fractions enter as they are: no entry holds 1/X_s; the row of an absent
+    species (X_s = 0) reduces to j_s = -(rho / Mbar) grad X_s / sum_{i != s} X_i / D_si;
+    negative values (undershoots of a discrete field) are used unchanged.  Solved per point with LAPACK (partial pivoting).
     """
     Y = np.asarray(Y, dtype=np.float64)
-    X = np.maximum(mole_fractions(Y), X_CLIP)
+    X = mole_fractions(Y)
     sh = (5,) + (1,) * (Y.ndim - 1)
     Mbar = 1.0 / np.sum(Y / sp.M.reshape(sh), axis=0)
     rest = Y.shape[1:]
     n = int(np.prod(rest)) if rest else 1
     Xf = X.reshape(5, n)
-    sx = np.sqrt(Xf)
     Df = np.asarray(Dsr, dtype=np.float64).reshape(5, 5, n)
     nd = gradX.shape[1]
-    K = np.zeros((n, 5, 5))
+    C = np.zeros((n, 5, 5))
     for s in range(5):
         for i in range(5):
             if i == s:
                 continue
-            K[:, s, s] += Xf[i] / Df[s, i]
-            K[:, s, i] = -sx[s] * sx[i] / Df[s, i]
-    g = (sp.M.reshape(5, 1) / Mbar.reshape(1, n)) * sx          # [5][n]
-    alpha = np.mean(np.diagonal(K, axis1=1, axis2=2), axis=1)
-    A = K + alpha[:, None, None] * np.einsum("sn,in->nsi", g, g)
-    b = -np.moveaxis(np.asarray(gradX, dtype=np.float64).reshape(5, nd, n) / sx[:, None, :], 2, 0)
-    u = np.linalg.solve(A, b)                                  # [n][5][nd]
-    J = np.asarray(rho, dtype=np.float64).reshape(n)[:, None, None] * g.T[:, :, None] * u
+            C[:, s, i] = Xf[s] / Df[s, i]
+            C[:, s, s] -= Xf[i] / Df[s, i]
+    m = (sp.M.reshape(5, 1) / Mbar.reshape(1, n)).T          # [n][5]
+    alpha = np.mean(np.abs(np.diagonal(C, axis1=1, axis2=2)), axis=1)
+    A = C + alpha[:, None, None] * m[:, None, :]              # + alpha 1 m^T
+    b = (np.asarray(rho, dtype=np.float64).reshape(n) / Mbar.reshape(n))[:, None, None] * \
+        np.moveaxis(np.asarray(gradX, dtype=np.float64).reshape(5, nd, n), 2, 0)
+    j = np.linalg.solve(A, b)                                 # [n][5][nd]
+    J = sp.M.reshape(1, 5, 1) * j
     return np.moveaxis(J, 0, 2).reshape((5, nd) + rest)
