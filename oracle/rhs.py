@@ -48,6 +48,11 @@ RK4_B = (1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
          1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
          2277821191437.0 / 14882151754819.0)
 RK_SCHEMES = {0: (RK3_A, RK3_B), 1: (RK4_A, RK4_B)}
+# The three-register TVD (strong-stability-preserving) RK3 of Shu and Osher, the third
+# scheme Sec. 3.1 names: with Q0 the step's initial state, stage k sets
+# Q <- a_k Q0 + b_k (Q + dt R(Q)).
+SSP_RK3 = ((0.0, 1.0), (3.0 / 4.0, 1.0 / 4.0), (1.0 / 3.0, 2.0 / 3.0))
+SSPRK3 = 2
 
 # wall extrapolation with zero normal derivative (point-0 closure set to zero)
 WALL_EXTRAP = (48.0 / 25.0, -36.0 / 25.0, 16.0 / 25.0, -3.0 / 25.0)
@@ -325,12 +330,25 @@ def apply_bc(Q, case):
 
 
 def rk_stage(Q, dQ, Q_ref, case, stage, dt, R=None):
-    """One low-storage stage k: dQ <- A_k dQ + dt R(Q); Q <- Q + B_k dQ; then the wall update."""
-    A, B = RK_SCHEMES[case.cfg.rk]
-    k = stage % len(A)
+    """One stage k of the configured scheme, then the wall update.
+
+    Low-storage (2N) schemes: dQ <- A_k dQ + dt R(Q); Q <- Q + B_k dQ.
+    Three-register TVD RK3: at k = 0 dQ <- Q (the step's initial state Q0); then
+    Q <- a_k Q0 + b_k (Q + dt R(Q)).
+    R, when given, is used instead of evaluating R(Q).
+    """
     if R is None:
         R = rhs(Q, Q_ref, case)
-    dQ[...] = A[k] * dQ + dt * R
-    Q[...] = Q + B[k] * dQ
+    if case.cfg.rk == SSPRK3:
+        k = stage % len(SSP_RK3)
+        a, b = SSP_RK3[k]
+        if k == 0:
+            dQ[...] = Q
+        Q[...] = a * dQ + b * (Q + dt * R)
+    else:
+        A, B = RK_SCHEMES[case.cfg.rk]
+        k = stage % len(A)
+        dQ[...] = A[k] * dQ + dt * R
+        Q[...] = Q + B[k] * dQ
     apply_bc(Q, case)
     return Q, dQ

@@ -153,40 +153,120 @@ def test_species_rows_sum_to_continuity():
     assert np.max(np.abs(Rr[:5].sum(0)[inner] - cont[inner])) <= 1e-12 * sc
 
 
+def _butcher(key):
+    """Butcher tableau (A, b, c) of a scheme, derived by running its stage formulas on
+    symbolic increments: every state is y0 + sum_j w_j k_j with k_j = h f(Y_j) the
+    increment of stage j, and Y_j the state that stage j evaluates."""
+    if key == R.SSPRK3:
+        ns = len(R.SSP_RK3)
+    else:
+        ns = len(R.RK_SCHEMES[key][0])
+    Y = [np.zeros(ns)]                      # weights of the state stage 0 evaluates
+    q = np.zeros(ns)
+    reg = np.zeros(ns)
+    for k in range(ns):
+        e = np.zeros(ns)
+        e[k] = 1.0                          # k_k
+        if key == R.SSPRK3:
+            a, b = R.SSP_RK3[k]
+            if k == 0:
+                reg = q.copy()              # Q0 = y0 (zero weights)
+            q = a * reg + b * (q + e)
+        else:
+            A, B = R.RK_SCHEMES[key]
+            reg = A[k] * reg + e
+            q = q + B[k] * reg
+        if k + 1 < ns:
+            Y.append(q.copy())
+    Am = np.array(Y)
+    return Am, q, Am.sum(1)
+
+
+@pytest.mark.parametrize("key,p", [(0, 3), (1, 4), (R.SSPRK3, 3)])
+def test_rk_order_conditions(key, p):
+    """Order conditions of the derived tableau up to the scheme's order (the SSP scheme
+    and Williamson's in exact rationals; the Carpenter-Kennedy coefficients are
+    13-digit rationals, hence 1e-12)."""
+    A, b, c = _butcher(key)
+    cond = [(b.sum(), 1.0), (b @ c, 1 / 2), (b @ c ** 2, 1 / 3), (b @ (A @ c), 1 / 6),
+            (b @ c ** 3, 1 / 4), (b @ (c * (A @ c)), 1 / 8), (b @ (A @ c ** 2), 1 / 12),
+            (b @ (A @ (A @ c)), 1 / 24)]
+    nc = {3: 4, 4: 8}[p]
+    for k, (v, ex) in enumerate(cond[:nc]):
+        assert abs(v - ex) < 1e-12, (key, k, v, ex)
+    if p == 3:
+        # third order, not fourth: the first fourth-order condition fails
+        assert abs(cond[4][0] - 0.25) > 1e-3 or abs(cond[7][0] - 1 / 24) > 1e-3
+
+
 def test_rk_stability_polynomials_and_order():
-    for key, p in [(0, 3), (1, 4)]:
-        A, B = R.RK_SCHEMES[key]
-        # amplification of y' = z y, coefficients of the polynomial in z
-        coef = np.polynomial.Polynomial([1.0])
-        q = np.polynomial.Polynomial([1.0])
-        dq = np.polynomial.Polynomial([0.0])
+    import math
+    for key, p in [(0, 3), (1, 4), (R.SSPRK3, 3)]:
+        # amplification factor of y' = z y as a polynomial in z
         z = np.polynomial.Polynomial([0.0, 1.0])
-        for a, b in zip(A, B):
-            dq = a * dq + z * q
-            q = q + b * dq
+        q = np.polynomial.Polynomial([1.0])
+        if key == R.SSPRK3:
+            q0 = q
+            for a, b in R.SSP_RK3:
+                q = a * q0 + b * (q + z * q)
+        else:
+            A, B = R.RK_SCHEMES[key]
+            dq = np.polynomial.Polynomial([0.0])
+            for a, b in zip(A, B):
+                dq = a * dq + z * q
+                q = q + b * dq
         c = q.coef
         for n in range(p + 1):
-            assert abs(c[n] - 1.0 / np.math.factorial(n) if hasattr(np, "math") else 0) < 1e-12 \
-                or abs(c[n] - 1.0 / float(__import__("math").factorial(n))) < 1e-12
-    # nonlinear convergence order on y' = y (1 - y) + sin(t) y... autonomous form with t as a state
+            assert abs(c[n] - 1.0 / math.factorial(n)) < 1e-12, (key, n, c[n])
+
+    # nonlinear convergence order on y' = y (1 - y) + sin(t) y (t carried as a state)
+    def f(y):
+        return np.array([y[0] * (1 - y[0]) + np.sin(y[1]) * y[0], 1.0])
+
     def run(key, nsteps):
-        A, B = R.RK_SCHEMES[key]
         y = np.array([0.3, 0.0])
         d = np.zeros(2)
         h = 1.0 / nsteps
         for _ in range(nsteps):
-            for a, b in zip(A, B):
-                rhs = np.array([y[0] * (1 - y[0]) + np.sin(y[1]) * y[0], 1.0])
-                d = a * d + h * rhs
-                y = y + b * d
+            if key == R.SSPRK3:
+                y0 = y.copy()
+                for a, b in R.SSP_RK3:
+                    y = a * y0 + b * (y + h * f(y))
+            else:
+                A, B = R.RK_SCHEMES[key]
+                for a, b in zip(A, B):
+                    d = a * d + h * f(y)
+                    y = y + b * d
         return y[0]
     from scipy.integrate import solve_ivp
     ex = solve_ivp(lambda t, y: [y[0] * (1 - y[0]) + np.sin(t) * y[0]], (0, 1), [0.3],
                    rtol=1e-13, atol=1e-15).y[0, -1]
-    for key, p in [(0, 3), (1, 4)]:
+    for key, p in [(0, 3), (1, 4), (R.SSPRK3, 3)]:
         e1 = abs(run(key, 20) - ex)
         e2 = abs(run(key, 40) - ex)
         assert abs(np.log2(e1 / e2) - p) < 0.3, (key, np.log2(e1 / e2))
+
+
+def test_ssp_rk3_stage_registers():
+    """The oracle's SSP stages on a linear right-hand side R(Q) = L Q (an exact operator
+    applied through the R argument): after three stages Q equals the Shu-Osher step
+    written out, and dQ holds the step's initial state."""
+    import dataclasses
+    cfg = dataclasses.replace(f.get_config("c1").scaled(12, 10), rk=R.SSPRK3)
+    Q, Qr, info = f.initial_field(cfg)
+    case = R.Case(cfg, info["x"], info["y"], info["z"])
+    L = 0.37
+    Q0 = Q.copy()
+    Qs, dQ = Q.copy(), np.zeros_like(Q)
+    h = 0.1
+    y = Q0.copy()
+    for k in range(3):
+        R.rk_stage(Qs, dQ, None, case, k, h, R=L * Qs)
+        a, b = R.SSP_RK3[k]
+        y = a * Q0 + b * (y + h * L * y)
+        R.apply_bc(y, case)
+        assert np.array_equal(dQ, Q0)
+    assert np.max(np.abs(Qs - y)) <= 1e-15 * np.max(np.abs(y))
 
 
 def test_rk3_coefficients_rational():
