@@ -42,12 +42,18 @@ typedef enum {
   HRX_EINVAL = -1,   /* bad argument or configuration */
   HRX_EHIP = -2,     /* a HIP runtime call failed */
   HRX_ENOMEM = -3,   /* scratch allocation failed in hrx_create */
-  HRX_EUNSUP = -4    /* valid request that this build does not support */
+  HRX_EUNSUP = -4,   /* valid request that this build does not support */
+  /* per-point failures found by the kernels (Sec. 3.4: every state evaluation solves a
+   * nonlinear equation, which can fail); reported by hrx_get_counters, never by the
+   * asynchronous compute calls themselves */
+  HRX_ENEWTON = -5,   /* the energy inversion did not converge at some point */
+  HRX_EDOMAIN = -6,   /* some energy lay below e(50 K), outside the inversion's domain */
+  HRX_ENONFINITE = -7 /* some state held a non-finite value or a non-positive density */
 } hrx_status;
 
 enum { HRX_GAS_CPG = 0, HRX_GAS_AIR5 = 1, HRX_GAS_TPG = 2 };
 enum { HRX_WALL_ADIABATIC = 0, HRX_WALL_ISOTHERMAL = 1 };
-enum { HRX_RK3_2N = 0, HRX_RK45_2N = 1 };
+enum { HRX_RK3_2N = 0, HRX_RK45_2N = 1, HRX_SSPRK3 = 2 };
 enum { HRX_PREC_FP64 = 0, HRX_PREC_MIXED = 1 };
 enum { HRX_THERMO_PLAIN = 0, HRX_THERMO_SURROGATE = 1 };
 enum { HRX_DIFF_RAMSHAW = 0, HRX_DIFF_STEFAN_MAXWELL = 1 };
@@ -61,7 +67,8 @@ typedef struct hrx_config {
   const double *x, *y, *z;  /* (host) separable coordinates, nondimensional; x, y
                                non-periodic, z uniform and periodic (may be NULL if nz = 1) */
   int fd_order;             /* 4 or 6: explicit central differences, one-sided ends */
-  int rk_scheme;            /* HRX_RK3_2N or HRX_RK45_2N */
+  int rk_scheme;            /* HRX_RK3_2N (Williamson), HRX_RK45_2N (Carpenter-Kennedy) or
+                               HRX_SSPRK3 (the three-register TVD RK3 of Shu and Osher) */
   int precision;            /* HRX_PREC_FP64, or HRX_PREC_MIXED: FP64 conserved state, RK
                                update, energy inversion, convective fluxes, stencil
                                differences and Arrhenius exponentials at T >= 2000 K;
@@ -107,6 +114,10 @@ typedef struct hrx_counters {
   int64_t newton_nonconverged;      /* points with no convergence in newton_max_iter */
   int64_t energy_below_min;         /* points with e < e(50 K) */
   int64_t surrogate_fallbacks;      /* points evaluated outside the surrogate's hull */
+  int64_t nonfinite;                /* points whose state held a non-finite value or a
+                                       non-positive density */
+  int64_t negative_density;         /* points with a negative partial (or, for the perfect
+                                       gases, total) density: undershoots, counted only */
 } hrx_counters;
 
 /* Validate cfg, derive the reference state (Sec. 2.1, Eqs. 7 and 11), the metrics and
@@ -124,21 +135,34 @@ int hrx_get_reference(const hrx_ctx *ctx, hrx_reference *out /* (host) */);
 int hrx_rhs_eval(hrx_ctx *ctx, const double *Q, const double *Q_ref, double *R,
                  void *hip_stream);
 
-/* One low-storage stage k = stage mod (number of stages of the scheme), Sec. 3.1:
- *   dQ <- A_k dQ + dt F(Q);  Q <- Q + B_k dQ;  then the wall-row update
- * (no-slip, non-catalytic zero-gradient mass fractions, isothermal or adiabatic
- * energy).  Q, dQ: [nvar][N], updated in place; dQ must be zero-initialised or hold
- * the previous stage's register.  Q_ref as in hrx_rhs_eval. */
+/* One explicit Runge-Kutta stage k = stage mod (number of stages of the scheme), Sec. 3.1
+ * (two-register low-storage RK3 and RK4, three-register TVD RK3), then the wall-row
+ * update (no-slip, non-catalytic zero-gradient mass fractions, isothermal or adiabatic
+ * energy).  Q, dQ: [nvar][N], updated in place.
+ *   HRX_RK3_2N, HRX_RK45_2N:  dQ <- A_k dQ + dt R;  Q <- Q + B_k dQ.  dQ must be
+ *     zero-initialised before stage 0 or hold the previous stage's register.
+ *   HRX_SSPRK3:  stage 0 stores the step's initial state Q0 in dQ and sets
+ *     Q <- Q + dt R; stages 1 and 2 set Q <- a_k Q0 + b_k (Q + dt R) with
+ *     (a, b) = (3/4, 1/4), (1/3, 2/3).  The three registers are Q, Q0 (in dQ) and R.
+ * R: NULL evaluates R = F(Q) - sigma (Q - Q_ref) inside the stage (fused with the
+ * update, nothing materialised); otherwise R [nvar][N] is a right-hand side the caller
+ * computed (e.g. by hrx_rhs_eval) and Q_ref is not used.  Q_ref as in hrx_rhs_eval.
+ * R must not alias Q or dQ. */
 int hrx_rk_stage(hrx_ctx *ctx, int stage, double dt, double *Q, double *dQ,
-                 const double *Q_ref, void *hip_stream);
+                 const double *Q_ref, const double *R, void *hip_stream);
 
 /* Pointwise 5-species-air state in SI units (Sec. 2.2.1, Sec. 3.4): from density
  * rho [kg/m^3], internal energy e [J/kg] (including formation enthalpies) and mass
  * fractions Y [5][n], return T [K] (Newton inversion of e(T)), p = rho R_mix T [Pa],
  * species enthalpies h [5][n] [J/kg], viscosity mu [Pa s], frozen conductivity kappa
  * [W/(m K)], averaged diffusion coefficients D [5][n] [m^2/s] (Eq. 19) and status
- * [n] (0 converged, 1 no convergence, 2 e below e(50 K)); status may be NULL.
- * Any of p, h, mu, kappa, D may be NULL to skip it.  ctx must be an air5 context. */
+ * [n] (0 converged, 1 no convergence in newton_max_iter, 2 e below e(50 K),
+ * 3 a non-finite input or rho <= 0); status may be NULL.  T is also an input: a value
+ * in (50 K, 1e5 K) starts the inversion there (a warm start; e(T) is convex, so the
+ * root is the same), anything else (0, NaN) starts it cold.  Any of p, h, mu, kappa, D
+ * may be NULL to skip it.  ctx must be an air5 context.  No allocation: in the surrogate
+ * form the network's outputs go through the context's workspace, in chunks of at most
+ * max(N, 2^20) points. */
 int hrx_thermo_eval(hrx_ctx *ctx, int64_t n, const double *rho, const double *e,
                     const double *Y, double *T, double *p, double *h, double *mu,
                     double *kappa, double *D, int32_t *status, void *hip_stream);
@@ -149,7 +173,10 @@ int hrx_chem_source(hrx_ctx *ctx, int64_t n, const double *rho_s, const double *
                     double *wdot, void *hip_stream);
 
 /* Accumulated failure counters; synchronises the context's last stream.  reset != 0
- * zeroes them afterwards. */
+ * zeroes them afterwards.  Returns HRX_OK when no point failed since the last reset,
+ * else the most severe failure counted (HRX_ENONFINITE, then HRX_EDOMAIN, then
+ * HRX_ENEWTON); *out is filled in either case.  Surrogate fallbacks and negative
+ * densities are counted, not failures. */
 int hrx_get_counters(hrx_ctx *ctx, hrx_counters *out /* (host) */, int reset);
 
 /* ---- Learned thermochemistry surrogate (motivated by Sec. 5: replacing the costly

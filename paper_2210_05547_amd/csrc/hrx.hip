@@ -35,6 +35,35 @@ namespace hrx {
 
 enum { CPG = 0, AIR5 = 1, TPG = 2 };
 enum { MODE_RHS = 0, MODE_RK = 1 };
+// form of an RK stage's update (Sec. 3.1): two-register low-storage (dQ <- A dQ + dt R,
+// Q <- Q + B dQ), or the three-register TVD RK3 with the step's initial state Q0 in dQ
+// (first stage: Q0 <- Q; every stage: Q <- A Q0 + B (Q + dt R))
+enum { RKF_2N = 0, RKF_SSP_FIRST = 1, RKF_SSP = 2 };
+
+// The update of one value of one component (q: the stage's input state, dq: the second
+// register, r: the right-hand side); writes the new state and register through the
+// references.  Shared by the fused divergence kernel and the unfused update.  Every
+// product and sum is rounded on its own, in the order the stage formulas are written
+// (no fused multiply-add): the update then adds no rounding of its own to what the
+// right-hand side carries.  The three-register form rounds at the size of the state
+// (not of the increment) several times per stage, and on a boundary layer's small
+// wall-normal momentum that rounding, not the right-hand side's, decides agreement with
+// any other evaluation of the same formulas after many stages.
+__device__ __forceinline__ void rk_update(int rkf, double A, double B, double dt, double r,
+                                          double q, double dq, double& q_new, double& dq_new,
+                                          bool& write_dq) {
+#pragma clang fp contract(off)
+  if (rkf == RKF_2N) {
+    dq_new = A * dq + dt * r;
+    q_new = q + B * dq_new;
+    write_dq = true;
+  } else {
+    const double q0 = rkf == RKF_SSP_FIRST ? q : dq;
+    q_new = A * q0 + B * (q + dt * r);
+    dq_new = q0;
+    write_dq = rkf == RKF_SSP_FIRST;
+  }
+}
 
 struct Dev {
   int nx, ny, nz, ndim, nvar, ns, fd_order;
@@ -57,7 +86,9 @@ struct Dev {
   const double *sx, *sy;          // sponge profiles
   const double *dlx, *dly, *dlz;  // local spacings dx/d(xi)
   const unsigned char *hold;      // [nz][3][nx] or null
-  unsigned long long *counters;   // [0] Newton non-converged, [1] below e(T_min)
+  unsigned long long *counters;   // [0] Newton non-converged, [1] below e(T_min),
+                                  // [2] surrogate fallbacks, [3] non-finite states,
+                                  // [4] negative densities
   // W plane offsets
   int nsrc, w_p, w_mu, w_kap, w_D, w_wdot, w_h, w_c;
   int nad;                        // artificial-diffusivity planes (3 + ns)
@@ -357,6 +388,23 @@ __device__ __forceinline__ void count(const Dev& d, int status) {
   if (status == 2) atomicAdd(&d.counters[1], 1ull);
 }
 
+// Count the lanes of the wavefront for which pred holds with one atomic (the first
+// active lane adds the population count of the ballot).
+__device__ __forceinline__ void wave_count(unsigned long long* c, bool pred) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0ull) return;
+  const unsigned long long act = __ballot(1);
+  if ((int)__lane_id() == __ffsll((long long)act) - 1) atomicAdd(c, (unsigned long long)__popcll(m));
+}
+
+// Finite state of positive density (else the point is counted as non-finite)
+__device__ __forceinline__ bool finite_state(const double* v, int n, double rho) {
+  bool ok = rho > 0.0 && isfinite(rho);
+#pragma unroll 9
+  for (int k = 0; k < n; ++k) ok = ok && isfinite(v[k]);
+  return ok;
+}
+
 // Temperature above which the mixed form keeps the Arrhenius exponentials in FP64.
 constexpr double T_HI_MIXED = 2000.0;
 
@@ -510,6 +558,13 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   const long N = d.N;
   if (GAS != AIR5) {
     const double rho = Q[idx];
+    {
+      double qv[5];
+#pragma unroll
+      for (int k = 0; k < ND + 2; ++k) qv[k] = Q[(long)k * N + idx];
+      wave_count(&d.counters[3], !finite_state(qv, ND + 2, rho));
+      wave_count(&d.counters[4], rho < 0.0);
+    }
     double u[3] = {0.0, 0.0, 0.0};
     double ke = 0.0;
 #pragma unroll
@@ -552,6 +607,21 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
   for (int s = 0; s < NS; ++s) rs[s] = Q[s * N + idx];
 #pragma unroll
   for (int a = 0; a < ND; ++a) mom[a] = Q[(NS + a) * N + idx];
+  {
+    double qv[NS + 4], rho = 0.0;
+    bool neg = false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      qv[s] = rs[s];
+      rho += rs[s];
+      neg = neg || rs[s] < 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < ND; ++a) qv[NS + a] = mom[a];
+    qv[NS + ND] = Q[(NS + ND) * N + idx];
+    wave_count(&d.counters[3], !finite_state(qv, NS + ND + 1, rho));
+    wave_count(&d.counters[4], neg);
+  }
   float ys[MLP_NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   bool net = false;
   if (SUR) {
@@ -891,7 +961,8 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
   constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);   // u, v, (w), T, (X_s)
   // mole-fraction derivatives formed per flux direction (fewer live registers) where the
   // kernel is register bound: with artificial diffusivity and in 3-D (measured)
-  constexpr bool DX_PER_DIR = AD || ND == 3;
+  // (the Stefan-Maxwell system takes every direction's gradients at once)
+  constexpr bool DX_PER_DIR = (AD || ND == 3) && !(SM && GAS == AIR5);
   extern __shared__ double smem[];
   const long N = d.N;
   Pt p;
@@ -1043,19 +1114,21 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
 #pragma unroll
     for (int s = 0; s < NS; ++s) h[s] = Wp[(d.w_h + s) * N + idx];
   }
-  // Stefan-Maxwell diffusion (Eq. 17).  With sx = sqrt(X)
-  // (X clipped below at 1e-12) and V = u / sx the system Q V = -grad X becomes
-  // K u = -grad X / sx with K_ss = sum_{i != s} X_i / D_si, K_si = -sx_s sx_i / D_si:
-  // symmetric, an O(1/D) diagonal even for vanishing species, null vector sx.  The mass
-  // constraint sum_s Y_s V_s = g . u = 0, g_s = (M_s / Mbar) sx_s, closes it:
-  // A = K + alpha g g^T (the added term vanishes on the solution; A is positive definite)
-  // is factored once per point as L D L^T and solved for each direction; then
-  // J_s = rho Y_s V_s = rho (M_s / Mbar) sx_s u_s.  Artificial diffusivities, if any,
-  // add a flux of the form of Eq. (18) with their coefficients alone (a_s below).
+  // Stefan-Maxwell diffusion (Eq. 17 with the driving forces of Eq. 16), in the molar
+  // fluxes j_s = J_s / M_s: sum_{i != s} (X_s j_i - X_i j_s) / D_si = (rho / Mbar) dX_s,
+  // i.e. C j = (rho / Mbar) grad X with C_si = X_s / D_si and C_ss = -sum_{i != s}
+  // X_i / D_si.  The columns of C sum to zero; the mass constraint sum_s M_s j_s = 0
+  // (Eq. 20) closes the system, added to every row: (C + alpha 1 m^T) j = (rho / Mbar)
+  // grad X with m_s = M_s / Mbar and alpha the mean |C_ss| (the added term vanishes on
+  // the solution).  The mole fractions enter unclipped.  The five-by-five system is
+  // solved for every direction at once by Gaussian elimination with partial pivoting
+  // (the row exchanges as selects, so that the matrix stays in registers); then
+  // J_s = M_s j_s.  Artificial diffusivities, if any, add a flux of the form of Eq. (18)
+  // with their coefficients alone (a_s below).
   constexpr bool sm = SM && GAS == AIR5;
-  RT Lm[NS][NS], Dd[NS], Dinv[NS], sxv[NS], isx[NS], gv[NS];
+  RT Jsm[NS][3];
   if constexpr (sm) {
-    RT iDm[NS][NS], Xc[NS], nsum = RT(0);
+    RT iDm[NS][NS], Xp[NS], nsum = RT(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) nsum += Y[s] / RT(molar_mass(s));
 #pragma unroll
@@ -1067,45 +1140,75 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
         iDm[r][s] = v;
       }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const RT x = RT(smem[(ND + 1 + s) * TILE_E + sidx]);
-      Xc[s] = x > RT(1e-12) ? x : RT(1e-12);
-      sxv[s] = sqrt(Xc[s]);
-      isx[s] = RT(1) / sxv[s];
-      gv[s] = RT(molar_mass(s)) * nsum * sxv[s];
-    }
-    RT A[NS][NS], tr = RT(0);
+    for (int s = 0; s < NS; ++s) Xp[s] = RT(smem[(ND + 1 + s) * TILE_E + sidx]);
+    RT A[NS][NS], Bm[NS][3], csum = RT(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      RT k = RT(0);
+      RT diag = RT(0);
 #pragma unroll
-      for (int i = 0; i < NS; ++i)
-        if (i != s) k += Xc[i] * iDm[s][i];
-      A[s][s] = k;
-      tr += k;
-#pragma unroll
-      for (int i = 0; i < s; ++i) A[s][i] = -sxv[s] * sxv[i] * iDm[s][i];
+      for (int i = 0; i < NS; ++i) {
+        if (i == s) continue;
+        A[s][i] = Xp[s] * iDm[s][i];
+        diag -= Xp[i] * iDm[s][i];
+      }
+      A[s][s] = diag;
+      csum += fabs(diag);
     }
-    const RT alpha = tr * RT(0.2);
+    const RT alpha = csum * RT(0.2);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const RT am = alpha * (RT(molar_mass(i)) * nsum);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) A[s][i] += am;
+    }
+    const RT bs = rho_r * nsum;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int i = 0; i <= s; ++i) A[s][i] += alpha * gv[s] * gv[i];
+      for (int b = 0; b < ND; ++b) Bm[s][b] = bs * dX[s][b];
+    RT ip[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      RT dk = A[k][k];
-#pragma unroll
-      for (int m = 0; m < k; ++m) dk -= Lm[k][m] * Lm[k][m] * Dd[m];
-      Dd[k] = dk;
-      Dinv[k] = RT(1) / dk;
+      // pivot: the largest |A[i][k]|, i >= k, brought to row k by compare-and-swap
 #pragma unroll
       for (int i = k + 1; i < NS; ++i) {
-        RT v = A[i][k];
+        const bool sw = fabs(A[i][k]) > fabs(A[k][k]);
 #pragma unroll
-        for (int m = 0; m < k; ++m) v -= Lm[i][m] * Lm[k][m] * Dd[m];
-        Lm[i][k] = v * Dinv[k];
+        for (int c = k; c < NS; ++c) {
+          const RT a = A[k][c], b = A[i][c];
+          A[k][c] = sw ? b : a;
+          A[i][c] = sw ? a : b;
+        }
+#pragma unroll
+        for (int c = 0; c < ND; ++c) {
+          const RT a = Bm[k][c], b = Bm[i][c];
+          Bm[k][c] = sw ? b : a;
+          Bm[i][c] = sw ? a : b;
+        }
+      }
+      ip[k] = RT(1) / A[k][k];
+#pragma unroll
+      for (int i = k + 1; i < NS; ++i) {
+        const RT l = A[i][k] * ip[k];
+#pragma unroll
+        for (int c = k + 1; c < NS; ++c) A[i][c] -= l * A[k][c];
+#pragma unroll
+        for (int c = 0; c < ND; ++c) Bm[i][c] -= l * Bm[k][c];
       }
     }
+#pragma unroll
+    for (int k = NS - 1; k >= 0; --k)
+#pragma unroll
+      for (int c = 0; c < ND; ++c) {
+        RT v = Bm[k][c];
+#pragma unroll
+        for (int m = k + 1; m < NS; ++m) v -= A[k][m] * Bm[m][c];
+        Bm[k][c] = v * ip[k];
+      }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int c = 0; c < ND; ++c) Jsm[s][c] = RT(molar_mass(s)) * Bm[s][c];
   }
 #pragma unroll
   for (int j = 0; j < ND; ++j) {
@@ -1118,23 +1221,8 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
       }
       RT corr = RT(0);
       if constexpr (sm) {
-        RT z[NS];
 #pragma unroll
-        for (int i = 0; i < NS; ++i) {   // forward: L y = -grad X / sx
-          RT v = -dX[i][j] * isx[i];
-#pragma unroll
-          for (int m = 0; m < i; ++m) v -= Lm[i][m] * z[m];
-          z[i] = v;
-        }
-#pragma unroll
-        for (int i = 0; i < NS; ++i) z[i] *= Dinv[i];
-#pragma unroll
-        for (int i = NS - 1; i >= 0; --i) {   // backward: L^T u = D^-1 y
-#pragma unroll
-          for (int m = i + 1; m < NS; ++m) z[i] -= Lm[m][i] * z[m];
-        }
-#pragma unroll
-        for (int s = 0; s < NS; ++s) J[s] = rho_r * gv[s] * z[s];
+        for (int s = 0; s < NS; ++s) J[s] = Jsm[s][j];
         if (AD) {
 #pragma unroll
           for (int s = 0; s < NS; ++s) corr += a_s[s] * dX[s][j];
@@ -1320,7 +1408,7 @@ __global__ __launch_bounds__(256 * NH) void k_div(Dev d, const double* __restric
                                              const RT* __restrict__ Wp, const double* Qin,
                                              const double* __restrict__ Qref, double* Rout,
                                              double* Qio, double* dQio, double A, double B,
-                                             double dt) {
+                                             double dt, int rkf) {
   constexpr int ns = (GAS == AIR5) ? NS : 1;
   constexpr int nvar = ns + ND + 1;
   constexpr int KC = div_chunk(ND);
@@ -1394,7 +1482,7 @@ __global__ __launch_bounds__(256 * NH) void k_div(Dev d, const double* __restric
       for (int kk = 0; kk < KC; ++kk) {
         const int k = min(k0 + kk, nvar - 1);
         qv_[kk] = (MODE == MODE_RK) ? Qio[k * N + idx] : Qin[k * N + idx];
-        dq_[kk] = (MODE == MODE_RK) ? dQio[k * N + idx] : 0.0;
+        dq_[kk] = (MODE == MODE_RK && rkf != RKF_SSP_FIRST) ? dQio[k * N + idx] : 0.0;
         if (PRE_W) wd_[kk] = (GAS == AIR5 && k < NS) ? Wp[(d.w_wdot + k) * N + idx] : RT(0);
       }
     }
@@ -1453,9 +1541,14 @@ __global__ __launch_bounds__(256 * NH) void k_div(Dev d, const double* __restric
       if (MODE == MODE_RHS) {
         Rout[k * N + idx] = R;
       } else {
-        const double dq = A * (PRE ? dq_p : dQio[k * N + idx]) + dt * R;
-        dQio[k * N + idx] = dq;
-        Qio[k * N + idx] = qv + B * dq;
+        // the SSP form's first stage does not read the register (it is set to Q0)
+        const double dqi =
+            (PRE || rkf == RKF_SSP_FIRST) ? dq_p : dQio[k * N + idx];
+        double qn, dqn;
+        bool wdq;
+        rk_update(rkf, A, B, dt, R, qv, dqi, qn, dqn, wdq);
+        if (wdq) dQio[k * N + idx] = dqn;
+        Qio[k * N + idx] = qn;
       }
     };
     if (PRE) {
@@ -1495,18 +1588,61 @@ __global__ __launch_bounds__(256 * NH) void k_div(Dev d, const double* __restric
   }
 }
 
+// Unfused stage update from a right-hand side R the caller computed: every component of
+// every point, rk_update as in the divergence kernel (the wall row follows in k_bc).
+__global__ __launch_bounds__(256) void k_rk_update(long N, int nvar, const double* __restrict__ R,
+                                                   double* Q, double* dQ, double A, double B,
+                                                   double dt, int rkf) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N) return;
+  for (int k = 0; k < nvar; ++k) {
+    const long o = (long)k * N + idx;
+    const double q = Q[o];
+    const double dq = rkf == RKF_SSP_FIRST ? 0.0 : dQ[o];
+    double qn, dqn;
+    bool wdq;
+    rk_update(rkf, A, B, dt, R[o], q, dq, qn, dqn, wdq);
+    if (wdq) dQ[o] = dqn;
+    Q[o] = qn;
+  }
+}
+
 // ------------------------------------------------------------------ pointwise SI calls
-// One SI state (rho, e, Y): energy inversion (from T_start > 0, else cold), pressure,
-// enthalpies, and transport from the surrogate's outputs ys = (ln T, ln mu, ln kappa,
-// ln(rho D_s)) when net is set, else the plain evaluation.  Null outputs are skipped.
+// One SI state (rho, e, Y): energy inversion (from T_start in (T_MIN, T_GUESS_MAX), else
+// cold), pressure, enthalpies, and transport from the surrogate's outputs ys = (ln T,
+// ln mu, ln kappa, ln(rho D_s)) when net is set, else the plain evaluation.  Null
+// outputs are skipped.  ld: leading dimension of the [5][.] arrays.  A non-finite input
+// or rho <= 0 gives status 3 (counted) and NaN outputs.
 template <class RT>
-__device__ __forceinline__ void thermo_point(long n, long i, double rtol, int max_iter,
+__device__ __forceinline__ void thermo_point(long ld, long i, double rtol, int max_iter,
                                              double r, double ee, const double* Y,
                                              double T_start, bool net,
                                              const float (&ys)[MLP_NOUT], double* Tout,
                                              double* pout, double* hout, double* muout,
                                              double* kout, double* Dout, int32_t* stout,
                                              unsigned long long* counters) {
+  const long n = ld;
+  {
+    double v[NS + 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = Y[s];
+    v[NS] = ee;
+    if (!finite_state(v, NS + 1, r)) {
+      atomicAdd(&counters[3], 1ull);
+      const double nan = __builtin_nan("");
+      Tout[i] = nan;
+      if (stout) stout[i] = 3;
+      if (pout) pout[i] = nan;
+      if (muout) muout[i] = nan;
+      if (kout) kout[i] = nan;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (hout) hout[s * n + i] = nan;
+        if (Dout) Dout[s * n + i] = nan;
+      }
+      return;
+    }
+  }
   int status, iters;
   SpeciesThermo st;   // species state at the last Newton iterate (within rtol of T)
   const double T = temperature_from_energy(ee, Y, rtol, max_iter, &status, &iters, T_start, &st);
@@ -1553,9 +1689,10 @@ __device__ __forceinline__ void thermo_point(long n, long i, double rtol, int ma
 
 // Plain form, or (SUR) the surrogate form's second pass reading the network's outputs
 // ys[8][n] (NaN in ys[0]: outside the hull, plain evaluation, counted when transport is
-// requested).
+// requested).  n points of arrays with leading dimension ld (SoA [5][ld] for Y, h, D).
+// Tout is read first: a temperature in (T_MIN, T_GUESS_MAX) starts the inversion.
 template <class RT, bool SUR = false>
-__global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int max_iter,
+__global__ __launch_bounds__(128) void k_thermo_eval(long n, long ld, double rtol, int max_iter,
                                                      const double* __restrict__ rho,
                                                      const double* __restrict__ e,
                                                      const double* __restrict__ Yin,
@@ -1572,7 +1709,7 @@ __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int ma
   if (i >= n) return;
   double Y[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + i];
+  for (int s = 0; s < NS; ++s) Y[s] = Yin[s * ld + i];
   float ys[MLP_NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   bool net = false;
   if (SUR) {
@@ -1581,8 +1718,12 @@ __global__ __launch_bounds__(128) void k_thermo_eval(long n, double rtol, int ma
     net = !isnan(ys[0]);
     if (!net && (muout || kout || Dout)) atomicAdd(&counters[2], 1ull);
   }
-  thermo_point<RT>(n, i, rtol, max_iter, rho[i], e[i], Y, net ? (double)__expf(ys[0]) : 0.0, net,
-                   ys, Tout, pout, hout, muout, kout, Dout, stout, counters);
+  // the caller's temperature if it is a valid start, else the network's, else cold
+  const double Tc = Tout[i];
+  const bool tc_ok = Tc > T_MIN && Tc < T_GUESS_MAX;
+  const double Ts = tc_ok ? Tc : (net ? (double)__expf(ys[0]) : 0.0);
+  thermo_point<RT>(ld, i, rtol, max_iter, rho[i], e[i], Y, Ts, net, ys, Tout, pout, hout, muout,
+                   kout, Dout, stout, counters);
 }
 
 template <class RT>
@@ -1903,10 +2044,10 @@ __device__ __forceinline__ void surrogate_outputs(const MlpNorm& nm, const float
 // LDS and walks the points in steps of 256; each wavefront computes the standardised
 // features of its 64 states and evaluates the network on the matrix cores.  Output:
 // ys[8][n] (FP32) = (ln T, ln mu, ln kappa, ln(rho D_1..5)) in SI, with ys[0] = NaN for
-// states outside the training hull.  States are SI (rho, e, Y) or, with FROM_Q, the
-// nondimensional conserved state Q.
+// states outside the training hull.  States are SI (rho, e, Y [5][ld]) or, with FROM_Q,
+// the nondimensional conserved state Q.
 template <int ND, bool FROM_Q>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_eval(Dev d, const MlpNorm* __restrict__ gnm, long n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_eval(Dev d, const MlpNorm* __restrict__ gnm, long n, long ld,
                                                   const double* __restrict__ rho,
                                                   const double* __restrict__ e,
                                                   const double* __restrict__ Yin,
@@ -1952,7 +2093,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       ee = (Q[(NS + ND) * n + ix] * irs - 0.5 * ke) * (d.c_inf * d.c_inf);
     } else {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + ix];
+      for (int s = 0; s < NS; ++s) Y[s] = Yin[s * ld + ix];
       r = rho[ix];
       ee = e[ix];
     }
@@ -2021,8 +2162,15 @@ namespace {
 enum { K_PRIM = 0, K_AD_SRC, K_AD_D4, K_AD_FX, K_AD_FY, K_AD_FZ, K_FLUX, K_DIV, K_BC, K_THERMO,
        K_CHEM };
 
-// Workspace of the surrogate's network outputs, [8][n] floats (grown on demand; a
-// reallocation synchronises the device).
+constexpr int NCOUNT = 8;   // device counters (see Dev::counters)
+
+// Points per network pass of hrx_thermo_eval in the surrogate form (its workspace
+// holds max(N, this) points; larger calls run in chunks).
+constexpr int64_t THERMO_CHUNK = 1 << 20;
+
+// Workspace of the surrogate's network outputs, [8][n] floats.  Sized once, by
+// hrx_set_thermo_mode (a set-up call, which also drops every captured graph); the
+// compute calls never grow it.
 int ensure_ys(hrx_ctx* c, int64_t n) {
   if (n <= c->ys_cap) return HRX_OK;
   if (c->ys) (void)hipFree(c->ys);
@@ -2125,6 +2273,9 @@ const char* hrx_strerror(int code) {
     case HRX_EHIP: return "HIP runtime error";
     case HRX_ENOMEM: return "device memory allocation failed";
     case HRX_EUNSUP: return "not supported by this build";
+    case HRX_ENEWTON: return "the energy inversion did not converge at some point";
+    case HRX_EDOMAIN: return "an energy below e(50 K) at some point";
+    case HRX_ENONFINITE: return "a non-finite state or a non-positive density at some point";
     default: return "unknown error";
   }
 }
@@ -2164,7 +2315,8 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   if (c.diffusion == HRX_DIFF_STEFAN_MAXWELL && c.gas != HRX_GAS_AIR5) return HRX_EUNSUP;
   if (c.nx < 8 || c.ny < 8 || c.nz < 1 || (c.nz > 1 && c.nz < 8)) return HRX_EINVAL;
   if (c.fd_order != 4 && c.fd_order != 6) return HRX_EINVAL;
-  if (c.rk_scheme != HRX_RK3_2N && c.rk_scheme != HRX_RK45_2N) return HRX_EINVAL;
+  if (c.rk_scheme != HRX_RK3_2N && c.rk_scheme != HRX_RK45_2N && c.rk_scheme != HRX_SSPRK3)
+    return HRX_EINVAL;
   if (c.precision != HRX_PREC_FP64 && c.precision != HRX_PREC_MIXED) return HRX_EINVAL;
   if (!c.x || !c.y || (c.nz > 1 && !c.z)) return HRX_EINVAL;
   if (c.sponge_in < 0 || c.sponge_out < 0 || c.sponge_top < 0 || c.sponge_in >= c.nx - 1 ||
@@ -2370,9 +2522,10 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   if (hipMalloc(&ctx->R, sizeof(double) * N * d.nvar) != hipSuccess) return fail(HRX_ENOMEM);
   if (d.ad_on && hipMalloc(&ctx->AD, rts * N * d.nad * 2) != hipSuccess) return fail(HRX_ENOMEM);
   d.ad = ctx->AD;
-  if (hipMalloc(&ctx->counters, 4 * sizeof(unsigned long long)) != hipSuccess)
+  if (hipMalloc(&ctx->counters, NCOUNT * sizeof(unsigned long long)) != hipSuccess)
     return fail(HRX_ENOMEM);
-  if ((rc = check(hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long))))) return fail(rc);
+  if ((rc = check(hipMemset(ctx->counters, 0, NCOUNT * sizeof(unsigned long long)))))
+    return fail(rc);
   d.counters = ctx->counters;
   {
     int dev = 0, ncu = 0;
@@ -2432,7 +2585,7 @@ constexpr long DIV_SPLIT_MAX_POINTS = 1L << 18;
 template <int GAS, int ND, int ORDER, int MODE, class RT>
 void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, const double* Q,
                 const double* Qref, double* R, double* Qio, double* dQ, double A, double B,
-                double dt) {
+                double dt, int rkf) {
   const Dev& d = ctx->dev;
   constexpr int nvar = (GAS == AIR5 ? NS : 1) + ND + 1;
   unsigned nt = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
@@ -2446,14 +2599,15 @@ void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, con
       // larger grids: one block runs both chunks, the first one's inputs preloaded
       if (split)
         k_div<GAS, ND, ORDER, MODE, RT, false, 2>
-            <<<nt, 2 * TTX * TTY, 2 * sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
+            <<<nt, 2 * TTX * TTY, 2 * sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt, rkf);
       else
         k_div<GAS, ND, ORDER, MODE, RT, true, 1>
-            <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
+            <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt, rkf);
       return;
     }
     k_div<GAS, ND, ORDER, MODE, RT, false, 1>
-        <<<split ? nt * nch : nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt);
+        <<<split ? nt * nch : nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt,
+                                                         rkf);
   });
 }
 
@@ -2471,7 +2625,7 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
     // network pass (its outputs in the context's ys workspace), then the pointwise pass
     const unsigned nbs = (unsigned)std::min<long>((N + 255) / 256, 2048);
     timed(ctx, K_PRIM, st, [&] {
-      k_mlp_eval<ND, true><<<nbs, 256, 0, st>>>(d, ctx->norm_dev, N, nullptr, nullptr, nullptr, Q,
+      k_mlp_eval<ND, true><<<nbs, 256, 0, st>>>(d, ctx->norm_dev, N, N, nullptr, nullptr, nullptr, Q,
                                                 ctx->ys, ctx->wsw, ctx->bias);
       k_prim<GAS, ND, RT, true><<<nb, bs, 0, st>>>(d, Q, Wd, Wp, ctx->ys);
     });
@@ -2512,7 +2666,7 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
 
 template <int GAS, int ND, int ORDER, class RT>
 int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, double* Qio,
-        double* dQ, double A, double B, double dt, hipStream_t st) {
+        double* dQ, double A, double B, double dt, int rkf, hipStream_t st) {
   const Dev& d = ctx->dev;
   int rc = launch_rhs_chain<GAS, ND, ORDER, RT>(ctx, mode == MODE_RHS ? Q : Qio, st);
   if (rc) return rc;
@@ -2522,10 +2676,10 @@ int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, 
   const RT* Wp = (const RT*)ctx->Wp;
   if (mode == MODE_RHS) {
     launch_div<GAS, ND, ORDER, MODE_RHS, RT>(ctx, st, F, Wp, Q, Qref, R, nullptr, nullptr, 0.0,
-                                             0.0, 0.0);
+                                             0.0, 0.0, RKF_2N);
   } else {
     launch_div<GAS, ND, ORDER, MODE_RK, RT>(ctx, st, F, Wp, nullptr, Qref, nullptr, Qio, dQ, A,
-                                            B, dt);
+                                            B, dt, rkf);
     constexpr int nvar = (GAS == AIR5 ? NS : 1) + ND + 1;
     constexpr int nch = (nvar + div_chunk(ND) - 1) / div_chunk(ND);
     // chunks of one tile in separate blocks (two chunks share a block in 2-D)
@@ -2539,14 +2693,14 @@ int run(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, 
 }
 
 int dispatch(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R, double* Qio,
-             double* dQ, double A, double B, double dt, hipStream_t st) {
+             double* dQ, double A, double B, double dt, int rkf, hipStream_t st) {
   const Dev& d = ctx->dev;
   const bool air = ctx->cfg.gas == HRX_GAS_AIR5, tpg = ctx->cfg.gas == HRX_GAS_TPG;
   const bool o6 = d.fd_order == 6;
   const bool mixed = ctx->cfg.precision == HRX_PREC_MIXED;
-#define HRX_RUN(G, NDV, O)                                                         \
-  return mixed ? run<G, NDV, O, float>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, st) \
-               : run<G, NDV, O, double>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, st)
+#define HRX_RUN(G, NDV, O)                                                              \
+  return mixed ? run<G, NDV, O, float>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, rkf, st) \
+               : run<G, NDV, O, double>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, rkf, st)
   if (d.ndim == 2) {
     if (air) { if (o6) HRX_RUN(AIR5, 2, 6); else HRX_RUN(AIR5, 2, 4); }
     else if (tpg) { if (o6) HRX_RUN(TPG, 2, 6); else HRX_RUN(TPG, 2, 4); }
@@ -2568,6 +2722,28 @@ const double RK4A[5] = {0.0, -567301805773.0 / 1357537059087.0,
 const double RK4B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
                         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                         2277821191437.0 / 14882151754819.0};
+// Shu-Osher TVD RK3 as Q <- a_k Q0 + b_k (Q + dt R(Q))
+const double SSPA[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
+const double SSPB[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
+
+// Wall-row pass after an unfused update (every gas and dimension)
+void launch_bc(hrx_ctx* ctx, double* Q, hipStream_t st) {
+  const Dev& d = ctx->dev;
+  const long nw = (long)(d.nx - 1) * d.nz;
+  const unsigned nb = blocks_for(nw, 128);
+  const bool air = ctx->cfg.gas == HRX_GAS_AIR5, tpg = ctx->cfg.gas == HRX_GAS_TPG;
+  timed(ctx, K_BC, st, [&] {
+    if (d.ndim == 2) {
+      if (air) k_bc<AIR5, 2><<<nb, 128, 0, st>>>(d, Q);
+      else if (tpg) k_bc<TPG, 2><<<nb, 128, 0, st>>>(d, Q);
+      else k_bc<CPG, 2><<<nb, 128, 0, st>>>(d, Q);
+    } else {
+      if (air) k_bc<AIR5, 3><<<nb, 128, 0, st>>>(d, Q);
+      else if (tpg) k_bc<TPG, 3><<<nb, 128, 0, st>>>(d, Q);
+      else k_bc<CPG, 3><<<nb, 128, 0, st>>>(d, Q);
+    }
+  });
+}
 
 }  // namespace
 
@@ -2578,19 +2754,40 @@ int hrx_rhs_eval(hrx_ctx* ctx, const double* Q, const double* Q_ref, double* R,
   if (!ctx || !Q || !R || R == Q) return HRX_EINVAL;
   hipStream_t st = (hipStream_t)hip_stream;
   ctx->last_stream = st;
-  return dispatch(ctx, MODE_RHS, Q, Q_ref, R, nullptr, nullptr, 0.0, 0.0, 0.0, st);
+  return dispatch(ctx, MODE_RHS, Q, Q_ref, R, nullptr, nullptr, 0.0, 0.0, 0.0, RKF_2N, st);
 }
 
 int hrx_rk_stage(hrx_ctx* ctx, int stage, double dt, double* Q, double* dQ, const double* Q_ref,
-                 void* hip_stream) {
+                 const double* R, void* hip_stream) {
   if (!ctx || !Q || !dQ || Q == dQ || stage < 0 || !std::isfinite(dt)) return HRX_EINVAL;
-  const bool rk3 = ctx->cfg.rk_scheme == HRX_RK3_2N;
-  const int ns = rk3 ? 3 : 5;
+  if (R && (R == Q || R == dQ)) return HRX_EINVAL;
+  const int sch = ctx->cfg.rk_scheme;
+  const int ns = sch == HRX_RK45_2N ? 5 : 3;
   const int k = stage % ns;
-  const double A = rk3 ? RK3A[k] : RK4A[k];
-  const double B = rk3 ? RK3B[k] : RK4B[k];
+  double A, B;
+  int rkf = RKF_2N;
+  if (sch == HRX_RK3_2N) {
+    A = RK3A[k];
+    B = RK3B[k];
+  } else if (sch == HRX_RK45_2N) {
+    A = RK4A[k];
+    B = RK4B[k];
+  } else {
+    A = SSPA[k];
+    B = SSPB[k];
+    rkf = k == 0 ? RKF_SSP_FIRST : RKF_SSP;
+  }
   hipStream_t st = (hipStream_t)hip_stream;
   ctx->last_stream = st;
+  if (R) {
+    // unfused: the caller's right-hand side, a pointwise update, the wall row
+    const Dev& d = ctx->dev;
+    timed(ctx, K_DIV, st, [&] {
+      k_rk_update<<<blocks_for(d.N, 256), 256, 0, st>>>(d.N, d.nvar, R, Q, dQ, A, B, dt, rkf);
+    });
+    launch_bc(ctx, Q, st);
+    return check(hipGetLastError());
+  }
   // After the first stage (which switches the energy inversion to warm starts), a
   // stage's kernel sequence is captured once per argument set into a HIP graph and
   // replayed: one launch instead of four or more.  Not on the null stream (it cannot
@@ -2601,7 +2798,7 @@ int hrx_rk_stage(hrx_ctx* ctx, int stage, double dt, double* Q, double* dQ, cons
         return check(hipGraphLaunch(g.exec, st));
     if (ctx->graphs.size() >= 16) clear_graphs(ctx);
     if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) return HRX_EHIP;
-    const int rc = dispatch(ctx, MODE_RK, nullptr, Q_ref, nullptr, Q, dQ, A, B, dt, st);
+    const int rc = dispatch(ctx, MODE_RK, nullptr, Q_ref, nullptr, Q, dQ, A, B, dt, rkf, st);
     hipGraph_t graph;
     if (hipStreamEndCapture(st, &graph) != hipSuccess || rc) return rc ? rc : HRX_EHIP;
     hipGraphExec_t exec;
@@ -2611,7 +2808,7 @@ int hrx_rk_stage(hrx_ctx* ctx, int stage, double dt, double* Q, double* dQ, cons
     ctx->graphs.push_back({Q, dQ, Q_ref, dt, k, st, exec});
     return check(hipGraphLaunch(exec, st));
   }
-  return dispatch(ctx, MODE_RK, nullptr, Q_ref, nullptr, Q, dQ, A, B, dt, st);
+  return dispatch(ctx, MODE_RK, nullptr, Q_ref, nullptr, Q, dQ, A, B, dt, rkf, st);
 }
 
 int hrx_thermo_eval(hrx_ctx* ctx, int64_t n, const double* rho, const double* e, const double* Y,
@@ -2624,26 +2821,29 @@ int hrx_thermo_eval(hrx_ctx* ctx, int64_t n, const double* rho, const double* e,
   ctx->last_stream = st;
   const bool mixed = ctx->cfg.precision == HRX_PREC_MIXED;
   const bool sur = ctx->thermo_mode == HRX_THERMO_SURROGATE;
-  if (sur) {
-    const int rc = ensure_ys(ctx, n);
-    if (rc) return rc;
-  }
+  if (sur && (!ctx->ys || ctx->ys_cap < 1)) return HRX_EINVAL;
+  const double rt = ctx->dev.newton_rtol;
+  const int mi = ctx->dev.newton_max;
   timed(ctx, K_THERMO, st, [&] {
     if (sur) {
-      const unsigned nbs = (unsigned)std::min<long>((n + 255) / 256, 2048);
-      k_mlp_eval<2, false><<<nbs, 256, 0, st>>>(ctx->dev, ctx->norm_dev, n, rho, e, Y, nullptr,
-                                               ctx->ys, ctx->wsw, ctx->bias);
-      k_thermo_eval<double, true><<<blocks_for(n, 128), 128, 0, st>>>(
-          n, ctx->dev.newton_rtol, ctx->dev.newton_max, rho, e, Y, T, p, h, mu, kappa, D, status,
-          ctx->counters, ctx->ys);
+      // the network's outputs for each chunk go through the workspace (no allocation)
+      for (int64_t off = 0; off < n; off += ctx->ys_cap) {
+        const int64_t m = std::min<int64_t>(ctx->ys_cap, n - off);
+        auto at = [&](auto* a) { return a ? a + off : a; };
+        const unsigned nbs = (unsigned)std::min<long>((m + 255) / 256, 2048);
+        k_mlp_eval<2, false><<<nbs, 256, 0, st>>>(ctx->dev, ctx->norm_dev, m, n, rho + off,
+                                                 e + off, Y + off, nullptr, ctx->ys, ctx->wsw,
+                                                 ctx->bias);
+        k_thermo_eval<double, true><<<blocks_for(m, 128), 128, 0, st>>>(
+            m, n, rt, mi, rho + off, e + off, Y + off, T + off, at(p), at(h), at(mu), at(kappa),
+            at(D), at(status), ctx->counters, ctx->ys);
+      }
     } else if (mixed)
       k_thermo_eval<float><<<blocks_for(n, 128), 128, 0, st>>>(
-          n, ctx->dev.newton_rtol, ctx->dev.newton_max, rho, e, Y, T, p, h, mu, kappa, D, status,
-          ctx->counters, nullptr);
+          n, n, rt, mi, rho, e, Y, T, p, h, mu, kappa, D, status, ctx->counters, nullptr);
     else
       k_thermo_eval<double><<<blocks_for(n, 128), 128, 0, st>>>(
-          n, ctx->dev.newton_rtol, ctx->dev.newton_max, rho, e, Y, T, p, h, mu, kappa, D, status,
-          ctx->counters, nullptr);
+          n, n, rt, mi, rho, e, Y, T, p, h, mu, kappa, D, status, ctx->counters, nullptr);
   });
   return check(hipGetLastError());
 }
@@ -2695,7 +2895,7 @@ int hrx_timing_read(hrx_ctx* ctx, double* ms, int64_t* launches) {
 
 int hrx_get_counters(hrx_ctx* ctx, hrx_counters* out, int reset) {
   if (!ctx || !out) return HRX_EINVAL;
-  unsigned long long h[4] = {0, 0, 0, 0};
+  unsigned long long h[NCOUNT] = {0};
   int rc = check(hipStreamSynchronize(ctx->last_stream));
   if (rc) return rc;
   rc = check(hipMemcpy(h, ctx->counters, sizeof(h), hipMemcpyDeviceToHost));
@@ -2703,8 +2903,14 @@ int hrx_get_counters(hrx_ctx* ctx, hrx_counters* out, int reset) {
   out->newton_nonconverged = (int64_t)h[0];
   out->energy_below_min = (int64_t)h[1];
   out->surrogate_fallbacks = (int64_t)h[2];
+  out->nonfinite = (int64_t)h[3];
+  out->negative_density = (int64_t)h[4];
   if (reset) rc = check(hipMemset(ctx->counters, 0, sizeof(h)));
-  return rc;
+  if (rc) return rc;
+  if (h[3]) return HRX_ENONFINITE;
+  if (h[1]) return HRX_EDOMAIN;
+  if (h[0]) return HRX_ENEWTON;
+  return HRX_OK;
 }
 
 }  // extern "C"
@@ -2818,7 +3024,7 @@ int hrx_set_thermo_mode(hrx_ctx* ctx, int mode) {
   // the network yields the averaged coefficients of Eq. (19), not the binary ones
   if (ctx->dev.sm) return HRX_EUNSUP;
   if (!ctx->mlp_params || !ctx->mlp_norm) return HRX_EINVAL;
-  const int rc = ensure_ys(ctx, ctx->dev.N);
+  const int rc = ensure_ys(ctx, std::max<int64_t>(ctx->dev.N, THERMO_CHUNK));
   if (rc) return rc;
   ctx->thermo_mode = mode;
   return HRX_OK;

@@ -17,12 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libhrx.so")
 
 GAS_CPG, GAS_AIR5 = 0, 1
 WALL_ADIABATIC, WALL_ISOTHERMAL = 0, 1
-RK3_2N, RK45_2N = 0, 1
+RK3_2N, RK45_2N, SSPRK3 = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 THERMO_PLAIN, THERMO_SURROGATE = 0, 1
 MLP_NPARAM = 9352
 
 HRX_OK = 0
+# per-point failures reported by hrx_get_counters (not raised by counters())
+HRX_ENEWTON, HRX_EDOMAIN, HRX_ENONFINITE = -5, -6, -7
 
 
 class HrxError(RuntimeError):
@@ -55,7 +57,8 @@ class Reference(C.Structure):
 
 class Counters(C.Structure):
     _fields_ = [("newton_nonconverged", C.c_int64), ("energy_below_min", C.c_int64),
-                ("surrogate_fallbacks", C.c_int64)]
+                ("surrogate_fallbacks", C.c_int64), ("nonfinite", C.c_int64),
+                ("negative_density", C.c_int64)]
 
 
 _lib = None
@@ -78,7 +81,7 @@ def load(path: str = LIB_PATH):
     lib.hrx_get_reference.restype = C.c_int
     lib.hrx_rhs_eval.argtypes = [vp, dp, dp, dp, vp]
     lib.hrx_rhs_eval.restype = C.c_int
-    lib.hrx_rk_stage.argtypes = [vp, C.c_int, C.c_double, dp, dp, dp, vp]
+    lib.hrx_rk_stage.argtypes = [vp, C.c_int, C.c_double, dp, dp, dp, dp, vp]
     lib.hrx_rk_stage.restype = C.c_int
     lib.hrx_thermo_eval.argtypes = [vp, i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
     lib.hrx_thermo_eval.restype = C.c_int
@@ -138,7 +141,7 @@ def _stream(stream):
 class Context:
     """Owns one hrx_ctx.  Built from a workload description (fields.FlowConfig)."""
 
-    def __init__(self, cfg, x, y, z=None, hold=None, precision=PREC_FP64):
+    def __init__(self, cfg, x, y, z=None, hold=None, precision=PREC_FP64, newton_max_iter=0):
         lib = load()
         self._keep = []
         c = _Config()
@@ -168,7 +171,7 @@ class Context:
             c.n_hold = len(h)
         else:
             c.hold, c.n_hold = None, 0
-        c.newton_max_iter, c.newton_rtol = 0, 0.0
+        c.newton_max_iter, c.newton_rtol = int(newton_max_iter), 0.0
         c.diffusion = getattr(cfg, "diffusion", 0)
         h = C.c_void_p()
         _check(lib.hrx_create(C.byref(c), C.byref(h)))
@@ -194,9 +197,15 @@ class Context:
         return {n: getattr(r, n) for n, _ in Reference._fields_}
 
     def counters(self, reset=False):
+        """Counter values, plus 'status': the failure code hrx_get_counters returned
+        (HRX_OK, HRX_ENEWTON, HRX_EDOMAIN or HRX_ENONFINITE)."""
         c = Counters()
-        _check(_lib.hrx_get_counters(self._h, C.byref(c), 1 if reset else 0))
-        return {n: getattr(c, n) for n, _ in Counters._fields_}
+        rc = _lib.hrx_get_counters(self._h, C.byref(c), 1 if reset else 0)
+        if rc not in (HRX_OK, HRX_ENEWTON, HRX_EDOMAIN, HRX_ENONFINITE):
+            _check(rc)
+        out = {n: getattr(c, n) for n, _ in Counters._fields_}
+        out["status"] = rc
+        return out
 
 
 KERNEL_NAMES = ("prim", "ad_src", "ad_d4", "ad_filter_x", "ad_filter_y", "ad_filter_z", "flux",
@@ -220,9 +229,10 @@ def rhs_eval(ctx, Q, Q_ref, R, stream=None):
     _check(_lib.hrx_rhs_eval(ctx._h, _ptr(Q), _ptr(Q_ref), _ptr(R), _stream(stream)))
 
 
-def rk_stage(ctx, stage, dt, Q, dQ, Q_ref, stream=None):
+def rk_stage(ctx, stage, dt, Q, dQ, Q_ref, stream=None, R=None):
+    """One RK stage; R (optional) is a precomputed right-hand side (unfused stage)."""
     _check(_lib.hrx_rk_stage(ctx._h, int(stage), float(dt), _ptr(Q), _ptr(dQ), _ptr(Q_ref),
-                             _stream(stream)))
+                             _ptr(R), _stream(stream)))
 
 
 def thermo_eval(ctx, n, rho, e, Y, T, p=None, h=None, mu=None, kappa=None, D=None, status=None,

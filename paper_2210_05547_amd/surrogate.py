@@ -24,7 +24,7 @@ def training_set(ctx, n, seed, device="cuda:0"):
     rho, _, Y, e = fields.air_states(n, seed, T_RANGE, LOGRHO_RANGE)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
     rd, ed, Yd = d(rho), d(e), d(Y)
-    T = torch.empty(n, dtype=torch.float64, device=device)
+    T = torch.zeros(n, dtype=torch.float64, device=device)   # cold start
     mu, ka = torch.empty_like(T), torch.empty_like(T)
     D = torch.empty((5, n), dtype=torch.float64, device=device)
     f = torch.empty((n, 7), dtype=torch.float32, device=device)

@@ -144,7 +144,7 @@ def test_mixed_pointwise():
     n = 30000
     rho, T0, Y, _ = fields.thermo_states(n, seed=21)
     e = oth.mixture_e(T0, Y)
-    T = torch.empty(n, dtype=torch.float64, device=DEV)
+    T = torch.zeros(n, dtype=torch.float64, device=DEV)   # no temperature guess: cold start
     mu = torch.empty_like(T)
     kap = torch.empty_like(T)
     D = torch.empty((5, n), dtype=torch.float64, device=DEV)

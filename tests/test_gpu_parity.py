@@ -48,7 +48,7 @@ def test_thermo_eval_parity(n):
     rho, T0, Y = rho[:n], T0[:n], Y[:, :n].copy()
     e = oth.mixture_e(T0, Y)                   # an energy the oracle maps back to T0
     d = {k: dev(v) for k, v in dict(rho=rho, e=e, Y=Y).items()}
-    out = dict(T=torch.empty(n, dtype=torch.float64, device=DEV),
+    out = dict(T=torch.zeros(n, dtype=torch.float64, device=DEV),   # cold start
                p=torch.empty(n, dtype=torch.float64, device=DEV),
                h=torch.empty((5, n), dtype=torch.float64, device=DEV),
                mu=torch.empty(n, dtype=torch.float64, device=DEV),
@@ -80,7 +80,7 @@ def test_thermo_eval_domain_status_and_counters():
     Y = np.tile(np.array([[0.7], [0.2], [0.05], [0.03], [0.02]]), (1, 4))
     e = oth.mixture_e(np.array([30.0, 300.0, 40.0, 3000.0]), Y)
     rho = np.ones(4)
-    T = torch.empty(4, dtype=torch.float64, device=DEV)
+    T = torch.zeros(4, dtype=torch.float64, device=DEV)
     st = torch.empty(4, dtype=torch.int32, device=DEV)
     hrx.thermo_eval(ctx, 4, dev(rho), dev(e), dev(Y), T, status=st)
     c = ctx.counters(reset=True)

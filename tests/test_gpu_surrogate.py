@@ -142,7 +142,7 @@ def test_network_matches_oracle_network(trained):
 def _thermo(ctx, raw, sel):
     n = len(raw["rho"][sel])
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)  # noqa: E731
-    T = torch.empty(n, dtype=torch.float64, device=DEV)
+    T = torch.zeros(n, dtype=torch.float64, device=DEV)   # no temperature guess: cold start
     mu, ka = torch.empty_like(T), torch.empty_like(T)
     D = torch.empty((5, n), dtype=torch.float64, device=DEV)
     st = torch.empty(n, dtype=torch.int32, device=DEV)
@@ -276,7 +276,7 @@ def test_surrogate_gain_measured(trained):
     ctx = trained["ctx"]
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)  # noqa: E731
     rd, ed, Yd = d(rho), d(e), d(Y)
-    T = torch.empty(n, dtype=torch.float64, device=DEV)
+    T = torch.zeros(n, dtype=torch.float64, device=DEV)   # no temperature guess: cold start
     p, mu, ka = torch.empty_like(T), torch.empty_like(T), torch.empty_like(T)
     h = torch.empty((5, n), dtype=torch.float64, device=DEV)
     D = torch.empty((5, n), dtype=torch.float64, device=DEV)
@@ -284,11 +284,13 @@ def test_surrogate_gain_measured(trained):
     for mode in (hrx.THERMO_PLAIN, hrx.THERMO_SURROGATE):
         hrx.set_thermo_mode(ctx, mode)
         for _ in range(2):
+            T.zero_()
             hrx.thermo_eval(ctx, n, rd, ed, Yd, T, p, h, mu, ka, D)
         ctx.counters(reset=True)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(10):
+            T.zero_()                          # every call starts its inversion cold
             hrx.thermo_eval(ctx, n, rd, ed, Yd, T, p, h, mu, ka, D)
         b.record()
         torch.cuda.synchronize()
