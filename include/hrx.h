@@ -48,7 +48,9 @@ typedef enum {
    * asynchronous compute calls themselves */
   HRX_ENEWTON = -5,   /* the energy inversion did not converge at some point */
   HRX_EDOMAIN = -6,   /* some energy lay below e(50 K), outside the inversion's domain */
-  HRX_ENONFINITE = -7 /* some state held a non-finite value or a non-positive density */
+  HRX_ENONFINITE = -7, /* some state held a non-finite value or a non-positive density */
+  HRX_ETOOBIG = -8     /* the problem does not fit the static workspace of
+                          hrx_rhs_eval_noalloc */
 } hrx_status;
 
 enum { HRX_GAS_CPG = 0, HRX_GAS_AIR5 = 1, HRX_GAS_TPG = 2 };
@@ -134,6 +136,23 @@ int hrx_get_reference(const hrx_ctx *ctx, hrx_reference *out /* (host) */);
  * rows.  R must not alias Q. */
 int hrx_rhs_eval(hrx_ctx *ctx, const double *Q, const double *Q_ref, double *R,
                  void *hip_stream);
+
+/* hrx_rhs_eval for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same right-hand
+ * side, with the scratch planes taken from a static device workspace of
+ * HRX_NOALLOC_MAX_BYTES that the library holds on every GPU it runs on (from its first
+ * hrx_create there until the process ends) instead of the context's.  The call itself
+ * allocates and frees nothing.  Inputs and outputs as in hrx_rhs_eval; the energy
+ * inversion starts cold.  The scratch of one call is 8 N (nWd + nF) + s N (nWp + 2 nad)
+ * bytes (each part rounded up to 256; s = 8, or 4 in the mixed form): about 336 B per
+ * point for 2-D 5-species air without artificial diffusivity, 500 B with it.
+ * Returns HRX_ETOOBIG when that exceeds HRX_NOALLOC_MAX_BYTES (nothing runs),
+ * HRX_EUNSUP in the surrogate form, HRX_EHIP if the workspace's address could not be
+ * obtained.  Every call on one GPU uses the same workspace: calls that overlap on one GPU
+ * (other streams, other threads, other contexts) race. */
+#define HRX_NOALLOC_MAX_BYTES (64u << 20)
+int hrx_rhs_eval_noalloc(hrx_ctx *ctx, const double *Q, const double *Q_ref, double *R,
+                         void *hip_stream);
 
 /* One explicit Runge-Kutta stage k = stage mod (number of stages of the scheme), Sec. 3.1
  * (two-register low-storage RK3 and RK4, three-register TVD RK3), then the wall-row

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -2113,6 +2114,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // ====================================================================== host side
 using namespace hrx;
 
+// Static device workspace of hrx_rhs_eval_noalloc: the scratch planes of one right-hand
+// side (pointwise state, transport, artificial-diffusivity and flux planes) for callers
+// that cannot allocate.  Every GPU the library runs on holds its own copy for the life
+// of the process; calls on one GPU share it, so calls that overlap on one GPU race.
+constexpr size_t NOALLOC_BYTES = (size_t)HRX_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+void* g_scratch[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+// Device address of the current device's copy of scratch (the host-side name is only a
+// stand-in): looked up once per device, with that device current.
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return HRX_EUNSUP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HRX_EHIP;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return HRX_OK;
+}
+}  // namespace
+
 struct hrx_ctx {
   hrx_config cfg;
   Dev dev;
@@ -2123,6 +2151,7 @@ struct hrx_ctx {
   int nWd = 0, nWp = 0;
   size_t rt_size = sizeof(double);
   double *metrics = nullptr;   // mx, my, mz, sx, sy, dlx, dly, dlz
+  void* noalloc = nullptr;     // this device's copy of the static workspace (see scratch)
   unsigned char *hold = nullptr;
   unsigned long long *counters = nullptr;
   bool small_grid = false;   // at most two wavefronts per SIMD at one thread per point
@@ -2276,6 +2305,8 @@ const char* hrx_strerror(int code) {
     case HRX_ENEWTON: return "the energy inversion did not converge at some point";
     case HRX_EDOMAIN: return "an energy below e(50 K) at some point";
     case HRX_ENONFINITE: return "a non-finite state or a non-positive density at some point";
+    case HRX_ETOOBIG:
+      return "the problem's scratch exceeds the static workspace of hrx_rhs_eval_noalloc";
     default: return "unknown error";
   }
 }
@@ -2533,6 +2564,9 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     if ((rc = check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev))))
       return fail(rc);
     ctx->small_grid = (long)N <= 2L * 64 * 4 * ncu;   // 4 SIMDs per compute unit
+    // the static workspace of hrx_rhs_eval_noalloc on this device (looked up once per
+    // device; a failure only disables that entry point)
+    if (scratch_address(dev, &ctx->noalloc) != HRX_OK) ctx->noalloc = nullptr;
   }
   // zeroed temperature plane: the first energy inversion starts cold
   if ((rc = check(hipMemset(ctx->Wd, 0, sizeof(double) * N * ctx->nWd)))) return fail(rc);
@@ -2755,6 +2789,46 @@ int hrx_rhs_eval(hrx_ctx* ctx, const double* Q, const double* Q_ref, double* R,
   hipStream_t st = (hipStream_t)hip_stream;
   ctx->last_stream = st;
   return dispatch(ctx, MODE_RHS, Q, Q_ref, R, nullptr, nullptr, 0.0, 0.0, 0.0, RKF_2N, st);
+}
+
+int hrx_rhs_eval_noalloc(hrx_ctx* ctx, const double* Q, const double* Q_ref, double* R,
+                         void* hip_stream) {
+  if (!ctx || !Q || !R || R == Q) return HRX_EINVAL;
+  // the surrogate form's network outputs are not part of the static layout
+  if (ctx->thermo_mode == HRX_THERMO_SURROGATE) return HRX_EUNSUP;
+  if (!ctx->noalloc) return HRX_EHIP;
+  const Dev& d = ctx->dev;
+  const size_t N = (size_t)d.N;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t bWd = al(sizeof(double) * N * ctx->nWd);
+  const size_t bWp = al(ctx->rt_size * N * ctx->nWp);
+  const size_t bF = al(sizeof(double) * N * ctx->nF);
+  const size_t bAD = d.ad_on ? al(ctx->rt_size * N * d.nad * 2) : 0;
+  if (bWd + bWp + bF + bAD > NOALLOC_BYTES) return HRX_ETOOBIG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  // The launches of this call take the static workspace in place of the context's
+  // scratch (the pointers are passed to the kernels by value at launch); the energy
+  // inversion starts cold, since the workspace holds whatever the last call left.
+  unsigned char* base = static_cast<unsigned char*>(ctx->noalloc);
+  double* const Wd0 = ctx->Wd;
+  void* const Wp0 = ctx->Wp;
+  double* const F0 = ctx->F;
+  void* const AD0 = ctx->AD;
+  const Dev dev0 = ctx->dev;
+  ctx->Wd = reinterpret_cast<double*>(base);
+  ctx->Wp = base + bWd;
+  ctx->F = reinterpret_cast<double*>(base + bWd + bWp);
+  ctx->AD = bAD ? base + bWd + bWp + bF : nullptr;
+  ctx->dev.ad = ctx->AD;
+  ctx->dev.warm = 0;
+  const int rc = dispatch(ctx, MODE_RHS, Q, Q_ref, R, nullptr, nullptr, 0.0, 0.0, 0.0, RKF_2N, st);
+  ctx->Wd = Wd0;
+  ctx->Wp = Wp0;
+  ctx->F = F0;
+  ctx->AD = AD0;
+  ctx->dev = dev0;
+  return rc;
 }
 
 int hrx_rk_stage(hrx_ctx* ctx, int stage, double dt, double* Q, double* dQ, const double* Q_ref,

@@ -25,10 +25,16 @@ MLP_NPARAM = 9352
 HRX_OK = 0
 # per-point failures reported by hrx_get_counters (not raised by counters())
 HRX_ENEWTON, HRX_EDOMAIN, HRX_ENONFINITE = -5, -6, -7
+HRX_ETOOBIG = -8
+NOALLOC_MAX_BYTES = 64 << 20     # HRX_NOALLOC_MAX_BYTES
 
 
 class HrxError(RuntimeError):
-    pass
+    """A call returned a negative hrx_status (in .code)."""
+
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
 
 
 class _Config(C.Structure):
@@ -81,6 +87,8 @@ def load(path: str = LIB_PATH):
     lib.hrx_get_reference.restype = C.c_int
     lib.hrx_rhs_eval.argtypes = [vp, dp, dp, dp, vp]
     lib.hrx_rhs_eval.restype = C.c_int
+    lib.hrx_rhs_eval_noalloc.argtypes = [vp, dp, dp, dp, vp]
+    lib.hrx_rhs_eval_noalloc.restype = C.c_int
     lib.hrx_rk_stage.argtypes = [vp, C.c_int, C.c_double, dp, dp, dp, dp, vp]
     lib.hrx_rk_stage.restype = C.c_int
     lib.hrx_thermo_eval.argtypes = [vp, i64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
@@ -119,7 +127,7 @@ def load(path: str = LIB_PATH):
 
 def _check(rc):
     if rc != HRX_OK:
-        raise HrxError(f"hrx error {rc}: {_lib.hrx_strerror(rc).decode()}")
+        raise HrxError(f"hrx error {rc}: {_lib.hrx_strerror(rc).decode()}", rc)
 
 
 def _ptr(t):
@@ -227,6 +235,11 @@ def timing_read(ctx):
 
 def rhs_eval(ctx, Q, Q_ref, R, stream=None):
     _check(_lib.hrx_rhs_eval(ctx._h, _ptr(Q), _ptr(Q_ref), _ptr(R), _stream(stream)))
+
+
+def rhs_eval_noalloc(ctx, Q, Q_ref, R, stream=None):
+    """hrx_rhs_eval_noalloc: the right-hand side with the library's static workspace."""
+    _check(_lib.hrx_rhs_eval_noalloc(ctx._h, _ptr(Q), _ptr(Q_ref), _ptr(R), _stream(stream)))
 
 
 def rk_stage(ctx, stage, dt, Q, dQ, Q_ref, stream=None, R=None):
