@@ -59,6 +59,7 @@ enum { HRX_RK3_2N = 0, HRX_RK45_2N = 1, HRX_SSPRK3 = 2 };
 enum { HRX_PREC_FP64 = 0, HRX_PREC_MIXED = 1 };
 enum { HRX_THERMO_PLAIN = 0, HRX_THERMO_SURROGATE = 1 };
 enum { HRX_DIFF_RAMSHAW = 0, HRX_DIFF_STEFAN_MAXWELL = 1 };
+enum { HRX_FD_EXPLICIT = 0, HRX_FD_COMPACT = 1 };
 
 /* Workload description (host).  Sec. 2.1 (reference scales, Eq. 7 and 11), Sec. 3.2
  * (sponges, wall), Sec. 3.3 (artificial diffusivity), Sec. 4 (case parameters). */
@@ -68,7 +69,7 @@ typedef struct hrx_config {
   int nx, ny, nz;           /* grid points; nz = 1 for a 2-D problem; nx, ny >= 8 */
   const double *x, *y, *z;  /* (host) separable coordinates, nondimensional; x, y
                                non-periodic, z uniform and periodic (may be NULL if nz = 1) */
-  int fd_order;             /* 4 or 6: explicit central differences, one-sided ends */
+  int fd_order;             /* 4 or 6: the order of the first derivatives (fd_scheme) */
   int rk_scheme;            /* HRX_RK3_2N (Williamson), HRX_RK45_2N (Carpenter-Kennedy) or
                                HRX_SSPRK3 (the three-register TVD RK3 of Shu and Osher) */
   int precision;            /* HRX_PREC_FP64, or HRX_PREC_MIXED: FP64 conserved state, RK
@@ -101,6 +102,15 @@ typedef struct hrx_config {
                                system of Eq. (17) solved per point (5-species air, else
                                HRX_EUNSUP; artificial diffusivities add a flux of the
                                form of Eq. 18) */
+  int fd_scheme;            /* first derivatives of the gradients and the divergence
+                               (Sec. 3.1): HRX_FD_EXPLICIT, central differences of order
+                               fd_order with one-sided 4th-order ends; HRX_FD_COMPACT,
+                               collocated compact (Pade) tridiagonal schemes of order
+                               fd_order (6: 6th-order interior, 4th-order Pade next to
+                               the ends; 4: Pade) with 3rd-order one-sided compact end
+                               rows, cyclic in z; nx <= 2048 (else HRX_EUNSUP).  The
+                               fourth differences and filters of the artificial
+                               diffusivity are explicit in both. */
 } hrx_config;
 
 typedef struct hrx_ctx hrx_ctx;
@@ -262,11 +272,12 @@ int hrx_mlp_train_step(hrx_ctx *ctx, int64_t n, const int32_t *idx, const float 
  * 2), 5 ad_filter_z, 6 flux, 7 div, 8 bc (3-D; in 2-D the wall condition runs
  * inside div), 9 thermo_eval,
  * 10 chem_source (in the surrogate form the network pass is counted with prim and
- * thermo_eval).
+ * thermo_eval), 11 the compact scheme's line solves (gradients and divergence), 12 the
+ * compact scheme's pointwise pass (sources, sponge, boundary rows, update).
  * hrx_timing_read synchronises, returns the summed milliseconds and launch counts
  * per kernel since enabling (arrays of HRX_NKERNELS, host) and keeps timing on.
  * hrx_timing_enable(ctx, 0) stops and releases the events. */
-#define HRX_NKERNELS 11
+#define HRX_NKERNELS 13
 int hrx_timing_enable(hrx_ctx *ctx, int on);
 int hrx_timing_read(hrx_ctx *ctx, double *ms /* (host) */, int64_t *launches /* (host) */);
 

@@ -30,6 +30,7 @@ Readings (where the paper is silent or garbled):
 """
 import numpy as np
 
+from . import compact as cp
 from . import species as sp
 from . import stencils as st
 from . import thermo
@@ -71,7 +72,10 @@ class Case:
         self.nvar = self.ns + self.ndim + 1
         self.x, self.y, self.z = np.asarray(x), np.asarray(y), np.asarray(z)
         o = cfg.fd_order
-        self.m = [st.metric(self.x, o), st.metric(self.y, o)]
+        # first derivatives: explicit stencils (module stencils) or compact (module compact)
+        self.compact = getattr(cfg, "fd_scheme", 0) == 1
+        met = cp.metric if self.compact else st.metric
+        self.m = [met(self.x, o), met(self.y, o)]
         if self.ndim == 3:
             self.m.append(st.metric_periodic(self.z))
         self.sigma = self._sponge()
@@ -104,7 +108,8 @@ class Case:
     def deriv(self, f, d):
         """Physical first derivative along direction d (0: x, 1: y, 2: z)."""
         ax = self.axis(d)
-        Df = st.first_derivative(f, ax, self.cfg.fd_order, periodic=(d == 2))
+        op = cp.first_derivative if self.compact else st.first_derivative
+        Df = op(f, ax, self.cfg.fd_order, periodic=(d == 2))
         sh = [1, 1, 1]
         sh[ax] = len(self.m[d])
         return Df * self.m[d].reshape(sh)

@@ -66,6 +66,13 @@ __device__ __forceinline__ void rk_update(int rkf, double A, double B, double dt
   }
 }
 
+// LU factors of one direction's compact-derivative matrix (see k_cd_x, k_cd_col)
+struct CLine {
+  const double *lo, *up, *iu;   // [n] LU factors (A' for the periodic direction)
+  const double* q;              // [n] periodic: A'^-1 u
+  double s, alpha;              // periodic: 1/(1 + v.q) and the off-diagonal alpha
+};
+
 struct Dev {
   int nx, ny, nz, ndim, nvar, ns, fd_order;
   long N;
@@ -97,6 +104,8 @@ struct Dev {
   int tgx, tgy;                   // 2-D LDS tiles per row / column
   int tgz;                        // 3-D (x, z) tiles along z
   int warm;                       // W holds a previous temperature field (Newton warm start)
+  int compact;                    // compact first derivatives (gradients from planes)
+  CLine cl[3];                    // compact factors of the x, y, z lines
   void* ad;                       // artificial-diffusivity source planes (RT), or null
 };
 
@@ -519,7 +528,8 @@ __device__ __forceinline__ void prim_air5(const Dev& d, double* __restrict__ Wd,
 #pragma unroll
   for (int a = 0; a < ND; ++a) Wd[a * N + idx] = u[a];
   Wd[ND * N + idx] = T;
-  if (ND == 3) {
+  if (ND == 3 || d.compact) {
+    // the 3-D flux and the compact line solves read X_s and p from planes
 #pragma unroll
     for (int s = 0; s < NS; ++s) Wd[(ND + 1 + s) * N + idx] = X[s];
     Wd[d.w_p * N + idx] = p;
@@ -951,14 +961,17 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
 // ------------------------------------------------------------------ k_flux
 // F planes (double): F[j][k] for direction j and conserved component k.  Convective
 // fluxes are formed in FP64; stresses, heat and diffusion fluxes in RT.
-template <int GAS, int ND, int ORDER, bool AD, class RT, bool SM>
+// CG: the gradients come from planes Gc[b][a] (direction b, source a; the compact
+// scheme's line solves), one thread per point, no tile.
+template <int GAS, int ND, int ORDER, bool AD, class RT, bool SM, bool CG = false>
 __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict__ Q,
                                           const double* __restrict__ Wd,
                                           const RT* __restrict__ Wp,
-                                          const RT* __restrict__ Gad, double* __restrict__ F) {
+                                          const RT* __restrict__ Gad, double* __restrict__ F,
+                                          const double* __restrict__ Gc = nullptr) {
   constexpr int ns = (GAS == AIR5) ? NS : 1;
   constexpr int nvar = ns + ND + 1;
-  constexpr bool XQ = GAS == AIR5 && ND == 2;   // X_s and p formed here from Q
+  constexpr bool XQ = GAS == AIR5 && ND == 2 && !CG;   // X_s and p formed here from Q
   constexpr int NSRC = ND + 1 + (GAS == AIR5 ? NS : 0);   // u, v, (w), T, (X_s)
   // mole-fraction derivatives formed per flux direction (fewer live registers) where the
   // kernel is register bound: with artificial diffusivity and in 3-D (measured)
@@ -967,9 +980,13 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
   extern __shared__ double smem[];
   const long N = d.N;
   Pt p;
-  long sidx;                // index of the point in the LDS tile
+  long sidx = 0;            // index of the point in the LDS tile
   Sten sd[3];
-  {
+  if constexpr (CG) {
+    const long gi = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= N) return;
+    p = point_of(d, gi);
+  } else {
     // 2-D: tile in (x, y); 3-D: tile in (x, z) at row j0, y differences from memory
     int i0, j0, k0 = 0;
     if (ND == 2) tile_origin(d, i0, j0);
@@ -1036,6 +1053,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
   constexpr int NPI = ORDER == 6 ? 3 : 2;
   // derivative of source plane a along direction b (z is periodic: central pairs only)
   auto deriv = [&](int a, int b) -> RT {
+    if constexpr (CG) return RT(Gc[((long)b * NSRC + a) * N + idx]);
     if (ND == 3 && b == 1) return sten_apply<RT>(sd[1], Wd + (long)a * N + idx) * md[1];
     const double* f = smem + a * TILE_E;
     if (b == 2) return sten_apply<RT, NPI>(sd[b], f) * md[b];
@@ -1141,7 +1159,8 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
         iDm[r][s] = v;
       }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) Xp[s] = RT(smem[(ND + 1 + s) * TILE_E + sidx]);
+    for (int s = 0; s < NS; ++s)
+      Xp[s] = RT(CG ? Wd[(ND + 1 + s) * N + idx] : smem[(ND + 1 + s) * TILE_E + sidx]);
     RT A[NS][NS], Bm[NS][3], csum = RT(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -1286,6 +1305,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     Dev d, const double* __restrict__ Q, const double* __restrict__ Wd,
     const RT* __restrict__ Wp, const RT* __restrict__ Gad, double* __restrict__ F) {
   flux_tile<GAS, ND, ORDER, AD, RT, SM>(d, Q, Wd, Wp, Gad, F);
+}
+
+// The flux of the compact scheme: gradients from the line solves' planes.
+template <int GAS, int ND, bool AD, class RT, bool SM = false>
+__global__ __launch_bounds__(256) void k_flux_c(Dev d, const double* __restrict__ Q,
+                                                const double* __restrict__ Wd,
+                                                const RT* __restrict__ Wp,
+                                                const RT* __restrict__ Gad,
+                                                double* __restrict__ F,
+                                                const double* __restrict__ Gc) {
+  flux_tile<GAS, ND, 6, AD, RT, SM, true>(d, Q, Wd, Wp, Gad, F, Gc);
 }
 
 // ------------------------------------------------------------------ k_bc (wall row)
@@ -1605,6 +1635,243 @@ __global__ __launch_bounds__(256) void k_rk_update(long N, int nvar, const doubl
     rk_update(rkf, A, B, dt, R[o], q, dq, qn, dqn, wdq);
     if (wdq) dQ[o] = dqn;
     Q[o] = qn;
+  }
+}
+
+// ------------------------------------------------------------------ compact derivatives
+// Collocated compact (Pade) first derivatives (Sec. 3.1 reading: the tridiagonal
+// schemes of Lele's family).  Along a line of n points, A f' = r(f) with r formed from
+// differences (unit spacing):
+//   sixth-order interior rows (2 <= i <= n-3):  7/9 (f+1 - f-1) + 1/36 (f+2 - f-2)
+//                                               A row (1/3, 1, 1/3)
+//   Pade rows (the fourth-order interior; points 1, n-2 of the sixth-order scheme):
+//                                               3/4 (f+1 - f-1),  A row (1/4, 1, 1/4)
+//   end point 0:    2 (f1 - f0) + 1/2 (f2 - f0),             A row (1, 2)
+//   end point n-1:  -(2 (f_{n-2} - f_{n-1}) + 1/2 (f_{n-3} - f_{n-1})), A row (2, 1)
+//   periodic:       the interior row at every point, indices wrapped.
+// The LU factors of A are the same for every line of a direction; the host forms them
+// once: multipliers lo_i (L unit lower), U with super-diagonal up_i and reciprocal
+// pivots iu_i.  Forward d_i = r_i - lo_i d_{i-1}; backward x_i = (d_i - up_i x_{i+1}) iu_i.
+// The periodic direction solves the cyclic system by Sherman-Morrison: A = A' + u v^T,
+// A' tridiagonal with corners (2, 1 + alpha^2), u = (-1, 0.., alpha), v = (1, 0.., -alpha);
+// x = y - s (y_0 - alpha y_{n-1}) q with A' y = r, A' q = u, s = 1/(1 + v.q).
+// (struct CLine: see above Dev)
+
+
+// Right-hand side of row i from the values w[0..4] = f_{i-2} .. f_{i+2} (entries outside
+// a non-periodic line are never read).
+__device__ __forceinline__ double crow(const double* w, int i, int n, int order, bool per) {
+  if (!per) {
+    if (i == 0) return 2.0 * (w[3] - w[2]) + 0.5 * (w[4] - w[2]);
+    if (i == n - 1) return -(2.0 * (w[1] - w[2]) + 0.5 * (w[0] - w[2]));
+  }
+  const bool six = order == 6 && (per || (i >= 2 && i <= n - 3));
+  if (six) return (7.0 / 9.0) * (w[3] - w[1]) + (1.0 / 36.0) * (w[4] - w[0]);
+  return 0.75 * (w[3] - w[1]);
+}
+
+// x lines: one wavefront per line, held in LDS (n <= CX_MAX).  Lane l owns the contiguous
+// chunk [l C, (l + 1) C) of the line; each recurrence (forward, then backward) is a
+// chain of affine maps, composed within the chunk, combined across the wavefront by a
+// scan, then evaluated with the chunk's incoming value.  Planes p = blockIdx.y of f
+// (stride fps) -> out (stride ops): out = scale m D f, or out += scale m D f (ACC).
+constexpr int CX_MAX = 2048;
+template <bool ACC>
+__global__ __launch_bounds__(64) void k_cd_x(int n, const double* __restrict__ f, long fps,
+                                             double* out, long ops, const double* __restrict__ m,
+                                             double scale, int order, CLine L) {
+  extern __shared__ double sm[];
+  double* sf = sm;
+  double* sd = sm + n;
+  const int lane = threadIdx.x;
+  const long line = blockIdx.x;
+  const double* fl = f + (long)blockIdx.y * fps + line * n;
+  double* ol = out + (long)blockIdx.y * ops + line * n;
+  for (int i = lane; i < n; i += 64) sf[i] = fl[i];
+  __syncthreads();
+  const int C = (n + 63) / 64;
+  const int a = min(lane * C, n), b = min(a + C, n);
+  auto rhs = [&](int i) {
+    double w[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int q = i + k - 2;
+      w[k] = (q >= 0 && q < n) ? sf[q] : 0.0;
+    }
+    return crow(w, i, n, order, false);
+  };
+  // forward: d_i = r_i - lo_i d_{i-1}; the chunk maps d_{a-1} to d_{b-1} as A x + B
+  double A = 1.0, B = 0.0;
+  for (int i = a; i < b; ++i) {
+    const double li = L.lo[i];
+    B = rhs(i) - li * B;
+    A = -li * A;
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+    const double Ap = __shfl_up(A, off), Bp = __shfl_up(B, off);
+    if (lane >= off) {
+      B = A * Bp + B;
+      A = A * Ap;
+    }
+  }
+  double prev = __shfl_up(B, 1);
+  if (lane == 0) prev = 0.0;
+  for (int i = a; i < b; ++i) {
+    const double di = rhs(i) - L.lo[i] * prev;
+    sd[i] = di;
+    prev = di;
+  }
+  // backward: x_i = (d_i - up_i x_{i+1}) iu_i; the chunk maps x_b to x_a as A x + B
+  A = 1.0;
+  B = 0.0;
+  for (int i = b - 1; i >= a; --i) {
+    const double iu = L.iu[i], u = L.up[i];
+    B = (sd[i] - u * B) * iu;
+    A = -(u * iu) * A;
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+    const double An = __shfl_down(A, off), Bn = __shfl_down(B, off);
+    if (lane + off < 64) {
+      B = A * Bn + B;
+      A = A * An;
+    }
+  }
+  double next = __shfl_down(B, 1);
+  if (lane == 63) next = 0.0;
+  for (int i = b - 1; i >= a; --i) {
+    const double xi = (sd[i] - L.up[i] * next) * L.iu[i];
+    sf[i] = xi;
+    next = xi;
+  }
+  __syncthreads();
+  for (int i = lane; i < n; i += 64) {
+    const double v = scale * m[i] * sf[i];
+    ol[i] = ACC ? ol[i] + v : v;
+  }
+}
+
+// y or z lines: one thread per line marching along it (threads of a block hold
+// consecutive x columns: every access is coalesced).  Line c = (cx, c2): first point
+// c2 * s2 + cx, n points at stride s.  The forward values go to W (out itself, or a
+// temporary plane when accumulating), the backward sweep turns them into x; the periodic
+// direction ends with the Sherman-Morrison correction.
+template <bool ACC, bool PER>
+__global__ __launch_bounds__(128) void k_cd_col(int n, long s, int ncx, int nc2, long s2,
+                                                const double* __restrict__ f, long fps,
+                                                double* out, long ops, double* W, long wps,
+                                                const double* __restrict__ m, double scale,
+                                                int order, CLine L) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (long)ncx * nc2) return;
+  const long c2 = c / ncx, cx = c - c2 * ncx;
+  const long base = c2 * s2 + cx;
+  const double* fl = f + (long)blockIdx.y * fps + base;
+  double* ol = out + (long)blockIdx.y * ops + base;
+  double* wl = (ACC ? W + (long)blockIdx.y * wps : out + (long)blockIdx.y * ops) + base;
+  auto F = [&](int q) {
+    if (PER) q = q < 0 ? q + n : (q >= n ? q - n : q);
+    return fl[(long)q * s];
+  };
+  double w[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const int q = k - 2;
+    w[k] = (PER || (q >= 0 && q < n)) ? F(q) : 0.0;
+  }
+  double prev = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double di = crow(w, i, n, order, PER) - L.lo[i] * prev;
+    wl[(long)i * s] = di;
+    prev = di;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = w[k + 1];
+    const int q = i + 3;
+    w[4] = (PER || q < n) ? F(q) : 0.0;
+  }
+  double next = 0.0, ylast = 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    const double xi = (wl[(long)i * s] - L.up[i] * next) * L.iu[i];
+    if (i == n - 1) ylast = xi;
+    next = xi;
+    if (PER) {
+      wl[(long)i * s] = xi;
+    } else {
+      const double v = scale * m[i] * xi;
+      ol[(long)i * s] = ACC ? ol[(long)i * s] + v : v;
+    }
+  }
+  if (PER) {
+    const double fac = L.s * (next - L.alpha * ylast);   // next = y_0
+    for (int i = 0; i < n; ++i) {
+      const double xi = wl[(long)i * s] - fac * L.q[i];
+      const double v = scale * m[i] * xi;
+      ol[(long)i * s] = ACC ? ol[(long)i * s] + v : v;
+    }
+  }
+}
+
+// Artificial-diffusivity sources |S| and theta of the compact scheme, pointwise from the
+// velocity-gradient planes Gc[b][a].
+template <int ND, class RT>
+__global__ __launch_bounds__(256) void k_ad_src_c(Dev d, const double* __restrict__ Gc,
+                                                  RT* __restrict__ A) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.N) return;
+  const long N = d.N;
+  RT G[3][3];
+#pragma unroll
+  for (int a = 0; a < ND; ++a)
+#pragma unroll
+    for (int b = 0; b < ND; ++b) G[a][b] = RT(Gc[((long)b * d.nsrc + a) * N + idx]);
+  RT s2 = RT(0);
+#pragma unroll
+  for (int a = 0; a < ND; ++a)
+#pragma unroll
+    for (int b = 0; b < ND; ++b) {
+      const RT sab = RT(0.5) * (G[a][b] + G[b][a]);
+      s2 += sab * sab;
+    }
+  RT theta = RT(0);
+#pragma unroll
+  for (int a = 0; a < ND; ++a) theta += G[a][a];
+  A[0 * N + idx] = sqrt(s2);
+  A[1 * N + idx] = theta;
+}
+
+// The compact scheme's pointwise pass: R = Racc (the divergence, -sum_j D_j F_j) + wdot -
+// sigma (Q - Q_ref), the held rows, then R out or the stage update (the wall row follows
+// in k_bc).
+template <int GAS, int ND, int MODE, class RT>
+__global__ __launch_bounds__(256) void k_fin(Dev d, const RT* __restrict__ Wp, const double* Qin,
+                                             const double* __restrict__ Qref, const double* Racc,
+                                             double* Rout, double* Qio, double* dQio, double A,
+                                             double B, double dt, int rkf) {
+  constexpr int ns = (GAS == AIR5) ? NS : 1;
+  constexpr int nvar = ns + ND + 1;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.N) return;
+  const long N = d.N;
+  const Pt p = point_of(d, idx);
+  const double sig = fmax(d.sx[p.i], d.sy[p.j]);
+  bool held = p.i == 0;
+  if (d.hold && p.j < 3) held = held || d.hold[((long)p.k * 3 + p.j) * d.nx + p.i];
+#pragma unroll
+  for (int k = 0; k < nvar; ++k) {
+    double R = Racc[k * N + idx];
+    if (GAS == AIR5 && k < NS) R = R + double(Wp[(d.w_wdot + k) * N + idx]);
+    const double qv = (MODE == MODE_RK) ? Qio[k * N + idx] : Qin[k * N + idx];
+    if (Qref != nullptr && sig != 0.0) R = R - sig * (qv - Qref[k * N + idx]);
+    if (held || (p.j == 0 && k >= ns && k < ns + ND)) R = 0.0;
+    if (MODE == MODE_RHS) {
+      Rout[k * N + idx] = R;
+    } else {
+      const double dq = rkf == RKF_SSP_FIRST ? 0.0 : dQio[k * N + idx];
+      double qn, dqn;
+      bool wdq;
+      rk_update(rkf, A, B, dt, R, qv, dq, qn, dqn, wdq);
+      if (wdq) dQio[k * N + idx] = dqn;
+      Qio[k * N + idx] = qn;
+    }
   }
 }
 
@@ -2147,6 +2414,8 @@ struct hrx_ctx {
   hrx_reference ref;
   int nF;
   double *Wd = nullptr, *F = nullptr, *R = nullptr;
+  double *G = nullptr, *Ct = nullptr;   // compact scheme: gradient planes, line temporaries
+  double *cmat = nullptr;               // compact scheme: factors of the x, y, z lines
   void *Wp = nullptr, *AD = nullptr;   // RT planes (double, or float in the mixed form)
   int nWd = 0, nWp = 0;
   size_t rt_size = sizeof(double);
@@ -2189,7 +2458,7 @@ struct hrx_ctx {
 namespace {
 
 enum { K_PRIM = 0, K_AD_SRC, K_AD_D4, K_AD_FX, K_AD_FY, K_AD_FZ, K_FLUX, K_DIV, K_BC, K_THERMO,
-       K_CHEM };
+       K_CHEM, K_CDERIV, K_FIN };
 
 constexpr int NCOUNT = 8;   // device counters (see Dev::counters)
 
@@ -2287,6 +2556,81 @@ void host_deriv(const std::vector<double>& f, int order, std::vector<double>& ou
   }
 }
 
+// Host copy of the compact factors of one direction (the device copy goes to cmat).
+struct HostCLine {
+  std::vector<double> lo, up, iu, q;
+  double s = 0.0, alpha = 0.0;
+};
+
+// LU factors of the compact matrix of a line of n points: the non-periodic matrix
+// (end rows (1, 2) and (2, 1), Pade rows (1/4, 1, 1/4), sixth-order rows (1/3, 1, 1/3)),
+// or for a periodic line the tridiagonal part A' of the cyclic matrix, with
+// q = A'^-1 u, s = 1/(1 + v.q) (Sherman-Morrison, u = (-1, 0.., alpha),
+// v = (1, 0.., -alpha)).
+HostCLine compact_factors(int n, int order, bool per) {
+  std::vector<double> sub(n, 0.0), dia(n, 1.0), sup(n, 0.0);
+  HostCLine L;
+  const double a6 = 1.0 / 3.0, a4 = 0.25;
+  if (!per) {
+    for (int i = 0; i < n; ++i) {
+      if (i == 0) sup[i] = 2.0;
+      else if (i == n - 1) sub[i] = 2.0;
+      else if (order == 6 && i >= 2 && i <= n - 3) sub[i] = sup[i] = a6;
+      else sub[i] = sup[i] = a4;
+    }
+  } else {
+    const double al = order == 6 ? a6 : a4;
+    for (int i = 0; i < n; ++i) sub[i] = sup[i] = al;
+    sub[0] = 0.0;
+    sup[n - 1] = 0.0;
+    dia[0] = 2.0;
+    dia[n - 1] = 1.0 + al * al;
+    L.alpha = al;
+  }
+  L.lo.assign(n, 0.0);
+  L.up = sup;
+  L.iu.assign(n, 0.0);
+  double u = dia[0];
+  L.iu[0] = 1.0 / u;
+  for (int i = 1; i < n; ++i) {
+    L.lo[i] = sub[i] / u;
+    u = dia[i] - L.lo[i] * L.up[i - 1];
+    L.iu[i] = 1.0 / u;
+  }
+  if (per) {
+    std::vector<double> r(n, 0.0);
+    r[0] = -1.0;
+    r[n - 1] = L.alpha;
+    L.q.assign(n, 0.0);
+    double prev = 0.0;
+    for (int i = 0; i < n; ++i) { r[i] -= L.lo[i] * prev; prev = r[i]; }
+    double next = 0.0;
+    for (int i = n - 1; i >= 0; --i) { L.q[i] = (r[i] - L.up[i] * next) * L.iu[i]; next = L.q[i]; }
+    L.s = 1.0 / (1.0 + L.q[0] - L.alpha * L.q[n - 1]);
+  }
+  return L;
+}
+
+// Compact first derivative (index space) of a host array on a non-periodic line.
+void host_compact_deriv(const std::vector<double>& f, int order, const HostCLine& L,
+                        std::vector<double>& out) {
+  const int n = (int)f.size();
+  out.assign(n, 0.0);
+  double prev = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double r;
+    if (i == 0) r = 2.0 * (f[1] - f[0]) + 0.5 * (f[2] - f[0]);
+    else if (i == n - 1) r = -(2.0 * (f[n - 2] - f[n - 1]) + 0.5 * (f[n - 3] - f[n - 1]));
+    else if (order == 6 && i >= 2 && i <= n - 3)
+      r = (7.0 / 9.0) * (f[i + 1] - f[i - 1]) + (1.0 / 36.0) * (f[i + 2] - f[i - 2]);
+    else r = 0.75 * (f[i + 1] - f[i - 1]);
+    out[i] = r - L.lo[i] * prev;
+    prev = out[i];
+  }
+  double next = 0.0;
+  for (int i = n - 1; i >= 0; --i) { out[i] = (out[i] - L.up[i] * next) * L.iu[i]; next = out[i]; }
+}
+
 int check(hipError_t e) { return e == hipSuccess ? HRX_OK : HRX_EHIP; }
 
 inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -2326,6 +2670,9 @@ void hrx_destroy(hrx_ctx* c) {
   (void)hipFree(c->R);
   (void)hipFree(c->AD);
   (void)hipFree(c->metrics);
+  (void)hipFree(c->G);
+  (void)hipFree(c->Ct);
+  (void)hipFree(c->cmat);
   (void)hipFree(c->hold);
   (void)hipFree(c->counters);
   (void)hipFree(c->ys);
@@ -2346,6 +2693,8 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   if (c.diffusion == HRX_DIFF_STEFAN_MAXWELL && c.gas != HRX_GAS_AIR5) return HRX_EUNSUP;
   if (c.nx < 8 || c.ny < 8 || c.nz < 1 || (c.nz > 1 && c.nz < 8)) return HRX_EINVAL;
   if (c.fd_order != 4 && c.fd_order != 6) return HRX_EINVAL;
+  if (c.fd_scheme != HRX_FD_EXPLICIT && c.fd_scheme != HRX_FD_COMPACT) return HRX_EINVAL;
+  if (c.fd_scheme == HRX_FD_COMPACT && c.nx > CX_MAX) return HRX_EUNSUP;
   if (c.rk_scheme != HRX_RK3_2N && c.rk_scheme != HRX_RK45_2N && c.rk_scheme != HRX_SSPRK3)
     return HRX_EINVAL;
   if (c.precision != HRX_PREC_FP64 && c.precision != HRX_PREC_MIXED) return HRX_EINVAL;
@@ -2442,8 +2791,19 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   d.ic_inf = 1.0 / d.c_inf;
   // ---------------------------------------------------------- metrics, spacing, sponge
   std::vector<double> x(c.x, c.x + c.nx), y(c.y, c.y + c.ny), Dx, Dy, Dx6, Dy6;
-  host_deriv(x, c.fd_order, Dx);
-  host_deriv(y, c.fd_order, Dy);
+  const bool compact = c.fd_scheme == HRX_FD_COMPACT;
+  HostCLine cl[3];
+  if (compact) {
+    // metrics d(xi)/dx = 1 / (D x) with the compact operator itself
+    cl[0] = compact_factors(c.nx, c.fd_order, false);
+    cl[1] = compact_factors(c.ny, c.fd_order, false);
+    if (c.nz > 1) cl[2] = compact_factors(c.nz, c.fd_order, true);
+    host_compact_deriv(x, c.fd_order, cl[0], Dx);
+    host_compact_deriv(y, c.fd_order, cl[1], Dy);
+  } else {
+    host_deriv(x, c.fd_order, Dx);
+    host_deriv(y, c.fd_order, Dy);
+  }
   host_deriv(x, 6, Dx6);
   host_deriv(y, 6, Dy6);
   const int nz = c.nz;
@@ -2553,6 +2913,31 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
   if (hipMalloc(&ctx->R, sizeof(double) * N * d.nvar) != hipSuccess) return fail(HRX_ENOMEM);
   if (d.ad_on && hipMalloc(&ctx->AD, rts * N * d.nad * 2) != hipSuccess) return fail(HRX_ENOMEM);
   d.ad = ctx->AD;
+  if (compact) {
+    // factors of the three directions: [lo, up, iu] per direction, then q of z
+    const int nzc = c.nz > 1 ? c.nz : 0;
+    std::vector<double> hc;
+    for (int a = 0; a < 3; ++a)
+      for (const std::vector<double>* v : {&cl[a].lo, &cl[a].up, &cl[a].iu})
+        hc.insert(hc.end(), v->begin(), v->end());
+    if (nzc) hc.insert(hc.end(), cl[2].q.begin(), cl[2].q.end());
+    if (hipMalloc(&ctx->cmat, hc.size() * sizeof(double)) != hipSuccess) return fail(HRX_ENOMEM);
+    if ((rc = check(hipMemcpy(ctx->cmat, hc.data(), hc.size() * sizeof(double),
+                              hipMemcpyHostToDevice))))
+      return fail(rc);
+    const double* q = ctx->cmat;
+    for (int a = 0; a < 3; ++a) {
+      const size_t n = cl[a].lo.size();
+      d.cl[a].lo = q; d.cl[a].up = q + n; d.cl[a].iu = q + 2 * n;
+      q += 3 * n;
+      d.cl[a].s = cl[a].s;
+      d.cl[a].alpha = cl[a].alpha;
+    }
+    d.cl[2].q = nzc ? q : nullptr;
+    d.compact = 1;
+    if (hipMalloc(&ctx->G, sizeof(double) * N * nd * d.nsrc) != hipSuccess) return fail(HRX_ENOMEM);
+    if (hipMalloc(&ctx->Ct, sizeof(double) * N * d.nvar) != hipSuccess) return fail(HRX_ENOMEM);
+  }
   if (hipMalloc(&ctx->counters, NCOUNT * sizeof(unsigned long long)) != hipSuccess)
     return fail(HRX_ENOMEM);
   if ((rc = check(hipMemset(ctx->counters, 0, NCOUNT * sizeof(unsigned long long)))))
@@ -2645,16 +3030,15 @@ void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, con
   });
 }
 
-template <int GAS, int ND, int ORDER, class RT>
-int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
+// The pointwise pass (and in the surrogate form the network pass before it)
+template <int GAS, int ND, class RT>
+void launch_prim(hrx_ctx* ctx, const double* Q, hipStream_t st) {
   const Dev& d = ctx->dev;
   const long N = d.N;
   const int bs = 128;
   const unsigned nb = blocks_for(N, bs);
-  const unsigned ng = (unsigned)d.gx * d.ny * d.nz;   // stencil-kernel grid
   double* Wd = ctx->Wd;
   RT* Wp = (RT*)ctx->Wp;
-  double* F = ctx->F;
   if (GAS == AIR5 && ctx->thermo_mode == HRX_THERMO_SURROGATE) {
     // network pass (its outputs in the context's ys workspace), then the pointwise pass
     const unsigned nbs = (unsigned)std::min<long>((N + 255) / 256, 2048);
@@ -2666,35 +3050,160 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
   } else {
     timed(ctx, K_PRIM, st, [&] { k_prim<GAS, ND, RT><<<nb, bs, 0, st>>>(d, Q, Wd, Wp, nullptr); });
   }
+}
+
+// The artificial-diffusivity smoothing passes after the sources: fourth differences with
+// the x and y filters, and (3-D) the z filter; returns the planes the flux reads.
+template <int GAS, int ND, class RT>
+const RT* launch_ad_smoothing(hrx_ctx* ctx, hipStream_t st) {
+  const Dev& d = ctx->dev;
+  const long N = d.N;
+  RT* A = (RT*)ctx->AD;
+  RT* B = A + (long)d.nad * N;
+  timed(ctx, K_AD_D4, st, [&] {
+    const int mseg = ND == 2 ? MSEG2 : MSEG3;
+    const int nstrip = (d.nx + MO - 1) / MO, nseg = (d.ny + mseg - 1) / mseg;
+    k_ad_march<GAS, ND, RT><<<(unsigned)((long)d.nz * nstrip * nseg * d.nad), MW, 0, st>>>(
+        d, A, B, nstrip, nseg, mseg);
+  });
+  if (ND == 3) {
+    const int nxs = (d.nx + 63) / 64, nzs = (d.nz + ZSEG - 1) / ZSEG;
+    timed(ctx, K_AD_FZ, st, [&] {
+      k_ad_filter_z<RT><<<(unsigned)((long)nxs * d.ny * nzs * d.nad), 64, 0, st>>>(d, B, A, nxs,
+                                                                                nzs);
+    });
+    return A;
+  }
+  return B;
+}
+
+template <int GAS, int ND, int ORDER, class RT>
+int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
+  const Dev& d = ctx->dev;
+  double* Wd = ctx->Wd;
+  RT* Wp = (RT*)ctx->Wp;
+  double* F = ctx->F;
+  launch_prim<GAS, ND, RT>(ctx, Q, st);
   if (d.ad_on) {
-    RT* A = (RT*)ctx->AD;
-    RT* B = A + (long)d.nad * N;
-    const RT* Gad;
     const unsigned nts = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
     timed(ctx, K_AD_SRC, st, [&] {
-      k_ad_src<GAS, ND, ORDER, RT><<<nts, TTX * TTY, ND * TILE_E * sizeof(double), st>>>(d, Wd, A);
+      k_ad_src<GAS, ND, ORDER, RT><<<nts, TTX * TTY, ND * TILE_E * sizeof(double), st>>>(
+          d, Wd, (RT*)ctx->AD);
     });
-    // fourth differences and the x and y filters in one pass (timed as ad_d4)
-    timed(ctx, K_AD_D4, st, [&] {
-      const int mseg = ND == 2 ? MSEG2 : MSEG3;
-      const int nstrip = (d.nx + MO - 1) / MO, nseg = (d.ny + mseg - 1) / mseg;
-      k_ad_march<GAS, ND, RT><<<(unsigned)((long)d.nz * nstrip * nseg * d.nad), MW, 0, st>>>(
-          d, A, B, nstrip, nseg, mseg);
-    });
-    if (ND == 3) {
-      const int nxs = (d.nx + 63) / 64, nzs = (d.nz + ZSEG - 1) / ZSEG;
-      timed(ctx, K_AD_FZ, st, [&] {
-        k_ad_filter_z<RT><<<(unsigned)((long)nxs * d.ny * nzs * d.nad), 64, 0, st>>>(d, B, A, nxs,
-                                                                                  nzs);
-      });
-      Gad = A;
-    } else {
-      Gad = B;
-    }
+    const RT* Gad = launch_ad_smoothing<GAS, ND, RT>(ctx, st);
     launch_flux<GAS, ND, ORDER, true, RT>(ctx, st, Q, Wd, Wp, Gad, F);
   } else {
     launch_flux<GAS, ND, ORDER, false, RT>(ctx, st, Q, Wd, Wp, nullptr, F);
   }
+  return check(hipGetLastError());
+}
+
+// Wall-row pass after an unfused update (every gas and dimension)
+void launch_bc(hrx_ctx* ctx, double* Q, hipStream_t st) {
+  const Dev& d = ctx->dev;
+  const long nw = (long)(d.nx - 1) * d.nz;
+  const unsigned nb = blocks_for(nw, 128);
+  const bool air = ctx->cfg.gas == HRX_GAS_AIR5, tpg = ctx->cfg.gas == HRX_GAS_TPG;
+  timed(ctx, K_BC, st, [&] {
+    if (d.ndim == 2) {
+      if (air) k_bc<AIR5, 2><<<nb, 128, 0, st>>>(d, Q);
+      else if (tpg) k_bc<TPG, 2><<<nb, 128, 0, st>>>(d, Q);
+      else k_bc<CPG, 2><<<nb, 128, 0, st>>>(d, Q);
+    } else {
+      if (air) k_bc<AIR5, 3><<<nb, 128, 0, st>>>(d, Q);
+      else if (tpg) k_bc<TPG, 3><<<nb, 128, 0, st>>>(d, Q);
+      else k_bc<CPG, 3><<<nb, 128, 0, st>>>(d, Q);
+    }
+  });
+}
+
+// Compact first derivatives of nplanes planes along direction dir: f (plane stride fps)
+// -> out (plane stride ops), out = scale m D f, or out += scale m D f (acc; the forward
+// values then go through the context's temporary planes).
+void launch_cd(hrx_ctx* ctx, int dir, const double* f, long fps, double* out, long ops,
+               int nplanes, bool acc, double scale, hipStream_t st) {
+  const Dev& d = ctx->dev;
+  const long N = d.N;
+  const int ord = d.fd_order;
+  timed(ctx, K_CDERIV, st, [&] {
+    if (dir == 0) {
+      const dim3 g((unsigned)(N / d.nx), (unsigned)nplanes);
+      const size_t sh = 2 * (size_t)d.nx * sizeof(double);
+      if (acc) k_cd_x<true><<<g, 64, sh, st>>>(d.nx, f, fps, out, ops, d.mx, scale, ord, d.cl[0]);
+      else k_cd_x<false><<<g, 64, sh, st>>>(d.nx, f, fps, out, ops, d.mx, scale, ord, d.cl[0]);
+    } else if (dir == 1) {
+      const dim3 g(blocks_for((long)d.nx * d.nz, 128), (unsigned)nplanes);
+      const long s2 = (long)d.nx * d.ny;
+      if (acc)
+        k_cd_col<true, false><<<g, 128, 0, st>>>(d.ny, d.nx, d.nx, d.nz, s2, f, fps, out, ops,
+                                                ctx->Ct, N, d.my, scale, ord, d.cl[1]);
+      else
+        k_cd_col<false, false><<<g, 128, 0, st>>>(d.ny, d.nx, d.nx, d.nz, s2, f, fps, out, ops,
+                                                 ctx->Ct, N, d.my, scale, ord, d.cl[1]);
+    } else {
+      const dim3 g(blocks_for((long)d.nx * d.ny, 128), (unsigned)nplanes);
+      const long s = (long)d.nx * d.ny;
+      if (acc)
+        k_cd_col<true, true><<<g, 128, 0, st>>>(d.nz, s, d.nx, d.ny, d.nx, f, fps, out, ops,
+                                               ctx->Ct, N, d.mz, scale, ord, d.cl[2]);
+      else
+        k_cd_col<false, true><<<g, 128, 0, st>>>(d.nz, s, d.nx, d.ny, d.nx, f, fps, out, ops,
+                                                ctx->Ct, N, d.mz, scale, ord, d.cl[2]);
+    }
+  });
+}
+
+// One right-hand side (and stage) with compact first derivatives:
+//   k_prim -> gradients of u, (v, w), T, (X_s) along every direction (line solves)
+//   -> [artificial diffusivity: sources from the gradient planes, smoothing]
+//   -> k_flux_c (fluxes from the gradient planes) -> divergence, -sum_j D_j F_j, by line
+//   solves accumulating into Racc -> k_fin (sources, sponge, held rows, update)
+//   -> wall pass (stages).
+template <int GAS, int ND, class RT>
+int run_compact(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double* R,
+                double* Qio, double* dQ, double A, double B, double dt, int rkf, hipStream_t st) {
+  const Dev& d = ctx->dev;
+  const long N = d.N;
+  constexpr int nvar = (GAS == AIR5 ? NS : 1) + ND + 1;
+  const double* Qs = mode == MODE_RHS ? Q : Qio;
+  double* Wd = ctx->Wd;
+  RT* Wp = (RT*)ctx->Wp;
+  double* F = ctx->F;
+  double* G = ctx->G;
+  const int nsrc = d.nsrc;
+  launch_prim<GAS, ND, RT>(ctx, Qs, st);
+  for (int b = 0; b < ND; ++b)
+    launch_cd(ctx, b, Wd, N, G + (long)b * nsrc * N, N, nsrc, false, 1.0, st);
+  const RT* Gad = nullptr;
+  const unsigned nb = blocks_for(N, 256);
+  if (d.ad_on) {
+    timed(ctx, K_AD_SRC, st, [&] { k_ad_src_c<ND, RT><<<nb, 256, 0, st>>>(d, G, (RT*)ctx->AD); });
+    Gad = launch_ad_smoothing<GAS, ND, RT>(ctx, st);
+  }
+  timed(ctx, K_FLUX, st, [&] {
+    if constexpr (GAS == AIR5) {
+      if (d.sm) {
+        if (d.ad_on) k_flux_c<GAS, ND, true, RT, true><<<nb, 256, 0, st>>>(d, Qs, Wd, Wp, Gad, F, G);
+        else k_flux_c<GAS, ND, false, RT, true><<<nb, 256, 0, st>>>(d, Qs, Wd, Wp, Gad, F, G);
+        return;
+      }
+    }
+    if (d.ad_on) k_flux_c<GAS, ND, true, RT><<<nb, 256, 0, st>>>(d, Qs, Wd, Wp, Gad, F, G);
+    else k_flux_c<GAS, ND, false, RT><<<nb, 256, 0, st>>>(d, Qs, Wd, Wp, Gad, F, G);
+  });
+  double* Racc = mode == MODE_RHS ? R : ctx->R;
+  for (int b = 0; b < ND; ++b)
+    launch_cd(ctx, b, F + (long)b * nvar * N, N, Racc, N, nvar, b > 0, -1.0, st);
+  timed(ctx, K_FIN, st, [&] {
+    if (mode == MODE_RHS)
+      k_fin<GAS, ND, MODE_RHS, RT><<<nb, 256, 0, st>>>(d, Wp, Q, Qref, Racc, R, nullptr, nullptr,
+                                                      0.0, 0.0, 0.0, RKF_2N);
+    else
+      k_fin<GAS, ND, MODE_RK, RT><<<nb, 256, 0, st>>>(d, Wp, nullptr, Qref, Racc, nullptr, Qio, dQ,
+                                                     A, B, dt, rkf);
+  });
+  if (mode == MODE_RK) launch_bc(ctx, Qio, st);
+  ctx->dev.warm = 1;
   return check(hipGetLastError());
 }
 
@@ -2732,6 +3241,21 @@ int dispatch(hrx_ctx* ctx, int mode, const double* Q, const double* Qref, double
   const bool air = ctx->cfg.gas == HRX_GAS_AIR5, tpg = ctx->cfg.gas == HRX_GAS_TPG;
   const bool o6 = d.fd_order == 6;
   const bool mixed = ctx->cfg.precision == HRX_PREC_MIXED;
+  if (d.compact) {
+#define HRX_RUNC(G, NDV)                                                                   \
+  return mixed ? run_compact<G, NDV, float>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, rkf, st) \
+               : run_compact<G, NDV, double>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, rkf, st)
+    if (d.ndim == 2) {
+      if (air) HRX_RUNC(AIR5, 2);
+      else if (tpg) HRX_RUNC(TPG, 2);
+      else HRX_RUNC(CPG, 2);
+    } else {
+      if (air) HRX_RUNC(AIR5, 3);
+      else if (tpg) HRX_RUNC(TPG, 3);
+      else HRX_RUNC(CPG, 3);
+    }
+#undef HRX_RUNC
+  }
 #define HRX_RUN(G, NDV, O)                                                              \
   return mixed ? run<G, NDV, O, float>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, rkf, st) \
                : run<G, NDV, O, double>(ctx, mode, Q, Qref, R, Qio, dQ, A, B, dt, rkf, st)
@@ -2760,24 +3284,6 @@ const double RK4B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 136
 const double SSPA[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
 const double SSPB[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
 
-// Wall-row pass after an unfused update (every gas and dimension)
-void launch_bc(hrx_ctx* ctx, double* Q, hipStream_t st) {
-  const Dev& d = ctx->dev;
-  const long nw = (long)(d.nx - 1) * d.nz;
-  const unsigned nb = blocks_for(nw, 128);
-  const bool air = ctx->cfg.gas == HRX_GAS_AIR5, tpg = ctx->cfg.gas == HRX_GAS_TPG;
-  timed(ctx, K_BC, st, [&] {
-    if (d.ndim == 2) {
-      if (air) k_bc<AIR5, 2><<<nb, 128, 0, st>>>(d, Q);
-      else if (tpg) k_bc<TPG, 2><<<nb, 128, 0, st>>>(d, Q);
-      else k_bc<CPG, 2><<<nb, 128, 0, st>>>(d, Q);
-    } else {
-      if (air) k_bc<AIR5, 3><<<nb, 128, 0, st>>>(d, Q);
-      else if (tpg) k_bc<TPG, 3><<<nb, 128, 0, st>>>(d, Q);
-      else k_bc<CPG, 3><<<nb, 128, 0, st>>>(d, Q);
-    }
-  });
-}
 
 }  // namespace
 
@@ -2804,7 +3310,9 @@ int hrx_rhs_eval_noalloc(hrx_ctx* ctx, const double* Q, const double* Q_ref, dou
   const size_t bWp = al(ctx->rt_size * N * ctx->nWp);
   const size_t bF = al(sizeof(double) * N * ctx->nF);
   const size_t bAD = d.ad_on ? al(ctx->rt_size * N * d.nad * 2) : 0;
-  if (bWd + bWp + bF + bAD > NOALLOC_BYTES) return HRX_ETOOBIG;
+  const size_t bG = d.compact ? al(sizeof(double) * N * d.ndim * d.nsrc) : 0;
+  const size_t bCt = d.compact ? al(sizeof(double) * N * d.nvar) : 0;
+  if (bWd + bWp + bF + bAD + bG + bCt > NOALLOC_BYTES) return HRX_ETOOBIG;
   hipStream_t st = (hipStream_t)hip_stream;
   ctx->last_stream = st;
   // The launches of this call take the static workspace in place of the context's
@@ -2815,11 +3323,15 @@ int hrx_rhs_eval_noalloc(hrx_ctx* ctx, const double* Q, const double* Q_ref, dou
   void* const Wp0 = ctx->Wp;
   double* const F0 = ctx->F;
   void* const AD0 = ctx->AD;
+  double* const G0 = ctx->G;
+  double* const Ct0 = ctx->Ct;
   const Dev dev0 = ctx->dev;
   ctx->Wd = reinterpret_cast<double*>(base);
   ctx->Wp = base + bWd;
   ctx->F = reinterpret_cast<double*>(base + bWd + bWp);
   ctx->AD = bAD ? base + bWd + bWp + bF : nullptr;
+  ctx->G = bG ? reinterpret_cast<double*>(base + bWd + bWp + bF + bAD) : nullptr;
+  ctx->Ct = bCt ? reinterpret_cast<double*>(base + bWd + bWp + bF + bAD + bG) : nullptr;
   ctx->dev.ad = ctx->AD;
   ctx->dev.warm = 0;
   const int rc = dispatch(ctx, MODE_RHS, Q, Q_ref, R, nullptr, nullptr, 0.0, 0.0, 0.0, RKF_2N, st);
@@ -2827,6 +3339,8 @@ int hrx_rhs_eval_noalloc(hrx_ctx* ctx, const double* Q, const double* Q_ref, dou
   ctx->Wp = Wp0;
   ctx->F = F0;
   ctx->AD = AD0;
+  ctx->G = G0;
+  ctx->Ct = Ct0;
   ctx->dev = dev0;
   return rc;
 }

@@ -73,6 +73,7 @@ class FlowConfig:
     diffusion: int = 0            # 0: Ramshaw (Eq. 18), 1: Stefan-Maxwell (Eq. 17)
     ad_coef: tuple = (0.002, 1.75, 0.01, 0.01, 100.0)   # C_mu, C_beta, C_kappa, C_D, C_Y
     fd_order: int = 6
+    fd_scheme: int = 0            # 0: explicit central differences, 1: compact (Pade)
     rk: int = 0                   # 0: 2N-RK3, 1: 2N-RK4(3)5, 2: three-register TVD RK3
     cfl: float = 0.5
     noise: float = 1e-4

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhrx.so")
 
 GAS_CPG, GAS_AIR5 = 0, 1
+FD_EXPLICIT, FD_COMPACT = 0, 1
 WALL_ADIABATIC, WALL_ISOTHERMAL = 0, 1
 RK3_2N, RK45_2N, SSPRK3 = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
@@ -51,7 +52,7 @@ class _Config(C.Structure):
         ("sigma_max", C.c_double),
         ("hold", C.POINTER(C.c_int64)), ("n_hold", C.c_int64),
         ("newton_max_iter", C.c_int), ("newton_rtol", C.c_double),
-        ("diffusion", C.c_int),
+        ("diffusion", C.c_int), ("fd_scheme", C.c_int),
     ]
 
 
@@ -181,6 +182,7 @@ class Context:
             c.hold, c.n_hold = None, 0
         c.newton_max_iter, c.newton_rtol = int(newton_max_iter), 0.0
         c.diffusion = getattr(cfg, "diffusion", 0)
+        c.fd_scheme = getattr(cfg, "fd_scheme", 0)
         h = C.c_void_p()
         _check(lib.hrx_create(C.byref(c), C.byref(h)))
         self._h = h
@@ -217,7 +219,7 @@ class Context:
 
 
 KERNEL_NAMES = ("prim", "ad_src", "ad_d4", "ad_filter_x", "ad_filter_y", "ad_filter_z", "flux",
-                "div", "bc", "thermo_eval", "chem_source")
+                "div", "bc", "thermo_eval", "chem_source", "cderiv", "fin")
 
 
 def timing_enable(ctx, on=True):

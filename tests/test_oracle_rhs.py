@@ -1,6 +1,7 @@
 """Pins of the oracle's right-hand side, boundaries, RK stages, AD and network.
 
-Closed forms: uniform flow (R = 0, or the chemical source alone), plane Couette flow
+Closed forms, with the explicit and with the compact first derivatives: uniform flow
+(R = 0, or the chemical source alone), plane Couette flow
 (only the viscous heating (mu/Re) a^2 remains, Eq. 9-10), uniform dilatation (fixes
 the -2/3 bulk term and the pressure work); symmetry under exchange of x and y; the
 species rows summing to the continuity equation (sum J_s = 0, Eq. 20); stability
@@ -44,16 +45,18 @@ def _cons_cpg(case, rho, u, v, T):
     return np.array([rho, rho * u, rho * v, rho * (e + 0.5 * (u * u + v * v))])
 
 
-def test_uniform_flow_cpg():
-    case = _case(_cpg_cfg())
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_uniform_flow_cpg(scheme):
+    case = _case(_cpg_cfg(fd_scheme=scheme))
     sh = (1, case.cfg.ny, case.cfg.nx)
     Q = _cons_cpg(case, np.full(sh, 1.3), np.full(sh, 5.0), np.full(sh, 0.7), np.full(sh, 3.0))
     Rr = R.rhs(Q, Q.copy(), case)
     assert np.max(np.abs(Rr)) < 1e-10
 
 
-def test_uniform_flow_air5_is_chemistry():
-    case = _case(_air_cfg())
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_uniform_flow_air5_is_chemistry(scheme):
+    case = _case(_air_cfg(fd_scheme=scheme))
     sh = (1, case.cfg.ny, case.cfg.nx)
     Y = np.array([0.70, 0.05, 0.05, 0.05, 0.15])
     Q = np.zeros((8,) + sh)
@@ -69,8 +72,9 @@ def test_uniform_flow_air5_is_chemistry():
     assert np.max(np.abs(Rr[5:])) < 1e-9
 
 
-def test_couette_viscous_heating_cpg():
-    cfg = _cpg_cfg(nx=20, ny=22)
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_couette_viscous_heating_cpg(scheme):
+    cfg = _cpg_cfg(nx=20, ny=22, fd_scheme=scheme)
     x = np.linspace(0.0, 2.0, cfg.nx)
     y = np.linspace(0.0, 1.0, cfg.ny)
     case = _case(cfg, x, y)
@@ -87,8 +91,9 @@ def test_couette_viscous_heating_cpg():
     assert np.max(np.abs(Rr[:3][..., 1:])) < 1e-12
 
 
-def test_uniform_dilatation_cpg():
-    cfg = _cpg_cfg(nx=26, ny=16)
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_uniform_dilatation_cpg(scheme):
+    cfg = _cpg_cfg(nx=26, ny=16, fd_scheme=scheme)
     x = np.linspace(1.0, 2.0, cfg.nx)
     y = np.linspace(0.0, 1.0, cfg.ny)
     case = _case(cfg, x, y)
@@ -111,8 +116,9 @@ def test_uniform_dilatation_cpg():
     assert np.max(np.abs(Rr[3][cols] - expect_E)) < 1e-12
 
 
-def test_transpose_symmetry_air5():
-    cfg = _air_cfg(nx=18, ny=18)
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_transpose_symmetry_air5(scheme):
+    cfg = _air_cfg(nx=18, ny=18, fd_scheme=scheme)
     c = np.linspace(0.0, 1.7, 18) ** 1.3
     case = _case(cfg, c, c)
     # smooth state built from primitives with the oracle's own energy
