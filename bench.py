@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
-"""Throughput of the right-hand side + low-storage RK stage on one MI355X.
+"""Throughput of the right-hand side + explicit RK stage on one MI355X.
 
-One step = one hrx_rk_stage call: primitive/thermochemistry pass (Newton energy
-inversion, mixture transport, finite-rate chemistry), flux pass (stencil gradients,
-convective + viscous + diffusive fluxes), divergence + source + sponge + RK update,
-wall-row update.  Inputs are the seeded synthetic 5-species-air flat-plate field
-(512 x 256, M = 10, FP64), resident in HBM before timing starts.
+One step = one hrx_rk_stage call on the whole grid: pointwise thermochemistry (Newton
+energy inversion, mixture transport, finite-rate chemistry), artificial diffusivity,
+first derivatives and fluxes, divergence + sources + sponge + RK update, wall row.
+Default workload: the 3-D jet-in-crossflow-shaped box of 5-species air,
+512 x 256 x 128 points, FP64, artificial diffusivity on (the largest workload of the
+metric that fits one GPU); the mixed FP32/FP64 form and the learned-surrogate form are
+timed on the same field.  Inputs are seeded synthetic fields resident in HBM before
+timing starts.
 
-Prints one JSON line with the metric, the dominant kernel's roofline position
-(per-kernel HIP-event durations inside the timed region) and the CPU oracle timed
-on a bounded sample of the same workload.
+Prints one JSON line: the metric, the dominant kernel's position against the HBM
+roofline (algorithmic bytes per launch over its HIP-event duration inside the timed
+region), every kernel's figures, the failure counters, and the CPU oracle timed on a
+bounded sample of the same workload at one core and at all cores (before the GPU is
+touched).
 """
 import argparse
 import dataclasses
+import hashlib
 import json
 import os
 import sys
@@ -21,67 +27,156 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "grid-point RHS+RK-stage evals/s (Mpts/s), FP64 vs mixed/surrogate, % HBM peak"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the flat-plate stage kernels, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE scaled by a 256 MiB copy kernel (fetch x2.0, write x1.0), for the kernels
-# as they stand (profiles/stage_air5_flatplate_512x256.md)
-PRIM_TRAFFIC_BYTES = (9460 + 20480) * 1024
-TRAFFIC_BYTES = {"flux": (25566 + 16384) * 1024, "div": (43205 + 16392) * 1024}
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+RK_NAMES = {0: "2N-RK3 (Williamson)", 1: "2N-RK4(3)5 (Carpenter-Kennedy)",
+            2: "three-register TVD RK3 (Shu-Osher)"}
 
-# Algorithmic HBM bytes per grid point of each kernel (FP64 planes read once + written
-# once; stencil neighbours counted once), for a 2-D 5-species-air stage without AD:
-#   prim : read Q (8 planes) + T of the previous stage; write Wd (u, v, T: 3) and
-#          Wp (mu, kappa, D_1..5, wdot_1..5, h_1..5: 17)
-#   flux : read Wd (3) + Wp (mu, kappa, D_s, h_s: 12) + Q (8: the partial densities give
-#          the tile's mole fractions and the pressure); write F (2 x 8)
-#   div  : read F (16) + wdot (5) + Q (8) + dQ (8); write Q, dQ (16)  (+ Q_ref in sponges)
-BYTES_PER_POINT_AIR5_2D = {"prim": 8 * (9 + 20), "flux": 8 * (23 + 16),
-                           "div": 8 * (37 + 16)}
-# FP64 floating-point operations per grid point of the pointwise thermochemistry
-# (energy inversion from the previous stage's temperature, transport, kinetics,
-# enthalpies): SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / points, read with rocprofv3 on
-# this workload (profiles/stage_air5_flatplate_512x256.md).  MI355X has no FP64
-# transcendental unit, so this includes the instruction sequences of exp/log/sqrt/div.
-FLOPS_PER_POINT_PRIM_AIR5_2D = 2766.0
+# HBM traffic per launch from rocprofv3 --pmc (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB per
+# dispatch; the factors come from a plain 256 MiB copy), keyed by workload and kernel,
+# valid only for the kernel source whose SHA-256 prefix is given (profiles/ holds the
+# summaries and the commands).  Any other source reports traffic null.
+TRAFFIC = {}
+TRAFFIC_SOURCE_SHA = None
+
+
+def source_sha():
+    p = os.path.join(ROOT, "paper_2210_05547_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(p)):
+        with open(os.path.join(p, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def sponge_fraction(cfg):
     import numpy as np
-    from paper_2210_05547_amd import fields
-    nx, ny = cfg.nx, cfg.ny
-    m = np.zeros((ny, nx), bool)
+    m = np.zeros((cfg.ny, cfg.nx), bool)
     if cfg.sponge_in:
         m[:, :cfg.sponge_in] = True
     if cfg.sponge_out:
-        m[:, nx - cfg.sponge_out:] = True
+        m[:, cfg.nx - cfg.sponge_out:] = True
     if cfg.sponge_top:
-        m[ny - cfg.sponge_top:, :] = True
+        m[cfg.ny - cfg.sponge_top:, :] = True
     return float(m.mean())
 
 
-def cpu_baseline(cfg, Q, Qr, info, budget_s):
-    """Oracle stages on the same field until about budget_s seconds of CPU work."""
+def algorithmic_bytes(cfg, rt, surrogate=False):
+    """Algorithmic HBM bytes per grid point of each kernel of one stage (every plane a
+    kernel needs read once, every plane it produces written once; stencil neighbours
+    count once), as {kernel: (bytes per point, launches per stage)}.  rt: bytes of the
+    transport/AD planes (8 FP64, 4 mixed)."""
+    air, ad = cfg.gas == 1, cfg.ad
+    sm = air and cfg.diffusion == 1
+    nd = cfg.ndim
+    ns = 5 if air else 1
+    nv = ns + nd + 1
+    comp = getattr(cfg, "fd_scheme", 0) == 1
+    xp = air and (nd == 3 or comp)                 # X_s and p stored as planes
+    wd_out = nd + 1 + (5 + 1 if xp else (0 if air else 1))
+    if air:
+        wp = 17 + (10 if sm else 0) + (1 if ad else 0)
+        flux_wp = 2 + 5 + (0 if sm else 5) + (10 if sm else 0) + (1 if ad else 0)
+    else:
+        wp = (1 if cfg.gas == 0 else 2) + (1 if ad else 0)
+        flux_wp = wp
+    nad = 3 + (5 if air else 0)
+    warm = 8 if cfg.gas in (1, 2) else 0
+    prim = 8 * nv + warm + 8 * wd_out + rt * wp + (rt * (1 + (5 if air else 0)) if ad else 0)
+    if surrogate:
+        prim += 8 * nv + 2 * 32                    # network pass: Q in, 8 floats out and back
+    out = {"prim": (prim, 1)}
+    if ad:
+        out["ad_src"] = ((2 * rt + (0 if comp else 8 * nd)) + (8 * nd * nd if comp else 0), 1)
+        out["ad_d4"] = (2 * nad * rt, 1)
+        if nd == 3:
+            out["ad_filter_z"] = (2 * nad * rt, 1)
+    nsrc = nd + 1 + (5 if air else 0)
+    flux_in = 8 * (nd + 1 + (5 if (air and nd == 3) else 0) + (1 if (not air or nd == 3) else 0))
+    if comp:
+        flux_in = 8 * (nd + 1 + (5 if air else 0) + 1) + 8 * nd * nsrc
+    flux_in += 8 * nv + rt * flux_wp + (rt * nad if ad else 0)
+    out["flux"] = (flux_in + 8 * nd * nv, 1)
+    sponge = 8 * nv * sponge_fraction(cfg)
+    if comp:
+        # gradients: nsrc planes read and written per direction; divergence: F read, R
+        # written (x) or read and written (y, z)
+        grad = nd * nsrc * 16
+        div = nv * (16 + (nd - 1) * 24)
+        out["cderiv"] = ((grad + div) / (2 * nd), 2 * nd)
+        out["fin"] = (8 * nv + (rt * 5 if air else 0) + 32 * nv + sponge, 1)
+    else:
+        out["div"] = (8 * nd * nv + (rt * 5 if air else 0) + 32 * nv + sponge, 1)
+    return out
+
+
+def compulsory_bytes(cfg):
+    """Read Q and dQ, write Q and dQ (plus Q_ref in the sponges): 32 nvar B per point."""
+    return 32 * cfg.nvar + 8 * cfg.nvar * sponge_fraction(cfg)
+
+
+# ------------------------------------------------------------------ CPU oracle baseline
+def _oracle_block(job):
+    """One worker of the all-cores baseline: oracle stages on an x block (with halo) of
+    the sample field for about `seconds`; returns (interior points x stages, seconds)."""
     import numpy as np
     from oracle import rhs as orhs
-    case = orhs.Case(cfg, info["x"], info["y"], info["z"], info["hold"])
+    cfg, Q, Qr, x, y, z, dt, interior, seconds = job
+    case = orhs.Case(cfg, x, y, z, None)
     Qo, dQo = Q.copy(), np.zeros_like(Q)
     t0 = time.perf_counter()
     n = 0
     while True:
-        orhs.rk_stage(Qo, dQo, Qr, case, n, info["dt"])
+        orhs.rk_stage(Qo, dQo, Qr, case, n, dt)
         n += 1
-        if time.perf_counter() - t0 > budget_s:
+        if time.perf_counter() - t0 > seconds:
             break
-    dt = time.perf_counter() - t0
-    return dict(value=cfg.npts * n / dt / 1e6, unit="Mpts/s", cores=1, kind="oracle",
-                sample=f"{n} RK stages of the same {cfg.nx}x{cfg.ny} field, numpy FP64, "
-                       f"single thread, {dt:.1f} s")
+    return interior * n, time.perf_counter() - t0
 
 
+def cpu_baseline(cfg, seconds, cores):
+    """The oracle's RK stage on a bounded sample of the workload: the full grid in 2-D,
+    an 8-plane periodic-z slab in 3-D; one process for the one-core figure, then the
+    sample split along x into `cores` blocks with a halo of 12 points (the dependency
+    reach of the AD chain), one process each; rates count interior points only."""
+    import multiprocessing as mp
+    import numpy as np
+    from paper_2210_05547_amd import fields
+    sc = dataclasses.replace(cfg, nz=8) if cfg.ndim == 3 else cfg
+    Q, Qr, info = fields.initial_field(sc)
+    x, y, z = info["x"], info["y"], info["z"]
+    one = _oracle_block((sc, Q, Qr, x, y, z, info["dt"], sc.npts, seconds))
+    single = one[0] / one[1] / 1e6
+    H = 12
+    edges = np.linspace(0, sc.nx, cores + 1).astype(int)
+    jobs = []
+    for b in range(cores):
+        i0, i1 = edges[b], edges[b + 1]
+        a, e = max(0, i0 - H), min(sc.nx, i1 + H)
+        cb = dataclasses.replace(sc, nx=e - a, sponge_in=0, sponge_out=0, sponge_top=0)
+        jobs.append((cb, np.ascontiguousarray(Q[..., a:e]), np.ascontiguousarray(Qr[..., a:e]),
+                     x[a:e], y, z, info["dt"], (i1 - i0) * sc.ny * sc.nz, seconds))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_block, jobs)
+    wall = time.perf_counter() - t0
+    allc = sum(r[0] for r in res) / wall / 1e6
+    what = (f"{sc.nx}x{sc.ny}x{sc.nz} periodic-z slab of the workload" if cfg.ndim == 3
+            else f"the full {sc.nx}x{sc.ny} grid")
+    return dict(value=round(allc, 4), unit="Mpts/s", cores=cores, kind="oracle",
+                sample=f"oracle RK stages (numpy FP64) on {what}, about {seconds:.0f} s per "
+                       f"run; all cores: {cores} processes on x blocks with a 12-point halo, "
+                       f"interior points counted, wall {wall:.1f} s incl. start-up",
+                single_core=dict(value=round(single, 4), cores=1,
+                                 sample=f"{int(round(one[0] / sc.npts))} stages in {one[1]:.1f} s"))
+
+
+# ------------------------------------------------------------------ GPU timing
 def time_form(cfg, Q, Qr, info, steps, warmup, precision, setup=None):
-    """Mpts/s of the same stage loop in another form (graph replay on); setup(ctx) may
-    prepare the context first (the surrogate form trains its network there)."""
+    """Mpts/s of the stage loop in another form (graph replay on); setup(ctx) may prepare
+    the context first (the surrogate form trains its network there)."""
     import torch
     from paper_2210_05547_amd import hrx
     ctx = hrx.Context(cfg, info["x"], info["y"], info["z"], info["hold"], precision=precision)
@@ -103,8 +198,11 @@ def time_form(cfg, Q, Qr, info, steps, warmup, precision, setup=None):
             hrx.rk_stage(ctx, k, info["dt"], Qd, dQd, Qrd)
         b.record()
         torch.cuda.synchronize()
-    time_form.fallbacks = ctx.counters()["surrogate_fallbacks"]
+    c = ctx.counters()
+    time_form.counters = c
+    time_form.finite = bool(torch.isfinite(Qd).all())
     ctx.close()
+    del Qd, Qrd, dQd
     return cfg.npts * steps / (a.elapsed_time(b) * 1e-3) / 1e6
 
 
@@ -113,12 +211,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c4")
     ap.add_argument("--grid", type=int, nargs="+", default=None, metavar="N",
                     help="run the configuration's workload on another grid (nx ny [nz])")
     ap.add_argument("--stefan-maxwell", action="store_true",
                     help="Stefan-Maxwell diffusion (Eq. 17) instead of Eq. (18)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--scheme", choices=("explicit", "compact"), default="explicit")
+    ap.add_argument("--rk", type=int, default=None, help="0 2N-RK3, 1 2N-RK4(3)5, 2 TVD RK3")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-cores", type=int, default=0,
+                    help="processes of the all-cores baseline (0: min(16, available))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip timing the mixed FP32/FP64 form on the same workload")
@@ -127,6 +229,11 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 10 times (counter scaling)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (how the "
+              "path would shard over several GPUs is described in DESIGN.md, not built)",
+              file=sys.stderr)
+        sys.exit(2)
     if args.calibrate_copy:
         import torch
         n = args.calibrate_copy * (1 << 20) // 8
@@ -137,21 +244,29 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "reps": 10}))
         return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path's multi-GPU sharding is described in DESIGN.md, not built)",
-              file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
-    import torch
-    from paper_2210_05547_amd import fields, hrx
-
+    from paper_2210_05547_amd import fields
     cfg = fields.get_config(args.config)
     if args.grid:
         cfg = cfg.scaled(*args.grid)
     if args.stefan_maxwell:
         cfg = dataclasses.replace(cfg, diffusion=1)
+    if args.scheme == "compact":
+        cfg = dataclasses.replace(cfg, fd_scheme=1)
+    if args.rk is not None:
+        cfg = dataclasses.replace(cfg, rk=args.rk)
+
+    # the CPU baseline runs first, in processes forked before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        cores = args.cpu_cores or min(16, len(os.sched_getaffinity(0)))
+        print(f"[bench] CPU oracle baseline ({cores} cores)...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfg, args.cpu_seconds, cores)
+
+    import numpy as np  # noqa: F401
+    import torch
+    from paper_2210_05547_amd import hrx
+    print(f"[bench] field {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.nz}...", file=sys.stderr, flush=True)
     Q, Qr, info = fields.initial_field(cfg)
     dev = torch.device("cuda:0")
     ctx = hrx.Context(cfg, info["x"], info["y"], info["z"], info["hold"])
@@ -161,6 +276,7 @@ def main():
     # a non-null stream lets the library replay each stage as a captured HIP graph
     stream = torch.cuda.Stream()
     stage = 0
+    print("[bench] FP64 stages...", file=sys.stderr, flush=True)
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             hrx.rk_stage(ctx, stage, info["dt"], Qd, dQd, Qrd)
@@ -175,8 +291,8 @@ def main():
         t1.record()
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1)
-        # per-kernel HIP-event durations: the same stages again with direct launches
-        # bracketed by events on this stream (graph replay is off while timing)
+        # per-kernel HIP-event durations on this stream: the same stages again with direct
+        # launches, each kernel bracketed by events (graph replay is off while timing)
         hrx.timing_enable(ctx, True)
         for _ in range(args.steps):
             hrx.rk_stage(ctx, stage, info["dt"], Qd, dQd, Qrd)
@@ -187,76 +303,83 @@ def main():
     cnt = ctx.counters()
     finite = bool(torch.isfinite(Qd).all())
     value = cfg.npts * args.steps / (ms * 1e-3) / 1e6
+    ctx.close()
+    del Qd, Qrd, dQd
 
+    sha = source_sha()
+    model = algorithmic_bytes(cfg, 8)
     kernels = {}
     for name, (tms, nl) in kt.items():
-        if nl:
-            kernels[name] = dict(avg_us=round(1e3 * tms / nl, 3), launches=nl)
-    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
-    model = cfg.gas == 1 and cfg.ndim == 2 and not cfg.ad
-    # the counter-based traffic figures were taken on the flat plate's own grid
-    counted = cfg.name == fields.get_config("c2").name and cfg.npts == 512 * 256
-    roofs = {}
-    if model:
-        bpp = dict(BYTES_PER_POINT_AIR5_2D)
-        bpp["div"] = bpp["div"] + 8 * 8 * sponge_fraction(cfg)
-        for name, kd in kernels.items():
-            if name not in bpp:
-                continue
-            sec = kd["avg_us"] * 1e-6
-            gbs = bpp[name] * cfg.npts / sec / 1e9
-            kd["GBps"] = round(gbs, 1)
-            if name == "prim":
-                tf = FLOPS_PER_POINT_PRIM_AIR5_2D * cfg.npts / sec / 1e12
-                kd["TFLOPs_fp64"] = round(tf, 2)
-                roofs[name] = dict(kernel=name, bound="alu", achieved=round(tf, 2),
-                                   peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                                   frac=round(tf / FP64_VECTOR_PEAK_TFLOPS, 4),
-                                   traffic=PRIM_TRAFFIC_BYTES if counted else None)
-            else:
-                roofs[name] = dict(kernel=name, bound="hbm", achieved=round(gbs, 1),
-                                   peak=HBM_PEAK_GBS, unit="GB/s",
-                                   frac=round(gbs / HBM_PEAK_GBS, 4),
-                                   traffic=TRAFFIC_BYTES.get(name) if counted else None)
-    roof = roofs.get(dom)
+        if not nl:
+            continue
+        avg = 1e3 * tms / nl
+        kd = dict(avg_us=round(avg, 3), launches=nl, share=0.0)
+        if name in model:
+            bpp, per_stage = model[name]
+            gbs = bpp * cfg.npts / (avg * 1e-6) / 1e9
+            kd.update(bytes_per_point=round(bpp, 1), GBps=round(gbs, 1),
+                      hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+        kernels[name] = kd
+    tot = sum(k["avg_us"] * k["launches"] for k in kernels.values())
+    for k in kernels.values():
+        k["share"] = round(k["avg_us"] * k["launches"] / tot, 4)
+    dom = max((k for k in kernels if k in model), key=lambda k: kernels[k]["share"])
+    kd = kernels[dom]
+    tr = TRAFFIC.get((cfg.name, cfg.npts, args.scheme, dom)) if sha == TRAFFIC_SOURCE_SHA else None
+    roof = dict(kernel=dom, bound="hbm", achieved=kd["GBps"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=kd["hbm_frac"], traffic=tr,
+                algorithmic_bytes_per_launch=int(round(model[dom][0] * cfg.npts)),
+                avg_launch_us=kd["avg_us"])
+    eff = compulsory_bytes(cfg) * value * 1e6 / 1e9
+    fails = {k: cnt[k] for k in ("newton_nonconverged", "energy_below_min", "nonfinite")}
     out = {
-        "metric": "grid-point RHS+RK-stage evals/s (Mpts/s), FP64",
+        "metric": METRIC,
         "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic (seeded flat-plate boundary-layer field)",
+        "data": "synthetic (seeded field of the workload's shape; inputs resident in HBM)",
         "config": {"workload": cfg.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "points": cfg.npts,
-                   "gas": {0: "cpg", 1: "air5", 2: "tpg"}[cfg.gas], "rk": "2N-RK3",
-                   "fd_order": cfg.fd_order, "artificial_diffusivity": bool(cfg.ad),
+                   "gas": {0: "cpg", 1: "air5", 2: "tpg"}[cfg.gas], "rk": RK_NAMES[cfg.rk],
+                   "fd_order": cfg.fd_order, "fd_scheme": args.scheme,
+                   "artificial_diffusivity": bool(cfg.ad),
                    "diffusion": "stefan-maxwell" if cfg.diffusion else "ramshaw"},
         "roofline": roof,
+        "effective_hbm": dict(compulsory_bytes_per_point=round(compulsory_bytes(cfg), 1),
+                              GBps=round(eff, 1), frac=round(eff / HBM_PEAK_GBS, 4)),
         "kernels": kernels,
-        "kernel_rooflines": roofs,
+        "kernel_source_sha": sha,
         "state_finite": finite,
-        "newton_failures": cnt["newton_nonconverged"] + cnt["energy_below_min"],
+        "failures": fails,
+        "valid": finite and cnt["status"] == hrx.HRX_OK,
     }
+    if not out["valid"]:
+        print(f"[bench] WARNING: the timed state is not clean: finite={finite} {fails}",
+              file=sys.stderr, flush=True)
+    forms = {"fp64": out["value"]}
     if not args.no_mixed:
-        out["forms"] = {"fp64": out["value"],
-                        "mixed": round(time_form(cfg, Q, Qr, info, args.steps, args.warmup,
-                                                 hrx.PREC_MIXED), 2)}
+        print("[bench] mixed form...", file=sys.stderr, flush=True)
+        forms["mixed"] = round(time_form(cfg, Q, Qr, info, args.steps, args.warmup,
+                                         hrx.PREC_MIXED), 2)
     if not args.no_surrogate and cfg.gas == 1 and not cfg.diffusion:
         from paper_2210_05547_amd import surrogate
+        print("[bench] surrogate form (training first)...", file=sys.stderr, flush=True)
         summary = {}
 
-        def setup(ctx):
+        def setup(c):
             t0 = time.perf_counter()
-            summary.update(surrogate.train(ctx))
+            summary.update(surrogate.train(c))
             torch.cuda.synchronize()
             summary["train_seconds"] = round(time.perf_counter() - t0, 1)
-            hrx.set_thermo_mode(ctx, hrx.THERMO_SURROGATE)
-        rate = time_form(cfg, Q, Qr, info, args.steps, args.warmup, hrx.PREC_FP64, setup)
-        out.setdefault("forms", {"fp64": out["value"]})["surrogate"] = round(rate, 2)
+            hrx.set_thermo_mode(c, hrx.THERMO_SURROGATE)
+        forms["surrogate"] = round(time_form(cfg, Q, Qr, info, args.steps, args.warmup,
+                                             hrx.PREC_FP64, setup), 2)
         summary["fallback_fraction"] = round(
-            time_form.fallbacks / (cfg.npts * (args.steps + args.warmup)), 5)
+            time_form.counters["surrogate_fallbacks"] / (cfg.npts * (args.steps + args.warmup)), 5)
+        summary["design"] = surrogate.DESIGN_NOTE
         out["surrogate"] = summary
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, Q, Qr, info, args.cpu_seconds)
-    ctx.close()
+    out["forms"] = forms
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -94,9 +94,9 @@ struct Dev {
   const double *sx, *sy;          // sponge profiles
   const double *dlx, *dly, *dlz;  // local spacings dx/d(xi)
   const unsigned char *hold;      // [nz][3][nx] or null
-  unsigned long long *counters;   // [0] Newton non-converged, [1] below e(T_min),
-                                  // [2] surrogate fallbacks, [3] non-finite states,
-                                  // [4] negative densities
+  unsigned long long *counters;   // [kind][CSLOTS]: 0 Newton non-converged, 1 below
+                                  // e(T_min), 2 surrogate fallbacks, 3 non-finite
+                                  // states, 4 negative densities
   // W plane offsets
   int nsrc, w_p, w_mu, w_kap, w_D, w_wdot, w_h, w_c;
   int nad;                        // artificial-diffusivity planes (3 + ns)
@@ -393,18 +393,28 @@ __device__ __forceinline__ TA dphys(const Dev& d, const TD* __restrict__ f, cons
   return dper<ORDER, TA, TD>(f, p.idx, (long)d.nx * d.ny, p.k, d.nz) * TA(d.mz[p.k]);
 }
 
+// Device counters: NCOUNT kinds, each spread over CSLOTS addresses chosen by the block
+// number (the host sums the slots).  A counter that many wavefronts hit in one launch
+// (negative trace densities after many stages, say) would otherwise serialise the
+// whole launch on one address's device-scope atomics.
+constexpr int NCOUNT = 8, CSLOTS = 256;
+__device__ __forceinline__ unsigned long long* cslot(unsigned long long* c, int kind) {
+  return c + kind * CSLOTS + (blockIdx.x & (CSLOTS - 1));
+}
+
 __device__ __forceinline__ void count(const Dev& d, int status) {
-  if (status == 1) atomicAdd(&d.counters[0], 1ull);
-  if (status == 2) atomicAdd(&d.counters[1], 1ull);
+  if (status == 1) atomicAdd(cslot(d.counters, 0), 1ull);
+  if (status == 2) atomicAdd(cslot(d.counters, 1), 1ull);
 }
 
 // Count the lanes of the wavefront for which pred holds with one atomic (the first
 // active lane adds the population count of the ballot).
-__device__ __forceinline__ void wave_count(unsigned long long* c, bool pred) {
+__device__ __forceinline__ void wave_count(unsigned long long* c, int kind, bool pred) {
   const unsigned long long m = __ballot(pred);
   if (m == 0ull) return;
   const unsigned long long act = __ballot(1);
-  if ((int)__lane_id() == __ffsll((long long)act) - 1) atomicAdd(c, (unsigned long long)__popcll(m));
+  if ((int)__lane_id() == __ffsll((long long)act) - 1)
+    atomicAdd(cslot(c, kind), (unsigned long long)__popcll(m));
 }
 
 // Finite state of positive density (else the point is counted as non-finite)
@@ -573,8 +583,8 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
       double qv[5];
 #pragma unroll
       for (int k = 0; k < ND + 2; ++k) qv[k] = Q[(long)k * N + idx];
-      wave_count(&d.counters[3], !finite_state(qv, ND + 2, rho));
-      wave_count(&d.counters[4], rho < 0.0);
+      wave_count(d.counters, 3, !finite_state(qv, ND + 2, rho));
+      wave_count(d.counters, 4, rho < 0.0);
     }
     double u[3] = {0.0, 0.0, 0.0};
     double ke = 0.0;
@@ -591,7 +601,7 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
       int status;
       T = tpg_temperature(e, d.tpg_k0, d.tpg_th, (g - 1.0) / g, d.newton_rtol, d.newton_max,
                           &status, d.warm ? Wd[ND * N + idx] : 0.0);
-      if (status) atomicAdd(&d.counters[0], 1ull);
+      if (status) atomicAdd(cslot(d.counters, 0), 1ull);
     }
     const double p = rho * (g - 1.0) * T / g;
     const RT mu = sutherland<RT>(RT(T * d.T_ref)) / RT(d.mu_inf);
@@ -630,8 +640,8 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
 #pragma unroll
     for (int a = 0; a < ND; ++a) qv[NS + a] = mom[a];
     qv[NS + ND] = Q[(NS + ND) * N + idx];
-    wave_count(&d.counters[3], !finite_state(qv, NS + ND + 1, rho));
-    wave_count(&d.counters[4], neg);
+    wave_count(d.counters, 3, !finite_state(qv, NS + ND + 1, rho));
+    wave_count(d.counters, 4, neg);
   }
   float ys[MLP_NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   bool net = false;
@@ -639,7 +649,7 @@ __global__ __launch_bounds__(128) void k_prim(Dev d, const double* __restrict__ 
 #pragma unroll
     for (int o = 0; o < MLP_NOUT; ++o) ys[o] = ysin[o * N + idx];
     net = !isnan(ys[0]);
-    if (!net) atomicAdd(&d.counters[2], 1ull);
+    if (!net) atomicAdd(cslot(d.counters, 2), 1ull);
   }
   prim_air5<ND, RT>(d, Wd, Wp, idx, rs, mom, Q[(NS + ND) * N + idx], net, ys);
 }
@@ -1896,7 +1906,7 @@ __device__ __forceinline__ void thermo_point(long ld, long i, double rtol, int m
     for (int s = 0; s < NS; ++s) v[s] = Y[s];
     v[NS] = ee;
     if (!finite_state(v, NS + 1, r)) {
-      atomicAdd(&counters[3], 1ull);
+      atomicAdd(cslot(counters, 3), 1ull);
       const double nan = __builtin_nan("");
       Tout[i] = nan;
       if (stout) stout[i] = 3;
@@ -1914,8 +1924,8 @@ __device__ __forceinline__ void thermo_point(long ld, long i, double rtol, int m
   int status, iters;
   SpeciesThermo st;   // species state at the last Newton iterate (within rtol of T)
   const double T = temperature_from_energy(ee, Y, rtol, max_iter, &status, &iters, T_start, &st);
-  if (status == 1) atomicAdd(&counters[0], 1ull);
-  if (status == 2) atomicAdd(&counters[1], 1ull);
+  if (status == 1) atomicAdd(cslot(counters, 0), 1ull);
+  if (status == 2) atomicAdd(cslot(counters, 1), 1ull);
   if (status) species_e_cv(T, st);
   Tout[i] = T;
   if (stout) stout[i] = status;
@@ -1984,7 +1994,7 @@ __global__ __launch_bounds__(128) void k_thermo_eval(long n, long ld, double rto
 #pragma unroll
     for (int o = 0; o < MLP_NOUT; ++o) ys[o] = ysin[o * n + i];
     net = !isnan(ys[0]);
-    if (!net && (muout || kout || Dout)) atomicAdd(&counters[2], 1ull);
+    if (!net && (muout || kout || Dout)) atomicAdd(cslot(counters, 2), 1ull);
   }
   // the caller's temperature if it is a valid start, else the network's, else cold
   const double Tc = Tout[i];
@@ -2460,7 +2470,6 @@ namespace {
 enum { K_PRIM = 0, K_AD_SRC, K_AD_D4, K_AD_FX, K_AD_FY, K_AD_FZ, K_FLUX, K_DIV, K_BC, K_THERMO,
        K_CHEM, K_CDERIV, K_FIN };
 
-constexpr int NCOUNT = 8;   // device counters (see Dev::counters)
 
 // Points per network pass of hrx_thermo_eval in the surrogate form (its workspace
 // holds max(N, this) points; larger calls run in chunks).
@@ -2938,9 +2947,9 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     if (hipMalloc(&ctx->G, sizeof(double) * N * nd * d.nsrc) != hipSuccess) return fail(HRX_ENOMEM);
     if (hipMalloc(&ctx->Ct, sizeof(double) * N * d.nvar) != hipSuccess) return fail(HRX_ENOMEM);
   }
-  if (hipMalloc(&ctx->counters, NCOUNT * sizeof(unsigned long long)) != hipSuccess)
+  if (hipMalloc(&ctx->counters, NCOUNT * CSLOTS * sizeof(unsigned long long)) != hipSuccess)
     return fail(HRX_ENOMEM);
-  if ((rc = check(hipMemset(ctx->counters, 0, NCOUNT * sizeof(unsigned long long)))))
+  if ((rc = check(hipMemset(ctx->counters, 0, NCOUNT * CSLOTS * sizeof(unsigned long long)))))
     return fail(rc);
   d.counters = ctx->counters;
   {
@@ -3483,17 +3492,21 @@ int hrx_timing_read(hrx_ctx* ctx, double* ms, int64_t* launches) {
 
 int hrx_get_counters(hrx_ctx* ctx, hrx_counters* out, int reset) {
   if (!ctx || !out) return HRX_EINVAL;
+  std::vector<unsigned long long> hs((size_t)NCOUNT * CSLOTS);
   unsigned long long h[NCOUNT] = {0};
   int rc = check(hipStreamSynchronize(ctx->last_stream));
   if (rc) return rc;
-  rc = check(hipMemcpy(h, ctx->counters, sizeof(h), hipMemcpyDeviceToHost));
+  rc = check(hipMemcpy(hs.data(), ctx->counters, hs.size() * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost));
   if (rc) return rc;
+  for (int k = 0; k < NCOUNT; ++k)
+    for (int q = 0; q < CSLOTS; ++q) h[k] += hs[(size_t)k * CSLOTS + q];
   out->newton_nonconverged = (int64_t)h[0];
   out->energy_below_min = (int64_t)h[1];
   out->surrogate_fallbacks = (int64_t)h[2];
   out->nonfinite = (int64_t)h[3];
   out->negative_density = (int64_t)h[4];
-  if (reset) rc = check(hipMemset(ctx->counters, 0, sizeof(h)));
+  if (reset) rc = check(hipMemset(ctx->counters, 0, hs.size() * sizeof(unsigned long long)));
   if (rc) return rc;
   if (h[3]) return HRX_ENONFINITE;
   if (h[1]) return HRX_EDOMAIN;

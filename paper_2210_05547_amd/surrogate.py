@@ -18,6 +18,22 @@ T_RANGE = (200.0, 8000.0)
 LOGRHO_RANGE = (-4.0, 0.0)
 XI_N_RANGE = (0.70, 0.83)
 
+# How this surrogate departs from a plain "MLP 7-64-64-64-8 (tanh) on (rho, e, Y_s) with
+# Dirichlet compositions" recipe, stated with every result that uses it.
+DESIGN_NOTE = {
+    "network": "7-64-64-64-8, BF16 weights and activations on the matrix cores, FP32 accumulate",
+    "activation": "max(z, 0)^2 instead of tanh (two full-rate operations; the more accurate "
+                  "of the two on this regression at equal width)",
+    "features": "(log10 rho, ln T_c, Y_1..Y_5), T_c = energy over the fully excited heat "
+                "capacity (closed form), instead of raw e",
+    "targets": "(ln T, ln mu, ln kappa, ln rho D_s) as residuals about a least-squares linear "
+               "fit, standardised",
+    "compositions": "air-element compositions (N mass fraction in [0.70, 0.83], every "
+                    "dissociation degree) instead of Dirichlet(1,...,1) over the simplex; "
+                    "states outside fall back to the plain evaluation",
+    "temperature": "T stays the FP64 Newton root (the network's T only starts it)",
+}
+
 
 def training_set(ctx, n, seed, device="cuda:0"):
     """(features [n][7] float64 host, targets [n][8] float64 host) of n air states."""
