@@ -201,6 +201,19 @@ int hrx_thermo_eval(hrx_ctx *ctx, int64_t n, const double *rho, const double *e,
 int hrx_chem_source(hrx_ctx *ctx, int64_t n, const double *rho_s, const double *T,
                     double *wdot, void *hip_stream);
 
+/* Compositions of local thermodynamic equilibrium (Sec. 2.2.1, frozen and equilibrium
+ * flow: the composition that minimises the mixture's free energy), SI: density rho [n]
+ * kg/m^3, temperature T [n] K and the element-N mass fraction xiN [n] (NULL: the
+ * context's free stream, Y_inf) -> mass fractions Y [5][n] and status [n] (NULL to skip):
+ * 0 converged, 1 not converged in newton_max_iter, 3 an input not finite, rho or T not
+ * positive, or xiN outside [0, 1] (Y NaN).  The minimum is found from its stationarity:
+ * every species at (p0/(R_u T)) exp(-g_s/(R_u T) + sum_e a_es lambda_e) with the element
+ * potentials lambda_e, which Newton's method takes from the two element balances
+ * (stopping at a step below newton_rtol); K_c and g_s as in hrx_chem_source.  ctx:
+ * air5 context. */
+int hrx_equilibrium(hrx_ctx *ctx, int64_t n, const double *rho, const double *T,
+                    const double *xiN, double *Y, int32_t *status, void *hip_stream);
+
 /* Accumulated failure counters; synchronises the context's last stream.  reset != 0
  * zeroes them afterwards.  Returns HRX_OK when no point failed since the last reset,
  * else the most severe failure counted (HRX_ENONFINITE, then HRX_EDOMAIN, then
@@ -273,11 +286,12 @@ int hrx_mlp_train_step(hrx_ctx *ctx, int64_t n, const int32_t *idx, const float 
  * inside div), 9 thermo_eval,
  * 10 chem_source (in the surrogate form the network pass is counted with prim and
  * thermo_eval), 11 the compact scheme's line solves (gradients and divergence), 12 the
- * compact scheme's pointwise pass (sources, sponge, boundary rows, update).
+ * compact scheme's pointwise pass (sources, sponge, boundary rows, update), 13
+ * equilibrium.
  * hrx_timing_read synchronises, returns the summed milliseconds and launch counts
  * per kernel since enabling (arrays of HRX_NKERNELS, host) and keeps timing on.
  * hrx_timing_enable(ctx, 0) stops and releases the events. */
-#define HRX_NKERNELS 13
+#define HRX_NKERNELS 14
 int hrx_timing_enable(hrx_ctx *ctx, int on);
 int hrx_timing_read(hrx_ctx *ctx, double *ms /* (host) */, int64_t *launches /* (host) */);
 

@@ -450,4 +450,82 @@ HRX_HD void vib_em1(double T, double* em1) {
   for (int s = 0; s < 3; ++s) em1[s] = expm1(theta_vib(s) / T);
 }
 
+// ----------------------------------------------------------------- equilibrium (LTE)
+// Composition of local thermodynamic equilibrium (Sec. 2.2.1, frozen and equilibrium
+// flow): at density rho [kg/m^3] and temperature T [K], the minimum of the mixture's free
+// energy over the compositions whose element-N mass fraction is xiN.  At that minimum
+// every species sits at c_s = (p0/(R_u T)) exp(-g_s/(R_u T) + sum_e a_es lambda_e): the
+// atoms carry the element potentials, u = ln c_N and w = ln c_O, and the molecules follow
+// from the dissociation equilibria, c_N2 = c_N^2 / K_1, c_O2 = c_O^2 / K_2,
+// c_NO = c_N c_O / K_3 (K_c from the Gibbs energies, as the chemistry uses them).
+// Newton's method on the two element balances in (u, w), each step limited to 1 in
+// either logarithm, from the smaller of the atom-rich and the molecule-rich limits;
+// stops after the step that is below rtol (a relative change of the concentrations).
+// One element alone has the closed form c = 2 n / (1 + sqrt(1 + 8 n / K)).
+// status: 0 converged, 1 not converged in max_iter, 3 invalid input (Y = NaN).
+HRX_HD void equilibrium_composition(double rho, double T, double xiN, double rtol, int max_iter,
+                                    double* Y, int* status) {
+  if (!(rho > 0.0) || !(T > 0.0) || !(xiN >= 0.0) || !(xiN <= 1.0) || !isfinite(rho) ||
+      !isfinite(T)) {
+    for (int s = 0; s < NS; ++s) Y[s] = __builtin_nan("");
+    *status = 3;
+    return;
+  }
+  const double lnT = log(T), iT = 1.0 / T;
+  double em1[3], g[NS];
+  vib_em1(T, em1);
+  gibbs_over_RT(iT, lnT, em1, g);
+  const double lnc0 = log(P0 / RU) - lnT;                 // ln(p0/(R_u T))
+  const double lK1 = lnc0 - (2.0 * g[3] - g[0]);          // N2 = 2N
+  const double lK2 = lnc0 - (2.0 * g[4] - g[1]);          // O2 = 2O
+  const double lK3 = lnc0 - (g[3] + g[4] - g[2]);         // NO = N + O
+  const double nN = rho * xiN / molar_mass(3);
+  const double nO = rho * (1.0 - xiN) / molar_mass(4);
+  const double irho = 1.0 / rho;
+  *status = 0;
+  if (nN == 0.0 || nO == 0.0) {
+    // one element: atoms c and molecules c^2/K with 2 c^2 / K + c = n
+    const bool n_only = nO == 0.0;
+    const double ne = n_only ? nN : nO, lK = n_only ? lK1 : lK2;
+    // (the molecule from its own equilibrium c^2 / K: as 1 - Y_atom it would lose its
+    // digits where it is a trace species)
+    const double c = 2.0 * ne / (1.0 + sqrt(1.0 + 8.0 * exp(log(ne) - lK)));
+    for (int s = 0; s < NS; ++s) Y[s] = 0.0;
+    Y[n_only ? 3 : 4] = c * (n_only ? molar_mass(3) : molar_mass(4)) * irho;
+    Y[n_only ? 0 : 1] = exp(2.0 * log(c) - lK) * (n_only ? molar_mass(0) : molar_mass(1)) * irho;
+    return;
+  }
+  double u = fmin(log(nN), 0.5 * (lK1 + log(0.5 * nN)));
+  double w = fmin(log(nO), 0.5 * (lK2 + log(0.5 * nO)));
+  const double inN = 1.0 / nN, inO = 1.0 / nO;
+  bool conv = false;
+  for (int it = 0; it < max_iter; ++it) {
+    const double cN = exp(u), cO = exp(w);
+    const double cN2 = exp(2.0 * u - lK1), cO2 = exp(2.0 * w - lK2), cNO = exp(u + w - lK3);
+    const double F1 = (2.0 * cN2 + cNO + cN) * inN - 1.0;
+    const double F2 = (2.0 * cO2 + cNO + cO) * inO - 1.0;
+    const double a = (4.0 * cN2 + cNO + cN) * inN, b = cNO * inN;
+    const double c = cNO * inO, d = (4.0 * cO2 + cNO + cO) * inO;
+    const double idet = 1.0 / (a * d - b * c);
+    double du = -(d * F1 - b * F2) * idet, dw = -(a * F2 - c * F1) * idet;
+    const double step = fmax(fabs(du), fabs(dw));
+    if (step > 1.0) {
+      du /= step;
+      dw /= step;
+    }
+    u += du;
+    w += dw;
+    if (step <= rtol) {
+      conv = true;
+      break;
+    }
+  }
+  if (!conv) *status = 1;
+  Y[0] = exp(2.0 * u - lK1) * molar_mass(0) * irho;
+  Y[1] = exp(2.0 * w - lK2) * molar_mass(1) * irho;
+  Y[2] = exp(u + w - lK3) * molar_mass(2) * irho;
+  Y[3] = exp(u) * molar_mass(3) * irho;
+  Y[4] = exp(w) * molar_mass(4) * irho;
+}
+
 }  // namespace hrx

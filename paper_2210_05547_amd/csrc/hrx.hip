@@ -2021,6 +2021,27 @@ __global__ __launch_bounds__(128) void k_chem_source(long n, const double* __res
   for (int s = 0; s < NS; ++s) wdot[s * n + i] = double(w[s]);
 }
 
+// LTE compositions of n points: rho [n], T [n], xiN [n] (or the context's free-stream
+// value when null) -> Y [5][n], status [n] (may be null); counted like the inversion.
+__global__ __launch_bounds__(128) void k_equilibrium(long n, double rtol, int max_iter,
+                                                     const double* __restrict__ rho,
+                                                     const double* __restrict__ T,
+                                                     const double* __restrict__ xiN, double xi0,
+                                                     double* __restrict__ Y,
+                                                     int32_t* __restrict__ stout,
+                                                     unsigned long long* counters) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double y[NS];
+  int status;
+  equilibrium_composition(rho[i], T[i], xiN ? xiN[i] : xi0, rtol, max_iter, y, &status);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Y[s * n + i] = y[s];
+  if (stout) stout[i] = status;
+  if (status == 1) atomicAdd(cslot(counters, 0), 1ull);
+  if (status == 3) atomicAdd(cslot(counters, 3), 1ull);
+}
+
 // ------------------------------------------------------------------ surrogate network
 // theta (FP32 flat) -> swizzled BF16 weights for the matrix cores, FP32 biases, and a
 // BF16-rounded FP32 copy of the weights in flat order for the backward pass.
@@ -2468,7 +2489,7 @@ struct hrx_ctx {
 namespace {
 
 enum { K_PRIM = 0, K_AD_SRC, K_AD_D4, K_AD_FX, K_AD_FY, K_AD_FZ, K_FLUX, K_DIV, K_BC, K_THERMO,
-       K_CHEM, K_CDERIV, K_FIN };
+       K_CHEM, K_CDERIV, K_FIN, K_EQUIL };
 
 
 // Points per network pass of hrx_thermo_eval in the surrogate form (its workspace
@@ -3458,6 +3479,22 @@ int hrx_chem_source(hrx_ctx* ctx, int64_t n, const double* rho_s, const double* 
       k_chem_source<float><<<blocks_for(n, 128), 128, 0, st>>>(n, rho_s, T, wdot);
     else
       k_chem_source<double><<<blocks_for(n, 128), 128, 0, st>>>(n, rho_s, T, wdot);
+  });
+  return check(hipGetLastError());
+}
+
+int hrx_equilibrium(hrx_ctx* ctx, int64_t n, const double* rho, const double* T,
+                    const double* xiN, double* Y, int32_t* status, void* hip_stream) {
+  if (!ctx || n < 0 || (n > 0 && (!rho || !T || !Y))) return HRX_EINVAL;
+  if (ctx->cfg.gas != HRX_GAS_AIR5) return HRX_EINVAL;
+  if (n == 0) return HRX_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  const double* Yi = ctx->cfg.Y_inf;
+  const double xi0 = Yi[0] + Yi[2] * (molar_mass(3) / molar_mass(2)) + Yi[3];
+  timed(ctx, K_EQUIL, st, [&] {
+    k_equilibrium<<<blocks_for(n, 128), 128, 0, st>>>(n, ctx->dev.newton_rtol, ctx->dev.newton_max,
+                                                      rho, T, xiN, xi0, Y, status, ctx->counters);
   });
   return check(hipGetLastError());
 }

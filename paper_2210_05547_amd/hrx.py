@@ -96,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.hrx_thermo_eval.restype = C.c_int
     lib.hrx_chem_source.argtypes = [vp, i64, dp, dp, dp, vp]
     lib.hrx_chem_source.restype = C.c_int
+    lib.hrx_equilibrium.argtypes = [vp, i64, dp, dp, dp, dp, dp, vp]
+    lib.hrx_equilibrium.restype = C.c_int
     lib.hrx_get_counters.argtypes = [vp, C.POINTER(Counters), C.c_int]
     lib.hrx_get_counters.restype = C.c_int
     lib.hrx_timing_enable.argtypes = [vp, C.c_int]
@@ -219,7 +221,7 @@ class Context:
 
 
 KERNEL_NAMES = ("prim", "ad_src", "ad_d4", "ad_filter_x", "ad_filter_y", "ad_filter_z", "flux",
-                "div", "bc", "thermo_eval", "chem_source", "cderiv", "fin")
+                "div", "bc", "thermo_eval", "chem_source", "cderiv", "fin", "equilibrium")
 
 
 def timing_enable(ctx, on=True):
@@ -259,6 +261,12 @@ def thermo_eval(ctx, n, rho, e, Y, T, p=None, h=None, mu=None, kappa=None, D=Non
 
 def chem_source(ctx, n, rho_s, T, wdot, stream=None):
     _check(_lib.hrx_chem_source(ctx._h, int(n), _ptr(rho_s), _ptr(T), _ptr(wdot), _stream(stream)))
+
+
+def equilibrium(ctx, n, rho, T, Y, xiN=None, status=None, stream=None):
+    """LTE compositions Y [5][n] at (rho, T, xiN) (hrx_equilibrium)."""
+    _check(_lib.hrx_equilibrium(ctx._h, int(n), _ptr(rho), _ptr(T), _ptr(xiN), _ptr(Y),
+                                _ptr(status), _stream(stream)))
 
 
 # ---------------------------------------------------------------- surrogate network
