@@ -44,3 +44,19 @@ def oracle_window(cfg, info, Q, Qr, ia, ib, jb):
     Qw = np.ascontiguousarray(Q[..., :jb, ia:ib])
     Qrw = np.ascontiguousarray(Qr[..., :jb, ia:ib])
     return case, Qw, Qrw
+
+
+def tie_free_rows(acts, margin=1e-5):
+    """Rows of the oracle's forward pass whose hidden activations (the inputs of layers
+    2..4, rounded to BF16 there) all lie farther than margin (relative) from a BF16
+    rounding midpoint, or are exactly zero (inactive units)."""
+    ok = np.ones(acts[0].shape[0], dtype=bool)
+    for a in acts[1:4]:
+        f = np.abs(a).astype(np.float32)
+        u = f.view(np.uint32)
+        lo = (u & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+        hi = ((u & np.uint32(0xFFFF0000)) + np.uint32(0x10000)).view(np.float32).astype(np.float64)
+        mid = 0.5 * (lo + hi)
+        d = np.abs(f.astype(np.float64) - mid) / np.maximum(f.astype(np.float64), 1e-300)
+        ok &= np.all((f == 0.0) | (d > margin), axis=1)
+    return ok
