@@ -259,6 +259,25 @@ int hrx_mlp_set_norm(hrx_ctx *ctx, const float *in_mean, const float *in_std,
  * hrx_mlp_set_norm above -- the inputs a training set needs.  No hull check. */
 int hrx_mlp_features(hrx_ctx *ctx, int64_t n, const double *rho, const double *e,
                      const double *Y, float *f, void *hip_stream);
+/* A training set from SI states rho [n], e [n], Y [5][n] (device): raw features
+ * F [n][7] (FP64: log10 rho, ln T_c, Y_1..Y_5 as for hrx_mlp_set_norm) and raw targets
+ * T [n][8] (ln T, ln mu, ln kappa, ln(rho D_1..5)) of the plain FP64 evaluation (cold
+ * energy inversion); status [n] as for hrx_thermo_eval (may be NULL). */
+int hrx_mlp_dataset(hrx_ctx *ctx, int64_t n, const double *rho, const double *e,
+                    const double *Y, double *F, double *T, int32_t *status, void *hip_stream);
+/* The composition around the network from a training set F [n][7], T [n][8] (device,
+ * FP64): the features' mean m and standard deviation s (population), the least-squares
+ * linear fit L [8][8] of every target in a = (1, (f - m)/s), and the mean rm and
+ * standard deviation rs of the residuals r = t - L a (all sums in FP64 on the device, the
+ * 8 x 8 normal equations solved on the host); writes the standardised rows
+ * Xs [n][7] = (f - m)/s and Ys [n][8] = (r - rm)/rs (FP32, device), installs the
+ * composition with the given training hull as hrx_mlp_set_norm does, and returns
+ * (host, may be NULL) stats [94] = m [7], s [7], rm [8], rs [8], L [8][8].  Set-up call
+ * (synchronises the stream); requires hrx_mlp_init; HRX_EINVAL for n < 2 or a zero
+ * spread. */
+int hrx_mlp_fit(hrx_ctx *ctx, int64_t n, const double *F, const double *T, float *Xs, float *Ys,
+                double log10rho_min, double log10rho_max, double T_lo, double T_hi,
+                double xiN_min, double xiN_max, double *stats /* (host) */, void *hip_stream);
 /* HRX_THERMO_SURROGATE makes hrx_thermo_eval, hrx_rhs_eval and hrx_rk_stage (air5) take
  * mu, kappa, D_s from the network and start the FP64 energy inversion from its T, for
  * points inside the hull; points outside fall back to the plain evaluation and are

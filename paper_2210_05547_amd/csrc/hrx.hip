@@ -2327,6 +2327,148 @@ __global__ __launch_bounds__(256) void k_mlp_features(long n, const double* __re
   for (int k = 0; k < MLP_NIN; ++k) f[i * MLP_NIN + k] = v[k];
 }
 
+// ---- training sets of the surrogate, prepared on the device
+// Raw features f (FP64 copy of the network's inputs, surrogate_features in FP64) and raw
+// targets t = (ln T, ln mu, ln kappa, ln(rho D_1..5)) of the plain FP64 evaluation (cold
+// energy inversion) of n SI states, rows f [n][7], t [n][8]; status as thermo_eval.
+__global__ __launch_bounds__(128) void k_mlp_dataset(long n, double rtol, int max_iter,
+                                                     const double* __restrict__ rho,
+                                                     const double* __restrict__ e,
+                                                     const double* __restrict__ Yin,
+                                                     double* __restrict__ F,
+                                                     double* __restrict__ Tt,
+                                                     int32_t* __restrict__ stout,
+                                                     unsigned long long* counters) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double Y[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Y[s] = Yin[s * n + i];
+  const double r = rho[i], ee = e[i];
+  double ef = 0.0, cf = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    ef += Y[s] * (hf0_molar(s) / molar_mass(s));
+    cf += Y[s] * (gas_const(s) * (is_diatomic(s) ? 3.5 : 1.5));
+  }
+  F[i * MLP_NIN + 0] = log10(r);
+  F[i * MLP_NIN + 1] = log((ee - ef) / cf);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) F[i * MLP_NIN + 2 + s] = Y[s];
+  const float ys0[MLP_NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  double T, mu, kap, D[NS];
+  int32_t st;
+  // one state through the plain evaluation (leading dimension 1: scalar outputs)
+  thermo_point<double>(1, 0, rtol, max_iter, r, ee, Y, 0.0, false, ys0, &T, nullptr, nullptr,
+                       &mu, &kap, D, &st, counters);
+  if (stout) stout[i] = st;
+  Tt[i * MLP_NOUT + 0] = log(T);
+  Tt[i * MLP_NOUT + 1] = log(mu);
+  Tt[i * MLP_NOUT + 2] = log(kap);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Tt[i * MLP_NOUT + 3 + s] = log(D[s] * r);
+}
+
+// Moments of a training set for the surrogate's composition, per wavefront (lane 0
+// writes the wavefront's sums to part[wave][K]; the host adds the wavefronts):
+//   MODE 0: sum f_k                        (K = 7)
+//   MODE 1: sum (f_k - m_k)^2              (K = 7)
+//   MODE 2: sum a_i a_j (i <= j), sum a_i t_o with a = (1, (f - m)/s)   (K = 36 + 64)
+//   MODE 3: sum r_o with r = t - L a       (K = 8)
+//   MODE 4: sum (r_o - rm_o)^2             (K = 8)
+// sv (device): m [7], 1/s [7], L [8][8] (row o: coefficients of a), rm [8].
+template <int MODE>
+__global__ __launch_bounds__(256) void k_fit_moments(long n, const double* __restrict__ F,
+                                                     const double* __restrict__ Tt,
+                                                     const double* __restrict__ sv,
+                                                     double* __restrict__ part) {
+  constexpr int K = MODE < 2 ? MLP_NIN : (MODE == 2 ? 36 + 64 : MLP_NOUT);
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    double f[MLP_NIN];
+#pragma unroll
+    for (int k = 0; k < MLP_NIN; ++k) f[k] = F[i * MLP_NIN + k];
+    if (MODE == 0) {
+#pragma unroll
+      for (int k = 0; k < MLP_NIN; ++k) acc[k] += f[k];
+      continue;
+    }
+    if (MODE == 1) {
+#pragma unroll
+      for (int k = 0; k < MLP_NIN; ++k) {
+        const double d = f[k] - sv[k];
+        acc[k] += d * d;
+      }
+      continue;
+    }
+    double a[8];
+    a[0] = 1.0;
+#pragma unroll
+    for (int k = 0; k < MLP_NIN; ++k) a[1 + k] = (f[k] - sv[k]) * sv[MLP_NIN + k];
+    if (MODE == 2) {
+      int q = 0;
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int r = p; r < 8; ++r) acc[q++] += a[p] * a[r];
+#pragma unroll
+      for (int o = 0; o < MLP_NOUT; ++o) {
+        const double t = Tt[i * MLP_NOUT + o];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) acc[36 + o * 8 + p] += a[p] * t;
+      }
+      continue;
+    }
+#pragma unroll
+    for (int o = 0; o < MLP_NOUT; ++o) {
+      double r = Tt[i * MLP_NOUT + o];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) r -= sv[2 * MLP_NIN + o * 8 + p] * a[p];
+      if (MODE == 3) {
+        acc[o] += r;
+      } else {
+        const double d = r - sv[2 * MLP_NIN + 64 + o];
+        acc[o] += d * d;
+      }
+    }
+  }
+  const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double v = acc[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    if ((threadIdx.x & 63) == 0) part[wave * K + k] = v;
+  }
+}
+
+// Standardised training rows: x = (f - m)/s (FP32) and y = (t - L a - rm)/rs (FP32).
+__global__ __launch_bounds__(256) void k_fit_apply(long n, const double* __restrict__ F,
+                                                   const double* __restrict__ Tt,
+                                                   const double* __restrict__ sv,
+                                                   float* __restrict__ Xs,
+                                                   float* __restrict__ Ys) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a[8];
+  a[0] = 1.0;
+#pragma unroll
+  for (int k = 0; k < MLP_NIN; ++k) {
+    a[1 + k] = (F[i * MLP_NIN + k] - sv[k]) * sv[MLP_NIN + k];
+    Xs[i * MLP_NIN + k] = (float)a[1 + k];
+  }
+#pragma unroll
+  for (int o = 0; o < MLP_NOUT; ++o) {
+    double r = Tt[i * MLP_NOUT + o];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) r -= sv[2 * MLP_NIN + o * 8 + p] * a[p];
+    Ys[i * MLP_NOUT + o] = (float)((r - sv[2 * MLP_NIN + 64 + o]) * sv[2 * MLP_NIN + 72 + o]);
+  }
+}
+
 // network outputs -> (ln T, ln mu, ln kappa, ln(rho D_s)) (SI), FP32
 __device__ __forceinline__ void surrogate_outputs(const MlpNorm& nm, const float* x,
                                                   const float* y, float* ys) {
@@ -2471,6 +2613,7 @@ struct hrx_ctx {
   float *bias = nullptr, *wq = nullptr, *save = nullptr, *ybuf = nullptr, *dybuf = nullptr,
         *delta = nullptr, *wpart = nullptr;
   uint16_t* wsw = nullptr;
+  double* fitbuf = nullptr;      // hrx_mlp_fit: statistics and per-wavefront moments
   MlpNorm* norm_dev = nullptr;   // composition statistics and hull (device copy)
   float* ys = nullptr;       // network outputs of the surrogate form, [8][ys_cap]
   int64_t ys_cap = 0;
@@ -2491,6 +2634,10 @@ namespace {
 enum { K_PRIM = 0, K_AD_SRC, K_AD_D4, K_AD_FX, K_AD_FY, K_AD_FZ, K_FLUX, K_DIV, K_BC, K_THERMO,
        K_CHEM, K_CDERIV, K_FIN, K_EQUIL };
 
+
+// Doubles of the surrogate fit's workspace: statistics, then 100 moments per wavefront of
+// 256 blocks of 4 wavefronts (hrx_mlp_fit)
+constexpr size_t FIT_DOUBLES = 2 * 7 + 64 + 2 * 8 + 256 * 4 * 100;
 
 // Points per network pass of hrx_thermo_eval in the surrogate form (its workspace
 // holds max(N, this) points; larger calls run in chunks).
@@ -2709,7 +2856,7 @@ void hrx_destroy(hrx_ctx* c) {
   (void)hipFree(c->norm_dev);
   for (void* q : {(void*)c->theta, (void*)c->adam_m, (void*)c->adam_v, (void*)c->grad,
                   (void*)c->bias, (void*)c->wq, (void*)c->save, (void*)c->ybuf, (void*)c->dybuf,
-                  (void*)c->delta, (void*)c->wpart, (void*)c->wsw})
+                  (void*)c->delta, (void*)c->wpart, (void*)c->wsw, (void*)c->fitbuf})
     (void)hipFree(q);
   delete c;
 }
@@ -3570,7 +3717,8 @@ int hrx_mlp_init(hrx_ctx* ctx, int64_t max_batch) {
       hipMalloc(&ctx->ybuf, B * MLP_NOUT * sizeof(float)) != hipSuccess ||
       hipMalloc(&ctx->dybuf, B * MLP_NOUT * sizeof(float)) != hipSuccess ||
       hipMalloc(&ctx->delta, B * 200 * sizeof(float)) != hipSuccess ||
-      hipMalloc(&ctx->wpart, (size_t)WG_MAXCH * P) != hipSuccess)
+      hipMalloc(&ctx->wpart, (size_t)WG_MAXCH * P) != hipSuccess ||
+      hipMalloc(&ctx->fitbuf, FIT_DOUBLES * sizeof(double)) != hipSuccess)
     return HRX_ENOMEM;
   if (hipMemset(ctx->adam_m, 0, P) != hipSuccess || hipMemset(ctx->adam_v, 0, P) != hipSuccess)
     return HRX_EHIP;
@@ -3649,6 +3797,191 @@ int hrx_mlp_features(hrx_ctx* ctx, int64_t n, const double* rho, const double* e
   ctx->last_stream = st;
   k_mlp_features<<<blocks_for(n, 256), 256, 0, st>>>(n, rho, e, Y, f);
   return check(hipGetLastError());
+}
+
+int hrx_mlp_dataset(hrx_ctx* ctx, int64_t n, const double* rho, const double* e,
+                    const double* Y, double* F, double* T, int32_t* status, void* hip_stream) {
+  if (!ctx || n < 0 || (n > 0 && (!rho || !e || !Y || !F || !T))) return HRX_EINVAL;
+  if (ctx->cfg.gas != HRX_GAS_AIR5) return HRX_EINVAL;
+  if (n == 0) return HRX_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  k_mlp_dataset<<<blocks_for(n, 128), 128, 0, st>>>(n, ctx->dev.newton_rtol, ctx->dev.newton_max,
+                                                    rho, e, Y, F, T, status, ctx->counters);
+  return check(hipGetLastError());
+}
+
+}  // extern "C"
+
+namespace {
+// Eigen-decomposition of a symmetric 8 x 8 matrix by cyclic Jacobi rotations (Golub and
+// Van Loan, the symmetric Schur step): A = V diag(lam) V^T, V's columns the eigenvectors.
+// A is overwritten.  Returns false when the sweeps do not converge.
+bool sym_eigen8(double A[8][8], double V[8][8], double lam[8]) {
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+  bool done = false;
+  for (int sweep = 0; sweep < 60 && !done; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) (i == j ? dia : off) += A[i][j] * A[i][j];
+    if (!(off <= 1e-28 * dia)) {
+      for (int p = 0; p < 7; ++p)
+        for (int q = p + 1; q < 8; ++q) {
+          if (A[p][q] == 0.0) continue;
+          const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+          for (int k = 0; k < 8; ++k) {      // A J
+            const double akp = A[k][p], akq = A[k][q];
+            A[k][p] = c * akp - s * akq;
+            A[k][q] = s * akp + c * akq;
+          }
+          for (int k = 0; k < 8; ++k) {      // J^T A
+            const double apk = A[p][k], aqk = A[q][k];
+            A[p][k] = c * apk - s * aqk;
+            A[q][k] = s * apk + c * aqk;
+          }
+          for (int k = 0; k < 8; ++k) {      // V J
+            const double vkp = V[k][p], vkq = V[k][q];
+            V[k][p] = c * vkp - s * vkq;
+            V[k][q] = s * vkp + c * vkq;
+          }
+        }
+    } else {
+      done = true;
+    }
+  }
+  for (int i = 0; i < 8; ++i) lam[i] = A[i][i];
+  return done;
+}
+
+// Sums of the wavefront partials of one moments pass (synchronises the stream).
+constexpr int FIT_NSV = 2 * MLP_NIN + 64 + 2 * MLP_NOUT, FIT_BLOCKS = 256;
+template <int MODE>
+int fit_pass(long n, const double* F, const double* Tt, const double* sv_dev, double* part,
+             int nblocks, hipStream_t st, std::vector<double>& out) {
+  constexpr int K = MODE < 2 ? MLP_NIN : (MODE == 2 ? 36 + 64 : MLP_NOUT);
+  k_fit_moments<MODE><<<nblocks, 256, 0, st>>>(n, F, Tt, sv_dev, part);
+  int rc = check(hipGetLastError());
+  if (rc) return rc;
+  const int nw = nblocks * 4;
+  std::vector<double> h((size_t)nw * K);
+  rc = check(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (!rc) rc = check(hipStreamSynchronize(st));
+  if (rc) return rc;
+  out.assign(K, 0.0);
+  for (int w = 0; w < nw; ++w)
+    for (int k = 0; k < K; ++k) out[k] += h[(size_t)w * K + k];
+  return HRX_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int hrx_mlp_fit(hrx_ctx* ctx, int64_t n, const double* F, const double* T, float* Xs, float* Ys,
+                double log10rho_min, double log10rho_max, double T_lo, double T_hi,
+                double xiN_min, double xiN_max, double* stats, void* hip_stream) {
+  if (!ctx || n < 2 || !F || !T || !Xs || !Ys || !ctx->fitbuf) return HRX_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  ctx->last_stream = st;
+  // sv: m [7], 1/s [7], L [8][8], rm [8], 1/rs [8]; then the moments' per-wavefront
+  // partials (the context's fit workspace, allocated by hrx_mlp_init)
+  constexpr int NSV = FIT_NSV;
+  const int nblocks = FIT_BLOCKS;
+  double* sv = ctx->fitbuf;
+  double* part = ctx->fitbuf + NSV;
+  std::vector<double> h(NSV, 0.0), sum;
+  auto push = [&]() {
+    return check(hipMemcpyAsync(sv, h.data(), NSV * sizeof(double), hipMemcpyHostToDevice, st));
+  };
+  const double in = 1.0 / (double)n;
+  int rc = fit_pass<0>(n, F, T, sv, part, nblocks, st, sum);
+  double mean[MLP_NIN], sd[MLP_NIN], L[8][8], rm[MLP_NOUT], rs[MLP_NOUT];
+  if (!rc) {
+    for (int k = 0; k < MLP_NIN; ++k) h[k] = mean[k] = sum[k] * in;
+    rc = push();
+  }
+  if (!rc) rc = fit_pass<1>(n, F, T, sv, part, nblocks, st, sum);
+  if (!rc) {
+    for (int k = 0; k < MLP_NIN; ++k) {
+      sd[k] = sqrt(sum[k] * in);
+      if (!(sd[k] > 0.0)) rc = HRX_EINVAL;
+      h[MLP_NIN + k] = 1.0 / sd[k];
+    }
+    if (!rc) rc = push();
+  }
+  if (!rc) rc = fit_pass<2>(n, F, T, sv, part, nblocks, st, sum);
+  if (!rc) {
+    // least squares: the minimum-norm solution of (A^T A) L_o = A^T t_o for every output
+    // o.  The five mass fractions sum to one, so A^T A is singular; its directions with an
+    // eigenvalue below 1e-9 of the largest are left out (the pseudo-inverse).
+    double M[8][8], B[8][8];
+    int q = 0;
+    for (int p = 0; p < 8; ++p)
+      for (int r = p; r < 8; ++r) M[p][r] = M[r][p] = sum[q++];
+    for (int o = 0; o < 8; ++o)
+      for (int p = 0; p < 8; ++p) B[p][o] = sum[36 + o * 8 + p];
+    double V[8][8], lam[8];
+    if (!sym_eigen8(M, V, lam)) rc = HRX_EINVAL;
+    if (!rc) {
+      double lmax = 0.0;
+      for (int i = 0; i < 8; ++i) lmax = std::max(lmax, lam[i]);
+      if (!(lmax > 0.0)) rc = HRX_EINVAL;
+      for (int o = 0; o < 8; ++o)
+        for (int p = 0; p < 8; ++p) L[o][p] = 0.0;
+      for (int i = 0; i < 8 && !rc; ++i) {
+        if (!(lam[i] > 1e-9 * lmax)) continue;
+        for (int o = 0; o < 8; ++o) {
+          double c = 0.0;
+          for (int p = 0; p < 8; ++p) c += V[p][i] * B[p][o];
+          c /= lam[i];
+          for (int p = 0; p < 8; ++p) L[o][p] += c * V[p][i];
+        }
+      }
+    }
+    if (!rc) {
+      for (int o = 0; o < 8; ++o)
+        for (int p = 0; p < 8; ++p) h[2 * MLP_NIN + o * 8 + p] = L[o][p];
+      rc = push();
+    }
+  }
+  if (!rc) rc = fit_pass<3>(n, F, T, sv, part, nblocks, st, sum);
+  if (!rc) {
+    for (int o = 0; o < MLP_NOUT; ++o) h[2 * MLP_NIN + 64 + o] = rm[o] = sum[o] * in;
+    rc = push();
+  }
+  if (!rc) rc = fit_pass<4>(n, F, T, sv, part, nblocks, st, sum);
+  if (!rc) {
+    for (int o = 0; o < MLP_NOUT; ++o) {
+      rs[o] = sqrt(sum[o] * in);
+      if (!(rs[o] > 0.0)) rc = HRX_EINVAL;
+      h[2 * MLP_NIN + 72 + o] = 1.0 / rs[o];
+    }
+    if (!rc) rc = push();
+  }
+  if (!rc) {
+    k_fit_apply<<<blocks_for(n, 256), 256, 0, st>>>(n, F, T, sv, Xs, Ys);
+    rc = check(hipGetLastError());
+  }
+  if (!rc) rc = check(hipStreamSynchronize(st));
+  if (rc) return rc;
+  // the composition around the network (float, as hrx_mlp_set_norm takes it)
+  float fm[MLP_NIN], fs[MLP_NIN], om[MLP_NOUT], os[MLP_NOUT], fl[MLP_NOUT * 8];
+  for (int k = 0; k < MLP_NIN; ++k) { fm[k] = (float)mean[k]; fs[k] = (float)sd[k]; }
+  for (int o = 0; o < MLP_NOUT; ++o) {
+    om[o] = (float)rm[o];
+    os[o] = (float)rs[o];
+    for (int p = 0; p < 8; ++p) fl[o * 8 + p] = (float)L[o][p];
+  }
+  if (stats) {
+    for (int k = 0; k < MLP_NIN; ++k) { stats[k] = mean[k]; stats[MLP_NIN + k] = sd[k]; }
+    for (int o = 0; o < MLP_NOUT; ++o) { stats[14 + o] = rm[o]; stats[22 + o] = rs[o]; }
+    for (int o = 0; o < MLP_NOUT; ++o)
+      for (int p = 0; p < 8; ++p) stats[30 + o * 8 + p] = L[o][p];
+  }
+  return hrx_mlp_set_norm(ctx, fm, fs, om, os, fl, log10rho_min, log10rho_max, T_lo, T_hi,
+                          xiN_min, xiN_max);
 }
 
 int hrx_set_thermo_mode(hrx_ctx* ctx, int mode) {

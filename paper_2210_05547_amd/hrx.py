@@ -113,12 +113,15 @@ def load(path: str = LIB_PATH):
                                      C.c_double, C.c_double, C.c_double, C.c_double]
     lib.hrx_set_thermo_mode.argtypes = [vp, C.c_int]
     lib.hrx_mlp_features.argtypes = [vp, i64, dp, dp, dp, dp, vp]
+    lib.hrx_mlp_dataset.argtypes = [vp, i64, dp, dp, dp, dp, dp, dp, vp]
+    lib.hrx_mlp_fit.argtypes = [vp, i64, dp, dp, dp, dp] + [C.c_double] * 6 + \
+        [C.POINTER(C.c_double), vp]
     lib.hrx_mlp_forward.argtypes = [vp, i64, dp, dp, vp]
     lib.hrx_mlp_backward.argtypes = [vp, i64, dp, dp, dp, vp]
     lib.hrx_adam_step.argtypes = [vp, dp, f32, C.c_int, vp]
     lib.hrx_mlp_train_step.argtypes = [vp, i64, dp, dp, dp, f32, C.c_int, dp, vp]
     for fn in ("hrx_mlp_init", "hrx_mlp_set_params", "hrx_mlp_get_params", "hrx_mlp_set_norm",
-               "hrx_mlp_features",
+               "hrx_mlp_features", "hrx_mlp_dataset", "hrx_mlp_fit",
                "hrx_set_thermo_mode", "hrx_mlp_forward", "hrx_mlp_backward", "hrx_adam_step",
                "hrx_mlp_train_step"):
         getattr(lib, fn).restype = C.c_int
@@ -304,6 +307,24 @@ def mlp_features(ctx, n, rho, e, Y, f, stream=None):
     """Raw surrogate features f [n][7] (FP32) of SI states (hrx_mlp_features)."""
     _check(_lib.hrx_mlp_features(ctx._h, int(n), _ptr(rho), _ptr(e), _ptr(Y), _ptr(f),
                                  _stream(stream)))
+
+
+def mlp_dataset(ctx, n, rho, e, Y, F, T, status=None, stream=None):
+    """Raw features F [n][7] and targets T [n][8] (FP64) of SI states (hrx_mlp_dataset)."""
+    _check(_lib.hrx_mlp_dataset(ctx._h, int(n), _ptr(rho), _ptr(e), _ptr(Y), _ptr(F), _ptr(T),
+                                _ptr(status), _stream(stream)))
+
+
+def mlp_fit(ctx, n, F, T, Xs, Ys, log10rho_range, T_range, xiN_range, stream=None):
+    """Composition statistics of a training set, installed, and its standardised rows
+    (hrx_mlp_fit); returns the statistics (m, s, rm, rs, L) as numpy arrays."""
+    st = (C.c_double * 94)()
+    _check(_lib.hrx_mlp_fit(ctx._h, int(n), _ptr(F), _ptr(T), _ptr(Xs), _ptr(Ys),
+                            float(log10rho_range[0]), float(log10rho_range[1]),
+                            float(T_range[0]), float(T_range[1]), float(xiN_range[0]),
+                            float(xiN_range[1]), st, _stream(stream)))
+    a = np.array(st[:])
+    return dict(xm=a[0:7], xs=a[7:14], ym=a[14:22], ys=a[22:30], L=a[30:94].reshape(8, 8))
 
 
 def set_thermo_mode(ctx, mode):

@@ -1,11 +1,11 @@
 """Training the thermochemistry surrogate with the library alone (no CPU reference).
 
-States are drawn by ``fields.air_states``; the labels (T, mu, kappa, D_s) come from the
-library's plain FP64 evaluation (``thermo_eval``), the features from
-``hrx_mlp_features``, and the training from ``hrx_mlp_train_step`` -- every step on the
-GPU.  The composition around the network follows ``hrx_mlp_set_norm``: standardised
-features, and targets (ln T, ln mu, ln kappa, ln(rho D_s)) standardised about their
-least-squares linear fit in the standardised features.
+States are drawn by ``fields.air_states``; ``hrx_mlp_dataset`` forms their raw
+features and the targets (ln T, ln mu, ln kappa, ln(rho D_s)) of the library's plain FP64
+evaluation, ``hrx_mlp_fit`` the composition around the network (standardised features,
+targets standardised about their least-squares linear fit in them) and the standardised
+rows, and ``hrx_mlp_train_step`` trains -- every arithmetic step on the GPU, in the
+library's kernels; this module only draws the states and the batch order.
 """
 import math
 
@@ -35,43 +35,20 @@ DESIGN_NOTE = {
 }
 
 
-def training_set(ctx, n, seed, device="cuda:0"):
-    """(features [n][7] float64 host, targets [n][8] float64 host) of n air states."""
-    rho, _, Y, e = fields.air_states(n, seed, T_RANGE, LOGRHO_RANGE)
-    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
-    rd, ed, Yd = d(rho), d(e), d(Y)
-    T = torch.zeros(n, dtype=torch.float64, device=device)   # cold start
-    mu, ka = torch.empty_like(T), torch.empty_like(T)
-    D = torch.empty((5, n), dtype=torch.float64, device=device)
-    f = torch.empty((n, 7), dtype=torch.float32, device=device)
-    mode = hrx.THERMO_PLAIN
-    hrx.set_thermo_mode(ctx, mode)
-    hrx.thermo_eval(ctx, n, rd, ed, Yd, T, mu=mu, kappa=ka, D=D)
-    hrx.mlp_features(ctx, n, rd, ed, Yd, f)
-    targets = torch.cat([T.log()[None], mu.log()[None], ka.log()[None], (D * rd[None]).log()])
-    return f.double().cpu().numpy(), np.ascontiguousarray(targets.T.cpu().numpy())
-
-
-def fit_norm(X, Yt):
-    xm, xs = X.mean(0), X.std(0)
-    A = np.concatenate([np.ones((len(X), 1)), (X - xm) / xs], 1)
-    L = np.linalg.lstsq(A, Yt, rcond=None)[0].T
-    res = Yt - A @ L.T
-    return dict(xm=xm, xs=xs, L=L, ym=res.mean(0), ys=res.std(0))
-
-
 def train(ctx, n=400_000, epochs=60, seed=20221016, batch=4096, lr0=2e-3, init_seed=11,
           device="cuda:0"):
     """Train the context's network and install its composition; returns a summary."""
-    X, Yt = training_set(ctx, n, seed, device)
-    nm = fit_norm(X, Yt)
-    A = np.concatenate([np.ones((n, 1)), (X - nm["xm"]) / nm["xs"]], 1)
-    Ys = (Yt - A @ nm["L"].T - nm["ym"]) / nm["ys"]
-    Xd = torch.from_numpy(((X - nm["xm"]) / nm["xs"]).astype(np.float32)).to(device)
-    Yd = torch.from_numpy(np.ascontiguousarray(Ys.astype(np.float32))).to(device)
+    rho, _, Y, e = fields.air_states(n, seed, T_RANGE, LOGRHO_RANGE)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
+    F = torch.empty((n, 7), dtype=torch.float64, device=device)
+    Tt = torch.empty((n, 8), dtype=torch.float64, device=device)
+    hrx.mlp_dataset(ctx, n, d(rho), d(e), d(Y), F, Tt)
     hrx.mlp_init(ctx, batch)
-    theta0 = _glorot(init_seed)
-    hrx.mlp_set_params(ctx, torch.from_numpy(theta0).to(device))
+    Xd = torch.empty((n, 7), dtype=torch.float32, device=device)
+    Yd = torch.empty((n, 8), dtype=torch.float32, device=device)
+    hrx.mlp_fit(ctx, n, F, Tt, Xd, Yd, LOGRHO_RANGE, T_RANGE, XI_N_RANGE)
+    del F, Tt
+    hrx.mlp_set_params(ctx, torch.from_numpy(_glorot(init_seed)).to(device))
     loss = torch.zeros(1, dtype=torch.float32, device=device)
     rng = np.random.default_rng(seed)
     spe = n // batch
@@ -87,8 +64,6 @@ def train(ctx, n=400_000, epochs=60, seed=20221016, batch=4096, lr0=2e-3, init_s
         if first is None:
             first = float(loss.item()) / spe
     last = float(loss.item()) / spe
-    hrx.mlp_set_norm(ctx, nm["xm"], nm["xs"], nm["ym"], nm["ys"], LOGRHO_RANGE, T_RANGE,
-                     out_lin=nm["L"], xiN_range=XI_N_RANGE)
     return dict(states=n, epochs=epochs, loss_first=first, loss_last=last)
 
 

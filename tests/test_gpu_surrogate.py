@@ -26,7 +26,7 @@ from oracle import mlp as omlp  # noqa: E402
 from oracle import rhs as orhs  # noqa: E402
 from oracle import thermo as oth  # noqa: E402
 from oracle import transport as otr  # noqa: E402
-from gpu_util import field_errors, normwise  # noqa: E402
+from gpu_util import field_errors, normwise, tie_free_rows  # noqa: E402
 from surrogate_util import (LOGRHO_RANGE, T_RANGE, XI_N_RANGE, element_N_fraction,  # noqa: E402
                             features, fit_norm, network_targets, raw_dataset, set_norm, states)
 
@@ -116,6 +116,36 @@ def test_features_match_oracle_side():
     assert np.max(np.abs(f.cpu().numpy() - ref)) <= 2e-5
 
 
+def test_dataset_and_fit_on_device():
+    """hrx_mlp_dataset's targets equal the oracle's (1e-12: the plain FP64 evaluation;
+    the features to rounding), and hrx_mlp_fit's statistics and standardised rows equal
+    a NumPy fit of the same rows (statistics 1e-10; rows to FP32 rounding)."""
+    n = 20000
+    X_o, Y_o, raw = raw_dataset(n, seed=31)
+    ctx = air_ctx()
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)  # noqa: E731
+    F = torch.empty((n, 7), dtype=torch.float64, device=DEV)
+    Tt = torch.empty((n, 8), dtype=torch.float64, device=DEV)
+    st = torch.empty(n, dtype=torch.int32, device=DEV)
+    hrx.mlp_dataset(ctx, n, d(raw["rho"]), d(raw["e"]), d(raw["Y"]), F, Tt, status=st)
+    Fh, Th = F.cpu().numpy(), Tt.cpu().numpy()
+    assert int((st != 0).sum()) == 0
+    for o in range(8):
+        assert normwise(Th[:, o], Y_o[:, o]) <= 1e-12, o
+    assert np.max(np.abs(Fh - X_o)) <= 1e-13 * np.max(np.abs(X_o))
+    hrx.mlp_init(ctx, 16)
+    Xs = torch.empty((n, 7), dtype=torch.float32, device=DEV)
+    Ys = torch.empty((n, 8), dtype=torch.float32, device=DEV)
+    stg = hrx.mlp_fit(ctx, n, F, Tt, Xs, Ys, LOGRHO_RANGE, T_RANGE, XI_N_RANGE)
+    nm = fit_norm(Fh, Th)
+    for k in ("xm", "xs", "ym", "ys", "L"):
+        assert np.max(np.abs(stg[k] - nm[k])) <= 1e-10 * max(1.0, np.max(np.abs(nm[k]))), k
+    Xr = (Fh - nm["xm"]) / nm["xs"]
+    Yr = network_targets(Fh, Th, nm)
+    assert np.max(np.abs(Xs.cpu().numpy() - Xr)) <= 1e-6 * np.max(np.abs(Xr))
+    assert np.max(np.abs(Ys.cpu().numpy() - Yr)) <= 1e-5 * np.max(np.abs(Yr))
+
+
 def test_training_reduces_loss(trained):
     h = trained["hist"]
     assert h[-1] < 0.05 * h[0]
@@ -134,9 +164,13 @@ def test_network_matches_oracle_network(trained):
     Xh = trained["Xs"][trained["held"]][:20000]
     Yd = torch.empty((len(Xh), 8), dtype=torch.float32, device=DEV)
     hrx.mlp_forward(trained["ctx"], len(Xh), torch.from_numpy(Xh).to(DEV), Yd)
-    ref, _ = omlp.forward(trained["theta"].cpu().numpy().astype(np.float64), Xh.astype(np.float64),
-                          bf16=True)
-    assert normwise(Yd.cpu().numpy(), ref) <= 2e-3
+    ref, acts = omlp.forward(trained["theta"].cpu().numpy().astype(np.float64),
+                             Xh.astype(np.float64), bf16=True)
+    Yg = Yd.cpu().numpy()
+    assert normwise(Yg, ref) <= 2e-3
+    ok = tie_free_rows(acts)          # no BF16 rounding decision near a tie
+    report("network_tie_free_rows_fraction", float(ok.mean()))
+    assert ok.mean() > 0.2 and normwise(Yg[ok], ref[ok]) <= 1e-4
 
 
 def _thermo(ctx, raw, sel):
@@ -241,6 +275,36 @@ def test_rhs_with_surrogate_on_sbli_field(trained):
     assert max(errs) <= 1e-3
 
 
+def test_rhs_with_surrogate_on_full_sbli_field(trained):
+    """The surrogate form on the whole 2048 x 512 SBLI-shaped field (the surrogate's
+    workload; the large-grid launch shapes): RHS within 1e-3 per field of the plain FP64
+    oracle, which also judges its error."""
+    cfg = fields.get_config("c3")
+    Q, Qr, info = fields.initial_field(cfg)
+    ctx = with_surrogate(air_ctx(cfg, info["hold"]), trained)
+    Qd = torch.from_numpy(Q).to(DEV)
+    Rd = torch.empty_like(Qd)
+    ctx.counters(reset=True)
+    hrx.rhs_eval(ctx, Qd, torch.from_numpy(Qr).to(DEV), Rd)
+    c = ctx.counters(reset=True)
+    Rg = Rd.cpu().numpy()
+    ctx.close()
+    del Qd, Rd
+    case = orhs.Case(cfg, info["x"], info["y"], info["z"], info["hold"])
+    R = orhs.rhs(Q, Qr, case)
+    errs = field_errors(Rg, R)
+    report("sbli_2048x512_rhs_errors_surrogate", [float(e) for e in errs])
+    report("sbli_2048x512_in_hull_fraction", 1.0 - c["surrogate_fallbacks"] / cfg.npts)
+    assert max(errs) <= 1e-3
+    assert c["surrogate_fallbacks"] < 0.01 * cfg.npts
+
+
+# The surrogate's measured gains over the plain evaluation, as DESIGN records them
+# (below 1: on MI355X the plain FP64 path is the faster one).  The guard fails if the
+# surrogate form falls more than 15 % behind them.
+DOCUMENTED_GAIN = dict(thermo_eval=0.86, sbli_stage=0.96)
+
+
 def _stage_rate(ctx, cfg, Q, Qr, dt, stages=40):
     Qd = torch.from_numpy(Q).to(DEV)
     Qrd = torch.from_numpy(Qr).to(DEV)
@@ -268,8 +332,9 @@ def test_surrogate_gain_measured(trained):
     * RK stages of the SBLI-shaped field, where the inversion starts warm from the
       previous stage and the network replaces the transport only.
     Both ratios are reported (surrogate_report.json); the assertions check that the
-    surrogate form ran on the network (no fallbacks) and kept the state finite, not
-    the sign of the gain."""
+    surrogate form ran on the network (no fallbacks), kept the state finite, and kept
+    within 15 % of the gains recorded in DOCUMENTED_GAIN (the sign is not asserted: the
+    recorded gains are below 1)."""
     n = 1 << 21
     rho, T0, Y = states(n, seed=123)
     e = oth.mixture_e(T0, Y)
@@ -314,3 +379,5 @@ def test_surrogate_gain_measured(trained):
     report("sbli_512x128_stage_Mpts_per_s", dict(plain=rate[0], surrogate=rate[1]))
     report("sbli_512x128_stage_gain", rate[1] / rate[0])
     assert res[0] > 0 and res[1] > 0
+    assert res[hrx.THERMO_PLAIN] / res[hrx.THERMO_SURROGATE] >= 0.85 * DOCUMENTED_GAIN["thermo_eval"]
+    assert rate[1] / rate[0] >= 0.85 * DOCUMENTED_GAIN["sbli_stage"]
