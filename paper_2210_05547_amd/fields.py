@@ -141,7 +141,11 @@ def _cfg_c3():
                       mach=5.92, T_inf=1110.5, p_inf=60967.0, Re=1631.8,
                       wall=WALL_ADIABATIC, sponge_in=40, sponge_out=80, sponge_top=48,
                       ad=True, delta0=1.0, shock_deflection_deg=12.0, shock_x_imp=119.05,
-                      species_noise=1e-3, cfl=0.25, seed=20221011 + 3)
+                      species_noise=1e-3, cfl=0.25, seed=20221011 + 3,
+                      # a weaker sponge (2 or 10) lets a mode at the corner of the held
+                      # inflow column and the top boundary grow until the energy there
+                      # drops below e(50 K) after about 300 stages
+                      sigma_max=50.0)
 
 
 def _cfg_c4():
