@@ -786,39 +786,35 @@ __global__ __launch_bounds__(64) void k_ad_filter_z(Dev d, const RT* __restrict_
 // plane (and one z plane in 3-D), and walks down the rows.  Lane l keeps its column's
 // five source rows (the fourth difference's y taps) and nine x-filtered rows (the y
 // filter's taps) in registers and exchanges only the current row through LDS for the x
-// taps: one global read per source value, about 17 LDS accesses per output and no
-// block barriers (one wavefront per block).  A segment starts 4 rows early (the y
-// filter's reach).  Within two points of a non-periodic end the fourth difference is the
-// one centred two points in (the stencil never leaves the line); filter taps outside
-// the domain carry zero weight and the weights are renormalised.  In 3-D the z term of
-// the fourth difference reads the planes k +- 1, k +- 2 from memory (consecutive blocks
-// hold consecutive planes, so they come from L2); the z filter follows as its own pass.
-// The row's source values (the lane's column, and the four extra x-tap columns of lanes
-// 0..3) are loaded one row ahead, so their latency overlaps the previous row's work; the
-// z taps are loaded in their own row (a prefetch of them too costs a wavefront per SIMD
-// and was slower).
-// Segments of 24 rows in 2-D (SBLI: about six wavefronts per SIMD, all resident; 6-9 %
-// faster than 32) and 32 in 3-D (enough wavefronts already; shorter segments add halo
-// rows) -- measured.
-constexpr int MW = 64, MO = MW - 8, MSEG2 = 24, MSEG3 = 32;
-template <int GAS, int ND, class RT>
+// taps: one global read per source value and about 17 LDS accesses per output.  A
+// segment starts 4 rows early (the y filter's reach).  Within two points of a
+// non-periodic end the fourth difference is the one centred two points in (the stencil
+// never leaves the line); filter taps outside the domain carry zero weight and the
+// weights are renormalised.  The z filter of 3-D grids follows as its own pass.
+// Memory reads inside the march are loaded one row before their use and consumed before
+// their register is refilled, every row refills whatever it did (lanes and wavefronts
+// that need no value read a valid one), and the rows' spacings come from LDS: the vector
+// memory counter is waited on in order, so a conditional load, a load used in its own
+// row or a register moved while its load is in flight makes the wait drain every load in
+// flight (measured on the jet box: 1.30 -> 0.85 ms with the 3-D form below).
+// Segments of 24 rows in 2-D (SBLI: about six wavefronts per SIMD, all resident) and 128
+// in 3-D (fewer halo rows; the grid still has 20 blocks per CU) -- measured.
+constexpr int MW = 64, MO = MW - 8, MSEG2 = 24, MSEG3 = 128;
+constexpr int AD_MARCH_NWZ = 4;   // z planes (wavefronts) per block of the 3-D march
+constexpr int AD_MARCH_PD = 1;    // rows a wavefront's loads run ahead (more: more registers)
+template <int GAS, class RT>
 __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A,
                                                 RT* __restrict__ B, int nstrip, int nseg,
                                                 int mseg) {
   __shared__ RT sa[MW + 4];   // source row q, columns i0 - 6 .. i0 + MW - 3
   __shared__ RT sd[MW];       // fourth differences of row q, columns i0 - 4 .. i0 + MW - 5
-  const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const long N = d.N, P = (long)nx * ny;
+  __shared__ double sdly[MSEG2 + 8];
+  const int nx = d.nx, ny = d.ny;
+  const long N = d.N;
   const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
   const unsigned per = nb >> 3;
   unsigned t = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
-  // block -> (z plane fastest in 3-D, strip, segment, AD plane)
-  int k = 0;
-  if (ND == 3) {
-    const unsigned tk = t / (unsigned)nz;
-    k = (int)(t - tk * (unsigned)nz);
-    t = tk;
-  }
+  // block -> (strip, segment, AD plane)
   const unsigned ts = t / (unsigned)nstrip;
   const int strip = (int)(t - ts * (unsigned)nstrip);
   const unsigned tg = ts / (unsigned)nseg;
@@ -826,18 +822,19 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
   const int v = (int)tg;
   const int l = threadIdx.x;
   const int i0 = strip * MO, y0 = seg * mseg, y1 = min(y0 + mseg, ny);
-  const long kb = (long)k * P;
-  const RT* f = A + (long)v * N + kb;       // this plane
+  const RT* f = A + (long)v * N;
   const bool sq = v < 2;
   // the lane's fourth-difference column, the centre of its x taps, its spacing
   const int gx = min(max(i0 - 4 + l, 0), nx - 1);
   const int ic = gx < 2 ? 2 : (gx > nx - 3 ? nx - 3 : gx);
   const int jx = ic - 2 - (i0 - 6);           // first x tap in sa
-  const RT dlx = RT(d.dlx[gx]);
+  const double dlxg = d.dlx[gx];
+  const RT dlx = RT(dlxg);
   const RT wxf = sq ? dlx * dlx : dlx;
-  // extra source columns for the x taps of the strip's end columns (lanes 0..3)
+  // extra source columns for the x taps of the strip's end columns (lanes 0..3; the
+  // other lanes read their own column there)
   const int ex = l < 2 ? i0 - 6 + l : i0 + MW - 6 + l;   // l = 2, 3 -> i0 + MW - 4, - 3
-  const int gex = min(max(ex, 0), nx - 1);
+  const int gex = l < 4 ? min(max(ex, 0), nx - 1) : gx;
   const int sex = l < 2 ? l : MW + l;                     // its slot in sa
   // x filter of output lane l (column i0 - 4 + l, lanes 4 .. MW - 5)
   RT wxs = RT(0);
@@ -853,23 +850,22 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
   const bool olane = l >= 4 && l < MW - 4 && ocol < nx;
   const RT iwx = olane ? RT(1) / wxs : RT(0);
   const int xl = min(max(l, 4), MW - 5) - 4;   // first x-filter tap in sd (in range)
-  // 3-D: the planes k - 2 .. k + 2 (periodic)
-  long kz[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    int q = k + m - 2;
-    q = ND == 3 ? (q < 0 ? q + nz : (q >= nz ? q - nz : q)) : 0;
-    kz[m] = (long)q * P - kb;
-  }
-  const RT fdz = ND == 3 ? RT(d.dlz[k]) : RT(0);
-  const RT wzf = sq ? fdz * fdz : fdz;
-  // source rows qc - 2 .. qc + 2 of the lane's column (qc = the y centre of row q)
   const int qs = y0 - 4, qe = y1 + 3;
-  int cur = min(max(max(qs, 0), 2), ny - 3);
-  RT a0 = f[(long)(cur - 2) * nx + gx], a1 = f[(long)(cur - 1) * nx + gx],
-     a2 = f[(long)cur * nx + gx], a3 = f[(long)(cur + 1) * nx + gx],
-     a4 = f[(long)(cur + 2) * nx + gx];
-  RT pf = f[(long)min(cur + 3, ny - 1) * nx + gx];   // the next row, one step ahead
+  for (int m = l; m <= qe - qs; m += MW) {
+    const int q = qs + m;
+    sdly[m] = (q >= 0 && q < ny) ? d.dly[q] : 0.0;
+  }
+  // the y taps: rows c - 2 .. c + 2 of the column, c = the row clamped to [2, ny - 3];
+  // the first row in range sets c, and every later row q with 3 <= q <= ny - 3 advances
+  // it by one, taking row q + 2 from pq (refilled with the next advancing row's)
+  auto row = [&](int r, int col) { return f[(long)min(max(r, 0), ny - 1) * nx + col]; };
+  const int q0 = max(qs, 0);
+  const int c0 = min(max(q0, 2), ny - 3);
+  const int qa = max(q0 + 1, 3);   // the first row that may advance
+  RT a0 = row(c0 - 2, gx), a1 = row(c0 - 1, gx), a2 = row(c0, gx), a3 = row(c0 + 1, gx),
+     a4 = row(c0 + 2, gx);
+  RT pq = row(qa + 2, gx);   // row (next advancing row) + 2
+  RT eq = row(q0, gex);      // the extra column's row q
   // interior y-filter weight sum (every tap inside the domain), in the filter's order
   RT wint = RT(0);
 #pragma unroll
@@ -878,54 +874,40 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
   RT xr[9];
 #pragma unroll
   for (int m = 0; m < 9; ++m) xr[m] = RT(0);
-  // the extra x-tap column's value of the next row to stage (lanes 0..3), one row ahead
-  RT exn = RT(0);
-  if (l < 4) exn = f[(long)max(qs, 0) * nx + gex];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   for (int q = qs; q <= qe; ++q) {
     RT xf = RT(0);
     if (q >= 0 && q < ny) {
-      const int want = q < 2 ? 2 : (q > ny - 3 ? ny - 3 : q);
-      if (want > cur) {
-        a0 = a1; a1 = a2; a2 = a3; a3 = a4; a4 = pf;
-        cur = want;
-        pf = f[(long)min(cur + 3, ny - 1) * nx + gx];
+      if (q > q0 && q >= 3 && q <= ny - 3) {
+        a0 = a1; a1 = a2; a2 = a3; a3 = a4; a4 = pq;
       }
+      const int cq = min(max(q, 2), ny - 3);
       RT aq = a2;   // row q in the ring (its centre away from the ends)
-      if (q != cur) {
-        const int dq = q - cur;
+      if (q != cq) {
+        const int dq = q - cq;
         aq = dq < 0 ? (dq == -1 ? a1 : a0) : (dq == 1 ? a3 : a4);
       }
-      RT zt[4];
-      if (ND == 3) {
-        const RT* fz = f + (long)q * nx + gx;
-        zt[0] = fz[kz[0]]; zt[1] = fz[kz[1]]; zt[2] = fz[kz[3]]; zt[3] = fz[kz[4]];
-      }
       sa[l + 2] = aq;
-      if (l < 4) {
-        sa[sex] = exn;
-        if (q + 1 < ny && q + 1 <= qe) exn = f[(long)(q + 1) * nx + gex];
-      }
+      if (l < 4) sa[sex] = eq;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const RT* ax = sa + jx;
       const RT qx = ax[0] - RT(4) * ax[1] + RT(6) * ax[2] - RT(4) * ax[3] + ax[4];
       const RT qy = a0 - RT(4) * a1 + RT(6) * a2 - RT(4) * a3 + a4;
-      const RT dly = RT(d.dly[q]);
+      const double dlyq = sdly[q - qs];
+      const RT dly = RT(dlyq);
       RT acc = RT(0);
       acc += qx * wxf;
       acc += qy * (sq ? dly * dly : dly);
-      if (ND == 3) {
-        const RT qz = zt[0] - RT(4) * zt[1] + RT(6) * aq - RT(4) * zt[2] + zt[3];
-        acc += qz * wzf;
-      }
       RT out = fabs(acc);
       if (GAS == AIR5 && v >= 3) {
         const RT over = RT(0.5) * (fabs(aq) - RT(1) + fabs(RT(1) - aq));
         out = RT(d.CD) * out;
         if (over != RT(0)) {
-          const RT fdb = ND == 2 ? RT(sqrt(d.dlx[gx] * d.dly[q]))
-                                 : RT(cbrt(d.dlx[gx] * d.dly[q] * d.dlz[k]));
+          const RT fdb = RT(sqrt(dlxg * dlyq));
           out = out + RT(d.CY) * over * fdb;
         }
       }
@@ -942,6 +924,9 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    // refills, whatever the row did, into the registers just read
+    pq = row(max(q + 1, qa) + 2, gx);
+    eq = row(max(q + 1, q0), gex);
 #pragma unroll
     for (int m = 0; m < 8; ++m) xr[m] = xr[m + 1];
     xr[8] = xf;
@@ -963,7 +948,208 @@ __global__ __launch_bounds__(MW) void k_ad_march(Dev d, const RT* __restrict__ A
         }
         res = yacc / wsum;
       }
-      if (olane) B[(long)v * N + kb + (long)r * nx + ocol] = res;
+      if (olane) B[(long)v * N + (long)r * nx + ocol] = res;
+    }
+  }
+}
+
+// The same pass in 3-D with the z taps of the fourth difference exchanged in LDS: a block
+// of NWZ wavefronts owns NWZ consecutive z planes of one strip, segment and AD plane
+// (wavefront w: plane k0 + w, z periodic), each marching down the rows as above.  At
+// every row each wavefront puts its row value into a z buffer (slot w + 2), and
+// wavefronts 0..3 also put the row of the planes k0 - 2, k0 - 1, k0 + NWZ, k0 + NWZ + 1
+// (slots 0, 1, NWZ + 2, NWZ + 3); after one block barrier the planes k +- 1, k +- 2 of
+// every wavefront's point are in LDS, where the one-wavefront march reads them from
+// memory.  The z buffer alternates between two halves by row, so one barrier per row
+// suffices.  Wavefronts whose plane lies past nz (a partial last group) carry the
+// periodic image of their plane and write nothing.
+// Every value a wavefront reads from memory inside the march is loaded PD rows before
+// its use, into one of PD rotating registers (slot = row mod PD; the rows are unrolled by
+// PD and a segment starts at a multiple of PD), and the y spacings come from LDS: the
+// vector memory counter is waited on in order, so a load used in its own row, or a
+// register moved while its load is in flight, would drain every load in flight.
+template <int GAS, class RT, int NWZ, int PD>
+__global__ __launch_bounds__(MW * NWZ) void k_ad_march3(Dev d, const RT* __restrict__ A,
+                                                       RT* __restrict__ B, int nstrip,
+                                                       int nseg, int mseg, int nzg) {
+  static_assert(NWZ >= 4, "wavefronts 0..3 load the halo planes");
+  static_assert(4 % PD == 0 && MSEG3 % PD == 0, "segments start at a multiple of PD");
+  __shared__ RT sa_all[NWZ][MW + 4];   // per wavefront: source row q, columns i0 - 6 ..
+  __shared__ RT sd_all[NWZ][MW];       // per wavefront: fourth differences of row q
+  __shared__ RT zb[2][NWZ + 4][MW];    // row q of planes k0 - 2 .. k0 + NWZ + 1
+  __shared__ double sdly[MSEG3 + 8];  // the segment's y spacings (rows qs .. qe)
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const long N = d.N, P = (long)nx * ny;
+  const unsigned b = (unsigned)blockIdx.x, nb = gridDim.x;
+  const unsigned per = nb >> 3;
+  unsigned t = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
+  // block -> (z group fastest, strip, segment, AD plane)
+  const unsigned tk = t / (unsigned)nzg;
+  const int zg = (int)(t - tk * (unsigned)nzg);
+  t = tk;
+  const unsigned ts = t / (unsigned)nstrip;
+  const int strip = (int)(t - ts * (unsigned)nstrip);
+  const unsigned tg = ts / (unsigned)nseg;
+  const int seg = (int)(ts - tg * (unsigned)nseg);
+  const int v = (int)tg;
+  const int w = threadIdx.x / MW, l = threadIdx.x - w * MW;
+  const int k0 = zg * NWZ;
+  const bool kact = k0 + w < nz;            // this wavefront's plane is a real one
+  const int k = (k0 + w) % nz;
+  RT* sa = sa_all[w];
+  RT* sd = sd_all[w];
+  const int i0 = strip * MO, y0 = seg * mseg, y1 = min(y0 + mseg, ny);
+  const long kb = (long)k * P;
+  const RT* f = A + (long)v * N + kb;       // this plane
+  const bool sq = v < 2;
+  const int gx = min(max(i0 - 4 + l, 0), nx - 1);
+  const int ic = gx < 2 ? 2 : (gx > nx - 3 ? nx - 3 : gx);
+  const int jx = ic - 2 - (i0 - 6);
+  const RT dlx = RT(d.dlx[gx]);
+  const RT wxf = sq ? dlx * dlx : dlx;
+  const int ex = l < 2 ? i0 - 6 + l : i0 + MW - 6 + l;
+  // lanes 4.. read their own column in the extra-column slots (loads stay unconditional)
+  const int gex = l < 4 ? min(max(ex, 0), nx - 1) : gx;
+  const int sex = l < 2 ? l : MW + l;
+  RT wxs = RT(0);
+  const int ocol = i0 - 4 + l;
+#pragma unroll
+  for (int m = -4; m <= 4; ++m) {
+    const int q = ocol + m;
+    wxs += (q >= 0 && q < nx) ? RT(c_gauss9[m < 0 ? -m : m]) : RT(0);
+  }
+  const bool incol = ocol >= 0 && ocol < nx;
+  const bool olane = kact && l >= 4 && l < MW - 4 && ocol < nx;
+  const RT iwx = olane ? RT(1) / wxs : RT(0);
+  const int xl = min(max(l, 4), MW - 5) - 4;
+  // the halo plane this wavefront reads (wavefronts 0..3), periodic in z
+  // (wavefronts 4.. read their own plane in the halo slots: loads stay unconditional)
+  const int hk = w < 2 ? k0 - 2 + w : (w < 4 ? k0 + NWZ + (w - 2) : k0 + w);
+  const RT* fh = A + (long)v * N + (long)(((hk % nz) + nz) % nz) * P;
+  const int hslot = w < 2 ? w : NWZ + w;    // w = 2, 3 -> slots NWZ + 2, NWZ + 3
+  const double dlxg = d.dlx[gx], dlzk = d.dlz[k];
+  const RT fdz = RT(dlzk);
+  const RT wzf = sq ? fdz * fdz : fdz;
+  const int qs = y0 - 4, qe = y1 + 3;
+  for (int m = threadIdx.x; m <= qe - qs; m += MW * NWZ) {
+    const int q = qs + m;
+    sdly[m] = (q >= 0 && q < ny) ? d.dly[q] : 0.0;
+  }
+  // the fourth difference's y taps: rows c - 2 .. c + 2 of the column, c = the row
+  // clamped to [2, ny - 3]; the first row in range sets c, and every later row q with
+  // 3 <= q <= ny - 3 advances it by one, taking row q + 2 from slot (q - qs) mod PD
+  const int q0 = max(qs, 0);
+  const int c0 = min(max(q0, 2), ny - 3);
+  auto row = [&](const RT* g, int r, int col) { return g[(long)min(max(r, 0), ny - 1) * nx + col]; };
+  RT a0 = row(f, c0 - 2, gx), a1 = row(f, c0 - 1, gx), a2 = row(f, c0, gx),
+     a3 = row(f, c0 + 1, gx), a4 = row(f, c0 + 2, gx);
+  // slot s holds, for its next consuming row, row r + 2 (pq; r the next advancing row of
+  // the slot) and row r (hq, eq; r the next row of the slot in range); ra[s], rb[s]: the
+  // slot's first such rows.  Every row refills its slot with the row its next consumer
+  // needs (the same row again when it consumed nothing)
+  const int qa = max(q0 + 1, 3);   // the first row that may advance
+  int ra[PD], rb[PD];
+  RT pq[PD], hq[PD], eq[PD];
+#pragma unroll
+  for (int s = 0; s < PD; ++s) {
+    ra[s] = qa + (((s - (qa - qs)) % PD) + PD) % PD;
+    rb[s] = q0 + (((s - (q0 - qs)) % PD) + PD) % PD;
+    pq[s] = row(f, ra[s] + 2, gx);
+    hq[s] = row(fh, rb[s], gx);
+    eq[s] = row(f, rb[s], gex);
+  }
+  RT wint = RT(0);
+#pragma unroll
+  for (int m = -4; m <= 4; ++m) wint += RT(c_gauss9[m < 0 ? -m : m]);
+  const RT iwint = RT(1) / wint;
+  RT xr[9];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) xr[m] = RT(0);
+  __syncthreads();   // sdly
+  for (int qb = qs; qb <= qe; qb += PD) {
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      const int q = qb + u;   // slot u: (q - qs) mod PD == u
+      const bool live = q <= qe;   // uniform (the last group may run past the segment)
+      RT xf = RT(0);
+      if (live && q >= 0 && q < ny) {   // uniform across the block
+        if (q > q0 && q >= 3 && q <= ny - 3) {
+          a0 = a1; a1 = a2; a2 = a3; a3 = a4; a4 = pq[u];
+        }
+        const int cq = min(max(q, 2), ny - 3);
+        RT aq = a2;
+        if (q != cq) {
+          const int dq = q - cq;
+          aq = dq < 0 ? (dq == -1 ? a1 : a0) : (dq == 1 ? a3 : a4);
+        }
+        RT (*z)[MW] = zb[q & 1];
+        z[w + 2][l] = aq;
+        if (w < 4) z[hslot][l] = hq[u];
+        sa[l + 2] = aq;
+        if (l < 4) sa[sex] = eq[u];
+        __syncthreads();
+        const RT* ax = sa + jx;
+        const RT qx = ax[0] - RT(4) * ax[1] + RT(6) * ax[2] - RT(4) * ax[3] + ax[4];
+        const RT qy = a0 - RT(4) * a1 + RT(6) * a2 - RT(4) * a3 + a4;
+        const double dlyq = sdly[q - qs];
+        const RT dly = RT(dlyq);
+        RT acc = RT(0);
+        acc += qx * wxf;
+        acc += qy * (sq ? dly * dly : dly);
+        {
+          const RT qz = z[w][l] - RT(4) * z[w + 1][l] + RT(6) * aq - RT(4) * z[w + 3][l] +
+                        z[w + 4][l];
+          acc += qz * wzf;
+        }
+        RT out = fabs(acc);
+        if (GAS == AIR5 && v >= 3) {
+          const RT over = RT(0.5) * (fabs(aq) - RT(1) + fabs(RT(1) - aq));
+          out = RT(d.CD) * out;
+          if (over != RT(0)) {
+            const RT fdb = RT(cbrt(dlxg * dlyq * dlzk));
+            out = out + RT(d.CY) * over * fdb;
+          }
+        }
+        sd[l] = incol ? out : RT(0);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        RT xa = RT(0);
+#pragma unroll
+        for (int m = 0; m < 9; ++m) xa += RT(c_gauss9[m < 4 ? 4 - m : m - 4]) * sd[xl + m];
+        xf = xa * iwx;
+        // sa and sd are rewritten next row only after every lane's reads above
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      // the slot's refills, issued whatever the row did, into the registers just read
+      pq[u] = row(f, max(q + PD, ra[u]) + 2, gx);
+      hq[u] = row(fh, max(q + PD, rb[u]), gx);
+      eq[u] = row(f, max(q + PD, rb[u]), gex);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) xr[m] = xr[m + 1];
+      xr[8] = xf;
+      const int r = q - 4;
+      if (live && r >= y0 && r < y1) {
+        RT yacc = RT(0), res;
+        if (r >= 4 && r < ny - 4) {
+#pragma unroll
+          for (int m = -4; m <= 4; ++m) yacc += RT(c_gauss9[m < 0 ? -m : m]) * xr[m + 4];
+          res = yacc * iwint;
+        } else {
+          RT wsum = RT(0);
+#pragma unroll
+          for (int m = -4; m <= 4; ++m) {
+            const int qq = r + m;
+            const RT wgt = (qq >= 0 && qq < ny) ? RT(c_gauss9[m < 0 ? -m : m]) : RT(0);
+            yacc += wgt * xr[m + 4];
+            wsum += wgt;
+          }
+          res = yacc / wsum;
+        }
+        if (olane) B[(long)v * N + kb + (long)r * nx + ocol] = res;
+      }
     }
   }
 }
@@ -3240,8 +3426,16 @@ const RT* launch_ad_smoothing(hrx_ctx* ctx, hipStream_t st) {
   timed(ctx, K_AD_D4, st, [&] {
     const int mseg = ND == 2 ? MSEG2 : MSEG3;
     const int nstrip = (d.nx + MO - 1) / MO, nseg = (d.ny + mseg - 1) / mseg;
-    k_ad_march<GAS, ND, RT><<<(unsigned)((long)d.nz * nstrip * nseg * d.nad), MW, 0, st>>>(
-        d, A, B, nstrip, nseg, mseg);
+    if constexpr (ND == 3) {
+      constexpr int NWZ = AD_MARCH_NWZ;
+      const int nzg = (d.nz + NWZ - 1) / NWZ;
+      k_ad_march3<GAS, RT, NWZ, AD_MARCH_PD><<<(unsigned)((long)nzg * nstrip * nseg * d.nad),
+                                               MW * NWZ, 0, st>>>(d, A, B, nstrip, nseg, mseg,
+                                                                 nzg);
+    } else {
+      k_ad_march<GAS, RT><<<(unsigned)((long)nstrip * nseg * d.nad), MW, 0, st>>>(
+          d, A, B, nstrip, nseg, mseg);
+    }
   });
   if (ND == 3) {
     const int nxs = (d.nx + 63) / 64, nzs = (d.nz + ZSEG - 1) / ZSEG;
