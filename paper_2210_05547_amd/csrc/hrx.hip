@@ -1815,6 +1815,218 @@ __global__ __launch_bounds__(256 * NH) void k_div(Dev d, const double* __restric
   }
 }
 
+// A first-derivative stencil over an LDS tile with 32-bit offsets (half the registers of
+// Sten, which a march keeps live across its rows); same pairs, weights and order.
+struct LSten {
+  int p[4], q[4];
+  double a[4];
+};
+__device__ __forceinline__ LSten lds_sten(const Sten& t) {
+  LSten l;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    l.p[m] = (int)t.p[m];
+    l.q[m] = (int)t.q[m];
+    l.a[m] = t.a[m];
+  }
+  return l;
+}
+template <class TA, int NP = 4>
+__device__ __forceinline__ TA lsten_apply(const LSten& t, const double* f) {
+  double d[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) d[m] = f[t.p[m]] - f[t.q[m]];
+  TA acc = TA(t.a[0]) * TA(d[0]);
+#pragma unroll
+  for (int m = 1; m < NP; ++m) acc += TA(t.a[m]) * TA(d[m]);
+  return acc;
+}
+// the central (periodic, staged) operator about LDS element b with stride s, as
+// sten_apply<TA, NPI> over make_sten_central
+template <int ORDER, class TA>
+__device__ __forceinline__ TA lds_central(const double* f, int b, int s) {
+  const double d0 = f[b + s] - f[b - s], d1 = f[b + 2 * s] - f[b - 2 * s];
+  TA acc = TA(ORDER == 6 ? 0.75 : 2.0 / 3.0) * TA(d0);
+  acc += TA(ORDER == 6 ? -0.15 : -1.0 / 12.0) * TA(d1);
+  if (ORDER == 6) acc += TA(1.0 / 60.0) * TA(f[b + 3 * s] - f[b - 3 * s]);
+  return acc;
+}
+
+// 3-D RK stage divergence as a march along y.  A block owns an (x, z) tile of TTX x TTY
+// points, one chunk of KCM components and a segment of rows, and walks down the rows: the
+// y fluxes of its points at rows j - H .. j + H (H = 3 for the sixth-order operator, 2
+// for the fourth) ride in a register ring, one global read per value, where the
+// row-per-block kernel reads every y neighbour from memory (six reads per value).  The x
+// and z flux tiles of each row are staged in LDS as there, double-buffered: the next
+// row's tile values are loaded into registers while the current row is computed (one
+// block barrier per row).  Loads inside the march follow the rule of the AD march (the
+// vector memory counter is waited on in order): the row's pointwise loads (the sponge's
+// reference state only where the sponge acts) come first, then the ring's and the next
+// tiles' loads, every one unconditional and consumed before its register is refilled.
+// The differences are formed and weighted in the same order as the row-per-block kernel,
+// so both give the same bits.  The four closure rows (0, 1, ny - 2, ny - 1) read their
+// one-sided stencils from memory.
+constexpr int KCM = 3;   // components per block of the march
+template <int GAS, int ORDER, class RT>
+__global__ __launch_bounds__(256) void k_div3m(Dev d, const double* __restrict__ F,
+                                               const RT* __restrict__ Wp,
+                                               const double* __restrict__ Qref, double* Qio,
+                                               double* dQio, double A, double B, double dt,
+                                               int rkf, int rseg, int nseg) {
+  constexpr int ND = 3;
+  constexpr int ns = (GAS == AIR5) ? NS : 1;
+  constexpr int nvar = ns + ND + 1;
+  constexpr int KC = KCM;
+  constexpr int H = ORDER == 6 ? 3 : 2, NR = 2 * H + 1;
+  constexpr int TOT = KC * (FXE + FYE);                  // one row's two flux tiles
+  constexpr int NT = TTX * TTY, PER = (TOT + NT - 1) / NT;
+  extern __shared__ double smem[];                       // two buffers of TOT
+  const long N = d.N;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  // block -> (z tile fastest, x tile, row segment, chunk); each XCD takes a contiguous range
+  const unsigned nb = gridDim.x, per = nb >> 3, b = blockIdx.x;
+  unsigned t = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
+  const unsigned tgz = (unsigned)d.tgz, tgx = (unsigned)d.tgx;
+  const int zt = (int)(t % tgz);
+  t /= tgz;
+  const int xt = (int)(t % tgx);
+  t /= tgx;
+  const int seg = (int)(t % (unsigned)nseg);
+  const int chunk = (int)(t / (unsigned)nseg);
+  const int i0 = xt * TTX, k0t = zt * TTY;
+  const int kbeg = chunk * KC, kn = min(KC, nvar - kbeg);
+  const int lt = threadIdx.x, tx = lt & (TTX - 1), ty = lt / TTX;
+  const int pi = i0 + tx, pk = k0t + ty;
+  const bool active = pi < nx && pk < nz;
+  const int ci = min(pi, nx - 1), ck = min(pk, nz - 1);   // clamped (inactive threads)
+  const int y0 = seg * rseg, y1 = min(y0 + rseg, ny);
+  const long P = (long)nx * ny;
+  const long col = (long)ck * P + ci;                       // point (ci, 0, ck)
+  const RT mx = RT(d.mx[ci]), mz = RT(d.mz[ck]);
+  const double sxi = d.sx[ci];
+  const LSten sx = lds_sten(make_sten<ORDER>((long)ty * TW + tx + THALO, 1, ci, nx));
+  const int zb = (ty + THALO) * TTX + tx;                   // the point in the z-flux tile
+  // element e (clamped to the last one) of a row's tiles: x fluxes (x halo) then z
+  // fluxes (periodic z halo); components past nvar read a valid plane, never used
+  auto tile_src = [&](int e, int j) -> long {
+    e = min(e, TOT - 1);
+    if (e < KC * FXE) {
+      const int kk = e / FXE, r = e - kk * FXE;
+      const int ly = r / TW, lx = r - ly * TW;
+      const int gi = min(max(i0 + lx - THALO, 0), nx - 1);
+      const int gk = min(k0t + ly, nz - 1);
+      return (long)min(kbeg + kk, nvar - 1) * N + ((long)gk * ny + j) * nx + gi;
+    }
+    e -= KC * FXE;
+    const int kk = e / FYE, r = e - kk * FYE;
+    const int ly = r / TTX, lx = r - ly * TTX;
+    const int gi = min(i0 + lx, nx - 1);
+    int gk = k0t + ly - THALO;
+    gk = gk < 0 ? gk + nz : (gk >= nz ? gk - nz : gk);
+    return ((long)2 * nvar + min(kbeg + kk, nvar - 1)) * N + ((long)gk * ny + j) * nx + gi;
+  };
+  double v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) v[q] = F[tile_src(lt + q * NT, y0)];
+  // the ring: y fluxes of rows j - H .. j + H (rows clamped to the grid); pf: the row
+  // j + H + 1, loaded one row ahead
+  double ry[KC][NR], pf[KC];
+  auto fy = [&](int kk, int row) {
+    const int k = min(kbeg + kk, nvar - 1);
+    row = min(max(row, 0), ny - 1);
+    return F[((long)nvar + k) * N + col + (long)row * nx];
+  };
+#pragma unroll
+  for (int kk = 0; kk < KC; ++kk) {
+#pragma unroll
+    for (int m = 0; m < NR - 1; ++m) ry[kk][m] = fy(kk, y0 - H + m);
+    pf[kk] = fy(kk, y0 + H);
+  }
+  const bool dq_in = rkf != RKF_SSP_FIRST;
+  for (int j = y0; j < y1; ++j) {
+    const long idx = col + (long)j * nx;
+    double* buf = smem + (j & 1) * TOT;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = lt + q * NT;
+      if (e < TOT) buf[e] = v[q];
+    }
+    // the row's pointwise inputs (every one loaded; unused ones are discarded)
+    const double sig = fmax(sxi, d.sy[j]);
+    double qv_[KC], dq_[KC], qr_[KC];
+    RT wd_[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int k = min(kbeg + kk, nvar - 1);
+      qv_[kk] = Qio[k * N + idx];
+      dq_[kk] = dQio[k * N + idx];
+      wd_[kk] = GAS == AIR5 ? Wp[(d.w_wdot + min(k, NS - 1)) * N + idx] : RT(0);
+      qr_[kk] = 0.0;
+      if (Qref != nullptr && sig != 0.0) qr_[kk] = Qref[k * N + idx];
+    }
+    // the ring's new row and the next row's tiles
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      ry[kk][NR - 1] = pf[kk];
+      pf[kk] = fy(kk, j + H + 1);
+    }
+    // this row's buffer is complete, and every thread is done with the buffer the next
+    // row overwrites (read two rows back)
+    __syncthreads();
+    const int jn = min(j + 1, ny - 1);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = F[tile_src(lt + q * NT, jn)];
+    if (active) {
+      const RT my = RT(d.my[j]);
+      bool held = (pi == 0);
+      if (d.hold && j < 3) held = held || d.hold[((long)pk * 3 + j) * nx + pi];
+      // row class of the y operator: central sixth order (c6), central fourth order, or a
+      // closure row read from memory
+      const bool c6 = ORDER == 6 && j >= 3 && j <= ny - 4;
+      const bool cen = c6 || (ORDER == 4 && j >= 2 && j <= ny - 3) ||
+                       (ORDER == 6 && (j == 2 || j == ny - 3));
+      const double a0 = c6 ? 0.75 : 2.0 / 3.0, a1 = c6 ? -0.15 : -1.0 / 12.0;
+      const double a2 = c6 ? 1.0 / 60.0 : 0.0;
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        if (kk >= kn) continue;
+        const int k = kbeg + kk;
+        RT acc = lsten_apply<RT>(sx, buf + kk * FXE) * mx;
+        RT ay;
+        if (cen) {
+          const double d0 = ry[kk][H + 1] - ry[kk][H - 1];
+          const double d1 = ry[kk][H + 2] - ry[kk][H - 2];
+          // the unused pairs difference the point with itself, as the stencil form does
+          const double dc = ry[kk][H] - ry[kk][H];
+          const double d2 = c6 ? ry[kk][NR - 1] - ry[kk][0] : dc;
+          ay = RT(a0) * RT(d0);
+          ay += RT(a1) * RT(d1);
+          ay += RT(a2) * RT(d2);
+          ay += RT(0.0) * RT(dc);
+        } else {
+          ay = sten_apply<RT>(make_sten<ORDER>(0, nx, j, ny), F + ((long)nvar + k) * N + idx);
+        }
+        acc += ay * my;
+        acc += lds_central<ORDER, RT>(buf + KC * FXE + kk * FYE, zb, TTX) * mz;
+        double R = -double(acc);
+        if (GAS == AIR5 && k < NS) R = R + double(wd_[kk]);
+        const double qv = qv_[kk];
+        if (Qref != nullptr && sig != 0.0) R = R - sig * (qv - qr_[kk]);
+        if (held || (j == 0 && k >= ns && k < ns + ND)) R = 0.0;
+        double qn, dqn;
+        bool wdq;
+        rk_update(rkf, A, B, dt, R, qv, dq_in ? dq_[kk] : 0.0, qn, dqn, wdq);
+        if (wdq) dQio[k * N + idx] = dqn;
+        Qio[k * N + idx] = qn;
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int m = 0; m < NR - 1; ++m) ry[kk][m] = ry[kk][m + 1];
+  }
+}
+
 // Unfused stage update from a right-hand side R the caller computed: every component of
 // every point, rk_update as in the divergence kernel (the wall row follows in k_bc).
 __global__ __launch_bounds__(256) void k_rk_update(long N, int nvar, const double* __restrict__ R,
@@ -3363,6 +3575,8 @@ void launch_flux(hrx_ctx* ctx, hipStream_t st, const double* Q, const double* Wd
 // Grids up to this many points run the component chunks of a tile side by side in k_div
 // (near two wavefronts per SIMD the chunks of a tile are latency bound).
 constexpr long DIV_SPLIT_MAX_POINTS = 1L << 18;
+// 3-D RK stages: the y march (k_div3m) instead of one row per block
+constexpr bool DIV_MARCH3 = true;
 
 template <int GAS, int ND, int ORDER, int MODE, class RT>
 void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, const double* Q,
@@ -3386,6 +3600,18 @@ void launch_div(hrx_ctx* ctx, hipStream_t st, const double* F, const RT* Wp, con
         k_div<GAS, ND, ORDER, MODE, RT, true, 1>
             <<<nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt, rkf);
       return;
+    }
+    if constexpr (ND == 3 && MODE == MODE_RK) {
+      if (DIV_MARCH3) {
+        // march along y in segments of rseg rows (shorter on small grids, for more blocks)
+        const int rseg = d.N >= (1L << 22) ? 32 : 8;
+        const int nseg = (d.ny + rseg - 1) / rseg;
+        constexpr int nchm = (nvar + KCM - 1) / KCM;
+        const size_t shm = (size_t)2 * KCM * (FXE + FYE) * sizeof(double);
+        k_div3m<GAS, ORDER, RT><<<(unsigned)(d.tgx * d.tgz * nseg * nchm), TTX * TTY, shm, st>>>(
+            d, F, Wp, Qref, Qio, dQ, A, B, dt, rkf, rseg, nseg);
+        return;
+      }
     }
     k_div<GAS, ND, ORDER, MODE, RT, false, 1>
         <<<split ? nt * nch : nt, TTX * TTY, sh, st>>>(d, F, Wp, Q, Qref, R, Qio, dQ, A, B, dt,
