@@ -2027,6 +2027,129 @@ __global__ __launch_bounds__(256) void k_div3m(Dev d, const double* __restrict__
   }
 }
 
+// 3-D artificial-diffusivity sources |S| and theta (as k_ad_src) as a march along y, in
+// the form of k_div3m: a block owns an (x, z) tile and a segment of rows; the velocity's
+// y neighbours ride in a register ring, the (x, z) tiles with their halos are
+// double-buffered in LDS, every load is unconditional and consumed before its register
+// is refilled, and the derivatives are formed as in k_ad_src (same bits).
+template <int ORDER, class RT>
+__global__ __launch_bounds__(256) void k_ad_src3m(Dev d, const double* __restrict__ Wd,
+                                                  RT* __restrict__ A, int rseg, int nseg) {
+  constexpr int ND = 3;
+  constexpr int H = ORDER == 6 ? 3 : 2, NR = 2 * H + 1;
+  constexpr int TOT = ND * TILE_E;                       // u, v, w tiles of one row
+  constexpr int NT = TTX * TTY, PER = (TOT + NT - 1) / NT;
+  extern __shared__ double smem[];                       // two buffers of TOT
+  const long N = d.N;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  // block -> (z tile fastest, x tile, row segment); each XCD takes a contiguous range
+  const unsigned nb = gridDim.x, per = nb >> 3, b = blockIdx.x;
+  unsigned t = b >= (per << 3) ? b : (b & 7u) * per + (b >> 3);
+  const unsigned tgz = (unsigned)d.tgz, tgx = (unsigned)d.tgx;
+  const int zt = (int)(t % tgz);
+  t /= tgz;
+  const int xt = (int)(t % tgx);
+  const int seg = (int)(t / tgx);
+  const int i0 = xt * TTX, k0t = zt * TTY;
+  const int lt = threadIdx.x, tx = lt & (TTX - 1), ty = lt / TTX;
+  const int pi = i0 + tx, pk = k0t + ty;
+  const bool active = pi < nx && pk < nz;
+  const int ci = min(pi, nx - 1), ck = min(pk, nz - 1);
+  const int y0 = seg * rseg, y1 = min(y0 + rseg, ny);
+  const long P = (long)nx * ny;
+  const long col = (long)ck * P + ci;
+  const RT mx = RT(d.mx[ci]), mz = RT(d.mz[ck]);
+  const int sidx = (ty + THALO) * TW + tx + THALO;
+  const LSten sx = lds_sten(make_sten<ORDER>(sidx, 1, ci, nx));
+  auto tile_src = [&](int e, int j) -> long {
+    e = min(e, TOT - 1);
+    const int v = e / TILE_E, r = e - v * TILE_E;
+    const int ly = r / TW, lx = r - ly * TW;
+    const int gi = min(max(i0 + lx - THALO, 0), nx - 1);
+    int gk = k0t + ly - THALO;
+    gk = gk < 0 ? gk + nz : (gk >= nz ? gk - nz : gk);
+    return (long)v * N + ((long)gk * ny + j) * nx + gi;
+  };
+  double vt[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) vt[q] = Wd[tile_src(lt + q * NT, y0)];
+  double ry[ND][NR], pf[ND];
+  auto fy = [&](int a, int row) {
+    row = min(max(row, 0), ny - 1);
+    return Wd[(long)a * N + col + (long)row * nx];
+  };
+#pragma unroll
+  for (int a = 0; a < ND; ++a) {
+#pragma unroll
+    for (int m = 0; m < NR - 1; ++m) ry[a][m] = fy(a, y0 - H + m);
+    pf[a] = fy(a, y0 + H);
+  }
+  for (int j = y0; j < y1; ++j) {
+    const long idx = col + (long)j * nx;
+    double* buf = smem + (j & 1) * TOT;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = lt + q * NT;
+      if (e < TOT) buf[e] = vt[q];
+    }
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+      ry[a][NR - 1] = pf[a];
+      pf[a] = fy(a, j + H + 1);
+    }
+    __syncthreads();
+    const int jn = min(j + 1, ny - 1);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) vt[q] = Wd[tile_src(lt + q * NT, jn)];
+    if (active) {
+      const RT my = RT(d.my[j]);
+      const bool c6 = ORDER == 6 && j >= 3 && j <= ny - 4;
+      const bool cen = c6 || (ORDER == 4 && j >= 2 && j <= ny - 3) ||
+                       (ORDER == 6 && (j == 2 || j == ny - 3));
+      const double a0 = c6 ? 0.75 : 2.0 / 3.0, a1 = c6 ? -0.15 : -1.0 / 12.0;
+      const double a2 = c6 ? 1.0 / 60.0 : 0.0;
+      RT G[3][3];
+#pragma unroll
+      for (int a = 0; a < ND; ++a) {
+        const double* f = buf + a * TILE_E;
+        G[a][0] = lsten_apply<RT>(sx, f) * mx;
+        RT gy;
+        if (cen) {
+          const double d0 = ry[a][H + 1] - ry[a][H - 1];
+          const double d1 = ry[a][H + 2] - ry[a][H - 2];
+          const double dc = ry[a][H] - ry[a][H];
+          const double d2 = c6 ? ry[a][NR - 1] - ry[a][0] : dc;
+          gy = RT(a0) * RT(d0);
+          gy += RT(a1) * RT(d1);
+          gy += RT(a2) * RT(d2);
+          gy += RT(0.0) * RT(dc);
+        } else {
+          gy = sten_apply<RT>(make_sten<ORDER>(0, nx, j, ny), Wd + (long)a * N + idx);
+        }
+        G[a][1] = gy * my;
+        G[a][2] = lds_central<ORDER, RT>(f, sidx, TW) * mz;
+      }
+      RT s2 = RT(0);
+#pragma unroll
+      for (int a = 0; a < ND; ++a)
+#pragma unroll
+        for (int c = 0; c < ND; ++c) {
+          const RT sab = RT(0.5) * (G[a][c] + G[c][a]);
+          s2 += sab * sab;
+        }
+      RT theta = RT(0);
+#pragma unroll
+      for (int a = 0; a < ND; ++a) theta += G[a][a];
+      A[0 * N + idx] = sqrt(s2);
+      A[1 * N + idx] = theta;
+    }
+#pragma unroll
+    for (int a = 0; a < ND; ++a)
+#pragma unroll
+      for (int m = 0; m < NR - 1; ++m) ry[a][m] = ry[a][m + 1];
+  }
+}
+
 // Unfused stage update from a right-hand side R the caller computed: every component of
 // every point, rk_update as in the divergence kernel (the wall row follows in k_bc).
 __global__ __launch_bounds__(256) void k_rk_update(long N, int nvar, const double* __restrict__ R,
@@ -3684,8 +3807,16 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
   if (d.ad_on) {
     const unsigned nts = ND == 2 ? (unsigned)d.tgx * d.tgy : (unsigned)(d.tgx * d.tgz * d.ny);
     timed(ctx, K_AD_SRC, st, [&] {
-      k_ad_src<GAS, ND, ORDER, RT><<<nts, TTX * TTY, ND * TILE_E * sizeof(double), st>>>(
-          d, Wd, (RT*)ctx->AD);
+      if constexpr (ND == 3) {
+        const int rseg = d.N >= (1L << 22) ? 32 : 8;
+        const int nseg = (d.ny + rseg - 1) / rseg;
+        k_ad_src3m<ORDER, RT><<<(unsigned)(d.tgx * d.tgz * nseg), TTX * TTY,
+                                 2 * ND * TILE_E * sizeof(double), st>>>(d, Wd, (RT*)ctx->AD,
+                                                                         rseg, nseg);
+      } else {
+        k_ad_src<GAS, ND, ORDER, RT><<<nts, TTX * TTY, ND * TILE_E * sizeof(double), st>>>(
+            d, Wd, (RT*)ctx->AD);
+      }
     });
     const RT* Gad = launch_ad_smoothing<GAS, ND, RT>(ctx, st);
     launch_flux<GAS, ND, ORDER, true, RT>(ctx, st, Q, Wd, Wp, Gad, F);
