@@ -37,8 +37,16 @@ RK_NAMES = {0: "2N-RK3 (Williamson)", 1: "2N-RK4(3)5 (Carpenter-Kennedy)",
 # dispatch; the factors come from a plain 256 MiB copy), keyed by workload and kernel,
 # valid only for the kernel source whose SHA-256 prefix is given (profiles/ holds the
 # summaries and the commands).  Any other source reports traffic null.
-TRAFFIC = {}
-TRAFFIC_SOURCE_SHA = None
+TRAFFIC = {
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'flux'): 13329370014,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'div'): 11061618058,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'cderiv'): 5218512570,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'div'): 509514128,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'flux'): 469552034,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'prim'): 30725333,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'div'): 61039862,
+}
+TRAFFIC_SOURCE_SHA = "40e370c937ae091a"
 
 
 def source_sha():
@@ -328,6 +336,10 @@ def main():
     tr = TRAFFIC.get((cfg.name, cfg.npts, args.scheme, dom)) if sha == TRAFFIC_SOURCE_SHA else None
     roof = dict(kernel=dom, bound="hbm", achieved=kd["GBps"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=kd["hbm_frac"], traffic=tr,
+                traffic_note=("HBM bytes per launch, rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE "
+                              "(profiles/stage_*.md of this workload)") if tr else
+                ("no counter run of this kernel source and workload" if sha != TRAFFIC_SOURCE_SHA
+                 else "no counter run of this workload"),
                 algorithmic_bytes_per_launch=int(round(model[dom][0] * cfg.npts)),
                 avg_launch_us=kd["avg_us"])
     eff = compulsory_bytes(cfg) * value * 1e6 / 1e9
