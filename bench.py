@@ -22,6 +22,7 @@ import hashlib
 import json
 import os
 import sys
+import re
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -257,6 +258,9 @@ def main():
     cfg = fields.get_config(args.config)
     if args.grid:
         cfg = cfg.scaled(*args.grid)
+        dims = [cfg.nx, cfg.ny] + ([cfg.nz] if cfg.ndim == 3 else [])
+        cfg = dataclasses.replace(cfg, name=re.sub(r"_\d+x\d+(x\d+)?$", "_" + "x".join(map(str, dims)),
+                                                    cfg.name))
     if args.stefan_maxwell:
         cfg = dataclasses.replace(cfg, diffusion=1)
     if args.scheme == "compact":
