@@ -85,8 +85,9 @@ def algorithmic_bytes(cfg, rt, surrogate=False):
     xp = air and (nd == 3 or comp)                 # X_s and p stored as planes
     wd_out = nd + 1 + (5 + 1 if xp else (0 if air else 1))
     if air:
-        wp = 17 + (10 if sm else 0) + (1 if ad else 0)
-        flux_wp = 2 + 5 + (0 if sm else 5) + (10 if sm else 0) + (1 if ad else 0)
+        # mu, kappa, D_s, wdot_s (+ 1/D_sr, + c); the flux forms h_s from T itself
+        wp = 12 + (10 if sm else 0) + (1 if ad else 0)
+        flux_wp = 2 + (0 if sm else 5) + (10 if sm else 0) + (1 if ad else 0)
     else:
         wp = (1 if cfg.gas == 0 else 2) + (1 if ad else 0)
         flux_wp = wp

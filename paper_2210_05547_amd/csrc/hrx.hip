@@ -98,7 +98,7 @@ struct Dev {
                                   // e(T_min), 2 surrogate fallbacks, 3 non-finite
                                   // states, 4 negative densities
   // W plane offsets
-  int nsrc, w_p, w_mu, w_kap, w_D, w_wdot, w_h, w_c;
+  int nsrc, w_p, w_mu, w_kap, w_D, w_wdot, w_c;
   int nad;                        // artificial-diffusivity planes (3 + ns)
   int gx;                         // x segments of TX points per grid row
   int tgx, tgy;                   // 2-D LDS tiles per row / column
@@ -546,9 +546,6 @@ __device__ __forceinline__ void prim_air5(const Dev& d, double* __restrict__ Wd,
   }
 #pragma unroll
   for (int s = 0; s < NS; ++s) Wp[(d.w_wdot + s) * N + idx] = RT(double(wd[s]) * d.wscale);
-  // species enthalpies h_s = e_s + R_s T (nondimensional) for the diffusive heat flux
-#pragma unroll
-  for (int s = 0; s < NS; ++s) Wp[(d.w_h + s) * N + idx] = RT((st.e[s] + gas_const(s) * Tk) * d.ic2);
   if (d.ad_on) {
     double cv = 0.0;
 #pragma unroll
@@ -1326,8 +1323,15 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
 #pragma unroll
         for (int b = 0; b < ND; ++b) dX[s][b] = deriv(ND + 1 + s, b);
     }
+    // species enthalpies h_s = e_s + R_s T (nondimensional) at the point's temperature,
+    // for the diffusive heat flux (formed here rather than stored by the pointwise pass)
+    {
+      const double Tk = double(Wd[ND * N + idx]) * d.T_ref;
+      SpeciesThermo sth;
+      species_e_cv(Tk, sth);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) h[s] = Wp[(d.w_h + s) * N + idx];
+      for (int s = 0; s < NS; ++s) h[s] = RT((sth.e[s] + gas_const(s) * Tk) * d.ic2);
+    }
   }
   // Stefan-Maxwell diffusion (Eq. 17 with the driving forces of Eq. 16), in the molar
   // fluxes j_s = J_s / M_s: sum_{i != s} (X_s j_i - X_i j_s) / D_si = (rho / Mbar) dX_s,
@@ -3591,7 +3595,6 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     d.w_kap = w++;
     d.w_D = w; w += NS;
     d.w_wdot = w; w += NS;
-    d.w_h = w; w += NS;
     if (c.diffusion == HRX_DIFF_STEFAN_MAXWELL) {
       d.sm = 1;
       d.w_iD = w; w += 10;
