@@ -100,7 +100,8 @@ def algorithmic_bytes(cfg, rt, surrogate=False):
     if ad:
         out["ad_src"] = ((2 * rt + (0 if comp else 8 * nd)) + (8 * nd * nd if comp else 0), 1)
         out["ad_d4"] = (2 * nad * rt, 1)
-        if nd == 3:
+        if nd == 3 and comp:
+            # (the explicit 3-D flux applies the z filter to the planes it reads)
             out["ad_filter_z"] = (2 * nad * rt, 1)
     nsrc = nd + 1 + (5 if air else 0)
     flux_in = 8 * (nd + 1 + (5 if (air and nd == 3) else 0) + (1 if (not air or nd == 3) else 0))

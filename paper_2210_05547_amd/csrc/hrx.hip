@@ -1152,11 +1152,15 @@ __global__ __launch_bounds__(MW * NWZ) void k_ad_march3(Dev d, const RT* __restr
 }
 
 // ------------------------------------------------------------------ k_flux
+// 3-D tiles apply the z filter of the artificial-diffusivity planes in the flux kernel
+// (their z halo is the filter's reach) instead of a pass of its own
+constexpr bool FLUX_ZFILTER = true;
 // F planes (double): F[j][k] for direction j and conserved component k.  Convective
 // fluxes are formed in FP64; stresses, heat and diffusion fluxes in RT.
 // CG: the gradients come from planes Gc[b][a] (direction b, source a; the compact
 // scheme's line solves), one thread per point, no tile.
-template <int GAS, int ND, int ORDER, bool AD, class RT, bool SM, bool CG = false>
+template <int GAS, int ND, int ORDER, bool AD, class RT, bool SM, bool CG = false,
+          bool ZF = false>
 __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict__ Q,
                                           const double* __restrict__ Wd,
                                           const RT* __restrict__ Wp,
@@ -1172,6 +1176,9 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
   constexpr bool DX_PER_DIR = (AD || ND == 3) && !(SM && GAS == AIR5);
   extern __shared__ double smem[];
   const long N = d.N;
+  // ZF (3-D tiles): Gad holds the AD planes before their z filter, applied here
+  constexpr int NADP = 3 + (GAS == AIR5 ? NS : 0);
+  RT gz[NADP];
   Pt p;
   long sidx = 0;            // index of the point in the LDS tile
   Sten sd[3];
@@ -1196,6 +1203,32 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
       gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
       return ((long)gk * d.ny + j0) * d.nx + gi;
     };
+    if constexpr (ND == 3 && AD && ZF) {
+      // the z filter of the artificial-diffusivity planes (Gad: the planes before it),
+      // with the z halo of the tile (the filter's reach) staged in the LDS the source tile
+      // uses next; the same taps and order as k_ad_filter_z
+      constexpr int ZE = TH * TTX;
+      stage_tile<NADP * ZE, TTX * TTY>(smem, [&](int e) {
+        const int v = e / ZE, r = e - v * ZE;
+        const int ly = r / TTX, lx = r - ly * TTX;
+        const int gi = min(i0 + lx, d.nx - 1);
+        int gk = k0 + ly - THALO;
+        gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
+        return double(Gad[(long)v * N + ((long)gk * d.ny + j0) * d.nx + gi]);
+      });
+      __syncthreads();
+      const int tx = threadIdx.x & (TTX - 1), ty = threadIdx.x / TTX;
+#pragma unroll 1   // unrolled, the flux's register allocation grew by 124 VGPRs
+      for (int v = 0; v < NADP; ++v) {
+        const double* c = smem + v * ZE + ty * TTX + tx;   // rows k - 4 .. k + 4
+        RT r = RT(c_gauss9[0]) * RT(c[4 * TTX]);
+#pragma unroll
+        for (int m = 1; m <= 4; ++m)
+          r += RT(c_gauss9[m]) * (RT(c[(4 - m) * TTX]) + RT(c[(4 + m) * TTX]));
+        gz[v] = r;
+      }
+      __syncthreads();
+    }
     // u, v, (w), T (and in 3-D X_s) from the pointwise pass's planes
     stage_tile<(XQ ? ND + 1 : NSRC) * TILE_E, TTX * TTY>(smem, [&](int e) {
       const int v = e / TILE_E;
@@ -1298,9 +1331,10 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
            (G[1][0] - G[0][1]) * (G[1][0] - G[0][1]);
     }
     const RT fsw = theta < RT(0) ? theta * theta / (theta * theta + w2 + RT(1e-32)) : RT(0);
-    mu_eff = mu_eff + RT(d.Cmu) * rho_r * Gad[0 * N + idx];
-    beta = RT(d.Cbeta) * rho_r * fsw * Gad[1 * N + idx];
-    kap_eff = kap_eff + RT(d.Ckap) * rho_r * cs / T * Gad[2 * N + idx];
+    auto gad = [&](int v) -> RT { return ZF ? gz[v] : Gad[v * N + idx]; };
+    mu_eff = mu_eff + RT(d.Cmu) * rho_r * gad(0);
+    beta = RT(d.Cbeta) * rho_r * fsw * gad(1);
+    kap_eff = kap_eff + RT(d.Ckap) * rho_r * cs / T * gad(2);
   }
   const double rhoE = Q[(ns + ND) * N + idx];
   // species diffusion (Eq. 18 read with grad X_s)
@@ -1314,7 +1348,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       RT Ds = SM ? RT(0) : Wp[(d.w_D + s) * N + idx];
-      if (AD) Ds = Ds + cs * Gad[(3 + s) * N + idx];
+      if (AD) Ds = Ds + cs * (ZF ? gz[3 + s] : Gad[(3 + s) * N + idx]);
       a_s[s] = rho_r * (RT(molar_mass(s)) / Mbar) * Ds;
     }
     if (!DX_PER_DIR) {
@@ -1495,7 +1529,8 @@ __global__ __launch_bounds__(256) void k_flux(Dev d, const double* __restrict__ 
                                               const double* __restrict__ Wd,
                                               const RT* __restrict__ Wp,
                                               const RT* __restrict__ Gad, double* __restrict__ F) {
-  flux_tile<GAS, ND, ORDER, AD, RT, SM>(d, Q, Wd, Wp, Gad, F);
+  flux_tile<GAS, ND, ORDER, AD, RT, SM, false, ND == 3 && AD && FLUX_ZFILTER>(d, Q, Wd, Wp, Gad,
+                                                                            F);
 }
 // The same for FP64 on 2-D grids of at most two wavefronts per SIMD: occupancy is then
 // bounded by the grid, not by registers, so the compiler may spend up to 256 VGPRs on
@@ -3770,7 +3805,7 @@ void launch_prim(hrx_ctx* ctx, const double* Q, hipStream_t st) {
 // The artificial-diffusivity smoothing passes after the sources: fourth differences with
 // the x and y filters, and (3-D) the z filter; returns the planes the flux reads.
 template <int GAS, int ND, class RT>
-const RT* launch_ad_smoothing(hrx_ctx* ctx, hipStream_t st) {
+const RT* launch_ad_smoothing(hrx_ctx* ctx, hipStream_t st, bool zpass = true) {
   const Dev& d = ctx->dev;
   const long N = d.N;
   RT* A = (RT*)ctx->AD;
@@ -3789,7 +3824,7 @@ const RT* launch_ad_smoothing(hrx_ctx* ctx, hipStream_t st) {
           d, A, B, nstrip, nseg, mseg);
     }
   });
-  if (ND == 3) {
+  if (ND == 3 && zpass) {
     const int nxs = (d.nx + 63) / 64, nzs = (d.nz + ZSEG - 1) / ZSEG;
     timed(ctx, K_AD_FZ, st, [&] {
       k_ad_filter_z<RT><<<(unsigned)((long)nxs * d.ny * nzs * d.nad), 64, 0, st>>>(d, B, A, nxs,
@@ -3821,7 +3856,8 @@ int launch_rhs_chain(hrx_ctx* ctx, const double* Q, hipStream_t st) {
             d, Wd, (RT*)ctx->AD);
       }
     });
-    const RT* Gad = launch_ad_smoothing<GAS, ND, RT>(ctx, st);
+    // 3-D: the flux applies the z filter itself (FLUX_ZFILTER)
+    const RT* Gad = launch_ad_smoothing<GAS, ND, RT>(ctx, st, !(ND == 3 && FLUX_ZFILTER));
     launch_flux<GAS, ND, ORDER, true, RT>(ctx, st, Q, Wd, Wp, Gad, F);
   } else {
     launch_flux<GAS, ND, ORDER, false, RT>(ctx, st, Q, Wd, Wp, nullptr, F);
