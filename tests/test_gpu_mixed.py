@@ -87,6 +87,15 @@ def test_mixed_c2_stefan_maxwell():
     _mixed_case(cfg, 3, "c2_sm_67x41")
 
 
+def test_mixed_stefan_maxwell_3d_and_with_ad():
+    """The Stefan-Maxwell flux in the mixed form on the 3-D jet and on the SBLI with
+    artificial diffusivity."""
+    cfg = dataclasses.replace(fields.get_config("c4").scaled(40, 32, 16), diffusion=1)
+    _mixed_case(cfg, 2, "c4_sm_40x32x16")
+    cfg = dataclasses.replace(fields.get_config("c3").scaled(96, 48), diffusion=1)
+    _mixed_case(cfg, 2, "c3_sm_96x48")
+
+
 def test_mixed_c2_full():
     _mixed_case(fields.get_config("c2"), 3, "c2")
 

@@ -242,6 +242,13 @@ def test_c3_full_size_stages():
     _run_case(fields.get_config("c3"), 2, rhs=False)
 
 
+def test_c3t_full_size():
+    """The thermally perfect SBLI at its full 2048 x 512 (artificial diffusivity with the
+    sound speed of gamma(T), adiabatic wall inside the divergence): right-hand side and
+    two RK stages."""
+    _run_case(fields.get_config("c3t"), 2)
+
+
 def test_c4_full_size_window():
     """The full 512 x 256 x 128 jet in the launch shapes the bench times: right-hand side
     and one RK stage of the whole grid on the GPU, checked against the oracle run on an
