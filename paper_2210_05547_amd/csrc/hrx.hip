@@ -176,6 +176,14 @@ __device__ __forceinline__ long xcd_block() {
   return (b & 7) * per + (b >> 3);
 }
 
+// Periodic index of q in [-n, 3n) on a line of n points (a 3-D tile's z halo reaches up
+// to 11 planes past the last tile origin, which is more than one period when nz = 9)
+__device__ __forceinline__ int wrap_per(int q, int n) {
+  q = q < 0 ? q + n : q;
+  q = q >= n ? q - n : q;
+  return q >= n ? q - n : q;
+}
+
 // Branch-free form of the same first-derivative operators: D f = sum_m a_m (f[p_m] - f[q_m])
 // over at most four pairs.  The pairs depend only on the position along the line, so
 // one Sten serves every field at a point and all field loads can be issued together.
@@ -673,7 +681,7 @@ __global__ __launch_bounds__(256) void k_ad_src(Dev d, const double* __restrict_
       return Wd[(long)v * N + (long)gj * d.nx + gi];
     }
     int gk = k0 + ly - THALO;
-    gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
+    gk = wrap_per(gk, d.nz);
     return Wd[(long)v * N + ((long)gk * d.ny + j0) * d.nx + gi];
   });
   __syncthreads();
@@ -758,7 +766,7 @@ __global__ __launch_bounds__(64) void k_ad_filter_z(Dev d, const RT* __restrict_
   RT* o = out + (long)v * N + (long)j * nx + i;
   const int z0 = zs * ZSEG, z1 = min(z0 + ZSEG, nz);
   auto at = [&](int q) {
-    q = q < 0 ? q + nz : (q >= nz ? q - nz : q);
+    q = wrap_per(q, nz);
     return f[(long)q * P];
   };
   RT w[9];   // planes k - 4 .. k + 4
@@ -1200,7 +1208,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
         return (long)gj * d.nx + gi;
       }
       int gk = k0 + ly - THALO;
-      gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
+      gk = wrap_per(gk, d.nz);
       return ((long)gk * d.ny + j0) * d.nx + gi;
     };
     if constexpr (ND == 3 && AD && ZF) {
@@ -1213,7 +1221,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
         const int ly = r / TTX, lx = r - ly * TTX;
         const int gi = min(i0 + lx, d.nx - 1);
         int gk = k0 + ly - THALO;
-        gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
+        gk = wrap_per(gk, d.nz);
         return double(Gad[(long)v * N + ((long)gk * d.ny + j0) * d.nx + gi]);
       });
       __syncthreads();
@@ -1780,7 +1788,7 @@ __global__ __launch_bounds__(256 * NH) void k_div(Dev d, const double* __restric
           return F[((long)nvar + k) * N + (long)gj * d.nx + gi];
         }
         int gk = k0t + ly - THALO;
-        gk = gk < 0 ? gk + d.nz : (gk >= d.nz ? gk - d.nz : gk);
+        gk = wrap_per(gk, d.nz);
         return F[((long)2 * nvar + k) * N + ((long)gk * d.ny + j0) * d.nx + gi];
       }, lt);
       __syncthreads();
@@ -1961,7 +1969,7 @@ __global__ __launch_bounds__(256) void k_div3m(Dev d, const double* __restrict__
     const int ly = r / TTX, lx = r - ly * TTX;
     const int gi = min(i0 + lx, nx - 1);
     int gk = k0t + ly - THALO;
-    gk = gk < 0 ? gk + nz : (gk >= nz ? gk - nz : gk);
+    gk = wrap_per(gk, nz);
     return ((long)2 * nvar + min(kbeg + kk, nvar - 1)) * N + ((long)gk * ny + j) * nx + gi;
   };
   double v[PER];
@@ -2106,7 +2114,7 @@ __global__ __launch_bounds__(256) void k_ad_src3m(Dev d, const double* __restric
     const int ly = r / TW, lx = r - ly * TW;
     const int gi = min(max(i0 + lx - THALO, 0), nx - 1);
     int gk = k0t + ly - THALO;
-    gk = gk < 0 ? gk + nz : (gk >= nz ? gk - nz : gk);
+    gk = wrap_per(gk, nz);
     return (long)v * N + ((long)gk * ny + j) * nx + gi;
   };
   double vt[PER];

@@ -96,6 +96,10 @@ def test_mixed_stefan_maxwell_3d_and_with_ad():
     _mixed_case(cfg, 2, "c3_sm_96x48")
 
 
+def test_mixed_c4_ragged_3d():
+    _mixed_case(fields.get_config("c4").scaled(37, 29, 13), 2, "c4_37x29x13")
+
+
 def test_mixed_c2_full():
     _mixed_case(fields.get_config("c2"), 3, "c2")
 

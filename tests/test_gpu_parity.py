@@ -242,6 +242,16 @@ def test_c3_full_size_stages():
     _run_case(fields.get_config("c3"), 2, rhs=False)
 
 
+@pytest.mark.parametrize("nz", [13, 9])
+def test_c4_ragged_3d(nz):
+    """3-D jet on a grid that no tile, segment or group divides: partial x tiles and
+    strips (37), a partial last row segment of the y marches (29 rows in segments of 8),
+    partial z tiles and a partial z group of the AD march (tiles of 8 planes, groups of 4),
+    and the periodic z halo of the last tile reaching more than one period past it at
+    nz = 9.  Right-hand side and three stages."""
+    _run_case(fields.get_config("c4").scaled(37, 29, nz), 3)
+
+
 def test_c3t_full_size():
     """The thermally perfect SBLI at its full 2048 x 512 (artificial diffusivity with the
     sound speed of gamma(T), adiabatic wall inside the divergence): right-hand side and
