@@ -47,7 +47,7 @@ TRAFFIC = {
     ('flatplate_air5_m10_512x256', 131072, 'explicit', 'prim'): 25474461,
     ('flatplate_air5_m10_512x256', 131072, 'explicit', 'div'): 61054950,
 }
-TRAFFIC_SOURCE_SHA = "eb283e8eaa89d446"
+TRAFFIC_SOURCE_SHA = "a1bd65fb59768494"
 
 
 def source_sha():
