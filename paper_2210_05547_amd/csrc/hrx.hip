@@ -25,6 +25,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "air5.h"
@@ -2328,6 +2329,120 @@ __global__ __launch_bounds__(64) void k_cd_x(int n, const double* __restrict__ f
   }
 }
 
+// The same solve with the chunk length a power of two C (>= the lines' n / 64) and up to
+// four lines per block sharing the LU factors: the right-hand sides are formed first,
+// each lane reading consecutive points (no bank conflicts), and kept transposed -- element
+// e at slot (e mod C) 64 + e / C -- with the factors, so that the lanes stepping through
+// their chunks touch 64 consecutive slots.  Where C = n / 64 exactly (every line of
+// 64 C points) the chunks, and so the results, are those of k_cd_x.
+template <bool ACC, int C>
+__global__ __launch_bounds__(256) void k_cd_xp(int n, long nlines, const double* __restrict__ f,
+                                               long fps, double* out, long ops,
+                                               const double* __restrict__ m, double scale,
+                                               int order, CLine L) {
+  constexpr int S = 64 * C;
+  constexpr int LC = C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : C == 8 ? 3 : 4;
+  static_assert((1 << LC) == C, "C a power of two up to 16");
+  extern __shared__ double sm[];
+  const int nw = blockDim.x >> 6;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* slo = sm;
+  double* sup = sm + S;
+  double* siu = sm + 2 * S;
+  double* sf = sm + (3 + 2 * w) * S;   // the line, by point
+  double* sr = sf + S;                 // r, then d, then x, transposed
+  auto slot = [](int e) { return (e & (C - 1)) * 64 + (e >> LC); };
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int q = slot(e);
+    slo[q] = L.lo[e];
+    sup[q] = L.up[e];
+    siu[q] = L.iu[e];
+  }
+  const long line = min((long)blockIdx.x * nw + w, nlines - 1);   // extra waves redo the last
+  const bool live = (long)blockIdx.x * nw + w < nlines;
+  const double* fl = f + (long)blockIdx.y * fps + line * n;
+  double* ol = out + (long)blockIdx.y * ops + line * n;
+  for (int i = lane; i < n; i += 64) sf[i] = fl[i];
+  __syncthreads();
+  for (int i = lane; i < n; i += 64) {
+    double wv[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int q = i + k - 2;
+      wv[k] = (q >= 0 && q < n) ? sf[q] : 0.0;
+    }
+    sr[slot(i)] = crow(wv, i, n, order, false);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int nk = max(0, min(C, n - lane * C));
+  // forward: d_i = r_i - lo_i d_{i-1}; the chunk maps d_{a-1} to d_{b-1} as A x + B
+  double A = 1.0, B = 0.0;
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    if (k < nk) {
+      const double li = slo[k * 64 + lane];
+      B = sr[k * 64 + lane] - li * B;
+      A = -li * A;
+    }
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+    const double Ap = __shfl_up(A, off), Bp = __shfl_up(B, off);
+    if (lane >= off) {
+      B = A * Bp + B;
+      A = A * Ap;
+    }
+  }
+  double prev = __shfl_up(B, 1);
+  if (lane == 0) prev = 0.0;
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    if (k < nk) {
+      const double di = sr[k * 64 + lane] - slo[k * 64 + lane] * prev;
+      sr[k * 64 + lane] = di;
+      prev = di;
+    }
+  }
+  // backward: x_i = (d_i - up_i x_{i+1}) iu_i; the chunk maps x_b to x_a as A x + B
+  A = 1.0;
+  B = 0.0;
+#pragma unroll
+  for (int k = C - 1; k >= 0; --k) {
+    if (k < nk) {
+      const double iu = siu[k * 64 + lane], u = sup[k * 64 + lane];
+      B = (sr[k * 64 + lane] - u * B) * iu;
+      A = -(u * iu) * A;
+    }
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+    const double An = __shfl_down(A, off), Bn = __shfl_down(B, off);
+    if (lane + off < 64) {
+      B = A * Bn + B;
+      A = A * An;
+    }
+  }
+  double next = __shfl_down(B, 1);
+  if (lane == 63) next = 0.0;
+#pragma unroll
+  for (int k = C - 1; k >= 0; --k) {
+    if (k < nk) {
+      const double xi = (sr[k * 64 + lane] - sup[k * 64 + lane] * next) * siu[k * 64 + lane];
+      sr[k * 64 + lane] = xi;
+      next = xi;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (live) {
+    for (int i = lane; i < n; i += 64) {
+      const double v = scale * m[i] * sr[slot(i)];
+      ol[i] = ACC ? ol[i] + v : v;
+    }
+  }
+}
+
 // y or z lines: one thread per line marching along it (threads of a block hold
 // consecutive x columns: every access is coalesced).  Line c = (cx, c2): first point
 // c2 * s2 + cx, n points at stride s.  The forward values go to W (out itself, or a
@@ -3902,10 +4017,41 @@ void launch_cd(hrx_ctx* ctx, int dir, const double* f, long fps, double* out, lo
   const int ord = d.fd_order;
   timed(ctx, K_CDERIV, st, [&] {
     if (dir == 0) {
-      const dim3 g((unsigned)(N / d.nx), (unsigned)nplanes);
-      const size_t sh = 2 * (size_t)d.nx * sizeof(double);
-      if (acc) k_cd_x<true><<<g, 64, sh, st>>>(d.nx, f, fps, out, ops, d.mx, scale, ord, d.cl[0]);
-      else k_cd_x<false><<<g, 64, sh, st>>>(d.nx, f, fps, out, ops, d.mx, scale, ord, d.cl[0]);
+      // chunks of C = the power of two >= nx / 64 points per lane, up to four lines per
+      // block within 64 KB of LDS (factors + two arrays per line)
+      const long nlines = N / d.nx;
+      int C = 1;
+      while (64 * C < d.nx) C *= 2;
+      const long S = 64L * C;
+      const int nw = (int)std::max(1L, std::min(4L, ((65536L / (8 * S)) - 3) / 2));
+      const dim3 g((unsigned)((nlines + nw - 1) / nw), (unsigned)nplanes);
+      const size_t sh = (size_t)(3 + 2 * nw) * S * sizeof(double);
+      auto go = [&](auto cc) {
+        constexpr int CC = decltype(cc)::value;
+        if (acc)
+          k_cd_xp<true, CC><<<g, 64 * nw, sh, st>>>(d.nx, nlines, f, fps, out, ops, d.mx, scale,
+                                                     ord, d.cl[0]);
+        else
+          k_cd_xp<false, CC><<<g, 64 * nw, sh, st>>>(d.nx, nlines, f, fps, out, ops, d.mx, scale,
+                                                      ord, d.cl[0]);
+      };
+      switch (C) {
+        case 1: go(std::integral_constant<int, 1>()); break;
+        case 2: go(std::integral_constant<int, 2>()); break;
+        case 4: go(std::integral_constant<int, 4>()); break;
+        case 8: go(std::integral_constant<int, 8>()); break;
+        case 16: go(std::integral_constant<int, 16>()); break;
+        default: {
+          // longer lines (C = 32 would need 80 KB of LDS per line): one wavefront per line
+          // with the line in LDS by point
+          const dim3 g1((unsigned)nlines, (unsigned)nplanes);
+          const size_t sh1 = 2 * (size_t)d.nx * sizeof(double);
+          if (acc)
+            k_cd_x<true><<<g1, 64, sh1, st>>>(d.nx, f, fps, out, ops, d.mx, scale, ord, d.cl[0]);
+          else
+            k_cd_x<false><<<g1, 64, sh1, st>>>(d.nx, f, fps, out, ops, d.mx, scale, ord, d.cl[0]);
+        }
+      }
     } else if (dir == 1) {
       const dim3 g(blocks_for((long)d.nx * d.nz, 128), (unsigned)nplanes);
       const long s2 = (long)d.nx * d.ny;

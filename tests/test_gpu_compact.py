@@ -78,7 +78,8 @@ def test_compact_c1_ssp_rk3():
     _run(compact(fields.get_config("c1").scaled(64, 40), rk=2), 9)
 
 
-@pytest.mark.parametrize("shape", [(40, 24), (67, 41)])
+# x lines of 40, 67, 200 and 700 points: the x solve's chunks of 1, 2, 4 and 16 points
+@pytest.mark.parametrize("shape", [(40, 24), (67, 41), (200, 40), (700, 24)])
 def test_compact_c2_air5_reduced(shape):
     _run(compact(fields.get_config("c2").scaled(*shape)), 4)
 
