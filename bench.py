@@ -39,15 +39,15 @@ RK_NAMES = {0: "2N-RK3 (Williamson)", 1: "2N-RK4(3)5 (Carpenter-Kennedy)",
 # valid only for the kernel source whose SHA-256 prefix is given (profiles/ holds the
 # summaries and the commands).  Any other source reports traffic null.
 TRAFFIC = {
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'flux'): 12619998528,
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'div'): 11053406335,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'cderiv'): 5218613684,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'div'): 510584442,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'flux'): 423847566,
-    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'prim'): 25472186,
-    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'div'): 61055334,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'flux'): 12619271040,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'div'): 11052190460,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'cderiv'): 5218593297,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'div'): 510590287,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'flux'): 424308791,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'prim'): 25475257,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'div'): 61047328,
 }
-TRAFFIC_SOURCE_SHA = "a1bd65fb59768494"
+TRAFFIC_SOURCE_SHA = "98bbf21fb17b2c89"
 
 
 def source_sha():
