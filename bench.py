@@ -241,8 +241,8 @@ def main():
                     help="only run a plain device copy of MIB MiB 10 times (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (how the "
-              "path would shard over several GPUs is described in DESIGN.md, not built)",
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sharding "
+              "the grid over several GPUs is not built)",
               file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:

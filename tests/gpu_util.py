@@ -1,5 +1,7 @@
 """Helpers shared by the GPU parity tests (error norms, oracle windows of a full grid)."""
 import dataclasses
+import json
+import os
 
 import numpy as np
 
@@ -60,3 +62,12 @@ def tie_free_rows(acts, margin=1e-5):
         d = np.abs(f.astype(np.float64) - mid) / np.maximum(f.astype(np.float64), 1e-300)
         ok &= np.all((f == 0.0) | (d > margin), axis=1)
     return ok
+
+
+def write_report(name, data):
+    """Writes a test's per-field figures as JSON into the folder that HRX_REPORT_DIR names,
+    when it names one (nothing is written otherwise)."""
+    out = os.environ.get("HRX_REPORT_DIR")
+    if out and os.path.isdir(out):
+        with open(os.path.join(out, name), "w") as f:
+            json.dump(data, f, indent=1)

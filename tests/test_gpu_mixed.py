@@ -5,11 +5,9 @@ the energy inversion, the Arrhenius exponentials at T >= 2000 K, the conserved s
 and the RK update in FP64.  Bar: 1e-5 relative, normwise per field, on every
 component of R, on the change of Q over the stages, and on mu, kappa, D_s, wdot_s of
 the pointwise calls.  Per-field errors are printed (and written to
-gpurun_out/mixed_errors.json when that folder exists).
+mixed_errors.json in the folder HRX_REPORT_DIR names, if set).
 """
 import dataclasses
-import json
-import os
 import sys
 
 import numpy as np
@@ -23,7 +21,7 @@ from oracle import chemistry as och  # noqa: E402
 from oracle import rhs as orhs  # noqa: E402
 from oracle import thermo as oth  # noqa: E402
 from oracle import transport as otr  # noqa: E402
-from gpu_util import JET_WINDOW, field_errors, normwise, oracle_window  # noqa: E402
+from gpu_util import JET_WINDOW, field_errors, normwise, oracle_window, write_report  # noqa: E402
 
 TOL = 1e-5
 DEV = "cuda:0"
@@ -40,10 +38,7 @@ def dev(a):
 
 def _record(name, errs):
     REPORT[name] = [float(e) for e in errs]
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out):
-        with open(os.path.join(out, "mixed_errors.json"), "w") as f:
-            json.dump(REPORT, f, indent=1)
+    write_report("mixed_errors.json", REPORT)
 
 
 def _mixed_case(cfg, stages, name):

@@ -10,7 +10,6 @@ surrogate's parity bar); held-out transport per point: RMS relative error <= 1e-
 99.9th percentile <= 5e-3, max <= 1e-2; out-of-hull points reproduce the plain
 evaluation to 1e-12.
 """
-import json
 import math
 import os
 import time
@@ -26,7 +25,7 @@ from oracle import mlp as omlp  # noqa: E402
 from oracle import rhs as orhs  # noqa: E402
 from oracle import thermo as oth  # noqa: E402
 from oracle import transport as otr  # noqa: E402
-from gpu_util import field_errors, normwise, tie_free_rows  # noqa: E402
+from gpu_util import field_errors, normwise, tie_free_rows, write_report  # noqa: E402
 from surrogate_util import (LOGRHO_RANGE, T_RANGE, XI_N_RANGE, element_N_fraction,  # noqa: E402
                             features, fit_norm, network_targets, raw_dataset, set_norm, states)
 
@@ -34,16 +33,13 @@ DEV = "cuda:0"
 NTOT = 1_000_000
 BATCH = 4096
 EPOCHS = int(os.environ.get("HRX_SURROGATE_EPOCHS", "200"))
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
 REPORT = {}
 
 
 def report(k, v):
     REPORT[k] = v
     print(" ", k, v, flush=True)
-    if os.path.isdir(OUT):
-        with open(os.path.join(OUT, "surrogate_report.json"), "w") as f:
-            json.dump(REPORT, f, indent=1)
+    write_report("surrogate_report.json", REPORT)
 
 
 def air_ctx(cfg=None, hold=None):
