@@ -185,6 +185,16 @@ __device__ __forceinline__ int wrap_per(int q, int n) {
   return q >= n ? q - n : q;
 }
 
+// Values a kernel touches once and no other block re-reads (the point's own state,
+// fluxes and updates) are loaded and stored with the nontemporal hint, so that they do
+// not displace from L2 the stencil neighbours that nearby blocks read again (measured on
+// the jet box: flux -4 %, 3-D divergence -3.5 %, same bits; on the 2-D SBLI the flux
+// -3 % from the loads alone).
+template <class T>
+__device__ __forceinline__ T ld_once(const T* p) { return __builtin_nontemporal_load(p); }
+template <class T>
+__device__ __forceinline__ void st_once(T v, T* p) { __builtin_nontemporal_store(v, p); }
+
 // Branch-free form of the same first-derivative operators: D f = sum_m a_m (f[p_m] - f[q_m])
 // over at most four pairs.  The pairs depend only on the position along the line, so
 // one Sten serves every field at a point and all field loads can be issued together.
@@ -1154,7 +1164,7 @@ __global__ __launch_bounds__(MW * NWZ) void k_ad_march3(Dev d, const RT* __restr
           }
           res = yacc / wsum;
         }
-        if (olane) B[(long)v * N + kb + (long)r * nx + ocol] = res;
+        if (olane) st_once(res, &B[(long)v * N + kb + (long)r * nx + ocol]);
       }
     }
   }
@@ -1304,7 +1314,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
   double u[3];
 #pragma unroll
   for (int a = 0; a < ND; ++a) u[a] = Wd[a * N + idx];
-  const RT mu = Wp[d.w_mu * N + idx];
+  const RT mu = ld_once(&Wp[d.w_mu * N + idx]);
   double rho, rs[NS], pr;
   RT Y[NS];
   if (GAS != AIR5) {
@@ -1314,24 +1324,24 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
     rho = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      rs[s] = Q[s * N + idx];
+      rs[s] = ld_once(&Q[s * N + idx]);
       rho += rs[s];
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) Y[s] = RT(rs[s] / rho);
-    pr = XQ ? air5_pressure(d, rs, Wd[ND * N + idx]) : Wd[d.w_p * N + idx];
+    pr = XQ ? air5_pressure(d, rs, Wd[ND * N + idx]) : ld_once(&Wd[d.w_p * N + idx]);
   }
   RT theta = RT(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a) theta += G[a][a];
-  const RT kap = (GAS == CPG) ? mu : Wp[d.w_kap * N + idx];
+  const RT kap = (GAS == CPG) ? mu : ld_once(&Wp[d.w_kap * N + idx]);
   RT mu_eff = mu / RT(d.Re);
   RT kap_eff = kap / RT(d.Re * d.Pr);
   RT beta = RT(0), cs = RT(0);
   const RT rho_r = RT(rho);
   if (AD) {
     const RT T = RT(Wd[ND * N + idx]);
-    cs = Wp[d.w_c * N + idx];
+    cs = ld_once(&Wp[d.w_c * N + idx]);
     RT w2;
     if (ND == 2) {
       w2 = (G[1][0] - G[0][1]) * (G[1][0] - G[0][1]);
@@ -1345,7 +1355,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
     beta = RT(d.Cbeta) * rho_r * fsw * gad(1);
     kap_eff = kap_eff + RT(d.Ckap) * rho_r * cs / T * gad(2);
   }
-  const double rhoE = Q[(ns + ND) * N + idx];
+  const double rhoE = ld_once(&Q[(ns + ND) * N + idx]);
   // species diffusion (Eq. 18 read with grad X_s)
   RT a_s[NS], h[NS];
   RT dX[NS][3];
@@ -1356,7 +1366,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
     const RT Mbar = RT(1) / nsum;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      RT Ds = SM ? RT(0) : Wp[(d.w_D + s) * N + idx];
+      RT Ds = SM ? RT(0) : ld_once(&Wp[(d.w_D + s) * N + idx]);
       if (AD) Ds = Ds + cs * (ZF ? gz[3 + s] : Gad[(3 + s) * N + idx]);
       a_s[s] = rho_r * (RT(molar_mass(s)) / Mbar) * Ds;
     }
@@ -1473,6 +1483,12 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
 #pragma unroll
       for (int c = 0; c < ND; ++c) Jsm[s][c] = RT(molar_mass(s)) * Bm[s][c];
   }
+  // the 3-D flux planes (27 of them) are far larger than the last-level cache and are
+  // stored nontemporal; the 2-D ones may still be cached when the divergence reads them
+  auto put = [](double v, double* q) {
+    if constexpr (ND == 3) st_once(v, q);
+    else *q = v;
+  };
 #pragma unroll
   for (int j = 0; j < ND; ++j) {
     double* Fj = F + (long)j * nvar * N;
@@ -1502,10 +1518,10 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
       for (int s = 0; s < NS; ++s) {
         // FP64: rho Y_s stands in for rho_s (equal to rounding; fewer live registers)
         const double rsj = sizeof(RT) == sizeof(double) ? rho * double(Y[s]) : rs[s];
-        Fj[s * N + idx] = rsj * u[j] + double(J[s]);
+        put(rsj * u[j] + double(J[s]), &Fj[s * N + idx]);
       }
     } else {
-      Fj[idx] = rho * u[j];
+      put(rho * u[j], &Fj[idx]);
     }
     RT tau[3];
 #pragma unroll
@@ -1516,9 +1532,9 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
         if (AD) t = t + beta * theta;
       }
       tau[a] = t;
-      double conv = Q[(ns + a) * N + idx] * u[j];
+      double conv = ld_once(&Q[(ns + a) * N + idx]) * u[j];
       if (a == j) conv = conv + pr;
-      Fj[(ns + a) * N + idx] = conv - double(t);
+      put(conv - double(t), &Fj[(ns + a) * N + idx]);
     }
     RT q = -kap_eff * dT[j];
     if (GAS == AIR5) {
@@ -1530,7 +1546,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
     RT work = RT(0);
 #pragma unroll
     for (int a = 0; a < ND; ++a) work += tau[a] * RT(u[a]);
-    Fj[(ns + ND) * N + idx] = (rhoE + pr) * u[j] - double(work - q);
+    put((rhoE + pr) * u[j] - double(work - q), &Fj[(ns + ND) * N + idx]);
   }
 }
 template <int GAS, int ND, int ORDER, bool AD, class RT, bool SM = false>
@@ -2006,9 +2022,9 @@ __global__ __launch_bounds__(256) void k_div3m(Dev d, const double* __restrict__
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       const int k = min(kbeg + kk, nvar - 1);
-      qv_[kk] = Qio[k * N + idx];
-      dq_[kk] = dQio[k * N + idx];
-      wd_[kk] = GAS == AIR5 ? Wp[(d.w_wdot + min(k, NS - 1)) * N + idx] : RT(0);
+      qv_[kk] = ld_once(&Qio[k * N + idx]);
+      dq_[kk] = ld_once(&dQio[k * N + idx]);
+      wd_[kk] = GAS == AIR5 ? ld_once(&Wp[(d.w_wdot + min(k, NS - 1)) * N + idx]) : RT(0);
       qr_[kk] = 0.0;
       if (Qref != nullptr && sig != 0.0) qr_[kk] = Qref[k * N + idx];
     }
@@ -2064,8 +2080,8 @@ __global__ __launch_bounds__(256) void k_div3m(Dev d, const double* __restrict__
         double qn, dqn;
         bool wdq;
         rk_update(rkf, A, B, dt, R, qv, dq_in ? dq_[kk] : 0.0, qn, dqn, wdq);
-        if (wdq) dQio[k * N + idx] = dqn;
-        Qio[k * N + idx] = qn;
+        if (wdq) st_once(dqn, &dQio[k * N + idx]);
+        st_once(qn, &Qio[k * N + idx]);
       }
     }
 #pragma unroll
