@@ -2282,7 +2282,18 @@ __global__ __launch_bounds__(64) void k_cd_x(int n, const double* __restrict__ f
   const long line = blockIdx.x;
   const double* fl = f + (long)blockIdx.y * fps + line * n;
   double* ol = out + (long)blockIdx.y * ops + line * n;
-  for (int i = lane; i < n; i += 64) sf[i] = fl[i];
+  // loads in groups of eight per lane, all in flight before their LDS stores
+  for (int i0 = 0; i0 < n; i0 += 512) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + lane + 64 * q;
+      v[q] = i < n ? ld_once(&fl[i]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (i0 + lane + 64 * q < n) sf[i0 + lane + 64 * q] = v[q];
+  }
   __syncthreads();
   const int C = (n + 63) / 64;
   const int a = min(lane * C, n), b = min(a + C, n);
@@ -2339,9 +2350,22 @@ __global__ __launch_bounds__(64) void k_cd_x(int n, const double* __restrict__ f
     next = xi;
   }
   __syncthreads();
-  for (int i = lane; i < n; i += 64) {
-    const double v = scale * m[i] * sf[i];
-    ol[i] = ACC ? ol[i] + v : v;
+  for (int i0 = 0; i0 < n; i0 += 512) {
+    double o[8], mv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = min(i0 + lane + 64 * q, n - 1);
+      mv[q] = m[i];
+      o[q] = ACC ? ld_once(&ol[i]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + lane + 64 * q;
+      if (i < n) {
+        const double v = scale * mv[q] * sf[i];
+        st_once(ACC ? o[q] + v : v, &ol[i]);
+      }
+    }
   }
 }
 
@@ -2378,7 +2402,18 @@ __global__ __launch_bounds__(256) void k_cd_xp(int n, long nlines, const double*
   const bool live = (long)blockIdx.x * nw + w < nlines;
   const double* fl = f + (long)blockIdx.y * fps + line * n;
   double* ol = out + (long)blockIdx.y * ops + line * n;
-  for (int i = lane; i < n; i += 64) sf[i] = fl[i];
+  {
+    // every load of the line in flight before the first LDS store
+    double v[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int i = lane + 64 * q;
+      v[q] = i < n ? ld_once(&fl[i]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+      if (lane + 64 * q < n) sf[lane + 64 * q] = v[q];
+  }
   __syncthreads();
   for (int i = lane; i < n; i += 64) {
     double wv[5];
@@ -2452,9 +2487,20 @@ __global__ __launch_bounds__(256) void k_cd_xp(int n, long nlines, const double*
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (live) {
-    for (int i = lane; i < n; i += 64) {
-      const double v = scale * m[i] * sr[slot(i)];
-      ol[i] = ACC ? ol[i] + v : v;
+    double o[C], mv[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int i = min(lane + 64 * q, n - 1);
+      mv[q] = m[i];
+      o[q] = ACC ? ld_once(&ol[i]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int i = lane + 64 * q;
+      if (i < n) {
+        const double v = scale * mv[q] * sr[slot(i)];
+        st_once(ACC ? o[q] + v : v, &ol[i]);
+      }
     }
   }
 }
@@ -2515,6 +2561,180 @@ __global__ __launch_bounds__(128) void k_cd_col(int n, long s, int ncx, int nc2,
       const double xi = wl[(long)i * s] - fac * L.q[i];
       const double v = scale * m[i] * xi;
       ol[(long)i * s] = ACC ? ol[(long)i * s] + v : v;
+    }
+  }
+}
+
+// The same y or z line solves with the lines held on chip: a block of four wavefronts
+// takes 16 consecutive lines (x columns c0 .. c0 + 15, first point c2 * s2 + c0, stride s)
+// of n <= 16 CL points.  The block stages them in LDS with row-wise (coalesced) loads;
+// wavefront w then owns lines 4w .. 4w + 3, lane (p, l) = (lane mod 16, lane / 16) the
+// chunk [p CL, (p + 1) CL) of line 4w + l.  Each lane forms its chunk's right-hand sides
+// into registers, and the two recurrences run as in k_cd_xp (affine maps composed within
+// the chunk, scanned across the line's 16 lanes, then evaluated); the periodic direction
+// adds the Sherman-Morrison correction in registers.  The results go back to LDS and
+// leave row-wise: f is read once and out written (ACC: read and written) once, where
+// the thread-per-line march also writes and re-reads the forward values.  Line element
+// (i, line) sits at slot (i mod CL) 64 + i / CL + 16 (line mod 4) of wavefront line / 4's
+// region, so that a step of the 64 lanes touches 64 consecutive slots; the factors are
+// held the same way ((i mod CL) 16 + i / CL).  f and out are streamed with the nontemporal
+// hint.  Up to CL = 16 the registers are capped at four wavefronts per SIMD (measured:
+// the jet box's y and z solves -6 %; CL = 32 would spill).
+template <bool ACC, bool PER, int CL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CL <= 16 ? 4 : 1))) void k_cd_colp(int n, long s, int ncx, long s2,
+                                                 const double* __restrict__ f, long fps,
+                                                 double* out, long ops,
+                                                 const double* __restrict__ m, double scale,
+                                                 int order, CLine L) {
+  constexpr int RG = 64 * CL;            // one wavefront's region (4 lines)
+  constexpr int NF = PER ? 4 : 3;        // factor arrays (lo, up, iu, q)
+  extern __shared__ double sm[];
+  double* sf = sm;                       // 4 regions
+  double* sfac = sm + 4 * RG;            // NF arrays of 16 CL
+  const int ngx = (ncx + 15) >> 4;
+  const long c2 = blockIdx.x / (unsigned)ngx;
+  const int c0 = (int)(blockIdx.x - c2 * ngx) * 16;
+  const long base = c2 * s2 + c0;
+  const double* fl = f + (long)blockIdx.y * fps + base;
+  double* ol = out + (long)blockIdx.y * ops + base;
+  const int t = threadIdx.x;
+  auto slot = [](int i, int line) {
+    return (line >> 2) * RG + (i & (CL - 1)) * 64 + (i / CL) + 16 * (line & 3);
+  };
+  // stage: element e = row * 16 + column (columns past ncx repeat the last one)
+  constexpr int PER_T = CL;              // 16 CL rows x 16 columns / 256 threads
+  double v[PER_T];
+#pragma unroll
+  for (int q = 0; q < PER_T; ++q) {
+    const int e = t + 256 * q, row = min(e >> 4, n - 1), col = min(e & 15, ncx - 1 - c0);
+    v[q] = ld_once(&fl[(long)row * s + col]);
+  }
+  for (int i = t; i < n; i += 256) {
+    const int fs = (i & (CL - 1)) * 16 + i / CL;
+    sfac[fs] = L.lo[i];
+    sfac[16 * CL + fs] = L.up[i];
+    sfac[32 * CL + fs] = L.iu[i];
+    if (PER) sfac[48 * CL + fs] = L.q[i];
+  }
+#pragma unroll
+  for (int q = 0; q < PER_T; ++q) {
+    const int e = t + 256 * q;
+    if ((e >> 4) < n) sf[slot(e >> 4, e & 15)] = v[q];
+  }
+  __syncthreads();
+  const int w = t >> 6, lane = t & 63, p = lane & 15;
+  const double* fw = sf + w * RG + (lane & 48);   // this lane's line, p added per row
+  // value of row q of the lane's line (q in [-2, n + 1]; periodic rows wrap, rows outside
+  // a non-periodic line are never used and read as 0)
+  auto at = [&](int q) -> double {
+    if (PER) q = q < 0 ? q + n : (q >= n ? q - n : q);
+    else if (q < 0 || q >= n) return 0.0;
+    return fw[(q & (CL - 1)) * 64 + q / CL];
+  };
+  const int a = p * CL, nk = max(0, min(CL, n - a));
+  double r[CL];
+  {
+    // rows a - 2 .. a + nk + 1 only (an empty chunk reads nothing)
+    double win[5];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) win[k + 1] = nk > 0 ? at(a + k - 2) : 0.0;
+#pragma unroll
+    for (int k = 0; k < CL; ++k) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) win[j] = win[j + 1];
+      win[4] = k < nk ? at(a + k + 2) : 0.0;
+      r[k] = k < nk ? crow(win, a + k, n, order, PER) : 0.0;
+    }
+  }
+  const double* flo = sfac + p;
+  const double* fup = sfac + 16 * CL + p;
+  const double* fiu = sfac + 32 * CL + p;
+  // forward: d_i = r_i - lo_i d_{i-1}; the chunk maps d_{a-1} to d_{a+nk-1} as A x + B
+  double A = 1.0, B = 0.0;
+#pragma unroll
+  for (int k = 0; k < CL; ++k) {
+    if (k < nk) {
+      const double li = flo[k * 16];
+      B = r[k] - li * B;
+      A = -li * A;
+    }
+  }
+  for (int off = 1; off < 16; off <<= 1) {
+    const double Ap = __shfl_up(A, off, 16), Bp = __shfl_up(B, off, 16);
+    if (p >= off) {
+      B = A * Bp + B;
+      A = A * Ap;
+    }
+  }
+  double prev = __shfl_up(B, 1, 16);
+  if (p == 0) prev = 0.0;
+#pragma unroll
+  for (int k = 0; k < CL; ++k) {
+    if (k < nk) {
+      r[k] = r[k] - flo[k * 16] * prev;
+      prev = r[k];
+    }
+  }
+  // backward: x_i = (d_i - up_i x_{i+1}) iu_i; the chunk maps x_{a+nk} to x_a as A x + B
+  A = 1.0;
+  B = 0.0;
+#pragma unroll
+  for (int k = CL - 1; k >= 0; --k) {
+    if (k < nk) {
+      const double iu = fiu[k * 16], u = fup[k * 16];
+      B = (r[k] - u * B) * iu;
+      A = -(u * iu) * A;
+    }
+  }
+  for (int off = 1; off < 16; off <<= 1) {
+    const double An = __shfl_down(A, off, 16), Bn = __shfl_down(B, off, 16);
+    if (p + off < 16) {
+      B = A * Bn + B;
+      A = A * An;
+    }
+  }
+  double next = __shfl_down(B, 1, 16);
+  if (p == 15) next = 0.0;
+#pragma unroll
+  for (int k = CL - 1; k >= 0; --k) {
+    if (k < nk) {
+      r[k] = (r[k] - fup[k * 16] * next) * fiu[k * 16];
+      next = r[k];
+    }
+  }
+  if (PER) {
+    // x = y - s (y_0 - alpha y_{n-1}) q
+    const int pl = (n - 1) / CL, kl = (n - 1) - pl * CL;
+    double yl = 0.0;
+#pragma unroll
+    for (int k = 0; k < CL; ++k)
+      if (k == kl) yl = r[k];
+    const double y0 = __shfl(r[0], 0, 16);
+    yl = __shfl(yl, pl, 16);
+    const double fac = L.s * (y0 - L.alpha * yl);
+    const double* fq = sfac + 48 * CL + p;
+#pragma unroll
+    for (int k = 0; k < CL; ++k)
+      if (k < nk) r[k] = r[k] - fac * fq[k * 16];
+  }
+  // every lane of the wavefront has read its neighbours' rows: results overwrite them
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  {
+    double* xw = sf + w * RG + lane;
+#pragma unroll
+    for (int k = 0; k < CL; ++k)
+      if (k < nk) xw[k * 64] = r[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER_T; ++q) {
+    const int e = t + 256 * q, row = e >> 4, col = e & 15;
+    if (row < n && c0 + col < ncx) {
+      const double x = scale * m[row] * sf[slot(row, col)];
+      double* o = ol + (long)row * s + col;
+      st_once(ACC ? ld_once(o) + x : x, o);
     }
   }
 }
@@ -4023,6 +4243,14 @@ void launch_bc(hrx_ctx* ctx, double* Q, hipStream_t st) {
   });
 }
 
+// k_cd_colp: the chunk length, the power of two >= n / 16 (up to 32: 80 KB of LDS)
+int cdcol_chunk(int n) {
+  int c = 1;
+  while (16 * c < n) c *= 2;
+  return c;
+}
+bool cdcol_fits(int n) { return n >= 2 && n <= 512; }
+
 // Compact first derivatives of nplanes planes along direction dir: f (plane stride fps)
 // -> out (plane stride ops), out = scale m D f, or out += scale m D f (acc; the forward
 // values then go through the context's temporary planes).
@@ -4067,6 +4295,36 @@ void launch_cd(hrx_ctx* ctx, int dir, const double* f, long fps, double* out, lo
           else
             k_cd_x<false><<<g1, 64, sh1, st>>>(d.nx, f, fps, out, ops, d.mx, scale, ord, d.cl[0]);
         }
+      }
+    } else if (cdcol_fits(dir == 1 ? d.ny : d.nz)) {
+      // lines of up to 512 points: 16 lines per block, held on chip (k_cd_colp)
+      const bool yl = dir == 1;
+      const int n = yl ? d.ny : d.nz;
+      const long s = yl ? (long)d.nx : (long)d.nx * d.ny;
+      const long s2 = yl ? (long)d.nx * d.ny : (long)d.nx;
+      const long nc2 = yl ? d.nz : d.ny;
+      const int CL = cdcol_chunk(n);
+      const dim3 g((unsigned)(((d.nx + 15) / 16) * nc2), (unsigned)nplanes);
+      const size_t sh = (size_t)(256 + 16 * (yl ? 3 : 4)) * CL * sizeof(double);
+      const double* mm = yl ? d.my : d.mz;
+      const CLine& cl = d.cl[dir];
+      auto go = [&](auto cc) {
+        constexpr int CC = decltype(cc)::value;
+        if (yl) {
+          if (acc) k_cd_colp<true, false, CC><<<g, 256, sh, st>>>(n, s, d.nx, s2, f, fps, out, ops, mm, scale, ord, cl);
+          else k_cd_colp<false, false, CC><<<g, 256, sh, st>>>(n, s, d.nx, s2, f, fps, out, ops, mm, scale, ord, cl);
+        } else {
+          if (acc) k_cd_colp<true, true, CC><<<g, 256, sh, st>>>(n, s, d.nx, s2, f, fps, out, ops, mm, scale, ord, cl);
+          else k_cd_colp<false, true, CC><<<g, 256, sh, st>>>(n, s, d.nx, s2, f, fps, out, ops, mm, scale, ord, cl);
+        }
+      };
+      switch (CL) {
+        case 1: go(std::integral_constant<int, 1>()); break;
+        case 2: go(std::integral_constant<int, 2>()); break;
+        case 4: go(std::integral_constant<int, 4>()); break;
+        case 8: go(std::integral_constant<int, 8>()); break;
+        case 16: go(std::integral_constant<int, 16>()); break;
+        default: go(std::integral_constant<int, 32>()); break;
       }
     } else if (dir == 1) {
       const dim3 g(blocks_for((long)d.nx * d.nz, 128), (unsigned)nplanes);

@@ -2,8 +2,9 @@
 fd_scheme = HRX_FD_COMPACT) against the oracle (oracle/compact.py in oracle/rhs.py).
 
 The line solves of the gradients and of the divergence (x: one wavefront per line with
-an affine scan; y, z: one thread per line, z cyclic) feed the same physics as the
-explicit path.  Bars as in test_gpu_parity: 1e-12 normwise per field for the FP64 path
+an affine scan; y, z: 16 lines per block held on chip, 16 chunks per line joined by an
+affine scan, z cyclic; lines over 512 points: one thread per line) feed the same physics
+as the explicit path.  Bars as in test_gpu_parity: 1e-12 normwise per field for the FP64 path
 (RHS and Q after the stages), 1e-5 for the mixed form.
 """
 import dataclasses
@@ -104,6 +105,18 @@ def test_compact_c4_jet_3d_reduced():
 
 def test_compact_c4_jet_3d_fourth_order():
     _run(compact(fields.get_config("c4").scaled(36, 24, 16), fd_order=4), 1)
+
+
+@pytest.mark.parametrize("shape", [(37, 45, 21), (21, 17, 9), (18, 70, 33)])
+def test_compact_c4_ragged_3d(shape):
+    """Line counts off the 16-line groups and line lengths off the 16-chunk split (empty
+    and partial chunks, y and cyclic z)."""
+    _run(compact(fields.get_config("c4").scaled(*shape)), 1)
+
+
+def test_compact_tall_lines_fallback():
+    """y lines over 512 points take the thread-per-line solve."""
+    _run(compact(fields.get_config("c2").scaled(20, 530)), 1)
 
 
 def test_compact_stefan_maxwell_and_tpg():
