@@ -39,15 +39,34 @@ RK_NAMES = {0: "2N-RK3 (Williamson)", 1: "2N-RK4(3)5 (Carpenter-Kennedy)",
 # valid only for the kernel source whose SHA-256 prefix is given (profiles/ holds the
 # summaries and the commands).  Any other source reports traffic null.
 TRAFFIC = {
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'flux'): 12619271040,
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'div'): 11052190460,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'cderiv'): 5218593297,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'div'): 510590287,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'flux'): 424308791,
-    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'prim'): 25475257,
-    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'div'): 61047328,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'flux'): 10417029495,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'div'): 10836349564,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'prim'): 5226808736,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'ad_d4'): 2487036928,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'ad_src'): 995690753,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'flux'): 11273504761,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'prim'): 5226590737,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'fin'): 6866685647,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_d4'): 2463394837,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_filter_z'): 2281594296,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_src'): 1476264180,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'cderiv'): 2818638005,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'div'): 510376156,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'prim'): 260069889,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'flux'): 414356944,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'ad_d4'): 171138379,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'ad_src'): 35601637,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'prim'): 25479353,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'div'): 61060525,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'flux'): 37728628,
+    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'div'): 27156517,
+    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'prim'): 11534354,
+    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'flux'): 19698875,
+    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'prim'): 35965227,
+    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'flux'): 43011897,
+    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'div'): 61073026,
 }
-TRAFFIC_SOURCE_SHA = "98bbf21fb17b2c89"
+TRAFFIC_SOURCE_SHA = "9abcb2fe217d237a"
 
 
 def source_sha():
@@ -106,7 +125,8 @@ def algorithmic_bytes(cfg, rt, surrogate=False):
     nsrc = nd + 1 + (5 if air else 0)
     flux_in = 8 * (nd + 1 + (5 if (air and nd == 3) else 0) + (1 if (not air or nd == 3) else 0))
     if comp:
-        flux_in = 8 * (nd + 1 + (5 if air else 0) + 1) + 8 * nd * nsrc
+        # u, T, p at the point (X_s too for Stefan-Maxwell) and the gradient planes
+        flux_in = 8 * (nd + 1 + 1 + (5 if sm else 0)) + 8 * nd * nsrc
     flux_in += 8 * nv + rt * flux_wp + (rt * nad if ad else 0)
     out["flux"] = (flux_in + 8 * nd * nv, 1)
     sponge = 8 * nv * sponge_fraction(cfg)
@@ -264,7 +284,7 @@ def main():
         cfg = dataclasses.replace(cfg, name=re.sub(r"_\d+x\d+(x\d+)?$", "_" + "x".join(map(str, dims)),
                                                     cfg.name))
     if args.stefan_maxwell:
-        cfg = dataclasses.replace(cfg, diffusion=1)
+        cfg = dataclasses.replace(cfg, diffusion=1, name=cfg.name.replace("air5_", "air5_sm_", 1))
     if args.scheme == "compact":
         cfg = dataclasses.replace(cfg, fd_scheme=1)
     if args.rk is not None:

@@ -1298,7 +1298,7 @@ __device__ __forceinline__ void flux_tile(const Dev& d, const double* __restrict
   constexpr int NPI = ORDER == 6 ? 3 : 2;
   // derivative of source plane a along direction b (z is periodic: central pairs only)
   auto deriv = [&](int a, int b) -> RT {
-    if constexpr (CG) return RT(Gc[((long)b * NSRC + a) * N + idx]);
+    if constexpr (CG) return RT(ld_once(&Gc[((long)b * NSRC + a) * N + idx]));
     if (ND == 3 && b == 1) return sten_apply<RT>(sd[1], Wd + (long)a * N + idx) * md[1];
     const double* f = smem + a * TILE_E;
     if (b == 2) return sten_apply<RT, NPI>(sd[b], f) * md[b];
@@ -2786,20 +2786,20 @@ __global__ __launch_bounds__(256) void k_fin(Dev d, const RT* __restrict__ Wp, c
   if (d.hold && p.j < 3) held = held || d.hold[((long)p.k * 3 + p.j) * d.nx + p.i];
 #pragma unroll
   for (int k = 0; k < nvar; ++k) {
-    double R = Racc[k * N + idx];
-    if (GAS == AIR5 && k < NS) R = R + double(Wp[(d.w_wdot + k) * N + idx]);
-    const double qv = (MODE == MODE_RK) ? Qio[k * N + idx] : Qin[k * N + idx];
+    double R = ld_once(&Racc[k * N + idx]);
+    if (GAS == AIR5 && k < NS) R = R + double(ld_once(&Wp[(d.w_wdot + k) * N + idx]));
+    const double qv = (MODE == MODE_RK) ? ld_once(&Qio[k * N + idx]) : ld_once(&Qin[k * N + idx]);
     if (Qref != nullptr && sig != 0.0) R = R - sig * (qv - Qref[k * N + idx]);
     if (held || (p.j == 0 && k >= ns && k < ns + ND)) R = 0.0;
     if (MODE == MODE_RHS) {
       Rout[k * N + idx] = R;
     } else {
-      const double dq = rkf == RKF_SSP_FIRST ? 0.0 : dQio[k * N + idx];
+      const double dq = rkf == RKF_SSP_FIRST ? 0.0 : ld_once(&dQio[k * N + idx]);
       double qn, dqn;
       bool wdq;
       rk_update(rkf, A, B, dt, R, qv, dq, qn, dqn, wdq);
-      if (wdq) dQio[k * N + idx] = dqn;
-      Qio[k * N + idx] = qn;
+      if (wdq) st_once(dqn, &dQio[k * N + idx]);
+      st_once(qn, &Qio[k * N + idx]);
     }
   }
 }
