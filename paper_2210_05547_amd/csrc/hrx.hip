@@ -2739,6 +2739,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CL <= 16 ? 
   }
 }
 
+// k_cd_colp: the chunk length, the power of two >= n / 16 (up to 32: 80 KB of LDS)
+int cdcol_chunk(int n) {
+  int c = 1;
+  while (16 * c < n) c *= 2;
+  return c;
+}
+bool cdcol_fits(int n) { return n >= 2 && n <= 512; }
+// the thread-per-line solve (lines over 512 points) keeps its forward values in nvar
+// temporary planes when it accumulates
+bool cd_needs_temp(const Dev& d) {
+  return d.compact && !(cdcol_fits(d.ny) && (d.ndim < 3 || cdcol_fits(d.nz)));
+}
+
 // Artificial-diffusivity sources |S| and theta of the compact scheme, pointwise from the
 // velocity-gradient planes Gc[b][a].
 template <int ND, class RT>
@@ -4031,7 +4044,8 @@ int hrx_create(const hrx_config* cfg, hrx_ctx** out) {
     d.cl[2].q = nzc ? q : nullptr;
     d.compact = 1;
     if (hipMalloc(&ctx->G, sizeof(double) * N * nd * d.nsrc) != hipSuccess) return fail(HRX_ENOMEM);
-    if (hipMalloc(&ctx->Ct, sizeof(double) * N * d.nvar) != hipSuccess) return fail(HRX_ENOMEM);
+    if (cd_needs_temp(d) && hipMalloc(&ctx->Ct, sizeof(double) * N * d.nvar) != hipSuccess)
+      return fail(HRX_ENOMEM);
   }
   if (hipMalloc(&ctx->counters, NCOUNT * CSLOTS * sizeof(unsigned long long)) != hipSuccess)
     return fail(HRX_ENOMEM);
@@ -4242,14 +4256,6 @@ void launch_bc(hrx_ctx* ctx, double* Q, hipStream_t st) {
     }
   });
 }
-
-// k_cd_colp: the chunk length, the power of two >= n / 16 (up to 32: 80 KB of LDS)
-int cdcol_chunk(int n) {
-  int c = 1;
-  while (16 * c < n) c *= 2;
-  return c;
-}
-bool cdcol_fits(int n) { return n >= 2 && n <= 512; }
 
 // Compact first derivatives of nplanes planes along direction dir: f (plane stride fps)
 // -> out (plane stride ops), out = scale m D f, or out += scale m D f (acc; the forward
@@ -4506,7 +4512,7 @@ int hrx_rhs_eval_noalloc(hrx_ctx* ctx, const double* Q, const double* Q_ref, dou
   const size_t bF = al(sizeof(double) * N * ctx->nF);
   const size_t bAD = d.ad_on ? al(ctx->rt_size * N * d.nad * 2) : 0;
   const size_t bG = d.compact ? al(sizeof(double) * N * d.ndim * d.nsrc) : 0;
-  const size_t bCt = d.compact ? al(sizeof(double) * N * d.nvar) : 0;
+  const size_t bCt = cd_needs_temp(d) ? al(sizeof(double) * N * d.nvar) : 0;
   if (bWd + bWp + bF + bAD + bG + bCt > NOALLOC_BYTES) return HRX_ETOOBIG;
   hipStream_t st = (hipStream_t)hip_stream;
   ctx->last_stream = st;
