@@ -2369,13 +2369,16 @@ __global__ __launch_bounds__(64) void k_cd_x(int n, const double* __restrict__ f
   }
 }
 
-// The same solve with the chunk length a power of two C (>= the lines' n / 64) and up to
-// four lines per block sharing the LU factors: the right-hand sides are formed first,
-// each lane reading consecutive points (no bank conflicts), and kept transposed -- element
-// e at slot (e mod C) 64 + e / C -- with the factors, so that the lanes stepping through
-// their chunks touch 64 consecutive slots.  Where C = n / 64 exactly (every line of
-// 64 C points) the chunks, and so the results, are those of k_cd_x.
-template <bool ACC, int C>
+// The same solve with the chunk length a power of two C (>= the lines' n / 64), four
+// wavefronts per block sharing the LU factors, and K lines per wavefront taken in turn:
+// a lane holds points lane + 64 q of the line in registers and forms their right-hand
+// sides with the neighbours taken from the lanes that hold them; the right-hand sides
+// are kept transposed -- element e at slot (e mod C) 64 + e / C -- with the factors, so
+// that the lanes stepping through their chunks touch 64 consecutive slots.  The next
+// line's loads are issued before the current line's solve, and the metric is loaded once
+// per wavefront.  Where C = n / 64 exactly (every line of 64 C points) the chunks are
+// those of k_cd_x.
+template <bool ACC, int C, int K>
 __global__ __launch_bounds__(256) void k_cd_xp(int n, long nlines, const double* __restrict__ f,
                                                long fps, double* out, long ops,
                                                const double* __restrict__ m, double scale,
@@ -2389,8 +2392,7 @@ __global__ __launch_bounds__(256) void k_cd_xp(int n, long nlines, const double*
   double* slo = sm;
   double* sup = sm + S;
   double* siu = sm + 2 * S;
-  double* sf = sm + (3 + 2 * w) * S;   // the line, by point
-  double* sr = sf + S;                 // r, then d, then x, transposed
+  double* sr = sm + (3 + w) * S;       // r, then d, then x, transposed
   auto slot = [](int e) { return (e & (C - 1)) * 64 + (e >> LC); };
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int q = slot(e);
@@ -2398,110 +2400,140 @@ __global__ __launch_bounds__(256) void k_cd_xp(int n, long nlines, const double*
     sup[q] = L.up[e];
     siu[q] = L.iu[e];
   }
-  const long line = min((long)blockIdx.x * nw + w, nlines - 1);   // extra waves redo the last
-  const bool live = (long)blockIdx.x * nw + w < nlines;
-  const double* fl = f + (long)blockIdx.y * fps + line * n;
-  double* ol = out + (long)blockIdx.y * ops + line * n;
-  {
-    // every load of the line in flight before the first LDS store
-    double v[C];
+  const long line0 = ((long)blockIdx.x * nw + w) * K;   // this wavefront's K lines
+  const double* fp = f + (long)blockIdx.y * fps;
+  double* op = out + (long)blockIdx.y * ops;
+  // the metric (the same for every line) and the first line, point lane + 64 q in v[q]
+  double v[C], mv[C];
 #pragma unroll
-    for (int q = 0; q < C; ++q) {
-      const int i = lane + 64 * q;
-      v[q] = i < n ? ld_once(&fl[i]) : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < C; ++q)
-      if (lane + 64 * q < n) sf[lane + 64 * q] = v[q];
+  for (int q = 0; q < C; ++q) {
+    const int i = min(lane + 64 * q, n - 1);
+    mv[q] = m[i];
+    v[q] = ld_once(&fp[min(line0, nlines - 1) * n + i]);
   }
-  __syncthreads();
-  for (int i = lane; i < n; i += 64) {
-    double wv[5];
+  __syncthreads();   // the factors, staged by the whole block
+  for (int kk = 0; kk < K; ++kk) {
+    const long line = min(line0 + kk, nlines - 1);   // lines past the end redo the last
+    const bool live = line0 + kk < nlines;
+    {
+      // right-hand sides: the neighbours i -+ 1, 2 from the lanes that hold them (from the
+      // previous or next q where they wrap past lane 0 or 63)
+      double m2p = 0.0, m1p = 0.0;
+      double m2 = __shfl(v[0], (lane - 2) & 63), m1 = __shfl(v[0], (lane - 1) & 63);
+      double p1 = __shfl(v[0], (lane + 1) & 63), p2 = __shfl(v[0], (lane + 2) & 63);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int q = i + k - 2;
-      wv[k] = (q >= 0 && q < n) ? sf[q] : 0.0;
-    }
-    sr[slot(i)] = crow(wv, i, n, order, false);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int nk = max(0, min(C, n - lane * C));
-  // forward: d_i = r_i - lo_i d_{i-1}; the chunk maps d_{a-1} to d_{b-1} as A x + B
-  double A = 1.0, B = 0.0;
-#pragma unroll
-  for (int k = 0; k < C; ++k) {
-    if (k < nk) {
-      const double li = slo[k * 64 + lane];
-      B = sr[k * 64 + lane] - li * B;
-      A = -li * A;
-    }
-  }
-  for (int off = 1; off < 64; off <<= 1) {
-    const double Ap = __shfl_up(A, off), Bp = __shfl_up(B, off);
-    if (lane >= off) {
-      B = A * Bp + B;
-      A = A * Ap;
-    }
-  }
-  double prev = __shfl_up(B, 1);
-  if (lane == 0) prev = 0.0;
-#pragma unroll
-  for (int k = 0; k < C; ++k) {
-    if (k < nk) {
-      const double di = sr[k * 64 + lane] - slo[k * 64 + lane] * prev;
-      sr[k * 64 + lane] = di;
-      prev = di;
-    }
-  }
-  // backward: x_i = (d_i - up_i x_{i+1}) iu_i; the chunk maps x_b to x_a as A x + B
-  A = 1.0;
-  B = 0.0;
-#pragma unroll
-  for (int k = C - 1; k >= 0; --k) {
-    if (k < nk) {
-      const double iu = siu[k * 64 + lane], u = sup[k * 64 + lane];
-      B = (sr[k * 64 + lane] - u * B) * iu;
-      A = -(u * iu) * A;
-    }
-  }
-  for (int off = 1; off < 64; off <<= 1) {
-    const double An = __shfl_down(A, off), Bn = __shfl_down(B, off);
-    if (lane + off < 64) {
-      B = A * Bn + B;
-      A = A * An;
-    }
-  }
-  double next = __shfl_down(B, 1);
-  if (lane == 63) next = 0.0;
-#pragma unroll
-  for (int k = C - 1; k >= 0; --k) {
-    if (k < nk) {
-      const double xi = (sr[k * 64 + lane] - sup[k * 64 + lane] * next) * siu[k * 64 + lane];
-      sr[k * 64 + lane] = xi;
-      next = xi;
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (live) {
-    double o[C], mv[C];
-#pragma unroll
-    for (int q = 0; q < C; ++q) {
-      const int i = min(lane + 64 * q, n - 1);
-      mv[q] = m[i];
-      o[q] = ACC ? ld_once(&ol[i]) : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < C; ++q) {
-      const int i = lane + 64 * q;
-      if (i < n) {
-        const double v = scale * mv[q] * sr[slot(i)];
-        st_once(ACC ? o[q] + v : v, &ol[i]);
+      for (int q = 0; q < C; ++q) {
+        double p1n = 0.0, p2n = 0.0;
+        if (q + 1 < C) {
+          p1n = __shfl(v[q + 1], (lane + 1) & 63);
+          p2n = __shfl(v[q + 1], (lane + 2) & 63);
+        }
+        const int i = lane + 64 * q;
+        if (i < n) {
+          double wv[5];
+          wv[0] = lane >= 2 ? m2 : m2p;
+          wv[1] = lane >= 1 ? m1 : m1p;
+          wv[2] = v[q];
+          wv[3] = lane <= 62 ? p1 : p1n;
+          wv[4] = lane <= 61 ? p2 : p2n;
+          sr[slot(i)] = crow(wv, i, n, order, false);
+        }
+        if (q + 1 < C) {
+          m2p = m2;
+          m1p = m1;
+          m2 = __shfl(v[q + 1], (lane - 2) & 63);
+          m1 = __shfl(v[q + 1], (lane - 1) & 63);
+          p1 = p1n;
+          p2 = p2n;
+        }
       }
     }
+    // the next line's loads, in flight during this line's solve
+    if (kk + 1 < K) {
+      const long ln = min(line0 + kk + 1, nlines - 1);
+#pragma unroll
+      for (int q = 0; q < C; ++q) v[q] = ld_once(&fp[ln * n + min(lane + 64 * q, n - 1)]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nk = max(0, min(C, n - lane * C));
+    // forward: d_i = r_i - lo_i d_{i-1}; the chunk maps d_{a-1} to d_{b-1} as A x + B
+    double A = 1.0, B = 0.0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      if (k < nk) {
+        const double li = slo[k * 64 + lane];
+        B = sr[k * 64 + lane] - li * B;
+        A = -li * A;
+      }
+    }
+    for (int off = 1; off < 64; off <<= 1) {
+      const double Ap = __shfl_up(A, off), Bp = __shfl_up(B, off);
+      if (lane >= off) {
+        B = A * Bp + B;
+        A = A * Ap;
+      }
+    }
+    double prev = __shfl_up(B, 1);
+    if (lane == 0) prev = 0.0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      if (k < nk) {
+        const double di = sr[k * 64 + lane] - slo[k * 64 + lane] * prev;
+        sr[k * 64 + lane] = di;
+        prev = di;
+      }
+    }
+    // backward: x_i = (d_i - up_i x_{i+1}) iu_i; the chunk maps x_b to x_a as A x + B
+    A = 1.0;
+    B = 0.0;
+#pragma unroll
+    for (int k = C - 1; k >= 0; --k) {
+      if (k < nk) {
+        const double iu = siu[k * 64 + lane], u = sup[k * 64 + lane];
+        B = (sr[k * 64 + lane] - u * B) * iu;
+        A = -(u * iu) * A;
+      }
+    }
+    for (int off = 1; off < 64; off <<= 1) {
+      const double An = __shfl_down(A, off), Bn = __shfl_down(B, off);
+      if (lane + off < 64) {
+        B = A * Bn + B;
+        A = A * An;
+      }
+    }
+    double next = __shfl_down(B, 1);
+    if (lane == 63) next = 0.0;
+#pragma unroll
+    for (int k = C - 1; k >= 0; --k) {
+      if (k < nk) {
+        const double xi = (sr[k * 64 + lane] - sup[k * 64 + lane] * next) * siu[k * 64 + lane];
+        sr[k * 64 + lane] = xi;
+        next = xi;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (live) {
+      double* ol = op + line * n;
+      double o[C];
+#pragma unroll
+      for (int q = 0; q < C; ++q) o[q] = ACC ? ld_once(&ol[min(lane + 64 * q, n - 1)]) : 0.0;
+#pragma unroll
+      for (int q = 0; q < C; ++q) {
+        const int i = lane + 64 * q;
+        if (i < n) {
+          const double x = scale * mv[q] * sr[slot(i)];
+          st_once(ACC ? o[q] + x : x, &ol[i]);
+        }
+      }
+    }
+    // every lane has read this line's results before the next line's are written
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -4267,23 +4299,35 @@ void launch_cd(hrx_ctx* ctx, int dir, const double* f, long fps, double* out, lo
   const int ord = d.fd_order;
   timed(ctx, K_CDERIV, st, [&] {
     if (dir == 0) {
-      // chunks of C = the power of two >= nx / 64 points per lane, up to four lines per
-      // block within 64 KB of LDS (factors + two arrays per line)
+      // chunks of C = the power of two >= nx / 64 points per lane, four wavefronts per
+      // block within 64 KB of LDS (factors + one array per wavefront)
       const long nlines = N / d.nx;
       int C = 1;
       while (64 * C < d.nx) C *= 2;
       const long S = 64L * C;
-      const int nw = (int)std::max(1L, std::min(4L, ((65536L / (8 * S)) - 3) / 2));
-      const dim3 g((unsigned)((nlines + nw - 1) / nw), (unsigned)nplanes);
-      const size_t sh = (size_t)(3 + 2 * nw) * S * sizeof(double);
+      const int nw = (int)std::max(1L, std::min(4L, (65536L / (8 * S)) - 3));
+      // K lines per wavefront (up to 8) while the launch keeps 2048 or more blocks
+      int K = 1;
+      while (K < 8 && nlines * nplanes >= (long)nw * (2 * K) * 2048) K *= 2;
+      const dim3 g((unsigned)((nlines + (long)nw * K - 1) / ((long)nw * K)), (unsigned)nplanes);
+      const size_t sh = (size_t)(3 + nw) * S * sizeof(double);
       auto go = [&](auto cc) {
         constexpr int CC = decltype(cc)::value;
-        if (acc)
-          k_cd_xp<true, CC><<<g, 64 * nw, sh, st>>>(d.nx, nlines, f, fps, out, ops, d.mx, scale,
-                                                     ord, d.cl[0]);
-        else
-          k_cd_xp<false, CC><<<g, 64 * nw, sh, st>>>(d.nx, nlines, f, fps, out, ops, d.mx, scale,
-                                                      ord, d.cl[0]);
+        auto gk = [&](auto kk) {
+          constexpr int KK = decltype(kk)::value;
+          if (acc)
+            k_cd_xp<true, CC, KK><<<g, 64 * nw, sh, st>>>(d.nx, nlines, f, fps, out, ops, d.mx,
+                                                           scale, ord, d.cl[0]);
+          else
+            k_cd_xp<false, CC, KK><<<g, 64 * nw, sh, st>>>(d.nx, nlines, f, fps, out, ops, d.mx,
+                                                            scale, ord, d.cl[0]);
+        };
+        switch (K) {
+          case 1: gk(std::integral_constant<int, 1>()); break;
+          case 2: gk(std::integral_constant<int, 2>()); break;
+          case 4: gk(std::integral_constant<int, 4>()); break;
+          default: gk(std::integral_constant<int, 8>()); break;
+        }
       };
       switch (C) {
         case 1: go(std::integral_constant<int, 1>()); break;

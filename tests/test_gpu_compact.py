@@ -2,7 +2,7 @@
 fd_scheme = HRX_FD_COMPACT) against the oracle (oracle/compact.py in oracle/rhs.py).
 
 The line solves of the gradients and of the divergence (x: one wavefront per line with
-an affine scan; y, z: 16 lines per block held on chip, 16 chunks per line joined by an
+an affine scan, up to 8 lines per wavefront in turn; y, z: 16 lines per block held on chip, 16 chunks per line joined by an
 affine scan, z cyclic; lines over 512 points: one thread per line) feed the same physics
 as the explicit path.  Bars as in test_gpu_parity: 1e-12 normwise per field for the FP64 path
 (RHS and Q after the stages), 1e-5 for the mixed form.
@@ -111,6 +111,13 @@ def test_compact_c4_jet_3d_fourth_order():
 def test_compact_c4_ragged_3d(shape):
     """Line counts off the 16-line groups and line lengths off the 16-chunk split (empty
     and partial chunks, y and cyclic z)."""
+    _run(compact(fields.get_config("c4").scaled(*shape)), 1)
+
+
+@pytest.mark.parametrize("shape", [(16, 127, 67), (100, 90, 25), (72, 61, 61)])
+def test_compact_x_lines_several_per_wavefront(shape):
+    """Grids with enough x lines that each wavefront of the x solve takes 8, 2 and 4 lines
+    in turn (line counts not a multiple of the lines per block)."""
     _run(compact(fields.get_config("c4").scaled(*shape)), 1)
 
 
