@@ -39,34 +39,34 @@ RK_NAMES = {0: "2N-RK3 (Williamson)", 1: "2N-RK4(3)5 (Carpenter-Kennedy)",
 # valid only for the kernel source whose SHA-256 prefix is given (profiles/ holds the
 # summaries and the commands).  Any other source reports traffic null.
 TRAFFIC = {
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'flux'): 10417029495,
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'div'): 10836349564,
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'prim'): 5226808736,
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'ad_d4'): 2487036928,
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'ad_src'): 995690753,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'flux'): 11273504761,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'prim'): 5226590737,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'fin'): 6866685647,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_d4'): 2463394837,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'flux'): 10420354968,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'div'): 10819204176,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'prim'): 5226817097,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'ad_d4'): 2481427874,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'ad_src'): 999554540,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'flux'): 11273500843,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'prim'): 5226705851,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'fin'): 6866683186,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_d4'): 2460931235,
     ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_filter_z'): 2281594296,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_src'): 1476264180,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'cderiv'): 2818638005,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'div'): 510376156,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'prim'): 260069889,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'flux'): 414356944,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'ad_d4'): 171138379,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'ad_src'): 35601637,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_src'): 1476263469,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'cderiv'): 2818649863,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'div'): 509909342,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'prim'): 260053408,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'flux'): 414190338,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'ad_d4'): 171198075,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'ad_src'): 35601708,
     ('flatplate_air5_m10_512x256', 131072, 'explicit', 'prim'): 25479353,
-    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'div'): 61060525,
-    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'flux'): 37728628,
-    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'div'): 27156517,
-    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'prim'): 11534354,
-    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'flux'): 19698875,
-    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'prim'): 35965227,
-    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'flux'): 43011897,
-    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'div'): 61073026,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'div'): 61059060,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'flux'): 37728585,
+    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'prim'): 35965355,
+    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'flux'): 43011983,
+    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'div'): 61110909,
+    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'div'): 27156674,
+    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'prim'): 11534510,
+    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'flux'): 19698405,
 }
-TRAFFIC_SOURCE_SHA = "9abcb2fe217d237a"
+TRAFFIC_SOURCE_SHA = "721ce8281577d4bc"
 
 
 def source_sha():
