@@ -28,9 +28,10 @@ Pins (tests/test_oracle_*.py) tie each module to something other than itself:
 printed constants, closed-form flows, exact rational stencil identities, 50-digit
 bisection, Gibbs-Helmholtz, detailed balance at an independently solved
 equilibrium, RK stability polynomials and convergence order, finite-difference
-gradients.  Parity unpinned (checked only through properties, not values): the
-artificial-diffusivity coefficient formulas of ``ad`` (a reading of Sec. 3.3, which
-prints none) and the absolute values of the Chapman-Enskog transport model beyond
-its pure-species/binary limits and a handbook plausibility check (Sec. 2.2.1 names
-the library that computes them but prints no model).
+gradients, closed forms of the artificial-diffusivity coefficients on a uniform grid
+(their formulas are a reading of Sec. 3.3, which prints none).  Parity unpinned
+(checked only through properties, not values): the absolute values of the
+Chapman-Enskog transport model beyond its pure-species/binary limits and a handbook
+plausibility check (Sec. 2.2.1 names the library that computes them but prints no
+model).
 """
