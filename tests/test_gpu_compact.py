@@ -121,6 +121,13 @@ def test_compact_x_lines_several_per_wavefront(shape):
     _run(compact(fields.get_config("c4").scaled(*shape)), 1)
 
 
+@pytest.mark.parametrize("base,shape", [("c2", (20, 300)), ("c4", (12, 300, 10)),
+                                        ("c4", (12, 16, 270))])
+def test_compact_long_on_chip_lines(base, shape):
+    """y and cyclic z lines of 257..512 points: the on-chip solve's longest chunks (32)."""
+    _run(compact(fields.get_config(base).scaled(*shape)), 1)
+
+
 def test_compact_tall_lines_fallback():
     """y lines over 512 points take the thread-per-line solve."""
     _run(compact(fields.get_config("c2").scaled(20, 530)), 1)
