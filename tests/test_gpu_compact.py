@@ -121,6 +121,11 @@ def test_compact_x_lines_several_per_wavefront(shape):
     _run(compact(fields.get_config("c4").scaled(*shape)), 1)
 
 
+def test_compact_x_lines_longest_chunks_several_per_wavefront():
+    """x lines of 520 points (chunks of 16 per lane) with two lines per wavefront."""
+    _run(compact(fields.get_config("c4").scaled(520, 20, 110)), 0)
+
+
 @pytest.mark.parametrize("base,shape", [("c2", (20, 300)), ("c4", (12, 300, 10)),
                                         ("c4", (12, 16, 270))])
 def test_compact_long_on_chip_lines(base, shape):
