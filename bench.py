@@ -39,34 +39,34 @@ RK_NAMES = {0: "2N-RK3 (Williamson)", 1: "2N-RK4(3)5 (Carpenter-Kennedy)",
 # valid only for the kernel source whose SHA-256 prefix is given (profiles/ holds the
 # summaries and the commands).  Any other source reports traffic null.
 TRAFFIC = {
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'flux'): 10420354968,
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'div'): 10819204176,
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'prim'): 5226817097,
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'ad_d4'): 2481427874,
-    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'ad_src'): 999554540,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'flux'): 11273500843,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'prim'): 5226705851,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'fin'): 6866683186,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_d4'): 2460931235,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_filter_z'): 2281594296,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_src'): 1476263469,
-    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'cderiv'): 2818649863,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'div'): 509909342,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'prim'): 260053408,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'flux'): 414190338,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'ad_d4'): 171198075,
-    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'ad_src'): 35601708,
-    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'prim'): 25479353,
-    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'div'): 61059060,
-    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'flux'): 37728585,
-    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'prim'): 35965355,
-    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'flux'): 43011983,
-    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'div'): 61110909,
-    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'div'): 27156674,
-    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'prim'): 11534510,
-    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'flux'): 19698405,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'flux'): 10418798643,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'div'): 10832650961,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'prim'): 5226785684,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'ad_d4'): 2488781520,
+    ('jisc_air5_m8_512x256x128', 16777216, 'explicit', 'ad_src'): 1004862212,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'flux'): 11273500530,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'prim'): 5226632943,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'fin'): 6866683414,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_d4'): 2464529902,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_filter_z'): 2281594325,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'ad_src'): 1476263483,
+    ('jisc_air5_m8_512x256x128', 16777216, 'compact', 'cderiv'): 2818649685,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'div'): 510500769,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'prim'): 260053849,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'flux'): 413994935,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'ad_d4'): 171196927,
+    ('sbli_air5_m5.92_2048x512', 1048576, 'explicit', 'ad_src'): 35601651,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'prim'): 25479495,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'div'): 61078061,
+    ('flatplate_air5_m10_512x256', 131072, 'explicit', 'flux'): 37727903,
+    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'prim'): 35965369,
+    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'flux'): 43011044,
+    ('flatplate_air5_sm_m10_512x256', 131072, 'explicit', 'div'): 61037132,
+    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'div'): 27156759,
+    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'prim'): 11534425,
+    ('flatplate_tpg_m6_512x256', 131072, 'explicit', 'flux'): 19698747,
 }
-TRAFFIC_SOURCE_SHA = "721ce8281577d4bc"
+TRAFFIC_SOURCE_SHA = "9f613edb3f76c77a"
 
 
 def source_sha():

@@ -42,7 +42,7 @@ typedef enum {
   HRX_EINVAL = -1,   /* bad argument or configuration */
   HRX_EHIP = -2,     /* a HIP runtime call failed */
   HRX_ENOMEM = -3,   /* scratch allocation failed in hrx_create */
-  HRX_EUNSUP = -4,   /* valid request that this build does not support */
+  HRX_EUNSUP = -4,   /* valid request that the library does not support */
   /* per-point failures found by the kernels (Sec. 3.4: every state evaluation solves a
    * nonlinear equation, which can fail); reported by hrx_get_counters, never by the
    * asynchronous compute calls themselves */

@@ -188,7 +188,7 @@ __device__ __forceinline__ int wrap_per(int q, int n) {
 // Values a kernel touches once and no other block re-reads (the point's own state,
 // fluxes and updates) are loaded and stored with the nontemporal hint, so that they do
 // not displace from L2 the stencil neighbours that nearby blocks read again (measured on
-// the jet box: flux -4 %, 3-D divergence -3.5 %, same bits; on the 2-D SBLI the flux
+// the 512 x 256 x 128 jet: flux -4 %, 3-D divergence -3.5 %, same bits; on the 2-D SBLI the flux
 // -3 % from the loads alone).
 template <class T>
 __device__ __forceinline__ T ld_once(const T* p) { return __builtin_nontemporal_load(p); }
@@ -812,7 +812,7 @@ __global__ __launch_bounds__(64) void k_ad_filter_z(Dev d, const RT* __restrict_
 // that need no value read a valid one), and the rows' spacings come from LDS: the vector
 // memory counter is waited on in order, so a conditional load, a load used in its own
 // row or a register moved while its load is in flight makes the wait drain every load in
-// flight (measured on the jet box: 1.30 -> 0.85 ms with the 3-D form below).
+// flight (measured on the 512 x 256 x 128 jet: 1.30 -> 0.85 ms with the 3-D form below).
 // Segments of 24 rows in 2-D (SBLI: about six wavefronts per SIMD, all resident) and 128
 // in 3-D (fewer halo rows; the grid still has 20 blocks per CU) -- measured.
 constexpr int MW = 64, MO = MW - 8, MSEG2 = 24, MSEG3 = 128;
@@ -2611,7 +2611,7 @@ __global__ __launch_bounds__(128) void k_cd_col(int n, long s, int ncx, int nc2,
 // region, so that a step of the 64 lanes touches 64 consecutive slots; the factors are
 // held the same way ((i mod CL) 16 + i / CL).  f and out are streamed with the nontemporal
 // hint.  Up to CL = 16 the registers are capped at four wavefronts per SIMD (measured:
-// the jet box's y and z solves -6 %; CL = 32 would spill).
+// the 512 x 256 x 128 jet's y and z solves -6 %; CL = 32 would spill).
 template <bool ACC, bool PER, int CL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CL <= 16 ? 4 : 1))) void k_cd_colp(int n, long s, int ncx, long s2,
                                                  const double* __restrict__ f, long fps,
@@ -3786,7 +3786,7 @@ const char* hrx_strerror(int code) {
     case HRX_EINVAL: return "invalid argument or configuration";
     case HRX_EHIP: return "HIP runtime error";
     case HRX_ENOMEM: return "device memory allocation failed";
-    case HRX_EUNSUP: return "not supported by this build";
+    case HRX_EUNSUP: return "not supported by this library";
     case HRX_ENEWTON: return "the energy inversion did not converge at some point";
     case HRX_EDOMAIN: return "an energy below e(50 K) at some point";
     case HRX_ENONFINITE: return "a non-finite state or a non-positive density at some point";
